@@ -1,0 +1,208 @@
+"""Oracle Stokes operator: assembled element matrices, SpMV and direct solve.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The matrix-free product of eq:matfree equals, up to rounding order, the
+assembled sparse product  y = sum_e I_e^T A_e I_e x.  This module therefore
+forms every element matrix explicitly from eq:elemmat, evaluated with the one
+quadrature point q_c = (1/3, 1/3, 0) of weight w_q = 1 (Sec. 4, eq:oneptenergy:
+V_e = w_q |det J(q_c)|; the reference wedge has volume 1/2 * 2 = 1), assembles
+them with scipy, and multiplies.  It deliberately does NOT use the strain
+contraction of eq:epsq / eq:localapply that the GPU kernel uses.
+
+Readings (the same on both sides):
+* geometry: isoparametric 6-node map x(xi, eta, zeta) = sum_j N_j x_j, x_j the
+  physical node positions (chordal triangle times linear radius);
+* pressure: W1 on the coarse grid (level - 1, nr / 2); its value inside a fine
+  wedge is the fine-W1 interpolant P p of the coarse nodal values, so that
+  B = P^T B_f with B_f the divergence form against fine W1 test functions;
+* sign: B is the weak form of -div, (B_f)_{i,(j,c)} = -V_e N_i(q_c) d_c phi_j(q_c);
+* Dirichlet: velocity rows on both spheres become identity rows and their
+  columns are dropped:  K_D = [[D A D + (I - D), D B^T], [B D, 0]];
+* per-wedge viscosity: eta(q_c) is the wedge's value; for temperature-driven
+  laws it is the law evaluated at the mean of the six nodal temperatures and
+  the wedge's mid radius (the value of the W1 interpolant at q_c);
+* pressure normalisation: the nodal mean over unique pressure nodes is zero.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .mesh import ShellMesh, SphereHierarchy, prolongation
+
+QC = (1.0 / 3.0, 1.0 / 3.0, 0.0)   # barycentre of the reference wedge (Sec. 4)
+W_Q = 1.0                          # weight of the one-point rule
+
+
+def ref_basis(xi: float, eta: float, zeta: float):
+    """eq:wedgebasis: N_j = N^lat_{j mod 3}(xi, eta) N^rad_{floor(j/3)}(zeta).
+
+    Returns (N[6], dN[6, 3]) with dN[j] = (dN_j/dxi, dN_j/deta, dN_j/dzeta).
+    """
+    nl = np.array([1.0 - xi - eta, xi, eta])
+    dnl = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])   # d/dxi, d/deta of N^lat
+    nrad = np.array([0.5 * (1.0 - zeta), 0.5 * (1.0 + zeta)])
+    dnrad = np.array([-0.5, 0.5])
+    N = np.empty(6)
+    dN = np.empty((6, 3))
+    for j in range(6):
+        a, b = j % 3, j // 3
+        N[j] = nl[a] * nrad[b]
+        dN[j, 0] = dnl[a, 0] * nrad[b]
+        dN[j, 1] = dnl[a, 1] * nrad[b]
+        dN[j, 2] = nl[a] * dnrad[b]
+    return N, dN
+
+
+def wedge_geometry(xw: np.ndarray, point=QC):
+    """Jacobian, |det J| and physical basis gradients at a reference point.
+
+    xw: [n, 6, 3] physical node positions of n wedges.  J[:, a, m] =
+    sum_j x_j[a] dN_j/dxi_m; grad phi_j = J^{-T} dN_j.  Returns (J, V, grads)
+    with V = w_q |det J| (eq:oneptenergy) and grads[n, 6, 3].
+    """
+    _, dN = ref_basis(*point)
+    J = np.einsum("wja,jm->wam", xw, dN)
+    V = W_Q * np.abs(np.linalg.det(J))
+    Jinv = np.linalg.inv(J)
+    grads = np.einsum("jm,wma->wja", dN, Jinv)   # row j: dN_j^T J^{-1} = (J^{-T} dN_j)^T
+    return J, V, grads
+
+
+def element_matrices(xw: np.ndarray, eta: np.ndarray):
+    """A_e of eq:elemmat with the one-point rule, for n wedges -> [n, 18, 18].
+
+    Local DoF a = 3 j + c is basis function phi_j times unit vector e_c.
+    (A_e)_ab = V_e eta_e [2 eps(phi_a) : eps(phi_b) - 2/3 div(phi_a) div(phi_b)].
+    """
+    _, V, g = wedge_geometry(xw)
+    n = len(xw)
+    eye = np.eye(3)
+    # eps(phi_j e_c) = 1/2 (e_c g_j^T + g_j e_c^T), shape [n, 6, 3(c), 3, 3]
+    outer = np.einsum("cm,wjn->wjcmn", eye, g)
+    eps = 0.5 * (outer + np.swapaxes(outer, 3, 4))
+    eps = eps.reshape(n, 18, 3, 3)
+    div = g.reshape(n, 18)                      # div(phi_j e_c) = d_c phi_j
+    epseps = np.einsum("wamn,wbmn->wab", eps, eps)
+    A = (V * eta)[:, None, None] * (2.0 * epseps - (2.0 / 3.0) * div[:, :, None] * div[:, None, :])
+    return A
+
+
+def element_divergence(xw: np.ndarray):
+    """B_f per wedge, [n, 6, 18]: (B_f)_{i,a} = -V_e N_i(q_c) div(phi_a) at q_c."""
+    N, _ = ref_basis(*QC)
+    _, V, g = wedge_geometry(xw)
+    div = g.reshape(len(xw), 18)
+    return -(V[:, None, None] * N[None, :, None] * div[:, None, :])
+
+
+class StokesOracle:
+    """Assembled FP64 Stokes saddle-point operator on the (mt, nr) shell."""
+
+    def __init__(self, mt: int, nr: int, eta_wedge: np.ndarray, r_in: float = 0.55,
+                 r_out: float = 1.0, hierarchy: SphereHierarchy | None = None,
+                 chunk: int = 200_000):
+        self.mesh = m = ShellMesh(mt, nr, r_in, r_out, hierarchy)
+        self.mt, self.nr = mt, nr
+        eta_wedge = np.asarray(eta_wedge, dtype=np.float64)
+        if eta_wedge.shape != (m.n_wedges,):
+            raise ValueError("eta_wedge must have one value per wedge")
+        wn = m.wedge_nodes()
+        xyz = m.node_xyz()
+        nu = 3 * m.n_nodes
+        A = sp.csr_matrix((nu, nu))
+        Bf = sp.csr_matrix((m.n_nodes, nu))
+        for s in range(0, m.n_wedges, chunk):
+            w = wn[s:s + chunk]
+            xw = xyz[w]
+            dof = (w[:, :, None] * 3 + np.arange(3)[None, None, :]).reshape(len(w), 18)
+            Ae = element_matrices(xw, eta_wedge[s:s + chunk])
+            rows = np.repeat(dof, 18, axis=1).ravel()
+            cols = np.tile(dof, (1, 18)).ravel()
+            A = A + sp.csr_matrix((Ae.ravel(), (rows, cols)), shape=(nu, nu))
+            Be = element_divergence(xw)
+            rows = np.repeat(w, 18, axis=1).ravel()
+            cols = np.tile(dof, (1, 6)).ravel()
+            Bf = Bf + sp.csr_matrix((Be.ravel(), (rows, cols)), shape=(m.n_nodes, nu))
+        self.A = A.tocsr()
+        self.Bf = Bf.tocsr()
+        self.P = prolongation(m.h, m.L, nr)                 # fine nodes x coarse pressure nodes
+        self.B = (self.P.T @ self.Bf).tocsr()               # B = P^T B_f
+        self.n_u = nu
+        self.n_p = self.P.shape[1]
+        bnd = np.repeat(m.boundary_nodes(), 3)
+        self.dirichlet = bnd
+        d = (~bnd).astype(np.float64)
+        D = sp.diags(d)
+        I_D = sp.diags(1.0 - d)
+        self.A_D = (D @ self.A @ D + I_D).tocsr()
+        self.BT_D = (D @ self.B.T).tocsr()
+        self.B_D = (self.B @ D).tocsr()
+        self.K = sp.bmat([[self.A_D, self.BT_D], [self.B_D, None]], format="csr")
+
+    # -- products -----------------------------------------------------------
+    def apply(self, u: np.ndarray, p: np.ndarray):
+        """y = K_D [u; p] with u as [n_nodes, 3] and p as [n_p]."""
+        x = np.concatenate([np.asarray(u, np.float64).ravel(), np.asarray(p, np.float64)])
+        y = self.K @ x
+        return y[:self.n_u].reshape(-1, 3), y[self.n_u:]
+
+    def apply_A(self, u: np.ndarray):
+        return (self.A_D @ np.asarray(u, np.float64).ravel()).reshape(-1, 3)
+
+    # -- solve --------------------------------------------------------------
+    def solve(self, f: np.ndarray, g: np.ndarray | None = None):
+        """Exact discrete solution of K_D [u; p] = [f; g] (Sec. 7 saddle point).
+
+        f's Dirichlet rows hold the prescribed boundary velocity.  One pressure
+        DoF is pinned to remove the constant-pressure null space, then the
+        pressure is projected to zero nodal mean.
+        """
+        b = np.concatenate([np.asarray(f, np.float64).ravel(),
+                            np.zeros(self.n_p) if g is None else np.asarray(g, np.float64)])
+        i0 = self.n_u                       # first pressure DoF
+        keep = np.ones(self.K.shape[0])
+        keep[i0] = 0.0
+        Mk = sp.diags(keep)
+        K = (Mk @ self.K @ Mk + sp.diags(1.0 - keep)).tocsc()
+        b[i0] = 0.0
+        x = spla.splu(K).solve(b)
+        u = x[:self.n_u].reshape(-1, 3)
+        p = x[self.n_u:]
+        return u, p - p.mean()
+
+    def diag_A(self):
+        return self.A_D.diagonal().reshape(-1, 3)
+
+
+def eta_from_temperature(mesh: ShellMesh, T_node: np.ndarray, E: float, F: float = 0.0):
+    """Per-wedge viscosity eta_e = exp(-E Tbar_e + F (1 - r_m,e)).
+
+    Tbar_e is the W1 interpolant of T at q_c (mean of the six nodal values) and
+    r_m,e the radius of q_c; the exponential law family is the Frank-Kamenetskii
+    form of Sec. 8 with a depth factor.
+    """
+    wn = mesh.wedge_nodes()
+    Tbar = T_node[wn].mean(axis=1)
+    k = np.tile(np.arange(mesh.nr), len(mesh.tris))
+    rm = 0.5 * (mesh.r[k] + mesh.r[k + 1])
+    return np.exp(-E * Tbar + F * (1.0 - rm))
+
+
+def buoyancy_rhs(mesh: ShellMesh, T_node: np.ndarray, Ra: float):
+    """f_(j,c) = sum_e V_e N_j(q_c) Ra T(q_c) rhat_c(q_c)  (eq:stokes right-hand side,
+    Boussinesq form rho = alpha = 1, one-point rule).  Returns [n_nodes, 3]."""
+    wn = mesh.wedge_nodes()
+    xyz = mesh.node_xyz()
+    xw = xyz[wn]
+    N, _ = ref_basis(*QC)
+    _, V, _ = wedge_geometry(xw)
+    xq = np.einsum("j,wja->wa", N, xw)
+    rhat = xq / np.linalg.norm(xq, axis=1)[:, None]
+    Tq = np.einsum("j,wj->w", N, T_node[wn])
+    f = np.zeros((mesh.n_nodes, 3))
+    contrib = (V * Tq * Ra)[:, None, None] * N[None, :, None] * rhat[:, None, :]
+    np.add.at(f, wn, contrib)
+    return f

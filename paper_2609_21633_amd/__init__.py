@@ -1,0 +1,12 @@
+"""MI355X-native matrix-free wedge Stokes library (TERRA-NG, arXiv 2609.21633).
+
+The compute path is the C-ABI library ``libtng.so`` (hand-written HIP kernels
+for gfx950, declared in ``include/tng.h``); this package is a thin ctypes
+binding with the same names.  PyTorch tensors only carry device memory and
+the stream.  Importing the binding does not load the library; the first call
+does, and fails loudly if ``libtng.so`` has not been built.
+"""
+from .binding import (  # noqa: F401
+    OP_A, OP_B, OP_BT, OP_DIRICHLET, TngError, Context, Mesh, eta_coarsen, eta_from_temperature,
+    interface_sum, lib, stokes_apply,
+)

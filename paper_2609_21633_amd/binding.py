@@ -1,0 +1,197 @@
+"""ctypes binding of include/tng.h: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtng.so")
+
+OP_A, OP_BT, OP_B, OP_DIRICHLET = 1, 2, 4, 8
+F64, F32 = 0, 1
+
+_lib = None
+_vp = C.c_void_p
+
+
+class TngError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tng error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libtng.so (once).  Raises if it was not built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    L.tng_last_error.restype = C.c_char_p
+    sig = {
+        "tng_ctx_create": [C.c_int, _vp, C.POINTER(_vp)],
+        "tng_ctx_set_stream": [_vp, _vp],
+        "tng_ctx_destroy": [_vp],
+        "tng_mesh_create": [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(_vp)],
+        "tng_mesh_counts": [_vp, C.c_int, C.POINTER(C.c_longlong)],
+        "tng_mesh_coords": [_vp, C.c_int, _vp, _vp],
+        "tng_mesh_dup_groups": [_vp, C.c_int, _vp],
+        "tng_mesh_destroy": [_vp],
+        "tng_stokes_apply": [_vp, _vp, C.c_int, C.c_int, C.c_uint, _vp, C.POINTER(_vp), _vp,
+                             C.POINTER(_vp), _vp],
+        "tng_interface_sum": [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)],
+        "tng_ctx_profile": [_vp, C.c_int],
+        "tng_ctx_kernel_stats": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
+        "tng_eta_from_temperature": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.c_double, _vp],
+        "tng_eta_coarsen": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != 0:
+        raise TngError(rc, lib().tng_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _ptr3(ts):
+    if ts is None:
+        return None
+    arr = (_vp * 3)(*[t.data_ptr() for t in ts])
+    return arr
+
+
+def _prec(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("fields must be float32 or float64")
+
+
+class Context:
+    """HIP device + stream that every call enqueues on (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = _vp()
+        check(lib().tng_ctx_create(device, _vp(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        check(lib().tng_ctx_set_stream(self.h, _vp(stream.cuda_stream)))
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around the main kernel of every call (on this stream)."""
+        check(lib().tng_ctx_profile(self.h, 1 if enable else 0))
+
+    def kernel_stats(self, name: str):
+        """(total milliseconds, launches) of a kernel since profiling was enabled."""
+        ms, n = C.c_double(), C.c_longlong()
+        check(lib().tng_ctx_kernel_stats(self.h, name.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tng_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """Shell mesh with `levels` levels; level l = (mt / 2^l, nr / 2^l)."""
+
+    def __init__(self, ctx: Context | None, mt: int, nr: int, r_in: float = 0.55,
+                 r_out: float = 1.0, levels: int = 2):
+        """ctx=None builds the host-side description only (no device arrays)."""
+        self.ctx, self.mt, self.nr, self.r_in, self.r_out, self.levels = ctx, mt, nr, r_in, r_out, levels
+        h = _vp()
+        check(lib().tng_mesh_create(None if ctx is None else ctx.h, mt, nr, r_in, r_out, levels,
+                                    C.byref(h)))
+        self.h = h
+
+    def counts(self, level: int = 0) -> dict:
+        out = (C.c_longlong * 8)()
+        check(lib().tng_mesh_counts(self.h, level, out))
+        keys = ("m", "n", "lat_slots", "lat_unique", "node_slots", "nodes_unique", "cells", "wedges")
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def shape(self, level: int = 0):
+        c = self.counts(level)
+        return (10, c["m"] + 1, c["m"] + 1, c["n"] + 1)
+
+    def wedge_shape(self, level: int = 0):
+        c = self.counts(level)
+        return (10, c["m"], c["m"], c["n"], 2)
+
+    def coords(self, level: int = 0):
+        import numpy as np
+        c = self.counts(level)
+        xyz = np.empty((10, c["m"] + 1, c["m"] + 1, 3))
+        r = np.empty(c["n"] + 1)
+        check(lib().tng_mesh_coords(self.h, level, _vp(xyz.ctypes.data), _vp(r.ctypes.data)))
+        return xyz, r
+
+    def unique_ids(self, level: int = 0):
+        import numpy as np
+        c = self.counts(level)
+        uid = np.empty((10, c["m"] + 1, c["m"] + 1), dtype=np.int32)
+        check(lib().tng_mesh_dup_groups(self.h, level, _vp(uid.ctypes.data)))
+        return uid
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tng_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stokes_apply(ctx: Context, mesh: Mesh, level: int, flags: int, eta, u, p, y_u, y_p):
+    """y = K(eta) [u; p] on `level` (blocks selected by flags).  u, y_u: 3 node fields
+    (a [3, ...] tensor or a list); p, y_p: pressure fields on level + 1; any of them
+    may be None when the selected blocks do not use it."""
+    ref = next(t for t in (u[0] if u is not None else None, y_u[0] if y_u is not None else None,
+                           p, y_p) if t is not None)
+    check(lib().tng_stokes_apply(ctx.h, mesh.h, level, _prec(ref), flags, _ptr(eta), _ptr3(u),
+                                 _ptr(p), _ptr3(y_u), _ptr(y_p)))
+
+
+def interface_sum(ctx: Context, mesh: Mesh, level: int, fields, mode: int = 0):
+    arr = (_vp * len(fields))(*[f.data_ptr() for f in fields])
+    check(lib().tng_interface_sum(ctx.h, mesh.h, level, _prec(fields[0]), mode, len(fields), arr))
+
+
+def eta_from_temperature(ctx: Context, mesh: Mesh, level: int, T, E: float, F: float, eta_out):
+    """Per-wedge viscosity exp(-E Tbar + F (1 - r_m)) from a nodal temperature field."""
+    check(lib().tng_eta_from_temperature(ctx.h, mesh.h, level, _prec(T), _ptr(T), E, F,
+                                         _ptr(eta_out)))
+
+
+def eta_coarsen(ctx: Context, mesh: Mesh, fine_level: int, eta_fine, eta_coarse):
+    check(lib().tng_eta_coarsen(ctx.h, mesh.h, fine_level, _prec(eta_fine), _ptr(eta_fine),
+                                _ptr(eta_coarse)))

@@ -1,0 +1,241 @@
+// C entry points: argument validation and dispatch to the launchers.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "tng_internal.hpp"
+
+namespace tng {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
+
+void build_mesh(tng_mesh* mesh, int levels);
+
+ScopedKernelTimer::ScopedKernelTimer(const tng_ctx* ctx, const char* name)
+    : ctx_(const_cast<tng_ctx*>(ctx)), name_(name) {
+    if (!ctx_->profile) return;
+    TNG_HIP(hipEventCreate(&a_));
+    TNG_HIP(hipEventCreate(&b_));
+    TNG_HIP(hipEventRecord(a_, ctx_->stream));
+}
+
+ScopedKernelTimer::~ScopedKernelTimer() {
+    if (!a_) return;
+    if (hipEventRecord(b_, ctx_->stream) == hipSuccess)
+        ctx_->stats[name_].pending.emplace_back(a_, b_);
+}
+
+namespace {
+void drain(tng_ctx* ctx) {
+    for (auto& kv : ctx->stats) {
+        for (auto& ev : kv.second.pending) {
+            float ms = 0;
+            if (hipEventSynchronize(ev.second) == hipSuccess &&
+                hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+                kv.second.total_ms += ms;
+                kv.second.launches += 1;
+            }
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+        kv.second.pending.clear();
+    }
+}
+}  // namespace
+
+}  // namespace tng
+
+tng_ctx::~tng_ctx() { tng::drain(this); }
+
+using tng::Error;
+
+extern "C" {
+
+const char* tng_last_error(void) { return tng::g_last_error.c_str(); }
+
+int tng_ctx_create(int device, void* hip_stream, tng_ctx** out) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(out != nullptr, "out is NULL");
+    int ndev = 0;
+    TNG_HIP(hipGetDeviceCount(&ndev));
+    TNG_REQUIRE(device >= 0 && device < ndev, "device ordinal out of range");
+    TNG_HIP(hipSetDevice(device));
+    auto* c = new tng_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    TNG_API_END
+}
+
+int tng_ctx_set_stream(tng_ctx* ctx, void* hip_stream) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    TNG_API_END
+}
+
+int tng_ctx_profile(tng_ctx* ctx, int enable) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    tng::drain(ctx);
+    ctx->profile = enable != 0;
+    if (enable) ctx->stats.clear();
+    TNG_API_END
+}
+
+int tng_ctx_kernel_stats(tng_ctx* ctx, const char* name, double* total_ms, long long* launches) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr && name != nullptr, "ctx or name is NULL");
+    tng::drain(ctx);
+    auto it = ctx->stats.find(name);
+    if (total_ms) *total_ms = it == ctx->stats.end() ? 0.0 : it->second.total_ms;
+    if (launches) *launches = it == ctx->stats.end() ? 0 : it->second.launches;
+    TNG_API_END
+}
+
+int tng_eta_from_temperature(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec,
+                             const void* T, double E, double F, void* eta_wedge) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(T != nullptr && eta_wedge != nullptr, "T or eta_wedge is NULL");
+    TNG_REQUIRE(std::isfinite(E) && std::isfinite(F), "E and F must be finite");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::launch_eta_from_T(ctx, L, prec, T, eta_wedge, E, F);
+    TNG_API_END
+}
+
+int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec,
+                    const void* eta_fine, void* eta_coarse) {
+    TNG_API_BEGIN
+    tng::device_level(ctx, mesh, fine_level);
+    const tng::Level& Lc = tng::device_level(ctx, mesh, fine_level + 1);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(eta_fine != nullptr && eta_coarse != nullptr, "eta pointer is NULL");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::launch_eta_coarsen(ctx, Lc, prec, eta_fine, eta_coarse);
+    TNG_API_END
+}
+
+int tng_ctx_destroy(tng_ctx* ctx) {
+    TNG_API_BEGIN
+    delete ctx;
+    TNG_API_END
+}
+
+int tng_mesh_create(tng_ctx* ctx, int mt, int nr, double r_in, double r_out, int levels,
+                    tng_mesh** out) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(out != nullptr, "out is NULL");
+    TNG_REQUIRE(mt >= 1 && (mt & (mt - 1)) == 0 && mt <= 4096, "mt must be a power of two <= 4096");
+    TNG_REQUIRE(nr >= 1 && nr <= 65536, "nr out of range");
+    TNG_REQUIRE(levels >= 1, "levels must be >= 1");
+    TNG_REQUIRE((mt >> (levels - 1)) >= 1 && ((mt >> (levels - 1)) << (levels - 1)) == mt,
+                "mt / 2^(levels-1) must be an integer >= 1");
+    TNG_REQUIRE((nr >> (levels - 1)) >= 1 && ((nr >> (levels - 1)) << (levels - 1)) == nr,
+                "nr / 2^(levels-1) must be an integer >= 1");
+    TNG_REQUIRE(r_in > 0.0 && r_out > r_in, "need 0 < r_in < r_out");
+    if (ctx) TNG_HIP(hipSetDevice(ctx->device));
+    auto* m = new tng_mesh();
+    m->ctx = ctx;
+    m->mt = mt;
+    m->nr = nr;
+    m->r_in = r_in;
+    m->r_out = r_out;
+    try {
+        tng::build_mesh(m, levels);
+    } catch (...) {
+        delete m;
+        throw;
+    }
+    *out = m;
+    TNG_API_END
+}
+
+int tng_mesh_counts(const tng_mesh* mesh, int level, long long out[8]) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::level_of(mesh, level);
+    TNG_REQUIRE(out != nullptr, "out is NULL");
+    out[0] = L.m;
+    out[1] = L.n;
+    out[2] = L.lat_slots();
+    out[3] = L.n_unique_lat;
+    out[4] = L.node_slots();
+    out[5] = (long long)L.n_unique_lat * (L.n + 1);
+    out[6] = L.cells();
+    out[7] = 2 * L.cells();
+    TNG_API_END
+}
+
+int tng_mesh_coords(const tng_mesh* mesh, int level, double* unit_xyz_host, double* r_host) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::level_of(mesh, level);
+    if (unit_xyz_host) std::memcpy(unit_xyz_host, L.unit.data(), L.unit.size() * sizeof(double));
+    if (r_host) std::memcpy(r_host, L.radii.data(), L.radii.size() * sizeof(double));
+    TNG_API_END
+}
+
+int tng_mesh_dup_groups(const tng_mesh* mesh, int level, int* unique_id_host) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::level_of(mesh, level);
+    TNG_REQUIRE(unique_id_host != nullptr, "unique_id_host is NULL");
+    std::memcpy(unique_id_host, L.uid.data(), L.uid.size() * sizeof(int));
+    TNG_API_END
+}
+
+int tng_mesh_destroy(tng_mesh* mesh) {
+    TNG_API_BEGIN
+    delete mesh;
+    TNG_API_END
+}
+
+int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec,
+                     unsigned op_flags, const void* eta_wedge, const void* const u[3],
+                     const void* p, void* const y_u[3], void* y_p) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE((op_flags & ~15u) == 0, "unknown op_flags bits");
+    const bool doA = op_flags & TNG_OP_A, doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
+    TNG_REQUIRE(doA || doBT || doB, "op_flags selects no operator block");
+    const tng::Level* Lp = nullptr;
+    if (doBT || doB) {
+        TNG_REQUIRE(level + 1 < (int)mesh->lv.size(), "pressure level (level + 1) not built");
+        Lp = &mesh->lv[level + 1];
+        TNG_REQUIRE(L.m % 2 == 0 && L.n % 2 == 0, "B/B^T need even m and n");
+    }
+    if (doA) TNG_REQUIRE(eta_wedge != nullptr, "eta_wedge is NULL");
+    if (doA || doB) {
+        TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
+    }
+    if (doA || doBT) TNG_REQUIRE(y_u != nullptr && y_u[0] && y_u[1] && y_u[2], "y_u is NULL");
+    if (doBT) TNG_REQUIRE(p != nullptr, "p is NULL");
+    if (doB) TNG_REQUIRE(y_p != nullptr, "y_p is NULL");
+    if ((op_flags & TNG_OP_DIRICHLET) && doA)
+        TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::launch_stokes_apply(ctx, L, Lp, prec, op_flags, eta_wedge, u, p, y_u, y_p);
+    TNG_API_END
+}
+
+int tng_interface_sum(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, int mode,
+                      int ncomp, void* const f[]) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(mode == 0 || mode == 1, "mode must be 0 (sum) or 1 (copy)");
+    TNG_REQUIRE(f != nullptr && ncomp >= 1 && ncomp <= 4, "bad field list");
+    for (int c = 0; c < ncomp; ++c) TNG_REQUIRE(f[c] != nullptr, "field pointer is NULL");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::launch_interface(ctx, L, prec, mode, ncomp, f);
+    TNG_API_END
+}
+
+}  // extern "C"

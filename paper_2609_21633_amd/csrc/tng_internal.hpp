@@ -1,0 +1,187 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <map>
+#include <vector>
+
+#include "tng.h"
+
+namespace tng {
+
+// Errors travel as exceptions inside the library and become return codes at
+// the C boundary (see TNG_API_BEGIN / TNG_API_END).
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+void clear_last_error();
+
+#define TNG_HIP(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::tng::Error(TNG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TNG_REQUIRE(cond, msg)                                                        \
+    do {                                                                              \
+        if (!(cond)) throw ::tng::Error(TNG_E_INVAL, (msg));                          \
+    } while (0)
+
+#define TNG_API_BEGIN try { ::tng::clear_last_error();
+#define TNG_API_END                                                                   \
+    return TNG_OK;                                                                    \
+    }                                                                                 \
+    catch (const ::tng::Error& e) {                                                   \
+        ::tng::set_last_error(e.what());                                              \
+        return e.code;                                                                \
+    }                                                                                 \
+    catch (const std::bad_alloc&) {                                                   \
+        ::tng::set_last_error("host allocation failed");                              \
+        return TNG_E_NOMEM;                                                           \
+    }                                                                                 \
+    catch (const std::exception& e) {                                                 \
+        ::tng::set_last_error(e.what());                                              \
+        return TNG_E_INVAL;                                                           \
+    }
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(TNG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const T* host, size_t count, hipStream_t s) {
+        TNG_REQUIRE(count <= n, "upload larger than buffer");
+        TNG_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+};
+
+// Number of per-triangle geometry values: rows rho1, rho2 of G^{-1}, row rho3
+// of G^{-1} divided by 6h, and h |det G| (see mesh.cpp).
+constexpr int GEO_PER_TRI = 10;
+constexpr int GEO_PER_COL = 2 * GEO_PER_TRI;
+
+struct Level {
+    int m = 0, n = 0;                 // lateral intervals per diamond edge, radial intervals
+    double r_in = 0, r_out = 0;
+    std::vector<double> unit;         // [10][m+1][m+1][3] unit vectors
+    std::vector<double> radii;        // [n+1]
+    std::vector<int> uid;             // [10][m+1][m+1] unique lateral id
+    int n_unique_lat = 0;
+    std::vector<int> grp_ptr_h, grp_slot_h;
+    int n_groups = 0;
+    std::vector<double> geo_h;        // [10][m][m][GEO_PER_COL] host copy
+    // device copies
+    DevBuf<double> geo64;             // [10][m][m][GEO_PER_COL]
+    DevBuf<float> geo32;
+    DevBuf<int> grp_ptr, grp_slot;    // duplicate groups (CSR over lateral slots)
+    DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
+
+    long long lat_slots() const { return 10LL * (m + 1) * (m + 1); }
+    long long node_slots() const { return lat_slots() * (n + 1); }
+    long long cells() const { return 10LL * m * m * n; }
+    double dr() const { return (r_out - r_in) / n; }
+};
+
+}  // namespace tng
+
+namespace tng {
+// Optional HIP-event timing of the main kernel of every call, on the stream
+// the kernel is launched on.
+struct KernelStats {
+    double total_ms = 0;
+    long long launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+}  // namespace tng
+
+struct tng_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 256;
+    bool profile = false;
+    std::map<std::string, tng::KernelStats> stats;
+    ~tng_ctx();
+};
+
+struct tng_mesh {
+    tng_ctx* ctx = nullptr;
+    int mt = 0, nr = 0;
+    double r_in = 0, r_out = 0;
+    std::vector<tng::Level> lv;
+};
+
+namespace tng {
+
+inline const Level& level_of(const tng_mesh* mesh, int level) {
+    TNG_REQUIRE(mesh != nullptr, "mesh is NULL");
+    TNG_REQUIRE(level >= 0 && level < (int)mesh->lv.size(), "level out of range");
+    return mesh->lv[level];
+}
+
+// Level of a mesh whose arrays live on the device (built with a context).
+inline const Level& device_level(const tng_ctx* ctx, const tng_mesh* mesh, int level) {
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    const Level& L = level_of(mesh, level);
+    TNG_REQUIRE(mesh->ctx != nullptr, "mesh was built without a context (host only)");
+    TNG_REQUIRE(mesh->ctx->device == ctx->device, "mesh belongs to another device");
+    return L;
+}
+
+// Kernel launchers (defined in the .hip translation units).
+void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec,
+                         unsigned flags, const void* eta, const void* const u[3], const void* p,
+                         void* const yu[3], void* yp);
+void launch_interface(const tng_ctx* ctx, const Level& L, tng_prec prec, int mode, int ncomp,
+                      void* const f[]);
+void launch_dirichlet_copy(const tng_ctx* ctx, const Level& L, tng_prec prec,
+                           const void* const u[3], void* const y[3]);
+void launch_eta_from_T(const tng_ctx* ctx, const Level& L, tng_prec prec, const void* Tn,
+                       void* eta, double E, double F);
+void launch_eta_coarsen(const tng_ctx* ctx, const Level& Lc, tng_prec prec, const void* ef,
+                        void* ec);
+
+// Records a start/stop event pair around a launch when profiling is on.
+class ScopedKernelTimer {
+  public:
+    ScopedKernelTimer(const tng_ctx* ctx, const char* name);
+    ~ScopedKernelTimer();
+  private:
+    tng_ctx* ctx_;
+    const char* name_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+}  // namespace tng

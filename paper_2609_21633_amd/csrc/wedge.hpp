@@ -1,0 +1,143 @@
+// Per-wedge arithmetic of the one-point W1-iso-W2 / W1 Stokes operator.
+//
+// Sec. 3 (eq:epsq, eq:localapply) contracts the gathered element DoFs into
+// the strain at the quadrature point and tests it against every basis
+// gradient; Sec. 4 fixes one point q_c = (1/3, 1/3, 0) of weight 1.  With
+// the isoparametric map x = r(zeta) s(xi, eta) the Jacobian at q_c factors as
+// J = G diag(r_m, r_m, h) with G = [s1 - s0 | s2 - s0 | s_c], so
+//   grad phi_j = (g_j1 / r_m) rho1 + (g_j2 / r_m) rho2 + (g_j3 / h) rho3,
+// where rho_m are the rows of G^{-1} and g_j the reference gradients
+//   g_0 = (-1/2, -1/2, -1/6), g_1 = (1/2, 0, -1/6), g_2 = (0, 1/2, -1/6),
+//   g_3 = (-1/2, -1/2, 1/6),  g_4 = (1/2, 0, 1/6),  g_5 = (0, 1/2, 1/6).
+// The constants 1/2 and 1/6 and the radial scalings are folded into the rows
+// (rho1~ = rho1 / (2 r_m), rho2~ = rho2 / (2 r_m), rho3' = rho3 / (6 h)), so
+// that with the nodal differences
+//   A_c = u1 + u4 - u0 - u3,  B_c = u2 + u5 - u0 - u3,  C_c = u3 + u4 + u5 - u0 - u1 - u2
+// the velocity gradient is  du_c/dx_a = A_c rho1~_a + B_c rho2~_a + C_c rho3'_a.
+// The element result y_j = V_e sigma grad phi_j with
+//   sigma = 2 eta dev sym(grad u) - pbar I      (eq:stress, the B^T block),
+//   V_e   = |det J(q_c)| = r_m^2 h |det G|      (eq:oneptenergy, w_q = 1),
+// reduces to y_j = sum_m g'_jm Z_m with Z_m = (V sigma) rho_m (folded rows)
+// and g'_j the reference gradients without their 1/2, 1/6 factors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tng {
+
+template <typename T>
+struct WedgeOut {
+    T y[6][3];   // contributions to the six wedge nodes, three components
+    T dv;        // -V_e div u (the B block before the pressure test weights)
+};
+
+// u[j][c]: nodal velocity of the six wedge nodes (0-2 bottom, 3-5 top).
+// g: ten geometry values of the triangle: rho1(3), rho2(3), rho3'(3), h|det G|.
+// s1 = 1 / (2 r_m), rm2 = r_m^2.  eta: wedge viscosity.  pbar: mean of the six
+// iso-interpolated pressure values (the pressure at q_c).
+template <typename T, bool DO_A, bool DO_BT, bool DO_B>
+__device__ __forceinline__ void wedge_apply(const T (&u)[6][3], const T* __restrict__ g, T s1,
+                                            T rm2, T eta, T pbar, WedgeOut<T>& o) {
+    const T r1[3] = {g[0] * s1, g[1] * s1, g[2] * s1};
+    const T r2[3] = {g[3] * s1, g[4] * s1, g[5] * s1};
+    const T r3[3] = {g[6], g[7], g[8]};
+    const T V = rm2 * g[9];
+    T L[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T s03 = u[0][c] + u[3][c];
+        const T A = (u[1][c] + u[4][c]) - s03;
+        const T B = (u[2][c] + u[5][c]) - s03;
+        const T C = (u[3][c] + u[4][c] + u[5][c]) - (u[0][c] + u[1][c] + u[2][c]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) L[c][a] = A * r1[a] + B * r2[a] + C * r3[a];
+    }
+    const T tr = L[0][0] + L[1][1] + L[2][2];
+    if (DO_B) o.dv = -V * tr;
+    if (DO_A || DO_BT) {
+        T S[3][3];
+        if (DO_A) {
+            const T e = eta * V;
+            const T e2 = e + e;
+            const T q = e2 * tr * T(1.0 / 3.0) + (DO_BT ? V * pbar : T(0));
+            S[0][0] = e2 * L[0][0] - q;
+            S[1][1] = e2 * L[1][1] - q;
+            S[2][2] = e2 * L[2][2] - q;
+            S[0][1] = S[1][0] = e * (L[0][1] + L[1][0]);
+            S[0][2] = S[2][0] = e * (L[0][2] + L[2][0]);
+            S[1][2] = S[2][1] = e * (L[1][2] + L[2][1]);
+        } else {
+            const T q = V * pbar;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) S[c][a] = (c == a) ? -q : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T z1 = S[c][0] * r1[0] + S[c][1] * r1[1] + S[c][2] * r1[2];
+            const T z2 = S[c][0] * r2[0] + S[c][1] * r2[1] + S[c][2] * r2[2];
+            const T z3 = S[c][0] * r3[0] + S[c][1] * r3[1] + S[c][2] * r3[2];
+            const T z12 = z1 + z2;
+            o.y[0][c] = -z12 - z3;
+            o.y[1][c] = z1 - z3;
+            o.y[2][c] = z2 - z3;
+            o.y[3][c] = z3 - z12;
+            o.y[4][c] = z1 + z3;
+            o.y[5][c] = z2 + z3;
+        }
+    }
+}
+
+// Iso-W1 pressure weights (Sec. 3: pressure W1 on the coarser grid).  A fine
+// cell (i, j, k) lies in coarse cell (i/2, j/2, k/2); its fine nodes are
+// coarse nodes or midpoints of coarse edges, so the pressure at q_c of a fine
+// wedge is a fixed combination of the coarse cell's 8 corner values:
+//   pbar = sum_lc LW[a][b][w][lc] * (RW[c][0] p(lc, K) + RW[c][1] p(lc, K+1)),
+// with a = i&1, b = j&1, c = k&1, w the wedge, lc = e_i + 2 e_j the lateral
+// corner of the coarse quad.  The same weights test the divergence against
+// the coarse pressure basis (B = P^T B_f), making B and B^T transposes.
+struct IsoWeights {
+    double lw[2][2][2][4];   // [a][b][w][lateral corner]
+    double rw[2][2];         // [c][bottom/top coarse layer]
+};
+
+constexpr void iso_lat_node(int x, int y, double w[4]) {
+    // fine node at (x, y) in {0,1,2}^2 inside a coarse quad with corners
+    // (0,0)->0, (2,0)->1, (0,2)->2, (2,2)->3 in fine units
+    for (int q = 0; q < 4; ++q) w[q] = 0.0;
+    if (x % 2 == 0 && y % 2 == 0) {
+        w[(x / 2) + 2 * (y / 2)] = 1.0;
+    } else if (x == 1 && y % 2 == 0) {
+        w[0 + 2 * (y / 2)] = 0.5;
+        w[1 + 2 * (y / 2)] = 0.5;
+    } else if (y == 1 && x % 2 == 0) {
+        w[(x / 2) + 0] = 0.5;
+        w[(x / 2) + 2] = 0.5;
+    } else {  // (1, 1): midpoint of the coarse split diagonal (2,0)-(0,2)
+        w[1] = 0.5;
+        w[2] = 0.5;
+    }
+}
+
+constexpr IsoWeights make_iso_weights() {
+    IsoWeights t{};
+    // lateral node offsets of wedge 0 and wedge 1 inside the fine cell
+    const int off[2][3][2] = {{{0, 0}, {1, 0}, {0, 1}}, {{1, 1}, {0, 1}, {1, 0}}};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int w = 0; w < 2; ++w) {
+                for (int q = 0; q < 4; ++q) t.lw[a][b][w][q] = 0.0;
+                for (int n = 0; n < 3; ++n) {
+                    double nw[4] = {0, 0, 0, 0};
+                    iso_lat_node(a + off[w][n][0], b + off[w][n][1], nw);
+                    for (int q = 0; q < 4; ++q) t.lw[a][b][w][q] += nw[q] / 3.0;
+                }
+            }
+    // radial: fine layers c and c+1 of the coarse interval, mean of the two
+    t.rw[0][0] = 0.75; t.rw[0][1] = 0.25;
+    t.rw[1][0] = 0.25; t.rw[1][1] = 0.75;
+    return t;
+}
+
+}  // namespace tng

@@ -1,0 +1,86 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, validates arguments, and its host mesh equals the oracle mesh."""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.mesh import ShellMesh, SphereHierarchy
+from tests._support import LayoutMap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2609_21633_amd as tng
+    return tng
+
+
+def test_library_exports_every_declared_symbol():
+    tng = _lib()
+    L = tng.lib()
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(tng_[a-z0-9_]+)\s*\(", src))
+    assert names, "no declarations found"
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_argument_validation_without_gpu():
+    import ctypes as C
+    tng = _lib()
+    L = tng.lib()
+    h = C.c_void_p()
+    assert L.tng_mesh_create(None, 3, 4, 0.55, 1.0, 1, C.byref(h)) == -1
+    assert b"power of two" in L.tng_last_error()
+    assert L.tng_mesh_create(None, 8, 8, 1.0, 0.5, 1, C.byref(h)) == -1
+    assert L.tng_mesh_create(None, 8, 6, 0.55, 1.0, 3, C.byref(h)) == -1
+    # a host-only mesh is rejected by device calls
+    m = tng.Mesh(None, 4, 4, levels=2)
+    y = (C.c_void_p * 3)(1, 2, 3)
+    rc = L.tng_stokes_apply(None, m.h, 0, 0, 1, C.c_void_p(1), y, None, y, None)
+    assert rc == -1
+    assert L.tng_stokes_apply(C.c_void_p(0), m.h, 5, 0, 1, None, y, None, y, None) == -1
+
+
+@pytest.mark.parametrize("mt,nr", [(2, 2), (4, 4), (8, 4), (16, 16)])
+def test_host_mesh_matches_oracle(mt, nr):
+    """a1: counts, coordinates (matched by position), duplicate groups of size
+    2 (edges), 3 (ring vertices) and 5 (poles), wedges = oracle wedges."""
+    tng = _lib()
+    m = tng.Mesh(None, mt, nr, levels=2 if mt > 1 else 1)
+    c = m.counts(0)
+    assert c["lat_unique"] == 10 * mt * mt + 2
+    assert c["lat_slots"] == 10 * (mt + 1) ** 2
+    assert c["cells"] == 10 * mt * mt * nr and c["wedges"] == 2 * c["cells"]
+    xyz, r = m.coords(0)
+    assert np.allclose(np.linalg.norm(xyz, axis=-1), 1.0, atol=1e-15)
+    om = ShellMesh(mt, nr)
+    lm = LayoutMap(xyz, r, om)
+    # coordinates agree to rounding, not just within the matching tolerance
+    assert np.abs(xyz.reshape(-1, 3) - om.s[lm.slot2lat]).max() < 1e-15
+    uid = m.unique_ids(0).ravel()
+    # same unique id <=> same oracle node
+    assert len(np.unique(uid)) == om.n_lat
+    pairs = np.unique(np.stack([uid, lm.slot2lat], 1), axis=0)
+    assert len(pairs) == om.n_lat
+    sizes = np.bincount(np.bincount(uid))
+    assert sizes[2] == 20 * (mt - 1) and sizes[3] == 10 and sizes[5] == 2
+    assert 10 * (mt + 1) ** 2 - (10 * mt * mt + 2) == 20 * mt + 8
+    # every oracle wedge appears exactly once
+    wi = lm.wedge_index()
+    assert np.array_equal(np.sort(wi.ravel()), np.arange(om.n_wedges))
+
+
+def test_pressure_level_nests():
+    """Level 1 nodes are the even-index nodes of level 0 (pressure on the coarser grid)."""
+    tng = _lib()
+    m = tng.Mesh(None, 8, 8, levels=3)
+    x0, r0 = m.coords(0)
+    x1, r1 = m.coords(1)
+    assert np.array_equal(x0[:, ::2, ::2], x1)
+    assert np.array_equal(r0[::2], r1)

@@ -5,7 +5,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtng.so")
+LIB_PATH = os.environ.get("TNG_LIB", os.path.join(HERE, "libtng.so"))
 
 OP_A, OP_BT, OP_B, OP_DIRICHLET = 1, 2, 4, 8
 F64, F32 = 0, 1

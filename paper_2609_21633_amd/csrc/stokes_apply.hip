@@ -23,7 +23,6 @@
 namespace tng {
 namespace {
 
-__constant__ IsoWeights c_isob = make_iso_weights();
 constexpr int TI_MAX = 8;   // cell columns (waves) per workgroup
 
 template <typename T>
@@ -53,22 +52,47 @@ __device__ __forceinline__ T shfl_up1(T v, int lane) {
 // Emit one node value: plain store when this workgroup holds its complete
 // sum, atomic add (onto zeroed memory) on tile or chunk seams.
 template <typename T>
-__device__ __forceinline__ void emit(T* y, long long idx, T v, bool seam) {
+__device__ __forceinline__ void emit(T* y, unsigned idx, T v, bool seam) {
     if (seam)
         atomicAdd(y + idx, v);
     else
         y[idx] = v;
 }
 
+template <typename T>
+struct IsoTable;
+template <>
+struct IsoTable<float> {
+    __device__ static const IsoWeights<float>& get();
+};
+template <>
+struct IsoTable<double> {
+    __device__ static const IsoWeights<double>& get();
+};
+__constant__ IsoWeights<float> c_iso32 = make_iso_weights<float>();
+__constant__ IsoWeights<double> c_iso64 = make_iso_weights<double>();
+__device__ const IsoWeights<float>& IsoTable<float>::get() { return c_iso32; }
+__device__ const IsoWeights<double>& IsoTable<double>::get() { return c_iso64; }
+
+// Coarse-layer slots of the divergence reduction: a lane's cells touch NKL
+// consecutive coarse layers starting at layer kb(lane).
+template <int CPL>
+struct CoarseMap {
+    static constexpr int NKL = CPL == 1 ? 2 : CPL / 2 + 1;
+};
+
 template <typename T, int CPL, bool DO_A, bool DO_BT, bool DO_B>
 __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a) {
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
+    constexpr bool LOAD_U = DO_A || DO_B;
     constexpr int XW = DO_U ? TI_MAX : 1;
     __shared__ T xch[2][XW][3][NL][64];
-    constexpr int PB_I = DO_B ? TI_MAX / 2 + 1 : 1;
-    constexpr int PB_K = DO_B ? 32 * CPL + 2 : 1;
-    __shared__ T pbuf[2][PB_I][PB_K];
+    constexpr int NKC = DO_B ? 32 * CPL + 1 : 1;          // coarse layers per chunk
+    constexpr int BW = DO_B ? TI_MAX : 1;
+    __shared__ T bsl[2][BW][4][NKC];                      // per-wave coarse partials
+    constexpr int NKL = CoarseMap<CPL>::NKL;
+    const IsoWeights<T>& iso = IsoTable<T>::get();
 
     const int TI = a.TI;
     const int lane = threadIdx.x & 63;
@@ -92,10 +116,11 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
     const int k0 = chunk * a.KC;
     const int kend = min(n, k0 + a.KC);                // cells [k0, kend) of this chunk
 
-    const long long ldj = n + 1;
-    const long long ldi = (long long)(m + 1) * ldj;
-    const long long colA = (long long)d * (m + 1) * ldi + (long long)i * ldi;   // node column i
-    const long long colB = colA + ldi;                                           // node column i + 1
+    // 32-bit offsets: every field of a supported level has < 2^31 entries
+    const unsigned ldj = n + 1;
+    const unsigned ldi = (unsigned)(m + 1) * ldj;
+    const unsigned colA = ((unsigned)d * (m + 1) + i) * ldi;   // node column i
+    const unsigned colB = colA + ldi;                          // node column i + 1
 
     int kk[NL];
 #pragma unroll
@@ -103,21 +128,56 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
     bool cell_ok[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) cell_ok[c] = kk[c] < kend;
-    // the lane holding the chunk's last cell also owns the node layer above it
     const bool top_lane = (kk[0] <= kend - 1) && (kend - 1 <= kk[CPL - 1]);
     const int top_c = kend - kk[0];
+    bool node_ok[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+        node_ok[c] = LOAD_U && kk[c] <= n && !(a.dirichlet && (kk[c] == 0 || kk[c] == n));
 
-    // velocity of node rows: column i (uA/uC) and i+1 (uB/uD); Dirichlet layers read as zero
-    T uA[NL][3], uB[NL][3];
-    auto load_u = [&](long long col, int jrow, T (&dst)[NL][3]) {
-        const long long base = col + (long long)jrow * ldj;
+    auto load_u = [&](unsigned col, int jrow, T (&dst)[NL][3]) {
+        const unsigned base = col + (unsigned)jrow * ldj;
 #pragma unroll
         for (int c = 0; c < NL; ++c) {
-            const int k = kk[c];
-            const bool ok = (DO_A || DO_B) && k <= n && !(a.dirichlet && (k == 0 || k == n));
-            dst[c][0] = ok ? a.u0[base + k] : T(0);
-            dst[c][1] = ok ? a.u1[base + k] : T(0);
-            dst[c][2] = ok ? a.u2[base + k] : T(0);
+            const unsigned o = base + (unsigned)kk[c];
+            dst[c][0] = node_ok[c] ? a.u0[o] : T(0);
+            dst[c][1] = node_ok[c] ? a.u1[o] : T(0);
+            dst[c][2] = node_ok[c] ? a.u2[o] : T(0);
+        }
+    };
+
+    const int mc = m / 2, nc = n / 2;
+    const unsigned pldj = nc + 1;
+    const unsigned pldi = (unsigned)(mc + 1) * pldj;
+    const unsigned pcol = (unsigned)d * (mc + 1) * pldi;
+    const int I = i >> 1, I0 = i0 >> 1;
+    const int ab = i & 1;
+    const int K0 = k0 >> 1;
+
+    // per-row inputs of the cell row: viscosities and coarse pressure corners
+    struct RowIn {
+        T eta[CPL][2];
+        T pc[CPL][4];
+    };
+    auto load_row = [&](int j, RowIn& r) {
+        const unsigned ecol = (((unsigned)d * m + i) * m + j) * (unsigned)n * 2u;
+        const int J = j >> 1;
+        const unsigned pb0 = pcol + (unsigned)I * pldi + (unsigned)J * pldj;
+        const unsigned pbq[4] = {pb0, pb0 + pldi, pb0 + pldj, pb0 + pldi + pldj};
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int k = cell_ok[c] ? kk[c] : k0;
+            if (DO_A) {
+                r.eta[c][0] = a.eta[ecol + 2u * k];
+                r.eta[c][1] = a.eta[ecol + 2u * k + 1u];
+            }
+            if (DO_BT) {
+                const int K = k >> 1, cb = k & 1;
+                const T rw0 = iso.rw[cb][0], rw1 = iso.rw[cb][1];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    r.pc[c][q] = rw0 * a.p[pbq[q] + K] + rw1 * a.p[pbq[q] + K + 1];
+            }
         }
     };
 
@@ -128,26 +188,37 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
 #pragma unroll
         for (int r = 0; r < 3; ++r) R0[c][r] = R1[c][r] = T(0);
 
-    if (DO_B)
-        for (int t = threadIdx.x; t < 2 * PB_I * PB_K; t += TI * 64) (&pbuf[0][0][0])[t] = T(0);
+    // divergence: owner threads keep the two open coarse rows in registers
+    constexpr int NOWN = 2;
+    const int ncoarse = (TI / 2 + 1) * NKC;
+    T pacc0[NOWN], pacc1[NOWN];
+#pragma unroll
+    for (int o = 0; o < NOWN; ++o) pacc0[o] = pacc1[o] = T(0);
+
+    T uA[NL][3], uB[NL][3], uC[NL][3], uD[NL][3];
+    RowIn rin;
     load_u(colA, jfirst, uA);
     load_u(colB, jfirst, uB);
-
-    const int mc = m / 2, nc = n / 2;
-    const long long pldj = nc + 1;
-    const long long pldi = (long long)(mc + 1) * pldj;
-    const long long pcol = (long long)d * (mc + 1) * pldi;
-    const int I = i >> 1, I0 = i0 >> 1;
-    const int ab = i & 1;
-    const int K0 = k0 >> 1;
-
-    __syncthreads();
+    if (jfirst <= jlast_cell) {
+        load_u(colA, jfirst + 1, uC);
+        load_u(colB, jfirst + 1, uD);
+        load_row(jfirst, rin);
+    }
 
     for (int j = jfirst; j <= jlast; ++j) {
         const bool row_cells = j <= jlast_cell;    // the extra last step only emits
         const bool owned = j >= j0;
         const int par = j & 1;
         const int J = j >> 1, bb = j & 1;
+        // prefetch the next cell row while this one is computed
+        T uE[NL][3], uF[NL][3];
+        RowIn rnext;
+        const bool pre = j + 1 <= jlast_cell;
+        if (pre) {
+            load_u(colA, j + 2, uE);
+            load_u(colB, j + 2, uF);
+            load_row(j + 1, rnext);
+        }
         T Nd[4][NL][3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -155,17 +226,13 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
             for (int c = 0; c < NL; ++c)
 #pragma unroll
                 for (int r = 0; r < 3; ++r) Nd[q][c][r] = T(0);
-        T uC[NL][3], uD[NL][3];
+        T cp[4][NKL];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int s = 0; s < NKL; ++s) cp[q][s] = T(0);
         if (row_cells) {
-            load_u(colA, j + 1, uC);
-            load_u(colB, j + 1, uD);
-            const T* g = a.geo + (((long long)d * m + i) * m + j) * GEO_PER_COL;
-            const long long ecol = ((((long long)d * m + i) * m + j) * n) * 2;
-            long long pb[4];
-            pb[0] = pcol + (long long)I * pldi + (long long)J * pldj;
-            pb[1] = pb[0] + pldi;
-            pb[2] = pb[0] + pldj;
-            pb[3] = pb[0] + pldi + pldj;
+            const T* g = a.geo + (((unsigned)d * m + i) * m + j) * (unsigned)GEO_PER_COL;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 if (!cell_ok[c]) continue;
@@ -173,13 +240,6 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                 const T rm = a.r_in + (T(k) + T(0.5)) * a.dr;
                 const T s1 = T(0.5) / rm;
                 const T rm2 = rm * rm;
-                const int K = k >> 1, cb = k & 1;
-                const T rw0 = T(c_isob.rw[cb][0]), rw1 = T(c_isob.rw[cb][1]);
-                T pc[4] = {0, 0, 0, 0};
-                if (DO_BT) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) pc[q] = rw0 * a.p[pb[q] + K] + rw1 * a.p[pb[q] + K + 1];
-                }
                 T tB[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int wd = 0; wd < 2; ++wd) {
@@ -198,13 +258,12 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                     T pbar = 0;
                     if (DO_BT) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) pbar += T(c_isob.lw[ab][bb][wd][q]) * pc[q];
+                        for (int q = 0; q < 4; ++q) pbar += iso.lw[ab][bb][wd][q] * rin.pc[c][q];
                     }
-                    const T eta = DO_A ? a.eta[ecol + 2 * k + wd] : T(0);
+                    const T eta = DO_A ? rin.eta[c][wd] : T(0);
                     WedgeOut<T> o;
                     wedge_apply<T, DO_A, DO_BT, DO_B>(uw, g + wd * GEO_PER_TRI, s1, rm2, eta, pbar, o);
                     if (DO_U) {
-                        // cell corner of each wedge node: 0=(i,j) 1=(i+1,j) 2=(i,j+1) 3=(i+1,j+1)
                         constexpr int cq[2][3] = {{0, 1, 2}, {3, 2, 1}};
 #pragma unroll
                         for (int jn = 0; jn < 3; ++jn)
@@ -216,17 +275,17 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                     }
                     if (DO_B) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) tB[q] += T(c_isob.lw[ab][bb][wd][q]) * o.dv;
+                        for (int q = 0; q < 4; ++q) tB[q] += iso.lw[ab][bb][wd][q] * o.dv;
                     }
                 }
-                if (DO_B && owned) {
-                    // coarse corner q = (I + (q&1), J + (q>>1)), layers K and K+1
-                    const int Kl = K - K0;
+                if (DO_B) {
+                    // coarse layers of this cell relative to the lane's first coarse layer
+                    const int cb = k & 1;
+                    const int sl = CPL == 1 ? 0 : ((k >> 1) - ((k0 + CPL * lane) >> 1));
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        T* cell = &pbuf[(J + (q >> 1)) & 1][(I - I0) + (q & 1)][Kl];
-                        atomicAdd(cell, rw0 * tB[q]);
-                        atomicAdd(cell + 1, rw1 * tB[q]);
+                        cp[q][sl] += iso.rw[cb][0] * tB[q];
+                        cp[q][sl + 1] += iso.rw[cb][1] * tB[q];
                     }
                 }
             }
@@ -246,10 +305,45 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
 #pragma unroll
                 for (int r = 0; r < 3; ++r) xch[par][w][r][c][lane] = R1[c][r] + Nd[1][c][r];
         }
+        if (DO_B && owned && row_cells) {
+            // radial reduction of the coarse partials to one value per coarse layer
+            if (CPL == 1) {
+                // lanes 2K' and 2K'+1 share coarse layers K', K'+1
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) cp[q][s2] += __shfl(cp[q][s2], (lane + 1) & 63, 64);
+                // the even lane's layer K'+1 part goes to the next even lane
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T t = __shfl(cp[q][1], (lane + 62) & 63, 64);
+                    const T top = cp[q][1];
+                    if ((lane & 1) == 0) {
+                        const int Kl = lane >> 1;
+                        bsl[par][w][q][Kl] = cp[q][0] + (lane >= 2 ? t : T(0));
+                        if (lane == 62) bsl[par][w][q][32] = top;
+                    }
+                }
+            } else {
+                // lane l covers coarse layers CPL/2*l .. CPL/2*l + CPL/2
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T t = __shfl(cp[q][NKL - 1], (lane + 63) & 63, 64);
+                    const int Kb = (CPL / 2) * lane;
+#pragma unroll
+                    for (int s2 = 0; s2 < NKL - 1; ++s2) {
+                        T v = cp[q][s2];
+                        if (s2 == 0 && lane > 0) v += t;
+                        bsl[par][w][q][Kb + s2] = v;
+                    }
+                    if (lane == 63) bsl[par][w][q][Kb + NKL - 1] = cp[q][NKL - 1];
+                }
+            }
+        }
         __syncthreads();
         if (DO_U && owned) {
-            const long long rowA = colA + (long long)j * ldj;
-            const long long rowB = colB + (long long)j * ldj;
+            const unsigned rowA = colA + (unsigned)j * ldj;
+            const unsigned rowB = colB + (unsigned)j * ldj;
             const bool seamL = (w == 0) && (i0 > 0);
             const bool right = (w == TI - 1);
             const bool seamR = (i0 + TI < m);
@@ -264,7 +358,7 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                     live = true;
                     seamK = (c == 0 && lane == 0 && k0 > 0);   // chunk bottom
                 }
-                if (a.dirichlet && (k == 0 || k == n)) live = false;   // rows set to u afterwards
+                if (a.dirichlet && (k == 0 || k == n)) live = false;   // rows set afterwards
                 if (!live) continue;
                 T v[3];
 #pragma unroll
@@ -273,15 +367,17 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                     if (w > 0) v[r] += xch[par][w - 1][r][c][lane];
                 }
                 const bool seam = seamL || seamK;
-                emit(a.y0, rowA + k, v[0], seam);
-                emit(a.y1, rowA + k, v[1], seam);
-                emit(a.y2, rowA + k, v[2], seam);
+                const unsigned oa = rowA + (unsigned)k;
+                emit(a.y0, oa, v[0], seam);
+                emit(a.y1, oa, v[1], seam);
+                emit(a.y2, oa, v[2], seam);
                 if (right) {
                     // node column i0 + TI: complete only on the diamond edge
                     const bool s2 = seamR || seamK;
-                    emit(a.y0, rowB + k, xch[par][w][0][c][lane], s2);
-                    emit(a.y1, rowB + k, xch[par][w][1][c][lane], s2);
-                    emit(a.y2, rowB + k, xch[par][w][2][c][lane], s2);
+                    const unsigned ob = rowB + (unsigned)k;
+                    emit(a.y0, ob, xch[par][w][0][c][lane], s2);
+                    emit(a.y1, ob, xch[par][w][1][c][lane], s2);
+                    emit(a.y2, ob, xch[par][w][2][c][lane], s2);
                 }
             }
         }
@@ -294,40 +390,75 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                     R1[c][r] = Nd[3][c][r];
                 }
         }
-        if (DO_B && owned && row_cells && (j & 1)) {
-            // coarse node row J has received all of this band's cells: flush it
-            T* prow = &pbuf[J & 1][0][0];
-            for (int t = threadIdx.x; t < PB_I * PB_K; t += TI * 64) {
-                const int il = t / PB_K, kl = t % PB_K;
-                const int Ig = I0 + il, Kg = K0 + kl;
-                const T v = prow[t];
-                if (il <= TI / 2 && Ig <= mc && Kg <= nc && v != T(0))
-                    atomicAdd(a.yp + pcol + (long long)Ig * pldi + (long long)J * pldj + Kg, v);
-                prow[t] = T(0);
+        if (DO_B && owned && row_cells) {
+            // owner threads add the (up to four) waves touching each coarse node, in
+            // a fixed order, into the open rows J (corners 0, 1) and J+1 (corners 2, 3)
+#pragma unroll
+            for (int o = 0; o < NOWN; ++o) {
+                const int idx = threadIdx.x + o * TI * 64;
+                if (idx < ncoarse) {
+                    const int il = idx / NKC, kl = idx % NKC;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int ws = 2 * (il - (q & 1));   // waves whose coarse column is il - (q&1)
+                        T v = T(0);
+                        if (ws >= 0 && ws < TI) v += bsl[par][ws][q][kl];
+                        if (ws + 1 >= 0 && ws + 1 < TI) v += bsl[par][ws + 1][q][kl];
+                        if (q < 2) pacc0[o] += v; else pacc1[o] += v;
+                    }
+                }
             }
-            __syncthreads();
+            if (j & 1) {
+                // coarse row J has received all of this band's cells
+                const bool rowseam = (J == (j0 >> 1) && j0 > 0);
+#pragma unroll
+                for (int o = 0; o < NOWN; ++o) {
+                    const int idx = threadIdx.x + o * TI * 64;
+                    if (idx < ncoarse) {
+                        const int il = idx / NKC, kl = idx % NKC;
+                        const int Ig = I0 + il, Kg = K0 + kl;
+                        if (Ig <= mc && Kg <= nc && kl <= (kend - k0) / 2) {
+                            const bool seam = rowseam || (il == 0 && I0 > 0) ||
+                                              (il == TI / 2 && Ig < mc) ||
+                                              (kl == 0 && K0 > 0) || (Kg < nc && kl == (kend - k0) / 2);
+                            emit(a.yp, pcol + (unsigned)Ig * pldi + (unsigned)J * pldj + (unsigned)Kg,
+                                 pacc0[o], seam);
+                        }
+                    }
+                    pacc0[o] = pacc1[o];
+                    pacc1[o] = T(0);
+                }
+            }
         }
-        if (row_cells) {
+        if (pre) {
 #pragma unroll
             for (int c = 0; c < NL; ++c)
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     uA[c][r] = uC[c][r];
                     uB[c][r] = uD[c][r];
+                    uC[c][r] = uE[c][r];
+                    uD[c][r] = uF[c][r];
                 }
+            rin = rnext;
         }
     }
     if (DO_B) {
-        // the coarse row above the band's last cell row is still pending
-        __syncthreads();
+        // the coarse row above the band's last cell row: complete only on the last band
         const int J = (jlast_cell >> 1) + 1;
-        T* prow = &pbuf[J & 1][0][0];
-        for (int t = threadIdx.x; t < PB_I * PB_K; t += TI * 64) {
-            const int il = t / PB_K, kl = t % PB_K;
-            const int Ig = I0 + il, Kg = K0 + kl;
-            const T v = prow[t];
-            if (il <= TI / 2 && Ig <= mc && Kg <= nc && v != T(0))
-                atomicAdd(a.yp + pcol + (long long)Ig * pldi + (long long)J * pldj + Kg, v);
+#pragma unroll
+        for (int o = 0; o < NOWN; ++o) {
+            const int idx = threadIdx.x + o * TI * 64;
+            if (idx < ncoarse) {
+                const int il = idx / NKC, kl = idx % NKC;
+                const int Ig = I0 + il, Kg = K0 + kl;
+                if (Ig <= mc && Kg <= nc && J <= mc && kl <= (kend - k0) / 2) {
+                    const bool seam = !last_band || (il == 0 && I0 > 0) || (il == TI / 2 && Ig < mc) ||
+                                      (kl == 0 && K0 > 0) || (Kg < nc && kl == (kend - k0) / 2);
+                    emit(a.yp, pcol + (unsigned)Ig * pldi + (unsigned)J * pldj + (unsigned)Kg, pacc0[o],
+                         seam);
+                }
+            }
         }
     }
 }
@@ -422,7 +553,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     // budget (two or more FP64 cells per lane spill), longer columns are split
     // into radial chunks
     int cpl = (L.n + 63) / 64;
-    const int cpl_max = is64 ? 1 : 4;
+    const int cpl_max = is64 ? 1 : 2;
     cpl = cpl <= 1 ? 1 : (cpl <= 2 ? 2 : 4);
     if (cpl > cpl_max) cpl = cpl_max;
     a.KC = 64 * cpl;
@@ -452,10 +583,8 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     } else {
         if (cpl == 1)
             launch_band_ops<T, 1>(ctx, a, key);
-        else if (cpl == 2)
-            launch_band_ops<T, 2>(ctx, a, key);
         else
-            launch_band_ops<T, 4>(ctx, a, key);
+            launch_band_ops<T, 2>(ctx, a, key);
     }
     const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
     if (doA || doBT) {

@@ -97,9 +97,10 @@ __device__ __forceinline__ void wedge_apply(const T (&u)[6][3], const T* __restr
 // with a = i&1, b = j&1, c = k&1, w the wedge, lc = e_i + 2 e_j the lateral
 // corner of the coarse quad.  The same weights test the divergence against
 // the coarse pressure basis (B = P^T B_f), making B and B^T transposes.
+template <typename T>
 struct IsoWeights {
-    double lw[2][2][2][4];   // [a][b][w][lateral corner]
-    double rw[2][2];         // [c][bottom/top coarse layer]
+    T lw[2][2][2][4];   // [a][b][w][lateral corner]
+    T rw[2][2];         // [c][bottom/top coarse layer]
 };
 
 constexpr void iso_lat_node(int x, int y, double w[4]) {
@@ -120,23 +121,25 @@ constexpr void iso_lat_node(int x, int y, double w[4]) {
     }
 }
 
-constexpr IsoWeights make_iso_weights() {
-    IsoWeights t{};
+template <typename T>
+constexpr IsoWeights<T> make_iso_weights() {
+    IsoWeights<T> t{};
     // lateral node offsets of wedge 0 and wedge 1 inside the fine cell
     const int off[2][3][2] = {{{0, 0}, {1, 0}, {0, 1}}, {{1, 1}, {0, 1}, {1, 0}}};
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int w = 0; w < 2; ++w) {
-                for (int q = 0; q < 4; ++q) t.lw[a][b][w][q] = 0.0;
+                double acc[4] = {0, 0, 0, 0};
                 for (int n = 0; n < 3; ++n) {
                     double nw[4] = {0, 0, 0, 0};
                     iso_lat_node(a + off[w][n][0], b + off[w][n][1], nw);
-                    for (int q = 0; q < 4; ++q) t.lw[a][b][w][q] += nw[q] / 3.0;
+                    for (int q = 0; q < 4; ++q) acc[q] += nw[q] / 3.0;
                 }
+                for (int q = 0; q < 4; ++q) t.lw[a][b][w][q] = T(acc[q]);
             }
     // radial: fine layers c and c+1 of the coarse interval, mean of the two
-    t.rw[0][0] = 0.75; t.rw[0][1] = 0.25;
-    t.rw[1][0] = 0.25; t.rw[1][1] = 0.75;
+    t.rw[0][0] = T(0.75); t.rw[0][1] = T(0.25);
+    t.rw[1][0] = T(0.25); t.rw[1][1] = T(0.75);
     return t;
 }
 

@@ -150,6 +150,100 @@ int tng_eta_from_temperature(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_
 int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec,
                     const void* eta_fine, void* eta_coarse);
 
+/* ---- multigrid pieces (Sec. 7; a6-a8) ----------------------------------- */
+/* Diagonal of K_D's viscous block on `level`: diag_(node,c) = sum over the
+ * node's wedges of V eta (|grad phi|^2 + (d_c phi)^2 / 3) (eq:elemmat, one
+ * point), 1 on Dirichlet rows.  diag[3]: device velocity field out. */
+int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+               void* const diag[3]);
+/* Row-sum lumped inverse-viscosity pressure mass of eq:pmass on the pressure
+ * level of `level` (i.e. level + 1): m_I = sum_e (V_e / eta_e) psi_I(q_c^e).
+ * mass: device node field of level + 1 out.  The Schur preconditioner is
+ * S^{-1} r = -r / m. */
+int tng_pressure_mass(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+                      void* mass);
+/* Chebyshev smoother: `steps` applications of x <- x + p(D^{-1} A)(b - A x),
+ * p the degree-`degree` Chebyshev polynomial for the eigenvalue interval
+ * [lmin, lmax] of D^{-1} A (A with Dirichlet rows, D = diag).  diag: the
+ * diagonal as returned by tng_diag_A.  x is updated in place.  Allocates
+ * scratch and synchronises. */
+int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+               const void* const diag[3], const void* const b[3], void* const x[3], int degree, int steps,
+               double lmin, double lmax);
+/* W1 transfer between fine_level and fine_level + 1 (index-space
+ * interpolation: coarse nodes copied, edge midpoints and odd layers averaged).
+ * Restriction c = P^T f with Dirichlet layers of c set to zero; prolongation
+ * f = P c (overwrites f).  Velocity fields of the two levels. */
+int tng_restrict(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec, const void* const f[3],
+                 void* const c[3]);
+int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec, const void* const c[3],
+                void* const f[3]);
+
+/* ---- Stokes solver (Sec. 7; a6-a12) ------------------------------------ */
+/* Options of the FGMRES / block-preconditioner / multigrid solve.
+ * mixed: 0 = everything FP64; 1 = FP64 iterative refinement (outer residual,
+ *   correction, pressure-mean projection, coarsest solve in FP64) around an
+ *   FP32 inner FGMRES (FP32 applies, smoothers and Krylov basis).
+ * restart: FGMRES restart length (paper: 10; 1..23).
+ * max_iters: FGMRES iteration limit (FP64 mode).  rtol: target of
+ *   ||b - K x||_2 / ||b||_2 over unique DoFs, both blocks, x0 = 0.
+ * cheb_degree, pre, post: Chebyshev smoother of degree cheb_degree on
+ *   D^{-1} A, pre/post steps per level (paper: 2, 2, 2), on the interval
+ *   [cheb_lo, cheb_hi] * lambda_max(D^{-1} A), lambda_max from power_its
+ *   seeded power iterations.
+ * levels: multigrid levels used (0 = all levels of the mesh); the coarsest
+ *   one is solved exactly and must have at most 1024 interior DoFs.
+ * inner_rtol, inner_max_iters, max_outer: mixed-precision inner tolerance and
+ *   iteration limit per refinement step, and the refinement step limit. */
+typedef struct {
+    int mixed;
+    int restart;
+    int max_iters;
+    double rtol;
+    int cheb_degree;
+    int pre, post;
+    int levels;
+    double cheb_lo, cheb_hi;
+    double inner_rtol;
+    int inner_max_iters;
+    int max_outer;
+    int power_its;
+} tng_solver_opts;
+
+/* outer_its: refinement steps (1 in FP64 mode); inner_its: FGMRES iterations
+ * in total; rel_res: final true FP64 relative residual; seconds: wall time
+ * of the call; status: TNG_OK or TNG_E_NOTCONV. */
+typedef struct {
+    int outer_its, inner_its;
+    double rel_res;
+    double seconds;
+    int status;
+} tng_solve_info;
+
+/* Fills the defaults listed above (FP64, restart 10, rtol 1e-8, degree 2, 2+2). */
+int tng_solver_opts_default(tng_solver_opts* opts);
+/* The solver keeps the multigrid hierarchy, Krylov basis and scratch on the
+ * device (library-owned) for the mesh's levels; the mesh must outlive it. */
+int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* opts, tng_solver** out);
+int tng_stokes_solver_destroy(tng_solver* solver);
+/* Viscosity-dependent setup: per-level averaged viscosity, diagonals and
+ * Chebyshev intervals, lumped pressure mass, dense coarsest inverse.
+ * eta_wedge: device FP64 wedge field of level 0.  Synchronises. */
+int tng_stokes_solver_setup(tng_solver* solver, const double* eta_wedge);
+/* Solves K_D [u; p] = [f; g] (saddle point of Sec. 7) with x0 = 0.
+ * eta_wedge: device FP64 wedge field, or NULL to reuse the last setup.
+ * f[3]: device FP64 velocity right-hand side (its Dirichlet rows are the
+ * prescribed boundary velocity; zero in all uses here); g: device FP64
+ * pressure right-hand side or NULL for zero.  u[3], p: device FP64 outputs;
+ * the pressure is returned with zero nodal mean over unique nodes.
+ * Synchronises.  Returns TNG_E_NOTCONV (outputs still written) if rtol was
+ * not reached within the limits or a NaN/Inf appeared. */
+int tng_stokes_solve(tng_solver* solver, const double* eta_wedge, const double* const f[3], const double* g,
+                     double* const u[3], double* p, tng_solve_info* info);
+/* One V-cycle of the velocity preconditioner on level 0, x = M^{-1} b, in the
+ * solver's Krylov precision (FP32 when mixed).  b, x: device velocity fields. */
+int tng_stokes_solver_vcycle(tng_solver* solver, const void* const b[3], void* const x[3]);
+
 /* Sum the copies of every duplicate group of a node field and write the sum
  * to all copies (the one-GPU analog of the post-apply halo sum, Sec. 2); with
  * mode 1 instead copy the first copy to all others.  ncomp fields in f[]. */

@@ -7,6 +7,6 @@ the stream.  Importing the binding does not load the library; the first call
 does, and fails loudly if ``libtng.so`` has not been built.
 """
 from .binding import (  # noqa: F401
-    OP_A, OP_B, OP_BT, OP_DIRICHLET, TngError, Context, Mesh, eta_coarsen, eta_from_temperature,
-    interface_sum, lib, stokes_apply,
+    OP_A, OP_B, OP_BT, OP_DIRICHLET, TngError, Context, Mesh, StokesSolver, diag_A, eta_coarsen,
+    eta_from_temperature, interface_sum, lib, pressure_mass, prolong, restrict, smooth, stokes_apply,
 )

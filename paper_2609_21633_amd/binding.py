@@ -45,6 +45,18 @@ def lib():
         "tng_ctx_kernel_stats": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
         "tng_eta_from_temperature": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.c_double, _vp],
         "tng_eta_coarsen": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
+        "tng_diag_A": [_vp, _vp, C.c_int, C.c_int, _vp, C.POINTER(_vp)],
+        "tng_pressure_mass": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
+        "tng_smooth": [_vp, _vp, C.c_int, C.c_int, _vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                       C.c_int, C.c_int, C.c_double, C.c_double],
+        "tng_restrict": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
+        "tng_prolong": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
+        "tng_solver_opts_default": [_vp],
+        "tng_stokes_solver_create": [_vp, _vp, _vp, C.POINTER(_vp)],
+        "tng_stokes_solver_destroy": [_vp],
+        "tng_stokes_solver_setup": [_vp, _vp],
+        "tng_stokes_solve": [_vp, _vp, C.POINTER(_vp), _vp, C.POINTER(_vp), _vp, _vp],
+        "tng_stokes_solver_vcycle": [_vp, C.POINTER(_vp), C.POINTER(_vp)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -195,3 +207,82 @@ def eta_from_temperature(ctx: Context, mesh: Mesh, level: int, T, E: float, F: f
 def eta_coarsen(ctx: Context, mesh: Mesh, fine_level: int, eta_fine, eta_coarse):
     check(lib().tng_eta_coarsen(ctx.h, mesh.h, fine_level, _prec(eta_fine), _ptr(eta_fine),
                                 _ptr(eta_coarse)))
+
+
+def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag):
+    """Diagonal of the viscous block (Dirichlet rows 1) into diag ([3, ...])."""
+    check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr3(diag)))
+
+
+def pressure_mass(ctx: Context, mesh: Mesh, level: int, eta, mass):
+    """Lumped inverse-viscosity pressure mass on level + 1."""
+    check(lib().tng_pressure_mass(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr(mass)))
+
+
+def smooth(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, steps: int,
+           lmin: float, lmax: float):
+    check(lib().tng_smooth(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr3(diag), _ptr3(b), _ptr3(x),
+                           degree, steps, lmin, lmax))
+
+
+def restrict(ctx: Context, mesh: Mesh, fine_level: int, f, c):
+    check(lib().tng_restrict(ctx.h, mesh.h, fine_level, _prec(f[0]), _ptr3(f), _ptr3(c)))
+
+
+def prolong(ctx: Context, mesh: Mesh, fine_level: int, c, f):
+    check(lib().tng_prolong(ctx.h, mesh.h, fine_level, _prec(c[0]), _ptr3(c), _ptr3(f)))
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("mixed", C.c_int), ("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double),
+                ("cheb_degree", C.c_int), ("pre", C.c_int), ("post", C.c_int), ("levels", C.c_int),
+                ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("inner_rtol", C.c_double),
+                ("inner_max_iters", C.c_int), ("max_outer", C.c_int), ("power_its", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_its", C.c_int), ("inner_its", C.c_int), ("rel_res", C.c_double),
+                ("seconds", C.c_double), ("status", C.c_int)]
+
+
+class StokesSolver:
+    """FGMRES + block-triangular Schur preconditioner + multigrid (library-owned state)."""
+
+    def __init__(self, ctx: Context, mesh: Mesh, **opts):
+        o = SolverOpts()
+        check(lib().tng_solver_opts_default(C.byref(o)))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self.opts = o
+        self.ctx, self.mesh = ctx, mesh
+        h = _vp()
+        check(lib().tng_stokes_solver_create(ctx.h, mesh.h, C.byref(o), C.byref(h)))
+        self.h = h
+
+    def setup(self, eta):
+        check(lib().tng_stokes_solver_setup(self.h, _ptr(eta)))
+
+    def solve(self, f, g, u, p, eta=None, raise_on_fail: bool = True) -> dict:
+        info = SolveInfo()
+        rc = lib().tng_stokes_solve(self.h, _ptr(eta), _ptr3(f), _ptr(g), _ptr3(u), _ptr(p), C.byref(info))
+        out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        out["rc"] = rc
+        if rc != 0 and raise_on_fail:
+            check(rc)
+        return out
+
+    def vcycle(self, b, x):
+        check(lib().tng_stokes_solver_vcycle(self.h, _ptr3(b), _ptr3(x)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tng_stokes_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <string>
 
+#include "mg.hpp"
 #include "tng_internal.hpp"
 
 namespace tng {
@@ -53,6 +54,29 @@ void drain(tng_ctx* ctx) {
 tng_ctx::~tng_ctx() { tng::drain(this); }
 
 using tng::Error;
+
+namespace tng {
+namespace {
+template <typename T>
+void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, const void* const diag[3], const void* const b[3],
+              void* const x[3], int degree, int steps, double lmin, double lmax) {
+    const long long ns = L.node_slots(), n3 = 3 * ns;
+    tng::DevBuf<T> invd(n3), bb(n3), xx(n3), y(n3), d(n3);
+    hipStream_t st = ctx->stream;
+    for (int c = 0; c < 3; ++c) {
+        TNG_HIP(hipMemcpyAsync(invd.p + c * ns, diag[c], ns * sizeof(T), hipMemcpyDeviceToDevice, st));
+        TNG_HIP(hipMemcpyAsync(bb.p + c * ns, b[c], ns * sizeof(T), hipMemcpyDeviceToDevice, st));
+        TNG_HIP(hipMemcpyAsync(xx.p + c * ns, x[c], ns * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    tng::vec_invert<T>(ctx, n3, invd.p);
+    tng::chebyshev_steps<T>(ctx, L, (const T*)eta, invd.p, bb.p, xx.p, y.p, d.p, degree, steps, lmin, lmax, false);
+    for (int c = 0; c < 3; ++c)
+        TNG_HIP(hipMemcpyAsync(x[c], xx.p + c * ns, ns * sizeof(T), hipMemcpyDeviceToDevice, st));
+    TNG_HIP(hipStreamSynchronize(st));   // scratch is freed on return
+}
+}  // namespace
+}  // namespace tng
+
 
 extern "C" {
 
@@ -235,6 +259,99 @@ int tng_interface_sum(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
     for (int c = 0; c < ncomp; ++c) TNG_REQUIRE(f[c] != nullptr, "field pointer is NULL");
     TNG_HIP(hipSetDevice(ctx->device));
     tng::launch_interface(ctx, L, prec, mode, ncomp, f);
+    TNG_API_END
+}
+
+int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+               void* const diag[3]) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(eta_wedge && diag && diag[0] && diag[1] && diag[2], "NULL argument");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        double* d[3] = {(double*)diag[0], (double*)diag[1], (double*)diag[2]};
+        tng::mg_diag_A<double>(ctx, L, (const double*)eta_wedge, d);
+    } else {
+        float* d[3] = {(float*)diag[0], (float*)diag[1], (float*)diag[2]};
+        tng::mg_diag_A<float>(ctx, L, (const float*)eta_wedge, d);
+    }
+    TNG_API_END
+}
+
+int tng_pressure_mass(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+                      void* mass) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    const tng::Level& Lp = tng::device_level(ctx, mesh, level + 1);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(eta_wedge && mass, "NULL argument");
+    TNG_REQUIRE(L.m % 2 == 0 && L.n % 2 == 0, "needs even m and n");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64)
+        tng::mg_pmass<double>(ctx, L, Lp, (const double*)eta_wedge, (double*)mass);
+    else
+        tng::mg_pmass<float>(ctx, L, Lp, (const float*)eta_wedge, (float*)mass);
+    TNG_API_END
+}
+
+int tng_restrict(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec, const void* const f[3],
+                 void* const c[3]) {
+    TNG_API_BEGIN
+    const tng::Level& Lf = tng::device_level(ctx, mesh, fine_level);
+    const tng::Level& Lc = tng::device_level(ctx, mesh, fine_level + 1);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(f && c && f[0] && f[1] && f[2] && c[0] && c[1] && c[2], "NULL argument");
+    TNG_REQUIRE(Lf.m % 2 == 0 && Lf.n % 2 == 0, "needs even m and n");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        const double* ff[3] = {(const double*)f[0], (const double*)f[1], (const double*)f[2]};
+        double* cc[3] = {(double*)c[0], (double*)c[1], (double*)c[2]};
+        tng::mg_restrict<double>(ctx, Lf, Lc, ff, cc);
+    } else {
+        const float* ff[3] = {(const float*)f[0], (const float*)f[1], (const float*)f[2]};
+        float* cc[3] = {(float*)c[0], (float*)c[1], (float*)c[2]};
+        tng::mg_restrict<float>(ctx, Lf, Lc, ff, cc);
+    }
+    TNG_API_END
+}
+
+int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec, const void* const c[3],
+                void* const f[3]) {
+    TNG_API_BEGIN
+    const tng::Level& Lf = tng::device_level(ctx, mesh, fine_level);
+    tng::device_level(ctx, mesh, fine_level + 1);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(f && c && f[0] && f[1] && f[2] && c[0] && c[1] && c[2], "NULL argument");
+    TNG_REQUIRE(Lf.m % 2 == 0 && Lf.n % 2 == 0, "needs even m and n");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        const double* cc[3] = {(const double*)c[0], (const double*)c[1], (const double*)c[2]};
+        double* ff[3] = {(double*)f[0], (double*)f[1], (double*)f[2]};
+        tng::mg_prolong<double>(ctx, Lf, cc, ff, false);
+    } else {
+        const float* cc[3] = {(const float*)c[0], (const float*)c[1], (const float*)c[2]};
+        float* ff[3] = {(float*)f[0], (float*)f[1], (float*)f[2]};
+        tng::mg_prolong<float>(ctx, Lf, cc, ff, false);
+    }
+    TNG_API_END
+}
+
+int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+               const void* const diag[3], const void* const b[3], void* const x[3], int degree, int steps,
+               double lmin, double lmax) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(eta_wedge && diag && b && x, "NULL argument");
+    for (int c = 0; c < 3; ++c) TNG_REQUIRE(diag[c] && b[c] && x[c], "NULL field pointer");
+    TNG_REQUIRE(degree >= 1 && steps >= 0, "bad degree or steps");
+    TNG_REQUIRE(lmin > 0 && lmax > lmin, "need 0 < lmin < lmax");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64)
+        tng::smooth_t<double>(ctx, L, eta_wedge, diag, b, x, degree, steps, lmin, lmax);
+    else
+        tng::smooth_t<float>(ctx, L, eta_wedge, diag, b, x, degree, steps, lmin, lmax);
     TNG_API_END
 }
 

@@ -193,6 +193,16 @@ void build_level(Level& L, int m, int n, double r_in, double r_out, bool device)
     TNG_HIP(hipMemcpy(L.grp_slot.p, L.grp_slot_h.data(), L.grp_slot_h.size() * sizeof(int), hipMemcpyHostToDevice));
     L.owner.alloc(owner.size());
     TNG_HIP(hipMemcpy(L.owner.p, owner.data(), owner.size(), hipMemcpyHostToDevice));
+    std::vector<double> im(10 * nl);
+    std::vector<float> im32(10 * nl);
+    for (size_t q = 0; q < 10 * nl; ++q) {
+        im[q] = 1.0 / (double)members[L.uid[q]].size();
+        im32[q] = (float)im[q];
+    }
+    L.inv_mult64.alloc(im.size());
+    TNG_HIP(hipMemcpy(L.inv_mult64.p, im.data(), im.size() * sizeof(double), hipMemcpyHostToDevice));
+    L.inv_mult32.alloc(im32.size());
+    TNG_HIP(hipMemcpy(L.inv_mult32.p, im32.data(), im32.size() * sizeof(float), hipMemcpyHostToDevice));
 }
 
 }  // namespace

@@ -1,0 +1,90 @@
+// Declarations of the multigrid / Krylov launchers (mg_kernels.hip) and the
+// small device-side helper objects they share with the solver.
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+
+#include "tng_internal.hpp"
+
+namespace tng {
+
+constexpr int MAX_MDOT = 24;          // vectors in one multi-dot / multi-axpy
+constexpr int DOT_BLOCKS = 1024;      // partial sums of a reduction
+constexpr int MAX_COARSE_DOF = 1024;  // dense coarsest-level solve
+
+template <typename T>
+constexpr tng_prec prec_of() {
+    return std::is_same<T, double>::value ? TNG_F64 : TNG_F32;
+}
+
+struct DotScratch {
+    DevBuf<double> part;   // DOT_BLOCKS x MAX_MDOT
+    DotScratch() : part((size_t)DOT_BLOCKS * MAX_MDOT) {}
+};
+
+// Dense inverse of the coarsest-level viscous operator over its unique
+// interior DoFs.
+struct CoarseDense {
+    int ndof = 0;
+    long long nslots = 0;
+    DevBuf<int> dof_slot;   // [ndof]: (owner slot << 2) | component
+    DevBuf<int> slot_dof;   // [3][nslots]: DoF of every copy, -1 on Dirichlet rows
+    DevBuf<int> copy_ptr;   // [ndof + 1]: copies of each DoF (CSR)
+    DevBuf<int> copy_slot;  //   (slot << 2) | component of every copy
+    DevBuf<double> Ainv;    // ndof x ndof
+};
+
+template <typename T>
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, T* const d[3]);
+template <typename T>
+void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag);
+template <typename T>
+void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* const f[3], bool add);
+template <typename T>
+void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]);
+template <typename T>
+void vec_cheb_update(const tng_ctx* ctx, long long n, double alpha, double beta, const T* b, const T* y,
+                     const T* invd, T* d, T* x);
+template <typename T>
+void vec_invert(const tng_ctx* ctx, long long n, T* a);
+template <typename TO, typename TI>
+void vec_cast(const tng_ctx* ctx, long long n, const TI* a, TO* b);
+template <typename T>
+void vec_axpby(const tng_ctx* ctx, long long n, double a, const T* x, double b, T* y);
+template <typename T>
+void vec_mdot(const tng_ctx* ctx, DotScratch& ds, long long n, int n1, long long nlat, const uint8_t* owner,
+              const T* x, const T* const* vs_dev, int nq, double* out_dev, bool accumulate);
+template <typename T>
+void vec_mul(const tng_ctx* ctx, long long n, const T* a, const T* b, T* c);
+template <typename T>
+void vec_maxpy(const tng_ctx* ctx, long long n, const double* coef_dev, double sign, const T* const* vs_dev,
+               int nq, T* y);
+template <typename T>
+void coarse_unit(const tng_ctx* ctx, const CoarseDense& cd, int col, T* const x[3]);
+template <typename T>
+void coarse_gather(const tng_ctx* ctx, const CoarseDense& cd, int col, const T* const y[3], double* Ad);
+void coarse_invert(const tng_ctx* ctx, CoarseDense& cd);
+template <typename T>
+void coarse_solve(const tng_ctx* ctx, const CoarseDense& cd, const T* const b[3], T* const x[3]);
+template <typename T>
+void vec_shift(const tng_ctx* ctx, long long n, const double* sum_cnt, T* p);
+template <typename T>
+void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z);
+template <typename T>
+void vec_fill(const tng_ctx* ctx, long long n, T v, T* a);
+template <typename T>
+void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
+               const T* const* vs_dev, int nq, double* out_dev, bool accumulate);
+template <typename T>
+void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a);
+template <typename T>
+void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* x, T* y);
+template <typename T>
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta);
+
+template <typename T>
+void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, const T* invd, const T* b, T* x, T* y,
+                     T* d, int deg, int steps, double lo, double hi, bool x_zero);
+
+}  // namespace tng

@@ -1,0 +1,758 @@
+// Multigrid and Krylov building blocks (Sec. 7): operator diagonal, lumped
+// inverse-viscosity pressure mass, W1 transfer operators, Chebyshev update,
+// BLAS-1 with deterministic reductions, precision casts, and the dense
+// coarsest-level solve.
+//
+// All velocity vectors are in the duplicated-diamond layout with equal values
+// in every copy of a shared node.  Gathers that run per diamond produce
+// partial sums on diamond-edge nodes; the interface kernel then adds the
+// copies.  Reductions count every unique node once (owner mask).
+#include "tng_internal.hpp"
+#include "mg.hpp"
+#include "wedge.hpp"
+
+namespace tng {
+namespace {
+
+inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__constant__ IsoWeights<double> c_isomg = make_iso_weights<double>();
+
+struct NodeIdx {
+    int d, i, j, k;
+};
+__device__ __forceinline__ NodeIdx decode_node(long long t, int m, int n) {
+    NodeIdx r;
+    r.k = (int)(t % (n + 1));
+    t /= (n + 1);
+    r.j = (int)(t % (m + 1));
+    t /= (m + 1);
+    r.i = (int)(t % (m + 1));
+    r.d = (int)(t / (m + 1));
+    return r;
+}
+
+// Gradient of the wedge basis function of local node (lat, top) at q_c, with
+// the constants folded as in wedge.hpp: sign pattern of the reference gradient
+// times the folded rows of G^{-1}.
+__device__ __forceinline__ void basis_grad(const double* g, double s1, int lat, int top, double out[3]) {
+    const double a = lat == 0 ? -1.0 : (lat == 1 ? 1.0 : 0.0);
+    const double b = lat == 0 ? -1.0 : (lat == 2 ? 1.0 : 0.0);
+    const double c = top ? 1.0 : -1.0;
+    for (int x = 0; x < 3; ++x) out[x] = a * s1 * g[x] + b * s1 * g[3 + x] + c * g[6 + x];
+}
+
+// diag(A)_(node,c) = sum over the node's wedges of V eta (|grad phi|^2 + 1/3 (d_c phi)^2),
+// the diagonal of eq:elemmat with the one-point rule.  Per-diamond partial sums.
+template <typename T>
+__global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restrict__ geo, int m, int n,
+                              double r_in, double dr, T* d0, T* d1, T* d2, long long nslots) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const NodeIdx q = decode_node(t, m, n);
+    double acc[3] = {0, 0, 0};
+    for (int ci = q.i - 1; ci <= q.i; ++ci) {
+        if (ci < 0 || ci >= m) continue;
+        for (int cj = q.j - 1; cj <= q.j; ++cj) {
+            if (cj < 0 || cj >= m) continue;
+            const int di = q.i - ci, dj = q.j - cj;
+            const double* gcol = geo + (((long long)q.d * m + ci) * m + cj) * GEO_PER_COL;
+            for (int ck = q.k - 1; ck <= q.k; ++ck) {
+                if (ck < 0 || ck >= n) continue;
+                const int top = q.k - ck;
+                const double rm = r_in + (ck + 0.5) * dr;
+                const double s1 = 0.5 / rm;
+                for (int wd = 0; wd < 2; ++wd) {
+                    // local lateral index of the node in this wedge, -1 if not a vertex
+                    int lat = -1;
+                    if (wd == 0) lat = (di == 0 && dj == 0) ? 0 : (di == 1 && dj == 0) ? 1 : (di == 0 && dj == 1) ? 2 : -1;
+                    else lat = (di == 1 && dj == 1) ? 0 : (di == 0 && dj == 1) ? 1 : (di == 1 && dj == 0) ? 2 : -1;
+                    if (lat < 0) continue;
+                    const double* g = gcol + wd * GEO_PER_TRI;
+                    double gr[3];
+                    basis_grad(g, s1, lat, top, gr);
+                    const double V = rm * rm * g[9];
+                    const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
+                    const double nn = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+                    for (int c = 0; c < 3; ++c) acc[c] += V * e * (nn + gr[c] * gr[c] / 3.0);
+                }
+            }
+        }
+    }
+    d0[t] = T(acc[0]);
+    d1[t] = T(acc[1]);
+    d2[t] = T(acc[2]);
+}
+
+// Lumped M_{1/eta} on the pressure level: m_I = sum_e (V_e / eta_e) psi_I(q_c^e)
+// (eq:pmass, row-sum lumping, one-point rule), gathered per coarse node.
+template <typename T>
+__global__ void pmass_kernel(const T* __restrict__ eta, const double* __restrict__ geo, int m, int n,
+                             double r_in, double dr, T* __restrict__ out, long long ncslots) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncslots) return;
+    const int mc = m / 2, nc = n / 2;
+    const NodeIdx q = decode_node(t, mc, nc);
+    double acc = 0.0;
+    for (int Ic = q.i - 1; Ic <= q.i; ++Ic) {
+        if (Ic < 0 || Ic >= mc) continue;
+        for (int Jc = q.j - 1; Jc <= q.j; ++Jc) {
+            if (Jc < 0 || Jc >= mc) continue;
+            const int lc = (q.i - Ic) + 2 * (q.j - Jc);
+            for (int Kc = q.k - 1; Kc <= q.k; ++Kc) {
+                if (Kc < 0 || Kc >= nc) continue;
+                const int rc = q.k - Kc;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const int ci = 2 * Ic + a, cj = 2 * Jc + b;
+                        const double* gcol = geo + (((long long)q.d * m + ci) * m + cj) * GEO_PER_COL;
+                        for (int c = 0; c < 2; ++c) {
+                            const int ck = 2 * Kc + c;
+                            const double rm = r_in + (ck + 0.5) * dr;
+                            const double rw = c_isomg.rw[c][rc];
+                            for (int wd = 0; wd < 2; ++wd) {
+                                const double V = rm * rm * gcol[wd * GEO_PER_TRI + 9];
+                                const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
+                                acc += V / e * c_isomg.lw[a][b][wd][lc] * rw;
+                            }
+                        }
+                    }
+            }
+        }
+    }
+    out[t] = T(acc);
+}
+
+// Prolongation (W1 interpolation in index space): a fine node that is a
+// coarse node copies it, one on a coarse edge takes the mean of the edge's
+// end nodes (edges along i, along j, or the split diagonal), radially odd
+// layers take the mean of the two coarse layers.  y += P x (add) or y = P x.
+template <typename T>
+__global__ void prolong_kernel(int mf, int nf, const T* __restrict__ c0, const T* __restrict__ c1,
+                               const T* __restrict__ c2, T* f0, T* f1, T* f2, int add, long long nslots) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const NodeIdx q = decode_node(t, mf, nf);
+    const int mc = mf / 2, nc = nf / 2;
+    int li[2], lj[2], nl;
+    if ((q.i & 1) == 0 && (q.j & 1) == 0) { li[0] = q.i / 2; lj[0] = q.j / 2; nl = 1; }
+    else if ((q.i & 1) && (q.j & 1) == 0) { li[0] = q.i / 2; lj[0] = q.j / 2; li[1] = q.i / 2 + 1; lj[1] = q.j / 2; nl = 2; }
+    else if ((q.i & 1) == 0 && (q.j & 1)) { li[0] = q.i / 2; lj[0] = q.j / 2; li[1] = q.i / 2; lj[1] = q.j / 2 + 1; nl = 2; }
+    else { li[0] = q.i / 2; lj[0] = q.j / 2 + 1; li[1] = q.i / 2 + 1; lj[1] = q.j / 2; nl = 2; }
+    int kr[2], nk;
+    if ((q.k & 1) == 0) { kr[0] = q.k / 2; nk = 1; } else { kr[0] = q.k / 2; kr[1] = q.k / 2 + 1; nk = 2; }
+    const T wl = nl == 1 ? T(1) : T(0.5), wk = nk == 1 ? T(1) : T(0.5);
+    T s[3] = {0, 0, 0};
+    const T* cs[3] = {c0, c1, c2};
+    for (int a = 0; a < nl; ++a)
+        for (int b = 0; b < nk; ++b) {
+            const long long ci = (((long long)q.d * (mc + 1) + li[a]) * (mc + 1) + lj[a]) * (nc + 1) + kr[b];
+            for (int c = 0; c < 3; ++c) s[c] += cs[c][ci];
+        }
+    T* fs[3] = {f0, f1, f2};
+    for (int c = 0; c < 3; ++c) {
+        const T v = s[c] * wl * wk;
+        fs[c][t] = add ? fs[c][t] + v : v;
+    }
+}
+
+// Restriction R = P^T, per diamond: a coarse node gathers the fine nodes it
+// interpolates to, each weighted by its interpolation weight and by
+// 1/multiplicity of the fine node (so the interface sum over diamond copies
+// counts every fine node once).  Dirichlet layers of the result are zero.
+template <typename T>
+__global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const T* __restrict__ f1,
+                                const T* __restrict__ f2, const T* __restrict__ inv_mult,
+                                T* c0, T* c1, T* c2, long long ncslots) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncslots) return;
+    const int mc = mf / 2, nc = nf / 2;
+    const NodeIdx q = decode_node(t, mc, nc);
+    T s[3] = {0, 0, 0};
+    if (q.k > 0 && q.k < nc) {
+        // lateral fine neighbours that interpolate from this coarse node
+        const int di[7] = {0, 1, -1, 0, 0, 1, -1};
+        const int dj[7] = {0, 0, 0, 1, -1, -1, 1};
+        const T wl[7] = {T(1), T(0.5), T(0.5), T(0.5), T(0.5), T(0.5), T(0.5)};
+        const T* fs[3] = {f0, f1, f2};
+        for (int l = 0; l < 7; ++l) {
+            const int fi = 2 * q.i + di[l], fj = 2 * q.j + dj[l];
+            if (fi < 0 || fi > mf || fj < 0 || fj > mf) continue;
+            const long long lat = ((long long)q.d * (mf + 1) + fi) * (mf + 1) + fj;
+            const T wm = wl[l] * inv_mult[lat];
+            for (int dk = -1; dk <= 1; ++dk) {
+                const int fk = 2 * q.k + dk;
+                const T w = dk == 0 ? wm : T(0.5) * wm;
+                const long long fidx = lat * (nf + 1) + fk;
+                for (int c = 0; c < 3; ++c) s[c] += w * fs[c][fidx];
+            }
+        }
+    }
+    c0[t] = s[0];
+    c1[t] = s[1];
+    c2[t] = s[2];
+}
+
+// One Chebyshev step of the smoother on D^{-1} A, fused after y = A x:
+//   d <- alpha d + beta D^{-1} (b - y),   x <- x + d.
+template <typename T>
+__global__ void cheb_update_kernel(long long n, T alpha, T beta, const T* __restrict__ b,
+                                   const T* __restrict__ y, const T* __restrict__ invd, T* d, T* x) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const T r = beta * invd[t] * (b[t] - y[t]);
+    const T dv = alpha == T(0) ? r : alpha * d[t] + r;   // d may hold garbage on the first step
+    d[t] = dv;
+    x[t] += dv;
+}
+
+template <typename T>
+__global__ void invert_kernel(long long n, T* a) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = T(1) / a[t];
+}
+
+// Dirichlet rows of a velocity diagonal are identity rows.
+template <typename T>
+__global__ void diag_dirichlet_kernel(long long ncol, int n, T* d0, T* d1, T* d2) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * ncol) return;
+    const long long idx = (t >> 1) * (n + 1) + ((t & 1) ? n : 0);
+    d0[idx] = T(1);
+    d1[idx] = T(1);
+    d2[idx] = T(1);
+}
+
+template <typename TO, typename TI>
+__global__ void cast_kernel(long long n, const TI* __restrict__ a, TO* __restrict__ b) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = TO(a[t]);
+}
+
+// y <- a x + b y  (x may alias nothing; pass b = 0 to overwrite)
+template <typename T>
+__global__ void axpby_kernel(long long n, T a, const T* __restrict__ x, T b, T* y) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    y[t] = b == T(0) ? a * x[t] : a * x[t] + b * y[t];
+}
+
+// Multi-dot partials: for every vector v_q (q < nq) the block sum of
+// mask(slot) x v_q over one segment; a second kernel adds the block sums in a
+// fixed order, so the result does not depend on timing.
+constexpr int DOT_BS = 256;
+template <typename T>
+__global__ void mdot_partial_kernel(unsigned n, unsigned n1, unsigned nlat, const uint8_t* __restrict__ owner,
+                                    const T* __restrict__ x, const T* const* __restrict__ vs, int nq,
+                                    double* __restrict__ part) {
+    __shared__ double sh[DOT_BS / 64][MAX_MDOT];
+    __shared__ const T* vp[MAX_MDOT];
+    if (threadIdx.x < nq) vp[threadIdx.x] = vs[threadIdx.x];
+    __syncthreads();
+    double acc[MAX_MDOT];
+#pragma unroll
+    for (int q = 0; q < MAX_MDOT; ++q) acc[q] = 0.0;
+    for (unsigned t = blockIdx.x * DOT_BS + threadIdx.x; t < n; t += gridDim.x * DOT_BS) {
+        if (!owner[(t / n1) % nlat]) continue;
+        const double xv = (double)x[t];
+#pragma unroll
+        for (int q = 0; q < MAX_MDOT; ++q)
+            if (q < nq) acc[q] += xv * (double)vp[q][t];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < MAX_MDOT; ++q) {
+        if (q >= nq) break;
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double v = 0.0;
+        for (int w = 0; w < DOT_BS / 64; ++w) v += sh[w][threadIdx.x];
+        part[(long long)blockIdx.x * MAX_MDOT + threadIdx.x] = v;
+    }
+}
+
+// y <- y + sign * sum_q coef[q] v_q, coefficients read from device memory
+template <typename T>
+__global__ void maxpy_kernel(unsigned n, const double* __restrict__ coef, double sign,
+                             const T* const* __restrict__ vs, int nq, T* y) {
+    __shared__ const T* vp[MAX_MDOT];
+    __shared__ double cf[MAX_MDOT];
+    if (threadIdx.x < nq) {
+        vp[threadIdx.x] = vs[threadIdx.x];
+        cf[threadIdx.x] = sign * coef[threadIdx.x];
+    }
+    __syncthreads();
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        double acc = (double)y[t];
+        for (int q = 0; q < nq; ++q) acc += cf[q] * (double)vp[q][t];
+        y[t] = T(acc);
+    }
+}
+
+template <typename T>
+__global__ void mul_kernel(unsigned n, const T* __restrict__ a, const T* __restrict__ b, T* c) {
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c[t] = a[t] * b[t];
+}
+
+template <typename T>
+__global__ void fillv_kernel(unsigned n, T v, T* a) {
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) a[t] = v;
+}
+
+__global__ void mdot_final_kernel(int nblocks, int nq, const double* __restrict__ part, double* out,
+                                  int accumulate) {
+    const int q = threadIdx.x;
+    if (q >= nq) return;
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += part[(long long)b * MAX_MDOT + q];
+    out[q] = accumulate ? out[q] + v : v;
+}
+
+// Dense coarsest level ------------------------------------------------------
+
+// Column `col` of the assembled coarsest operator restricted to unique
+// interior DoFs: y = A e_col has been computed in the slot layout; gather the
+// owner copies into row-major dense storage (A is symmetric).
+template <typename T>
+__global__ void coarse_gather_col_kernel(int ndof, const int* __restrict__ dof_slot, const T* __restrict__ y0,
+                                         const T* __restrict__ y1, const T* __restrict__ y2, int col,
+                                         double* __restrict__ Ad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ndof) return;
+    const int s = dof_slot[r];
+    const int c = s & 3;
+    const long long slot = s >> 2;
+    const T v = c == 0 ? y0[slot] : (c == 1 ? y1[slot] : y2[slot]);
+    Ad[(long long)col * ndof + r] = (double)v;
+}
+
+// Gauss-Jordan inversion of an SPD matrix in one workgroup (no pivoting is
+// needed for SPD matrices).  a: ndof x ndof, overwritten by its inverse.
+__global__ void __launch_bounds__(1024) gauss_jordan_kernel(int nd, double* a) {
+    __shared__ double prow[MAX_COARSE_DOF];
+    __shared__ double pcol[MAX_COARSE_DOF];
+    for (int p = 0; p < nd; ++p) {
+        __syncthreads();
+        const double piv = a[(long long)p * nd + p];
+        for (int x = threadIdx.x; x < nd; x += blockDim.x) {
+            prow[x] = a[(long long)p * nd + x];
+            pcol[x] = a[(long long)x * nd + p];
+        }
+        __syncthreads();
+        const double ip = 1.0 / piv;
+        const long long total = (long long)nd * nd;
+        for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+            const int r = (int)(e / nd), c = (int)(e % nd);
+            double v;
+            if (r == p && c == p) v = ip;
+            else if (r == p) v = prow[c] * ip;
+            else if (c == p) v = -pcol[r] * ip;
+            else v = a[e] - pcol[r] * prow[c] * ip;
+            a[e] = v;
+        }
+    }
+}
+
+// x = A^{-1} b on the coarsest level: gather b at owner slots of interior
+// DoFs, dense symmetric matvec, scatter to every copy; other rows set to zero
+// (their right-hand side is zero in a V-cycle: Dirichlet rows).
+template <typename T>
+__global__ void __launch_bounds__(1024) coarse_solve_kernel(int nd, const int* __restrict__ dof_slot,
+                                                            const int* __restrict__ slot_dof, long long nslots,
+                                                            const double* __restrict__ Ainv,
+                                                            const T* __restrict__ b0, const T* __restrict__ b1,
+                                                            const T* __restrict__ b2, T* x0, T* x1, T* x2) {
+    __shared__ double rhs[MAX_COARSE_DOF];
+    __shared__ double sol[MAX_COARSE_DOF];
+    for (int r = threadIdx.x; r < nd; r += blockDim.x) {
+        const int s = dof_slot[r];
+        const int c = s & 3;
+        const long long slot = s >> 2;
+        rhs[r] = (double)(c == 0 ? b0[slot] : (c == 1 ? b1[slot] : b2[slot]));
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nd; r += blockDim.x) {
+        double v = 0.0;
+        for (int c = 0; c < nd; ++c) v += Ainv[(long long)c * nd + r] * rhs[c];
+        sol[r] = v;
+    }
+    __syncthreads();
+    for (long long t = threadIdx.x; t < 3 * nslots; t += blockDim.x) {
+        const int c = (int)(t / nslots);
+        const long long slot = t % nslots;
+        const int dof = slot_dof[c * nslots + slot];
+        const T v = dof >= 0 ? T(sol[dof]) : T(0);
+        if (c == 0) x0[slot] = v;
+        else if (c == 1) x1[slot] = v;
+        else x2[slot] = v;
+    }
+}
+
+template <typename T>
+__global__ void unit_vector_kernel(long long nslots, const int* __restrict__ slot_dof, int col, T* x0, T* x1,
+                                   T* x2) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * nslots) return;
+    const int c = (int)(t / nslots);
+    const long long slot = t % nslots;
+    const T v = slot_dof[c * nslots + slot] == col ? T(1) : T(0);
+    if (c == 0) x0[slot] = v;
+    else if (c == 1) x1[slot] = v;
+    else x2[slot] = v;
+}
+
+// Pressure: zero nodal mean projection helper  p <- p - mean
+template <typename T>
+__global__ void shift_kernel(long long n, const double* __restrict__ sum_cnt, T* p) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] -= T(sum_cnt[0] / sum_cnt[1]);
+}
+
+// Schur preconditioner on the pressure: z = -r / m (Sec. 7, eq:pmass)
+template <typename T>
+__global__ void schur_diag_kernel(long long n, const T* __restrict__ r, const T* __restrict__ mdiag, T* z) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) z[t] = -r[t] / mdiag[t];
+}
+
+// Multi-dot over a Stokes vector [u0 u1 u2 p] (velocity slots of one level
+// followed by its pressure slots): owner masks of both grids.
+template <typename T>
+__global__ void smdot_partial_kernel(unsigned ns, unsigned n1u, unsigned nlat_u, const uint8_t* __restrict__ ou,
+                                     unsigned np, unsigned n1p, const uint8_t* __restrict__ op,
+                                     const T* __restrict__ x, const T* const* __restrict__ vs, int nq,
+                                     double* __restrict__ part) {
+    __shared__ double sh[DOT_BS / 64][MAX_MDOT];
+    __shared__ const T* vp[MAX_MDOT];
+    if (threadIdx.x < nq) vp[threadIdx.x] = vs[threadIdx.x];
+    __syncthreads();
+    double acc[MAX_MDOT];
+#pragma unroll
+    for (int q = 0; q < MAX_MDOT; ++q) acc[q] = 0.0;
+    const unsigned nu = 3u * ns, n = nu + np;
+    for (unsigned t = blockIdx.x * DOT_BS + threadIdx.x; t < n; t += gridDim.x * DOT_BS) {
+        bool own;
+        if (t < nu) own = ou[(t / n1u) % nlat_u];
+        else own = op[(t - nu) / n1p];
+        if (!own) continue;
+        const double xv = (double)x[t];
+#pragma unroll
+        for (int q = 0; q < MAX_MDOT; ++q)
+            if (q < nq) acc[q] += xv * (double)vp[q][t];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < MAX_MDOT; ++q) {
+        if (q >= nq) break;
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double v = 0.0;
+        for (int w = 0; w < DOT_BS / 64; ++w) v += sh[w][threadIdx.x];
+        part[(long long)blockIdx.x * MAX_MDOT + threadIdx.x] = v;
+    }
+}
+
+// Counter-based uniform numbers in [-1, 1) (splitmix64 of seed and index).
+template <typename T>
+__global__ void rand_kernel(unsigned n, unsigned long long seed, T* a) {
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(t + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z = z ^ (z >> 31);
+        a[t] = T((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+    }
+}
+
+// y <- y / sqrt(s[0])  (normalise by a device-side squared norm)
+template <typename T>
+__global__ void scale_rsqrt_kernel(unsigned n, const double* __restrict__ s, const T* __restrict__ x, T* y) {
+    const double f = 1.0 / sqrt(s[0]);
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+        y[t] = T(f * (double)x[t]);
+}
+
+// Column `col` of D A D on the coarsest level, assembled from the one-point
+// element matrices (eq:elemmat) of every wedge around every copy of the
+// column's node; one thread per column, fixed loop order.
+template <typename T>
+__global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr, const int* __restrict__ copy_slot,
+                                       const int* __restrict__ slot_dof, long long nslots, const T* __restrict__ eta,
+                                       const double* __restrict__ geo, int m, int n, double r_in, double dr,
+                                       double* __restrict__ Ad) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= nd) return;
+    for (int r = 0; r < nd; ++r) Ad[(long long)col * nd + r] = 0.0;
+    for (int cp = copy_ptr[col]; cp < copy_ptr[col + 1]; ++cp) {
+        const int sc = copy_slot[cp];
+        const long long slot = sc >> 2;
+        const int ccomp = sc & 3;
+        const NodeIdx q = decode_node(slot, m, n);
+        for (int ci = q.i - 1; ci <= q.i; ++ci) {
+            if (ci < 0 || ci >= m) continue;
+            for (int cj = q.j - 1; cj <= q.j; ++cj) {
+                if (cj < 0 || cj >= m) continue;
+                const int di = q.i - ci, dj = q.j - cj;
+                const double* gcol = geo + (((long long)q.d * m + ci) * m + cj) * GEO_PER_COL;
+                for (int ck = q.k - 1; ck <= q.k; ++ck) {
+                    if (ck < 0 || ck >= n) continue;
+                    const int top = q.k - ck;
+                    const double rm = r_in + (ck + 0.5) * dr;
+                    const double s1 = 0.5 / rm;
+                    for (int wd = 0; wd < 2; ++wd) {
+                        const int cdi[2][3] = {{0, 1, 0}, {1, 0, 1}};
+                        const int cdj[2][3] = {{0, 0, 1}, {1, 1, 0}};
+                        int lat = -1;
+                        for (int l = 0; l < 3; ++l)
+                            if (cdi[wd][l] == di && cdj[wd][l] == dj) lat = l;
+                        if (lat < 0) continue;
+                        const double* g = gcol + wd * GEO_PER_TRI;
+                        const double V = rm * rm * g[9];
+                        const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
+                        double gj[3];
+                        basis_grad(g, s1, lat, top, gj);
+                        for (int l2 = 0; l2 < 6; ++l2) {
+                            const int lat2 = l2 % 3, top2 = l2 / 3;
+                            double gl[3];
+                            basis_grad(g, s1, lat2, top2, gl);
+                            const long long s2 = (((long long)q.d * (m + 1) + ci + cdi[wd][lat2]) * (m + 1) +
+                                                  cj + cdj[wd][lat2]) * (n + 1) + ck + top2;
+                            const double gg = gj[0] * gl[0] + gj[1] * gl[1] + gj[2] * gl[2];
+                            for (int d2 = 0; d2 < 3; ++d2) {
+                                const int row = slot_dof[d2 * nslots + s2];
+                                if (row < 0) continue;
+                                // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c - 2/3 (g_j)_c (g_l)_d]
+                                const double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
+                                                          (2.0 / 3.0) * gj[ccomp] * gl[d2]);
+                                Ad[(long long)col * nd + row] += v;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, T* const d[3]) {
+    const long long ns = L.node_slots();
+    diag_A_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(),
+                                                             d[0], d[1], d[2], ns);
+    TNG_HIP(hipGetLastError());
+    void* f[3] = {d[0], d[1], d[2]};
+    launch_interface(ctx, L, prec_of<T>(), 0, 3, f);
+    diag_dirichlet_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(L.lat_slots(), L.n, d[0],
+                                                                                  d[1], d[2]);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag) {
+    const long long ns = Lp.node_slots();
+    pmass_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(), mdiag, ns);
+    TNG_HIP(hipGetLastError());
+    void* f[1] = {mdiag};
+    launch_interface(ctx, Lp, prec_of<T>(), 0, 1, f);
+}
+
+template <typename T>
+void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* const f[3], bool add) {
+    const long long ns = Lf.node_slots();
+    prolong_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(Lf.m, Lf.n, c[0], c[1], c[2], f[0], f[1], f[2],
+                                                              add ? 1 : 0, ns);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]) {
+    const long long ns = Lc.node_slots();
+    const T* im = std::is_same<T, double>::value ? (const T*)Lf.inv_mult64.p : (const T*)Lf.inv_mult32.p;
+    restrict_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(Lf.m, Lf.n, f[0], f[1], f[2], im, c[0], c[1],
+                                                               c[2], ns);
+    TNG_HIP(hipGetLastError());
+    void* g[3] = {c[0], c[1], c[2]};
+    launch_interface(ctx, Lc, prec_of<T>(), 0, 3, g);
+}
+
+template <typename T>
+void vec_cheb_update(const tng_ctx* ctx, long long n, double alpha, double beta, const T* b, const T* y,
+                     const T* invd, T* d, T* x) {
+    cheb_update_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, T(alpha), T(beta), b, y, invd, d, x);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_invert(const tng_ctx* ctx, long long n, T* a) {
+    invert_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, a);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename TO, typename TI>
+void vec_cast(const tng_ctx* ctx, long long n, const TI* a, TO* b) {
+    cast_kernel<TO, TI><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, a, b);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_axpby(const tng_ctx* ctx, long long n, double a, const T* x, double b, T* y) {
+    axpby_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, T(a), x, T(b), y);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_mdot(const tng_ctx* ctx, DotScratch& ds, long long n, int n1, long long nlat, const uint8_t* owner,
+              const T* x, const T* const* vs_dev, int nq, double* out_dev, bool accumulate) {
+    TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-dot");
+    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
+    mdot_partial_kernel<T><<<nb, DOT_BS, 0, ctx->stream>>>((unsigned)n, (unsigned)n1, (unsigned)nlat, owner, x,
+                                                            vs_dev, nq, ds.part.p);
+    TNG_HIP(hipGetLastError());
+    mdot_final_kernel<<<1, 64, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_maxpy(const tng_ctx* ctx, long long n, const double* coef_dev, double sign, const T* const* vs_dev,
+               int nq, T* y) {
+    TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-axpy");
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    maxpy_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, coef_dev, sign, vs_dev, nq, y);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
+               const T* const* vs_dev, int nq, double* out_dev, bool accumulate) {
+    TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-dot");
+    const long long n = 3 * Lu.node_slots() + Lp.node_slots();
+    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
+    smdot_partial_kernel<T><<<nb, DOT_BS, 0, ctx->stream>>>(
+        (unsigned)Lu.node_slots(), (unsigned)(Lu.n + 1), (unsigned)Lu.lat_slots(), Lu.owner.p,
+        (unsigned)Lp.node_slots(), (unsigned)(Lp.n + 1), Lp.owner.p, x, vs_dev, nq, ds.part.p);
+    TNG_HIP(hipGetLastError());
+    mdot_final_kernel<<<1, 64, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a) {
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    rand_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, seed, a);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* x, T* y) {
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    scale_rsqrt_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, s, x, y);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta) {
+    coarse_assemble_kernel<T><<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(
+        cd.ndof, cd.copy_ptr.p, cd.copy_slot.p, cd.slot_dof.p, cd.nslots, eta, L.geo64.p, L.m, L.n, L.r_in,
+        L.dr(), cd.Ainv.p);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_mul(const tng_ctx* ctx, long long n, const T* a, const T* b, T* c) {
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    mul_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, a, b, c);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_fill(const tng_ctx* ctx, long long n, T v, T* a) {
+    if (n <= 0) return;
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    fillv_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, v, a);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void coarse_unit(const tng_ctx* ctx, const CoarseDense& cd, int col, T* const x[3]) {
+    unit_vector_kernel<T><<<nblk(3 * cd.nslots, 256), 256, 0, ctx->stream>>>(cd.nslots, cd.slot_dof.p, col, x[0],
+                                                                             x[1], x[2]);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void coarse_gather(const tng_ctx* ctx, const CoarseDense& cd, int col, const T* const y[3], double* Ad) {
+    coarse_gather_col_kernel<T><<<nblk(cd.ndof, 256), 256, 0, ctx->stream>>>(cd.ndof, cd.dof_slot.p, y[0], y[1],
+                                                                              y[2], col, Ad);
+    TNG_HIP(hipGetLastError());
+}
+
+void coarse_invert(const tng_ctx* ctx, CoarseDense& cd) {
+    gauss_jordan_kernel<<<1, 1024, 0, ctx->stream>>>(cd.ndof, cd.Ainv.p);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void coarse_solve(const tng_ctx* ctx, const CoarseDense& cd, const T* const b[3], T* const x[3]) {
+    coarse_solve_kernel<T><<<1, 1024, 0, ctx->stream>>>(cd.ndof, cd.dof_slot.p, cd.slot_dof.p, cd.nslots,
+                                                        cd.Ainv.p, b[0], b[1], b[2], x[0], x[1], x[2]);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_shift(const tng_ctx* ctx, long long n, const double* sum_cnt, T* p) {
+    shift_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, sum_cnt, p);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z) {
+    schur_diag_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, r, mdiag, z);
+    TNG_HIP(hipGetLastError());
+}
+
+#define TNG_INST(T)                                                                                        \
+    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, T* const[3]);                      \
+    template void mg_pmass<T>(const tng_ctx*, const Level&, const Level&, const T*, T*);                  \
+    template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
+    template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
+                                 T* const[3]);                                                             \
+    template void vec_cheb_update<T>(const tng_ctx*, long long, double, double, const T*, const T*,       \
+                                     const T*, T*, T*);                                                    \
+    template void vec_invert<T>(const tng_ctx*, long long, T*);                                           \
+    template void vec_axpby<T>(const tng_ctx*, long long, double, const T*, double, T*);                  \
+    template void vec_mdot<T>(const tng_ctx*, DotScratch&, long long, int, long long, const uint8_t*,     \
+                              const T*, const T* const*, int, double*, bool);                              \
+    template void coarse_unit<T>(const tng_ctx*, const CoarseDense&, int, T* const[3]);                   \
+    template void coarse_gather<T>(const tng_ctx*, const CoarseDense&, int, const T* const[3], double*);  \
+    template void coarse_solve<T>(const tng_ctx*, const CoarseDense&, const T* const[3], T* const[3]);    \
+    template void vec_shift<T>(const tng_ctx*, long long, const double*, T*);                             \
+    template void vec_schur<T>(const tng_ctx*, long long, const T*, const T*, T*);                       \
+    template void vec_maxpy<T>(const tng_ctx*, long long, const double*, double, const T* const*, int, T*); \
+    template void vec_fill<T>(const tng_ctx*, long long, T, T*);                                          \
+    template void vec_mul<T>(const tng_ctx*, long long, const T*, const T*, T*);                          \
+    template void vec_smdot<T>(const tng_ctx*, DotScratch&, const Level&, const Level&, const T*,         \
+                               const T* const*, int, double*, bool);                                       \
+    template void vec_rand<T>(const tng_ctx*, long long, unsigned long long, T*);                         \
+    template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
+    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*);
+TNG_INST(double)
+TNG_INST(float)
+#undef TNG_INST
+template void vec_cast<float, double>(const tng_ctx*, long long, const double*, float*);
+template void vec_cast<double, float>(const tng_ctx*, long long, const float*, double*);
+
+}  // namespace tng

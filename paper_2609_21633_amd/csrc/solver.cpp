@@ -1,0 +1,712 @@
+// Stokes solver (Sec. 7): FGMRES right-preconditioned by the block-triangular
+// Schur preconditioner of eq:block-precond,
+//   z_p = S^{-1} r_p = -diag(M_{1/eta})^{-1} r_p       (eq:pmass, lumped),
+//   z_u = A^{-1} (r_u - B^T z_p),  A^{-1} ~ one geometric multigrid V-cycle
+// with Chebyshev smoothing (degree 2, pre/post steps per level), re-discretised
+// coarse operators on averaged viscosity, and an exact solve on the coarsest
+// level.  Mixed precision: FP64 iterative refinement around an FP32 inner
+// FGMRES whose operator applies, smoothers and Krylov basis are FP32 (the
+// coarsest solve stays FP64).
+//
+// All vectors live on the device in the duplicated-diamond layout; a Stokes
+// vector is [u0 | u1 | u2 | p] with the velocity of level 0 and the pressure
+// of level 1.  Host work is limited to the small Hessenberg least-squares
+// problem; every FGMRES iteration reads back one short array of dots.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "mg.hpp"
+
+namespace tng {
+
+template <typename T>
+struct MGLevel {
+    const Level* L = nullptr;
+    long long ns = 0;
+    DevBuf<T> eta;                      // wedge viscosity of this level
+    DevBuf<T> invd;                     // 3 ns: inverse diagonal of A
+    DevBuf<T> x, b, r, y, d;            // 3 ns scratch
+    DevBuf<const T*> xy;                // device pointers {x, y} for reductions
+    double lmax = 1.0;                  // largest eigenvalue of D^{-1} A (estimate)
+    T* c(DevBuf<T>& v, int k) { return v.p + (long long)k * ns; }
+};
+
+template <typename T>
+struct KrylovWS {
+    int restart = 0;
+    long long N = 0;
+    DevBuf<T> V, Z, w, t;
+    DevBuf<const T*> vptr, zptr, wptr;
+    DevBuf<double> coef;                // device dots / coefficients
+    T* Vi(int i) { return V.p + (long long)i * N; }
+    T* Zi(int i) { return Z.p + (long long)i * N; }
+};
+
+}  // namespace tng
+
+struct tng_solver {
+    tng_ctx* ctx = nullptr;
+    tng_mesh* mesh = nullptr;
+    tng_solver_opts opts{};
+    int nlev = 0;
+    std::vector<tng::MGLevel<double>> h64;
+    std::vector<tng::MGLevel<float>> h32;
+    tng::CoarseDense cd;
+    std::unique_ptr<tng::DotScratch> ds;
+    tng::KrylovWS<double> k64;
+    tng::KrylovWS<float> k32;
+    tng::DevBuf<double> pm64;           // lumped M_{1/eta} on the pressure level
+    tng::DevBuf<float> pm32;
+    tng::DevBuf<double> ones_p;         // pressure-level ones (mean projection)
+    tng::DevBuf<double> xo, ro, bo;     // outer FP64 vectors (mixed precision)
+    tng::DevBuf<float> r32, d32;
+    tng::DevBuf<double> scal;           // device scalars
+    tng::DevBuf<const double*> dptr;    // [bo, ro, pressure of xo, k64.w]
+    double* host = nullptr;             // pinned read-back buffer
+    bool ready = false;
+    long long ns0 = 0, np = 0, N = 0;
+    ~tng_solver() {
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+namespace tng {
+namespace {
+
+const Level& L0(const tng_solver* s) { return s->mesh->lv[0]; }
+const Level& L1(const tng_solver* s) { return s->mesh->lv[1]; }
+
+void sync(const tng_solver* s) { TNG_HIP(hipStreamSynchronize(s->ctx->stream)); }
+
+// read n doubles from device scalars into the pinned host buffer
+void readback(tng_solver* s, const double* dev, int n) {
+    TNG_HIP(hipMemcpyAsync(s->host, dev, n * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream));
+    sync(s);
+}
+
+template <typename T>
+std::vector<MGLevel<T>>& hier(tng_solver* s);
+template <>
+std::vector<MGLevel<double>>& hier<double>(tng_solver* s) { return s->h64; }
+template <>
+std::vector<MGLevel<float>>& hier<float>(tng_solver* s) { return s->h32; }
+template <typename T>
+KrylovWS<T>& kws(tng_solver* s);
+template <>
+KrylovWS<double>& kws<double>(tng_solver* s) { return s->k64; }
+template <>
+KrylovWS<float>& kws<float>(tng_solver* s) { return s->k32; }
+template <typename T>
+T* pmass(tng_solver* s);
+template <>
+double* pmass<double>(tng_solver* s) { return s->pm64.p; }
+template <>
+float* pmass<float>(tng_solver* s) { return s->pm32.p; }
+
+// ---- operators ------------------------------------------------------------
+template <typename T>
+void apply_K(tng_solver* s, const T* eta0, const T* x, T* y) {
+    const long long ns = s->ns0;
+    const void* u[3] = {x, x + ns, x + 2 * ns};
+    void* yu[3] = {y, y + ns, y + 2 * ns};
+    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_A | TNG_OP_BT | TNG_OP_B | TNG_OP_DIRICHLET,
+                        eta0, u, x + 3 * ns, yu, y + 3 * ns);
+}
+
+template <typename T>
+void apply_A(tng_solver* s, int l, const T* eta, const T* x, T* y) {
+    const Level& L = s->mesh->lv[l];
+    const long long ns = L.node_slots();
+    const void* u[3] = {x, x + ns, x + 2 * ns};
+    void* yu[3] = {y, y + ns, y + 2 * ns};
+    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, eta, u, nullptr, yu,
+                        nullptr);
+}
+
+template <typename T>
+void apply_BT(tng_solver* s, const T* p, T* yu) {
+    const long long ns = s->ns0;
+    void* y[3] = {yu, yu + ns, yu + 2 * ns};
+    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_BT | TNG_OP_DIRICHLET, nullptr, nullptr, p, y,
+                        nullptr);
+}
+
+// squared owner-masked norm of a velocity vector of level l into device scalar
+template <typename T>
+void vel_dot(tng_solver* s, int l, const T* x, const T* const* ydev, double* out) {
+    const Level& L = s->mesh->lv[l];
+    vec_mdot<T>(s->ctx, *s->ds, 3 * L.node_slots(), L.n + 1, L.lat_slots(), L.owner.p, x, ydev, 1, out, false);
+}
+
+// ---- smoother, V-cycle ----------------------------------------------------
+}  // namespace
+
+// Chebyshev smoother on D^{-1} A (Saad's three-term recurrence) for the
+// eigenvalue interval [lo, hi]: every step is a polynomial of degree `deg`
+// (deg operator applies; the first one is skipped when x starts at zero).
+template <typename T>
+void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, const T* invd, const T* b, T* x, T* y,
+                     T* d, int deg, int steps, double lo, double hi, bool x_zero) {
+    const long long ns = L.node_slots(), n3 = 3 * ns;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    auto applyA = [&](const T* xin, T* yout) {
+        const void* u[3] = {xin, xin + ns, xin + 2 * ns};
+        void* yu[3] = {yout, yout + ns, yout + 2 * ns};
+        launch_stokes_apply(ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, eta, u, nullptr, yu,
+                            nullptr);
+    };
+    for (int st = 0; st < steps; ++st) {
+        if (x_zero && st == 0) {
+            vec_fill<T>(ctx, n3, T(0), x);
+            vec_fill<T>(ctx, n3, T(0), y);
+        } else {
+            applyA(x, y);
+        }
+        vec_cheb_update<T>(ctx, n3, 0.0, 1.0 / theta, b, y, invd, d, x);
+        double rho_old = 1.0 / sigma;
+        for (int k = 1; k < deg; ++k) {
+            applyA(x, y);
+            const double rho = 1.0 / (2.0 * sigma - rho_old);
+            vec_cheb_update<T>(ctx, n3, rho * rho_old, 2.0 * rho / delta, b, y, invd, d, x);
+            rho_old = rho;
+        }
+    }
+}
+
+namespace {
+
+template <typename T>
+void chebyshev(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
+    MGLevel<T>& M = hier<T>(s)[l];
+    chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, M.invd.p, b, x, M.y.p, M.d.p, std::max(1, s->opts.cheb_degree),
+                       steps, s->opts.cheb_lo * M.lmax, s->opts.cheb_hi * M.lmax, x_zero);
+}
+
+template <typename T>
+void vcycle(tng_solver* s, int l, const T* b, T* x) {
+    auto& H = hier<T>(s);
+    MGLevel<T>& M = H[l];
+    const long long ns = M.ns;
+    if (l == s->nlev - 1) {
+        const T* bb[3] = {b, b + ns, b + 2 * ns};
+        T* xx[3] = {x, x + ns, x + 2 * ns};
+        coarse_solve<T>(s->ctx, s->cd, bb, xx);
+        return;
+    }
+    chebyshev<T>(s, l, b, x, true, s->opts.pre);
+    // r = b - A x
+    apply_A<T>(s, l, M.eta.p, x, M.r.p);
+    vec_axpby<T>(s->ctx, 3 * ns, 1.0, b, -1.0, M.r.p);
+    MGLevel<T>& C = H[l + 1];
+    const T* rf[3] = {M.r.p, M.r.p + ns, M.r.p + 2 * ns};
+    T* bc[3] = {C.b.p, C.b.p + C.ns, C.b.p + 2 * C.ns};
+    mg_restrict<T>(s->ctx, *M.L, *C.L, rf, bc);
+    vcycle<T>(s, l + 1, C.b.p, C.x.p);
+    const T* xc[3] = {C.x.p, C.x.p + C.ns, C.x.p + 2 * C.ns};
+    T* xf[3] = {x, x + ns, x + 2 * ns};
+    mg_prolong<T>(s->ctx, *M.L, xc, xf, true);
+    chebyshev<T>(s, l, b, x, false, s->opts.post);
+}
+
+// block-triangular Schur preconditioner: z = P^{-1} v
+template <typename T>
+void precond(tng_solver* s, const T* v, T* z) {
+    KrylovWS<T>& K = kws<T>(s);
+    const long long ns = s->ns0, np = s->np;
+    vec_schur<T>(s->ctx, np, v + 3 * ns, pmass<T>(s), z + 3 * ns);
+    apply_BT<T>(s, z + 3 * ns, K.t.p);                           // t = B^T z_p
+    vec_axpby<T>(s->ctx, 3 * ns, 1.0, v, -1.0, K.t.p);           // t = v_u - B^T z_p
+    vcycle<T>(s, 0, K.t.p, z);                                   // z_u ~ A^{-1} t
+}
+
+double host_norm_from_dev(tng_solver* s, const double* dev) {
+    readback(s, dev, 1);
+    return std::sqrt(std::max(0.0, s->host[0]));
+}
+
+// ---- FGMRES ---------------------------------------------------------------
+// Solves K x = b to a relative (to ||b||) tolerance; x is overwritten (x0 = 0).
+template <typename T>
+int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxit, int* its_out,
+           double* relres_out) {
+    KrylovWS<T>& K = kws<T>(s);
+    const Level& Lu = L0(s);
+    const Level& Lp = L1(s);
+    const long long N = s->N;
+    const int m = K.restart;
+    double* dsc = K.coef.p;               // [0, 2*MAX_MDOT + 2)
+    vec_fill<T>(s->ctx, N, T(0), x);
+    // beta = ||b||; K.wptr[0] points at b (fixed at creation)
+    vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, b, K.wptr.p, 1, dsc, false);
+    const double bnorm = host_norm_from_dev(s, dsc);
+    int its = 0;
+    if (!(bnorm > 0.0)) {
+        *its_out = 0;
+        *relres_out = 0.0;
+        return std::isfinite(bnorm) ? TNG_OK : TNG_E_NOTCONV;
+    }
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+    double beta = bnorm;
+    // V0 = b / beta
+    vec_axpby<T>(s->ctx, N, 1.0 / beta, b, 0.0, K.Vi(0));
+    double res = beta;
+    bool done = false;
+    while (!done) {
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < m; ++j) {
+            precond<T>(s, K.Vi(j), K.Zi(j));
+            apply_K<T>(s, eta0, K.Zi(j), K.w.p);
+            // classical Gram-Schmidt, twice
+            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc, false);
+            vec_maxpy<T>(s->ctx, N, dsc, -1.0, K.vptr.p, j + 1, K.w.p);
+            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc + MAX_MDOT, false);
+            vec_maxpy<T>(s->ctx, N, dsc + MAX_MDOT, -1.0, K.vptr.p, j + 1, K.w.p);
+            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.wptr.p + 1, 1, dsc + 2 * MAX_MDOT, false);
+            vec_scale_rsqrt<T>(s->ctx, N, dsc + 2 * MAX_MDOT, K.w.p, K.Vi(j + 1));
+            readback(s, dsc, 2 * MAX_MDOT + 1);
+            double* h = &H[(size_t)j * (m + 1)];
+            for (int i = 0; i <= j; ++i) h[i] = s->host[i] + s->host[MAX_MDOT + i];
+            h[j + 1] = std::sqrt(std::max(0.0, s->host[2 * MAX_MDOT]));
+            if (!std::isfinite(h[j + 1])) return TNG_E_NOTCONV;
+            for (int i = 0; i < j; ++i) {
+                const double t0 = cs[i] * h[i] + sn[i] * h[i + 1];
+                h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+                h[i] = t0;
+            }
+            const double den = std::hypot(h[j], h[j + 1]);
+            cs[j] = den > 0 ? h[j] / den : 1.0;
+            sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+            h[j] = den;
+            h[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            res = std::fabs(g[j + 1]);
+            ++its;
+            jend = j;
+            if (res <= rtol * bnorm || its >= maxit || h[j] == 0.0) {
+                done = true;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular), x += Z y
+        for (int i = jend; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k <= jend; ++k) acc -= H[(size_t)k * (m + 1) + i] * y[k];
+            y[i] = acc / H[(size_t)i * (m + 1) + i];
+        }
+        std::memcpy(s->host, y.data(), (jend + 1) * sizeof(double));
+        TNG_HIP(hipMemcpyAsync(dsc + 3 * MAX_MDOT, s->host, (jend + 1) * sizeof(double), hipMemcpyHostToDevice,
+                               s->ctx->stream));
+        vec_maxpy<T>(s->ctx, N, dsc + 3 * MAX_MDOT, 1.0, K.zptr.p, jend + 1, x);
+        sync(s);   // the pinned buffer is reused below
+        if (done) break;
+        // restart from the true residual
+        apply_K<T>(s, eta0, x, K.w.p);
+        vec_axpby<T>(s->ctx, N, 1.0, b, -1.0, K.w.p);
+        vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.wptr.p + 1, 1, dsc, false);
+        beta = host_norm_from_dev(s, dsc);
+        res = beta;
+        if (beta <= rtol * bnorm) break;
+        if (!std::isfinite(beta)) return TNG_E_NOTCONV;
+        vec_axpby<T>(s->ctx, N, 1.0 / beta, K.w.p, 0.0, K.Vi(0));
+    }
+    *its_out = its;
+    *relres_out = res / bnorm;
+    return std::isfinite(res) ? TNG_OK : TNG_E_NOTCONV;
+}
+
+// p <- p - mean(p) over unique pressure nodes of the outer solution xo
+void remove_pressure_mean(tng_solver* s) {
+    const Level& P = L1(s);
+    double* p = s->xo.p + 3 * s->ns0;
+    vec_mdot<double>(s->ctx, *s->ds, P.node_slots(), P.n + 1, P.lat_slots(), P.owner.p, s->ones_p.p,
+                     s->dptr.p + 2, 1, s->scal.p + 32, false);
+    vec_shift<double>(s->ctx, P.node_slots(), s->scal.p + 32, p);
+}
+
+// ---- setup ----------------------------------------------------------------
+void build_coarse_maps(tng_solver* s) {
+    const Level& C = s->mesh->lv[s->nlev - 1];
+    const int m = C.m, n = C.n;
+    const long long nl = C.lat_slots(), nsl = C.node_slots();
+    // owner slot of every unique lateral id
+    std::vector<int> owner_of(C.n_unique_lat, -1);
+    for (long long q = 0; q < nl; ++q)
+        if (owner_of[C.uid[q]] < 0) owner_of[C.uid[q]] = (int)q;
+    std::vector<int> dof_of_uid_k((size_t)C.n_unique_lat * (n + 1) * 3, -1);
+    std::vector<int> dof_slot;
+    for (long long q = 0; q < nl; ++q) {
+        if (owner_of[C.uid[q]] != q) continue;
+        for (int k = 1; k < n; ++k)
+            for (int c = 0; c < 3; ++c) {
+                dof_of_uid_k[((size_t)C.uid[q] * (n + 1) + k) * 3 + c] = (int)dof_slot.size();
+                dof_slot.push_back((int)(((q * (n + 1) + k) << 2) | c));
+            }
+    }
+    const int nd = (int)dof_slot.size();
+    if (nd > MAX_COARSE_DOF)
+        throw Error(TNG_E_INVAL, "coarsest level has " + std::to_string(nd) + " interior DoFs (max " +
+                                     std::to_string(MAX_COARSE_DOF) + "); build more levels");
+    std::vector<int> slot_dof((size_t)3 * nsl, -1);
+    std::vector<std::vector<int>> copies(nd);
+    for (long long q = 0; q < nl; ++q)
+        for (int k = 1; k < n; ++k)
+            for (int c = 0; c < 3; ++c) {
+                const int dof = dof_of_uid_k[((size_t)C.uid[q] * (n + 1) + k) * 3 + c];
+                const long long slot = q * (n + 1) + k;
+                slot_dof[(size_t)c * nsl + slot] = dof;
+                copies[dof].push_back((int)((slot << 2) | c));
+            }
+    std::vector<int> cptr(1, 0), cslot;
+    for (auto& v : copies) {
+        cslot.insert(cslot.end(), v.begin(), v.end());
+        cptr.push_back((int)cslot.size());
+    }
+    s->cd.ndof = nd;
+    s->cd.nslots = nsl;
+    s->cd.dof_slot.alloc(nd);
+    TNG_HIP(hipMemcpy(s->cd.dof_slot.p, dof_slot.data(), nd * sizeof(int), hipMemcpyHostToDevice));
+    s->cd.slot_dof.alloc(slot_dof.size());
+    TNG_HIP(hipMemcpy(s->cd.slot_dof.p, slot_dof.data(), slot_dof.size() * sizeof(int), hipMemcpyHostToDevice));
+    s->cd.copy_ptr.alloc(cptr.size());
+    TNG_HIP(hipMemcpy(s->cd.copy_ptr.p, cptr.data(), cptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    s->cd.copy_slot.alloc(cslot.size());
+    TNG_HIP(hipMemcpy(s->cd.copy_slot.p, cslot.data(), cslot.size() * sizeof(int), hipMemcpyHostToDevice));
+    s->cd.Ainv.alloc((size_t)nd * nd);
+}
+
+template <typename T>
+void alloc_hierarchy(tng_solver* s, bool scratch) {
+    auto& H = hier<T>(s);
+    H.clear();
+    H.resize(s->nlev);
+    for (int l = 0; l < s->nlev; ++l) {
+        MGLevel<T>& M = H[l];
+        M.L = &s->mesh->lv[l];
+        M.ns = M.L->node_slots();
+        M.eta.alloc(2 * M.L->cells());
+        if (!scratch) continue;
+        const long long n3 = 3 * M.ns;
+        M.invd.alloc(n3);
+        M.x.alloc(n3);
+        M.b.alloc(n3);
+        M.r.alloc(n3);
+        M.y.alloc(n3);
+        M.d.alloc(n3);
+        const T* xy[2] = {M.x.p, M.y.p};
+        M.xy.alloc(2);
+        TNG_HIP(hipMemcpy(M.xy.p, xy, sizeof(xy), hipMemcpyHostToDevice));
+    }
+}
+
+template <typename T>
+void alloc_krylov(tng_solver* s, const T* rhs) {
+    KrylovWS<T>& K = kws<T>(s);
+    const int m = s->opts.restart;
+    K.restart = m;
+    K.N = s->N;
+    K.V.alloc((size_t)(m + 1) * s->N);
+    K.Z.alloc((size_t)m * s->N);
+    K.w.alloc(s->N);
+    K.t.alloc(3 * s->ns0);
+    K.coef.alloc(4 * MAX_MDOT);
+    std::vector<const T*> vp(m + 1), zp(m), wp(2);
+    for (int i = 0; i <= m; ++i) vp[i] = K.Vi(i);
+    for (int i = 0; i < m; ++i) zp[i] = K.Zi(i);
+    wp[0] = rhs;
+    wp[1] = K.w.p;
+    K.vptr.alloc(m + 1);
+    K.zptr.alloc(m);
+    K.wptr.alloc(2);
+    TNG_HIP(hipMemcpy(K.vptr.p, vp.data(), vp.size() * sizeof(T*), hipMemcpyHostToDevice));
+    TNG_HIP(hipMemcpy(K.zptr.p, zp.data(), zp.size() * sizeof(T*), hipMemcpyHostToDevice));
+    TNG_HIP(hipMemcpy(K.wptr.p, wp.data(), wp.size() * sizeof(T*), hipMemcpyHostToDevice));
+}
+
+// largest eigenvalue of D^{-1} A on level l by seeded power iteration
+template <typename T>
+double power_lmax(tng_solver* s, int l) {
+    MGLevel<T>& M = hier<T>(s)[l];
+    const long long n3 = 3 * M.ns;
+    vec_rand<T>(s->ctx, n3, 0x5eed0000ULL + (unsigned long long)l, M.x.p);
+    {
+        void* f[3] = {M.x.p, M.x.p + M.ns, M.x.p + 2 * M.ns};
+        launch_interface(s->ctx, *M.L, prec_of<T>(), 1, 3, f);
+    }
+    const T* const* xp = M.xy.p;
+    const T* const* yp = M.xy.p + 1;
+    double lam = 1.0;
+    for (int it = 0; it < s->opts.power_its; ++it) {
+        apply_A<T>(s, l, M.eta.p, M.x.p, M.y.p);
+        vec_mul<T>(s->ctx, n3, M.invd.p, M.y.p, M.y.p);
+        vel_dot<T>(s, l, M.x.p, xp, s->scal.p);
+        vel_dot<T>(s, l, M.y.p, yp, s->scal.p + 1);
+        readback(s, s->scal.p, 2);
+        const double nx = std::sqrt(s->host[0]), ny = std::sqrt(s->host[1]);
+        if (!(nx > 0) || !std::isfinite(ny)) throw Error(TNG_E_NOTCONV, "power iteration failed");
+        lam = ny / nx;
+        vec_axpby<T>(s->ctx, n3, 1.0 / ny, M.y.p, 0.0, M.x.p);
+    }
+    return lam;
+}
+
+template <typename T>
+void setup_level_operators(tng_solver* s) {
+    auto& H = hier<T>(s);
+    for (int l = 0; l < s->nlev - 1; ++l) {
+        MGLevel<T>& M = H[l];
+        T* d[3] = {M.invd.p, M.invd.p + M.ns, M.invd.p + 2 * M.ns};
+        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, d);
+        vec_invert<T>(s->ctx, 3 * M.ns, M.invd.p);
+        M.lmax = power_lmax<T>(s, l);
+    }
+}
+
+void setup_viscosity(tng_solver* s, const double* eta_dev) {
+    const bool mixed = s->opts.mixed != 0;
+    auto& H = s->h64;
+    TNG_HIP(hipMemcpyAsync(H[0].eta.p, eta_dev, 2 * L0(s).cells() * sizeof(double), hipMemcpyDeviceToDevice,
+                           s->ctx->stream));
+    for (int l = 0; l + 1 < s->nlev; ++l) launch_eta_coarsen(s->ctx, s->mesh->lv[l + 1], TNG_F64, H[l].eta.p, H[l + 1].eta.p);
+    // coarsest level: dense inverse of D A D over its interior DoFs
+    coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p);
+    coarse_invert(s->ctx, s->cd);
+    mg_pmass<double>(s->ctx, L0(s), L1(s), H[0].eta.p, s->pm64.p);
+    if (!mixed) {
+        setup_level_operators<double>(s);
+    } else {
+        for (int l = 0; l < s->nlev; ++l)
+            vec_cast<float, double>(s->ctx, 2 * s->mesh->lv[l].cells(), H[l].eta.p, s->h32[l].eta.p);
+        vec_cast<float, double>(s->ctx, s->np, s->pm64.p, s->pm32.p);
+        setup_level_operators<float>(s);
+    }
+    sync(s);
+    s->ready = true;
+}
+
+}  // namespace
+
+template void chebyshev_steps<double>(const tng_ctx*, const Level&, const double*, const double*, const double*,
+                                      double*, double*, double*, int, int, double, double, bool);
+template void chebyshev_steps<float>(const tng_ctx*, const Level&, const float*, const float*, const float*,
+                                     float*, float*, float*, int, int, double, double, bool);
+}  // namespace tng
+
+using tng::Error;
+
+extern "C" {
+
+int tng_solver_opts_default(tng_solver_opts* o) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(o != nullptr, "opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->mixed = 0;
+    o->restart = 10;
+    o->max_iters = 200;
+    o->rtol = 1e-8;
+    o->cheb_degree = 2;
+    o->pre = 2;
+    o->post = 2;
+    o->levels = 0;
+    o->cheb_lo = 0.1;
+    o->cheb_hi = 1.1;
+    o->inner_rtol = 1e-4;
+    o->inner_max_iters = 30;
+    o->max_outer = 20;
+    o->power_its = 10;
+    TNG_API_END
+}
+
+int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* opts, tng_solver** out) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr && mesh != nullptr && opts != nullptr && out != nullptr, "NULL argument");
+    TNG_REQUIRE(mesh->ctx != nullptr, "mesh was built without a context");
+    TNG_REQUIRE(mesh->lv.size() >= 2, "the solver needs at least two mesh levels");
+    TNG_REQUIRE(opts->restart >= 1 && opts->restart + 1 <= tng::MAX_MDOT, "restart must be in 1..23");
+    TNG_REQUIRE(opts->rtol > 0 && opts->max_iters >= 1, "bad tolerance or iteration limit");
+    TNG_REQUIRE(opts->cheb_degree >= 1 && opts->pre >= 0 && opts->post >= 0, "bad smoother options");
+    TNG_REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "bad Chebyshev interval");
+    TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
+    const int nlev = opts->levels > 0 ? opts->levels : (int)mesh->lv.size();
+    TNG_REQUIRE(nlev >= 2 && nlev <= (int)mesh->lv.size(), "levels out of range");
+    for (int l = 0; l + 1 < nlev; ++l)
+        TNG_REQUIRE(mesh->lv[l].m % 2 == 0 && mesh->lv[l].n % 2 == 0, "every non-coarsest level needs even m, n");
+    TNG_HIP(hipSetDevice(ctx->device));
+    auto s = std::make_unique<tng_solver>();
+    s->ctx = ctx;
+    s->mesh = mesh;
+    s->opts = *opts;
+    s->nlev = nlev;
+    s->ns0 = mesh->lv[0].node_slots();
+    s->np = mesh->lv[1].node_slots();
+    s->N = 3 * s->ns0 + s->np;
+    s->ds = std::make_unique<tng::DotScratch>();
+    tng::build_coarse_maps(s.get());
+    const bool mixed = opts->mixed != 0;
+    tng::alloc_hierarchy<double>(s.get(), !mixed);
+    s->pm64.alloc(s->np);
+    s->xo.alloc(s->N);
+    s->ro.alloc(s->N);
+    s->bo.alloc(s->N);
+    if (mixed) {
+        tng::alloc_hierarchy<float>(s.get(), true);
+        s->r32.alloc(s->N);
+        s->d32.alloc(s->N);
+        tng::alloc_krylov<float>(s.get(), s->r32.p);
+        s->pm32.alloc(s->np);
+    } else {
+        tng::alloc_krylov<double>(s.get(), s->bo.p);
+    }
+    s->ones_p.alloc(s->np);
+    tng::vec_fill<double>(ctx, s->np, 1.0, s->ones_p.p);
+    s->scal.alloc(64);
+    {
+        const double* dp[4] = {s->bo.p, s->ro.p, s->xo.p + 3 * s->ns0, s->k64.w.p};
+        s->dptr.alloc(4);
+        TNG_HIP(hipMemcpy(s->dptr.p, dp, sizeof(dp), hipMemcpyHostToDevice));
+        // count of unique pressure nodes for the mean projection
+        const tng::Level& P = mesh->lv[1];
+        const double cnt = (double)P.n_unique_lat * (P.n + 1);
+        TNG_HIP(hipMemcpy(s->scal.p + 33, &cnt, sizeof(double), hipMemcpyHostToDevice));
+    }
+    TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host), 256 * sizeof(double), hipHostMallocDefault));
+    TNG_HIP(hipStreamSynchronize(ctx->stream));
+    *out = s.release();
+    TNG_API_END
+}
+
+int tng_stokes_solver_destroy(tng_solver* s) {
+    TNG_API_BEGIN
+    delete s;
+    TNG_API_END
+}
+
+int tng_stokes_solver_setup(tng_solver* s, const double* eta_wedge) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(s != nullptr && eta_wedge != nullptr, "NULL argument");
+    TNG_HIP(hipSetDevice(s->ctx->device));
+    tng::setup_viscosity(s, eta_wedge);
+    TNG_API_END
+}
+
+int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const f[3], const double* g,
+                     double* const u[3], double* p, tng_solve_info* info) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(s != nullptr && f != nullptr && u != nullptr && p != nullptr, "NULL argument");
+    for (int c = 0; c < 3; ++c) TNG_REQUIRE(f[c] != nullptr && u[c] != nullptr, "NULL field pointer");
+    TNG_HIP(hipSetDevice(s->ctx->device));
+    auto t0 = std::chrono::steady_clock::now();
+    if (eta_wedge) tng::setup_viscosity(s, eta_wedge);
+    TNG_REQUIRE(s->ready, "no viscosity: pass eta_wedge or call tng_stokes_solver_setup first");
+    const long long ns = s->ns0, np = s->np, N = s->N;
+    hipStream_t st = s->ctx->stream;
+    const bool mixed = s->opts.mixed != 0;
+    double* bvec = s->bo.p;
+    double* xo = s->xo.p;
+    double* ro = s->ro.p;
+    for (int c = 0; c < 3; ++c)
+        TNG_HIP(hipMemcpyAsync(bvec + c * ns, f[c], ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (g)
+        TNG_HIP(hipMemcpyAsync(bvec + 3 * ns, g, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+        tng::vec_fill<double>(s->ctx, np, 0.0, bvec + 3 * ns);
+    const double* const* bp = s->dptr.p;         // -> bo
+    const double* const* rp = s->dptr.p + 1;     // -> ro
+    tng::vec_smdot<double>(s->ctx, *s->ds, tng::L0(s), tng::L1(s), bvec, bp, 1, s->scal.p + 1, false);
+    tng::readback(s, s->scal.p + 1, 1);
+    const double bn = std::sqrt(s->host[0]);
+    int status = TNG_OK;
+    int inner_total = 0, outer = 0;
+    double relres = bn > 0 ? 1.0 : 0.0;
+    auto true_residual = [&]() {
+        tng::remove_pressure_mean(s);
+        tng::apply_K<double>(s, s->h64[0].eta.p, xo, ro);
+        tng::vec_axpby<double>(s->ctx, N, 1.0, bvec, -1.0, ro);
+        tng::vec_smdot<double>(s->ctx, *s->ds, tng::L0(s), tng::L1(s), ro, rp, 1, s->scal.p, false);
+        tng::readback(s, s->scal.p, 1);
+        return bn > 0 ? std::sqrt(s->host[0]) / bn : 0.0;
+    };
+    if (!mixed) {
+        int its = 0;
+        double est = 0.0;
+        status = tng::fgmres<double>(s, s->h64[0].eta.p, bvec, xo, s->opts.rtol, s->opts.max_iters, &its, &est);
+        inner_total = its;
+        outer = 1;
+        relres = true_residual();
+        if (!std::isfinite(relres)) status = TNG_E_NOTCONV;
+    } else {
+        tng::vec_fill<double>(s->ctx, N, 0.0, xo);
+        TNG_HIP(hipMemcpyAsync(ro, bvec, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        while (relres > s->opts.rtol && outer < s->opts.max_outer) {
+            tng::vec_cast<float, double>(s->ctx, N, ro, s->r32.p);
+            int its = 0;
+            double inner_rel = 0.0;
+            const int rc = tng::fgmres<float>(s, s->h32[0].eta.p, s->r32.p, s->d32.p, s->opts.inner_rtol,
+                                              s->opts.inner_max_iters, &its, &inner_rel);
+            inner_total += its;
+            ++outer;
+            if (rc != TNG_OK) {
+                status = rc;
+                break;
+            }
+            // x += d in FP64, then the FP64 residual r = b - K x
+            tng::vec_cast<double, float>(s->ctx, N, s->d32.p, ro);
+            tng::vec_axpby<double>(s->ctx, N, 1.0, ro, 1.0, xo);
+            relres = true_residual();
+            if (!std::isfinite(relres)) {
+                status = TNG_E_NOTCONV;
+                break;
+            }
+        }
+    }
+    if (status == TNG_OK && !(relres <= s->opts.rtol)) status = TNG_E_NOTCONV;
+    for (int c = 0; c < 3; ++c)
+        TNG_HIP(hipMemcpyAsync(u[c], xo + c * ns, ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+    TNG_HIP(hipMemcpyAsync(p, xo + 3 * ns, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+    TNG_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->outer_its = outer;
+        info->inner_its = inner_total;
+        info->rel_res = relres;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->status = status;
+    }
+    if (status != TNG_OK) {
+        tng::set_last_error("Stokes solve did not reach rtol (rel_res " + std::to_string(relres) + ")");
+        return status;
+    }
+    TNG_API_END
+}
+
+// One V-cycle of the solver's velocity preconditioner on level 0 (x = M^{-1} b),
+// in the solver's Krylov precision.  Needs a prior setup.
+int tng_stokes_solver_vcycle(tng_solver* s, const void* const b[3], void* const x[3]) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(s != nullptr && b != nullptr && x != nullptr, "NULL argument");
+    TNG_REQUIRE(s->ready, "call tng_stokes_solver_setup first");
+    TNG_HIP(hipSetDevice(s->ctx->device));
+    const long long ns = s->ns0;
+    hipStream_t st = s->ctx->stream;
+    if (s->opts.mixed) {
+        auto& M = s->h32[0];
+        for (int c = 0; c < 3; ++c)
+            TNG_HIP(hipMemcpyAsync(M.b.p + c * ns, b[c], ns * sizeof(float), hipMemcpyDeviceToDevice, st));
+        tng::vcycle<float>(s, 0, M.b.p, s->k32.t.p);
+        for (int c = 0; c < 3; ++c)
+            TNG_HIP(hipMemcpyAsync(x[c], s->k32.t.p + c * ns, ns * sizeof(float), hipMemcpyDeviceToDevice, st));
+    } else {
+        auto& M = s->h64[0];
+        for (int c = 0; c < 3; ++c)
+            TNG_HIP(hipMemcpyAsync(M.b.p + c * ns, b[c], ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+        tng::vcycle<double>(s, 0, M.b.p, s->k64.t.p);
+        for (int c = 0; c < 3; ++c)
+            TNG_HIP(hipMemcpyAsync(x[c], s->k64.t.p + c * ns, ns * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    TNG_API_END
+}
+
+}  // extern "C"

@@ -108,6 +108,8 @@ struct Level {
     DevBuf<float> geo32;
     DevBuf<int> grp_ptr, grp_slot;    // duplicate groups (CSR over lateral slots)
     DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
+    DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node
+    DevBuf<float> inv_mult32;
 
     long long lat_slots() const { return 10LL * (m + 1) * (m + 1); }
     long long node_slots() const { return lat_slots() * (n + 1); }

@@ -1,0 +1,159 @@
+"""GPU parity of the multigrid pieces and of the Stokes solve (Sec. 7) with
+the FP64 oracle: operator diagonal, lumped pressure mass, transfers,
+Chebyshev smoother, V-cycle symmetry, and the solution of K_D x = b compared
+with the oracle's sparse direct solve."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle.mesh import ShellMesh
+from oracle.solver_ref import chebyshev, lumped_pressure_mass, restrict_velocity, velocity_prolongation
+from oracle.stokes import StokesOracle
+from tests._support import LayoutMap
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_21633_amd as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(tng):
+    return tng.Context(0)
+
+
+_cache = {}
+
+
+def case(tng, ctx, mt, seed=0):
+    if (mt, seed) in _cache:
+        return _cache[(mt, seed)]
+    import torch
+    levels = int(np.log2(mt))           # down to (2, 2)
+    mesh = tng.Mesh(ctx, mt, mt, levels=levels)
+    om = ShellMesh(mt, mt)
+    omp = ShellMesh(mt // 2, mt // 2, hierarchy=om.h)
+    lm = LayoutMap(*mesh.coords(0), om)
+    lmp = LayoutMap(*mesh.coords(1), omp)
+    eta, _, _ = synthetic.uniform_operator_inputs(om.n_wedges, om.n_nodes, omp.n_nodes, seed)
+    orc = StokesOracle(mt, mt, eta, hierarchy=om.h)
+    eta_t = torch.tensor(eta[lm.wedge_index()], device="cuda")
+    _cache[(mt, seed)] = (mesh, om, omp, lm, lmp, eta, orc, eta_t)
+    return _cache[(mt, seed)]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def vel(lm, arr):
+    import torch
+    return torch.tensor(lm.to_lib(arr), device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("mt", [8, 16])
+def test_diag_and_pressure_mass(tng, ctx, mt):
+    import torch
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, mt)
+    d = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    tng.diag_A(ctx, mesh, 0, eta_t, d)
+    pm = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    tng.pressure_mass(ctx, mesh, 0, eta_t, pm)
+    torch.cuda.synchronize()
+    assert rel(lm.from_lib(d.cpu().numpy(), check_dups=1e-13), orc.diag_A()) < 1e-12
+    assert rel(lmp.from_lib(pm.cpu().numpy(), check_dups=1e-13), lumped_pressure_mass(orc, eta)) < 1e-12
+
+
+def test_transfers(tng, ctx):
+    import torch
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    lmc = LayoutMap(*mesh.coords(1), omp)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((om.n_nodes, 3))
+    f[om.boundary_nodes()] = 0.0
+    c = torch.empty((3,) + mesh.shape(1), dtype=torch.float64, device="cuda")
+    tng.restrict(ctx, mesh, 0, vel(lm, f), c)
+    cc = rng.standard_normal((omp.n_nodes, 3))
+    cc[omp.boundary_nodes()] = 0.0
+    fo = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    tng.prolong(ctx, mesh, 0, vel(lmc, cc), fo)
+    torch.cuda.synchronize()
+    want_c = restrict_velocity(orc, f, omp.boundary_nodes())
+    assert rel(lmc.from_lib(c.cpu().numpy(), check_dups=1e-13), want_c) < 1e-13
+    want_f = (velocity_prolongation(orc) @ cc.ravel()).reshape(-1, 3)
+    assert rel(lm.from_lib(fo.cpu().numpy(), check_dups=1e-13), want_f) < 1e-13
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 1e-5)])
+def test_chebyshev_smoother(tng, ctx, dtype, tol):
+    import torch
+    dt = getattr(torch, dtype)
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal((om.n_nodes, 3))
+    x = rng.standard_normal((om.n_nodes, 3))
+    bnd = om.boundary_nodes()
+    b[bnd] = 0.0
+    x[bnd] = 0.0
+    d = torch.empty((3,) + mesh.shape(0), dtype=dt, device="cuda")
+    tng.diag_A(ctx, mesh, 0, eta_t.to(dt), d)
+    xt = vel(lm, x).to(dt)
+    tng.smooth(ctx, mesh, 0, eta_t.to(dt), d, vel(lm, b).to(dt), xt, 2, 2, 0.3, 3.3)
+    want = chebyshev(orc.A_D, orc.diag_A().ravel(), b.ravel(), x.ravel(), 2, 2, 0.3, 3.3).reshape(-1, 3)
+    got = lm.from_lib(xt.double().cpu().numpy())
+    assert rel(got, want) < tol
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_vcycle_is_symmetric(tng, ctx, mixed):
+    """Symmetric smoothing and R = P^T make the V-cycle a symmetric operator."""
+    import torch
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 16)
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed)
+    s.setup(eta_t)
+    dt = torch.float32 if mixed else torch.float64
+    rng = np.random.default_rng(5)
+    bnd = om.boundary_nodes()
+    vs = []
+    for _ in range(2):
+        v = rng.standard_normal((om.n_nodes, 3))
+        v[bnd] = 0.0
+        vs.append(v)
+    out = []
+    for v in vs:
+        x = torch.empty((3,) + mesh.shape(0), dtype=dt, device="cuda")
+        s.vcycle(vel(lm, v).to(dt), x)
+        torch.cuda.synchronize()
+        out.append(lm.from_lib(x.double().cpu().numpy(), check_dups=1e-5 if mixed else 1e-12))
+    a, b = np.sum(vs[0] * out[1]), np.sum(vs[1] * out[0])
+    assert abs(a - b) / max(abs(a), abs(b)) < (1e-5 if mixed else 1e-11)
+    # a useful preconditioner: positive on the interior
+    assert np.sum(vs[0] * out[0]) > 0
+
+
+@pytest.mark.parametrize("mt,mixed", [(8, 0), (16, 0), (8, 1), (16, 1)])
+def test_solve_matches_direct_solve(tng, ctx, mt, mixed):
+    """Solution of K_D [u; p] = [f; 0] vs the oracle's sparse direct solve."""
+    import torch
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, mt)
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((om.n_nodes, 3))
+    f[om.boundary_nodes()] = 0.0
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-10, max_iters=400)
+    u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    info = s.solve(vel(lm, f), None, u, p, eta=eta_t)
+    uo, po = orc.solve(f)
+    gu = lm.from_lib(u.cpu().numpy(), check_dups=1e-12)
+    gp = lmp.from_lib(p.cpu().numpy(), check_dups=1e-12)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"solve ({mt},{mt}) mixed={mixed}: its {info['inner_its']} outer {info['outer_its']} "
+          f"res {info['rel_res']:.2e} err u {eu:.2e} p {ep:.2e} t {info['seconds']:.3f}s")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7

@@ -244,6 +244,49 @@ int tng_stokes_solve(tng_solver* solver, const double* eta_wedge, const double* 
  * solver's Krylov precision (FP32 when mixed).  b, x: device velocity fields. */
 int tng_stokes_solver_vcycle(tng_solver* solver, const void* const b[3], void* const x[3]);
 
+/* ---- buoyancy and energy (a13, a14) -------------------------------------- */
+/* Buoyancy right-hand side of eq:stokes in Boussinesq form (rho = alpha = 1):
+ * f_(i,c) = sum_e V_e N_i(q_c) Ra T(q_c) rhat_c(q_c), one-point rule, T(q_c)
+ * the mean of the wedge's nodal temperatures and rhat the direction of x(q_c);
+ * Dirichlet rows zero.  T: device node field; f[3]: device velocity out. */
+int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
+                     void* const f[3]);
+/* Backward-Euler SUPG energy operator (unit diffusivity, Sec. 6 scheme list):
+ * y_i = sum_e V_e [ N_i T_i / dt + grad phi_i . grad T + N_i ubar . grad T
+ *                   + tau_e (ubar . grad phi_i)(ubar . grad T) ],
+ * ubar the wedge's mean velocity, tau_e = h/(2|ubar|)(coth Pe - 1/Pe),
+ * Pe = |ubar| h / 2, h = V_e^(1/3); identity rows on both spheres (Dirichlet
+ * temperature; columns kept).  u[3], T in, y out: device fields of `level`. */
+int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* const u[3],
+                     double dt, const void* T, void* y);
+
+/* Coupled time step.  Ra: Rayleigh number; eta = exp(-E T + F (1 - r));
+ * dt > 0 fixes the time step, else dt = courant * min_e h_e / |ubar_e|;
+ * T_inner / T_outer: temperature on the inner / outer sphere; the energy
+ * solve is Jacobi-preconditioned GMRES(energy_restart) to energy_rtol. */
+typedef struct {
+    double Ra, E, F;
+    double dt, courant;
+    double T_inner, T_outer;
+    double energy_rtol;
+    int energy_max_iters, energy_restart;
+} tng_step_opts;
+
+typedef struct {
+    tng_solve_info stokes;
+    int energy_its;
+    double energy_rel_res;
+    double dt;
+    double seconds;
+} tng_step_info;
+
+/* One step: eta(T^n), f = Ra T^n rhat, Stokes solve for (u, p), dt, then the
+ * energy solve (M/dt + K + C(u) + S(u)) T^{n+1} = M (T^n/dt + H).  H: device
+ * FP64 internal heating node field or NULL; T: device FP64, in/out; u[3], p:
+ * device FP64 outputs (solver levels 0 / 1).  Synchronises. */
+int tng_energy_step(tng_solver* solver, const tng_step_opts* opts, const double* H, double* T,
+                    double* const u[3], double* p, tng_step_info* info);
+
 /* Sum the copies of every duplicate group of a node field and write the sum
  * to all copies (the one-GPU analog of the post-apply halo sum, Sec. 2); with
  * mode 1 instead copy the first copy to all others.  ncomp fields in f[]. */

@@ -57,6 +57,9 @@ def lib():
         "tng_stokes_solver_setup": [_vp, _vp],
         "tng_stokes_solve": [_vp, _vp, C.POINTER(_vp), _vp, C.POINTER(_vp), _vp, _vp],
         "tng_stokes_solver_vcycle": [_vp, C.POINTER(_vp), C.POINTER(_vp)],
+        "tng_rhs_buoyancy": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
+        "tng_energy_apply": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
+        "tng_energy_step": [_vp, _vp, _vp, _vp, C.POINTER(_vp), _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -245,6 +248,25 @@ class SolveInfo(C.Structure):
                 ("seconds", C.c_double), ("status", C.c_int)]
 
 
+class StepOpts(C.Structure):
+    _fields_ = [("Ra", C.c_double), ("E", C.c_double), ("F", C.c_double), ("dt", C.c_double),
+                ("courant", C.c_double), ("T_inner", C.c_double), ("T_outer", C.c_double),
+                ("energy_rtol", C.c_double), ("energy_max_iters", C.c_int), ("energy_restart", C.c_int)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("stokes", SolveInfo), ("energy_its", C.c_int), ("energy_rel_res", C.c_double),
+                ("dt", C.c_double), ("seconds", C.c_double)]
+
+
+def rhs_buoyancy(ctx: Context, mesh: Mesh, level: int, T, Ra: float, f):
+    check(lib().tng_rhs_buoyancy(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _ptr3(f)))
+
+
+def energy_apply(ctx: Context, mesh: Mesh, level: int, u, dt: float, T, y):
+    check(lib().tng_energy_apply(ctx.h, mesh.h, level, _prec(T), _ptr3(u), dt, _ptr(T), _ptr(y)))
+
+
 class StokesSolver:
     """FGMRES + block-triangular Schur preconditioner + multigrid (library-owned state)."""
 
@@ -269,6 +291,20 @@ class StokesSolver:
         rc = lib().tng_stokes_solve(self.h, _ptr(eta), _ptr3(f), _ptr(g), _ptr3(u), _ptr(p), C.byref(info))
         out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
         out["rc"] = rc
+        if rc != 0 and raise_on_fail:
+            check(rc)
+        return out
+
+    def energy_step(self, T, u, p, H=None, Ra=1e5, E=0.0, F=0.0, dt=0.0, courant=1.0, T_inner=1.0,
+                    T_outer=0.0, energy_rtol=1e-8, energy_max_iters=200, energy_restart=20,
+                    raise_on_fail: bool = True) -> dict:
+        """One coupled step: Stokes solve with eta(T), then the energy solve (T in/out)."""
+        o = StepOpts(Ra, E, F, dt, courant, T_inner, T_outer, energy_rtol, energy_max_iters, energy_restart)
+        info = StepInfo()
+        rc = lib().tng_energy_step(self.h, C.byref(o), _ptr(H), _ptr(T), _ptr3(u), _ptr(p), C.byref(info))
+        out = {"rc": rc, "energy_its": info.energy_its, "energy_rel_res": info.energy_rel_res,
+               "dt": info.dt, "seconds": info.seconds,
+               "stokes": {k: getattr(info.stokes, k) for k, _ in SolveInfo._fields_}}
         if rc != 0 and raise_on_fail:
             check(rc)
         return out

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtng.so")
-SOURCES = ["capi.cpp", "mesh.cpp", "stokes_apply.hip", "interface.hip", "fields.hip", "mg_kernels.hip", "solver.cpp"]
+SOURCES = ["capi.cpp", "mesh.cpp", "stokes_apply.hip", "interface.hip", "fields.hip", "mg_kernels.hip", "solver.cpp", "energy.hip", "energy.cpp"]
 ARCH = "gfx950"
 
 

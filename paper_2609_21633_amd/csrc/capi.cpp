@@ -262,6 +262,42 @@ int tng_interface_sum(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
     TNG_API_END
 }
 
+int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
+                     void* const f[3]) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(T && f && f[0] && f[1] && f[2], "NULL argument");
+    TNG_REQUIRE(std::isfinite(Ra), "Ra must be finite");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        double* ff[3] = {(double*)f[0], (double*)f[1], (double*)f[2]};
+        tng::buoyancy_rhs<double>(ctx, L, (const double*)T, Ra, ff);
+    } else {
+        float* ff[3] = {(float*)f[0], (float*)f[1], (float*)f[2]};
+        tng::buoyancy_rhs<float>(ctx, L, (const float*)T, Ra, ff);
+    }
+    TNG_API_END
+}
+
+int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* const u[3],
+                     double dt, const void* T, void* y) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(u && u[0] && u[1] && u[2] && T && y, "NULL argument");
+    TNG_REQUIRE(dt > 0 && std::isfinite(dt), "dt must be positive");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        const double* uu[3] = {(const double*)u[0], (const double*)u[1], (const double*)u[2]};
+        tng::energy_apply<double>(ctx, L, uu, dt, (const double*)T, (double*)y);
+    } else {
+        const float* uu[3] = {(const float*)u[0], (const float*)u[1], (const float*)u[2]};
+        tng::energy_apply<float>(ctx, L, uu, dt, (const float*)T, (float*)y);
+    }
+    TNG_API_END
+}
+
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
                void* const diag[3]) {
     TNG_API_BEGIN

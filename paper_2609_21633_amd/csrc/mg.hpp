@@ -83,6 +83,19 @@ void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* 
 template <typename T>
 void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta);
 
+struct EnergyWS;
+EnergyWS* energy_ws_create();
+void energy_ws_destroy(EnergyWS* w);
+int energy_solve(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], const double* H,
+                 double dt, double T_in, double T_out, double* T, double rtol, int maxit, int restart, int* its,
+                 double* rel);
+double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double courant);
+void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]);
+template <typename T>
+void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
+template <typename T>
+void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]);
+
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, const T* invd, const T* b, T* x, T* y,
                      T* d, int deg, int steps, double lo, double hi, bool x_zero);

@@ -67,8 +67,11 @@ struct tng_solver {
     double* host = nullptr;             // pinned read-back buffer
     bool ready = false;
     long long ns0 = 0, np = 0, N = 0;
+    tng::EnergyWS* ews = nullptr;       // energy step workspace (created on first use)
+    tng::DevBuf<double> eta_step, f_step;
     ~tng_solver() {
         if (host) (void)hipHostFree(host);
+        if (ews) tng::energy_ws_destroy(ews);
     }
 };
 
@@ -678,6 +681,55 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     if (status != TNG_OK) {
         tng::set_last_error("Stokes solve did not reach rtol (rel_res " + std::to_string(relres) + ")");
         return status;
+    }
+    TNG_API_END
+}
+
+int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, double* T, double* const u[3],
+                    double* p, tng_step_info* info) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(s != nullptr && o != nullptr && T != nullptr && u != nullptr && p != nullptr, "NULL argument");
+    for (int c = 0; c < 3; ++c) TNG_REQUIRE(u[c] != nullptr, "NULL velocity pointer");
+    TNG_REQUIRE(std::isfinite(o->Ra) && std::isfinite(o->E) && std::isfinite(o->F), "non-finite parameter");
+    TNG_REQUIRE(o->dt > 0 || o->courant > 0, "need dt > 0 or courant > 0");
+    TNG_REQUIRE(o->energy_restart >= 1 && o->energy_restart + 1 <= tng::MAX_MDOT, "energy_restart in 1..23");
+    TNG_HIP(hipSetDevice(s->ctx->device));
+    auto t0 = std::chrono::steady_clock::now();
+    const tng::Level& L = tng::L0(s);
+    const long long ns = s->ns0;
+    if (!s->ews) s->ews = tng::energy_ws_create();
+    if (s->eta_step.n == 0) s->eta_step.alloc(2 * L.cells());
+    if (s->f_step.n == 0) s->f_step.alloc(3 * ns);
+    // viscosity of the current temperature, buoyancy, Stokes solve
+    tng::launch_eta_from_T(s->ctx, L, TNG_F64, T, s->eta_step.p, o->E, o->F);
+    double* f[3] = {s->f_step.p, s->f_step.p + ns, s->f_step.p + 2 * ns};
+    tng::energy_buoyancy(s->ctx, L, T, o->Ra, f);
+    const double* fc[3] = {f[0], f[1], f[2]};
+    tng_solve_info sinfo{};
+    const int rc = tng_stokes_solve(s, s->eta_step.p, fc, nullptr, u, p, &sinfo);
+    if (rc != TNG_OK && rc != TNG_E_NOTCONV) return rc;
+    // time step and energy solve
+    const double* uc[3] = {u[0], u[1], u[2]};
+    const double dt = o->dt > 0 ? o->dt : tng::energy_cfl_dt(s->ctx, L, *s->ews, uc, o->courant);
+    int eits = 0;
+    double erel = 0.0;
+    const int erc = tng::energy_solve(s->ctx, L, *s->ews, uc, H, dt, o->T_inner, o->T_outer, T, o->energy_rtol,
+                                      o->energy_max_iters, o->energy_restart, &eits, &erel);
+    TNG_HIP(hipStreamSynchronize(s->ctx->stream));
+    if (info) {
+        info->stokes = sinfo;
+        info->energy_its = eits;
+        info->energy_rel_res = erel;
+        info->dt = dt;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc != TNG_OK) {
+        tng::set_last_error("Stokes solve of the time step did not converge");
+        return rc;
+    }
+    if (erc != TNG_OK) {
+        tng::set_last_error("energy solve did not reach energy_rtol");
+        return erc;
     }
     TNG_API_END
 }

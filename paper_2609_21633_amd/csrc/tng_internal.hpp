@@ -109,6 +109,7 @@ struct Level {
     DevBuf<int> grp_ptr, grp_slot;    // duplicate groups (CSR over lateral slots)
     DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
     DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node
+    DevBuf<double> unit64;            // [10][m+1][m+1][3] unit vectors
     DevBuf<float> inv_mult32;
 
     long long lat_slots() const { return 10LL * (m + 1) * (m + 1); }

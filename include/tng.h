@@ -287,6 +287,36 @@ typedef struct {
 int tng_energy_step(tng_solver* solver, const tng_step_opts* opts, const double* H, double* T,
                     double* const u[3], double* p, tng_step_info* info);
 
+/* ---- serving (a15) --------------------------------------------------------- */
+/* Request server for streams of Stokes solves.  levels: nlevels pairs
+ * (mt, nr), each kept resident with its multigrid hierarchy.  Requests are
+ * admitted FIFO per level into solver slots; a slot is a solver with its own
+ * HIP stream and host worker, reused for later requests of its level, and
+ * slots run concurrently on the device.  A new slot is created only while the
+ * measured per-slot memory of its level keeps the total within
+ * hbm_budget_bytes (an idle slot of another level is released to make room
+ * when needed); at most max_slots slots per level.  opts: solver options of
+ * every slot (normally mixed precision). */
+int tng_server_create(tng_ctx* ctx, const int* levels, int nlevels, size_t hbm_budget_bytes, int max_slots,
+                      const tng_solver_opts* opts, tng_server** out);
+/* Queues a solve with eta = 10^(log10_contrast)^(-T) = exp(-ln(contrast) T)
+ * and right-hand side Ra T rhat (buoyancy, g = 0) on level level_idx.  T:
+ * device FP64 node field of that level; u_out[3], p_out: device FP64 outputs.
+ * All three stay borrowed until the request is done.  Returns a ticket;
+ * TNG_E_BUDGET if one slot of the level cannot fit the budget. */
+int tng_server_submit(tng_server* srv, int level_idx, const double* T, double log10_contrast, double Ra,
+                      double* const u_out[3], double* p_out, long long* ticket);
+/* done = 1 when finished; then info, latency (submit -> result on the device)
+ * and queueing time (submit -> start) are filled and the request's own
+ * status is returned (a failed request does not affect the others). */
+int tng_server_poll(tng_server* srv, long long ticket, int* done, tng_solve_info* info, double* latency_s,
+                    double* queue_s);
+/* Blocks until the ticket (or, for ticket <= 0, every request) is done. */
+int tng_server_wait(tng_server* srv, long long ticket);
+int tng_server_stats(tng_server* srv, long long* bytes_in_use, int* slots, int* busy, int* queued);
+/* Waits for running requests, drops queued ones, frees everything. */
+int tng_server_destroy(tng_server* srv);
+
 /* Sum the copies of every duplicate group of a node field and write the sum
  * to all copies (the one-GPU analog of the post-apply halo sum, Sec. 2); with
  * mode 1 instead copy the first copy to all others.  ncomp fields in f[]. */

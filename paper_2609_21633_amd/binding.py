@@ -60,6 +60,15 @@ def lib():
         "tng_rhs_buoyancy": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
         "tng_energy_apply": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
         "tng_energy_step": [_vp, _vp, _vp, _vp, C.POINTER(_vp), _vp, _vp],
+        "tng_server_create": [_vp, C.POINTER(C.c_int), C.c_int, C.c_size_t, C.c_int, _vp, C.POINTER(_vp)],
+        "tng_server_submit": [_vp, C.c_int, _vp, C.c_double, C.c_double, C.POINTER(_vp), _vp,
+                              C.POINTER(C.c_longlong)],
+        "tng_server_poll": [_vp, C.c_longlong, C.POINTER(C.c_int), _vp, C.POINTER(C.c_double),
+                            C.POINTER(C.c_double)],
+        "tng_server_wait": [_vp, C.c_longlong],
+        "tng_server_stats": [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int)],
+        "tng_server_destroy": [_vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -315,6 +324,62 @@ class StokesSolver:
     def close(self):
         if getattr(self, "h", None):
             lib().tng_stokes_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server: levels = [(mt, nr), ...]; every slot runs a (normally
+    mixed-precision) solver on its own stream."""
+
+    def __init__(self, ctx: Context, levels, budget_bytes: int, max_slots: int = 64, **opts):
+        o = SolverOpts()
+        check(lib().tng_solver_opts_default(C.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        flat = (C.c_int * (2 * len(levels)))(*[x for lv in levels for x in lv])
+        h = _vp()
+        check(lib().tng_server_create(ctx.h, flat, len(levels), int(budget_bytes), max_slots, C.byref(o),
+                                      C.byref(h)))
+        self.h, self.ctx, self.levels = h, ctx, list(levels)
+        self._keep = {}
+
+    def submit(self, level_idx: int, T, log10_contrast: float, Ra: float, u, p) -> int:
+        t = C.c_longlong()
+        check(lib().tng_server_submit(self.h, level_idx, _ptr(T), log10_contrast, Ra, _ptr3(u), _ptr(p),
+                                      C.byref(t)))
+        self._keep[t.value] = (T, u, p)      # borrowed buffers stay alive until done
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        done = C.c_int()
+        info = SolveInfo()
+        lat, q = C.c_double(), C.c_double()
+        rc = lib().tng_server_poll(self.h, ticket, C.byref(done), C.byref(info), C.byref(lat), C.byref(q))
+        out = {"done": bool(done.value), "rc": rc}
+        if done.value:
+            out.update({k: getattr(info, k) for k, _ in SolveInfo._fields_})
+            out["latency"] = lat.value
+            out["queue"] = q.value
+            self._keep.pop(ticket, None)
+        return out
+
+    def wait(self, ticket: int = 0):
+        check(lib().tng_server_wait(self.h, ticket))
+
+    def stats(self) -> dict:
+        b, sl, bu, qu = C.c_longlong(), C.c_int(), C.c_int(), C.c_int()
+        check(lib().tng_server_stats(self.h, C.byref(b), C.byref(sl), C.byref(bu), C.byref(qu)))
+        return {"bytes_in_use": b.value, "slots": sl.value, "busy": bu.value, "queued": qu.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tng_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -9,14 +9,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtng.so")
-SOURCES = ["capi.cpp", "mesh.cpp", "stokes_apply.hip", "interface.hip", "fields.hip", "mg_kernels.hip", "solver.cpp", "energy.hip", "energy.cpp"]
+SOURCES = ["capi.cpp", "mesh.cpp", "stokes_apply.hip", "interface.hip", "fields.hip", "mg_kernels.hip", "solver.cpp", "energy.hip", "energy.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 
 def hipcc_command(out: str = LIB) -> list[str]:
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-munsafe-fp-atomics",
+           "-munsafe-fp-atomics", "-pthread",
            # no packed FP32 instructions anywhere in device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",

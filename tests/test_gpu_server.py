@@ -1,0 +1,118 @@
+"""Request server (continuous admission of Stokes solves): each result is the
+same alone and in the mix, requests that do not fit the budget are refused,
+a failing request does not disturb the others, and a tight budget still
+serves every request (slots are queued, reused and released)."""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+LEVELS = [(8, 8), (16, 16)]
+
+
+@pytest.fixture(scope="module")
+def tng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_21633_amd as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(tng):
+    return tng.Context(0)
+
+
+def request_fields(tng, ctx, mt, nr, seed):
+    import torch
+    mesh = tng.Mesh(None, mt, nr, levels=1)
+    xyz, r = mesh.coords(0)
+    T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=seed, lmin=1, lmax=16)
+    shape = (10, mt + 1, mt + 1, nr + 1)
+    Tt = torch.tensor(T.reshape(shape), device="cuda")
+    u = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    p = torch.empty((10, mt // 2 + 1, mt // 2 + 1, nr // 2 + 1), dtype=torch.float64, device="cuda")
+    return Tt, u, p
+
+
+def test_alone_equals_in_mix(tng, ctx):
+    import torch
+    srv = tng.Server(ctx, LEVELS, budget_bytes=8 << 30, max_slots=4, mixed=1, rtol=1e-8)
+    T0, u0, p0 = request_fields(tng, ctx, 16, 16, 1000)
+    t = srv.submit(1, T0, 3.0, 1e5, u0, p0)
+    srv.wait(t)
+    r0 = srv.poll(t)
+    assert r0["rc"] == 0 and r0["rel_res"] <= 1e-8
+    alone_u, alone_p = u0.cpu().numpy().copy(), p0.cpu().numpy().copy()
+    # the same request again, in a mix of six
+    reqs = []
+    for i in range(6):
+        lvl = i % 2
+        mt, nr = LEVELS[lvl]
+        if i == 3:
+            Tt, u, p = T0, torch.empty_like(u0), torch.empty_like(p0)
+            lvl = 1
+        else:
+            Tt, u, p = request_fields(tng, ctx, mt, nr, 1001 + i)
+        lc = 3.0 if i == 3 else 2.0 + 0.5 * i
+        reqs.append((srv.submit(lvl, Tt, lc, 1e5, u, p), u, p))
+    srv.wait(0)
+    for t, u, p in reqs:
+        r = srv.poll(t)
+        assert r["done"] and r["rc"] == 0, r
+    _, um, pm = reqs[3]
+    du = np.linalg.norm(um.cpu().numpy() - alone_u) / np.linalg.norm(alone_u)
+    dp = np.linalg.norm(pm.cpu().numpy() - alone_p) / np.linalg.norm(alone_p)
+    print(f"alone vs mix: du {du:.2e} dp {dp:.2e}", srv.stats())
+    assert du < 1e-7 and dp < 1e-7
+    srv.close()
+
+
+def test_budget_refusal(tng, ctx):
+    srv = tng.Server(ctx, LEVELS, budget_bytes=1 << 20, max_slots=2, mixed=1)
+    T, u, p = request_fields(tng, ctx, 8, 8, 5)
+    with pytest.raises(tng.TngError) as e:
+        srv.submit(0, T, 3.0, 1e5, u, p)
+    assert e.value.code == -5
+    srv.close()
+
+
+def test_failed_request_is_isolated(tng, ctx):
+    import torch
+    srv = tng.Server(ctx, LEVELS, budget_bytes=8 << 30, max_slots=3, mixed=1)
+    good = [request_fields(tng, ctx, 8, 8, 20 + i) for i in range(3)]
+    bad = request_fields(tng, ctx, 8, 8, 30)
+    bad[0][0, 1, 1, 2] = float("nan")
+    tickets = [srv.submit(0, *g[:1], 3.0, 1e5, g[1], g[2]) for g in good[:1]]
+    tb = srv.submit(0, bad[0], 3.0, 1e5, bad[1], bad[2])
+    tickets += [srv.submit(0, g[0], 3.0, 1e5, g[1], g[2]) for g in good[1:]]
+    srv.wait(0)
+    assert srv.poll(tb)["rc"] == -4
+    for t in tickets:
+        r = srv.poll(t)
+        assert r["rc"] == 0 and r["rel_res"] <= 1e-8
+    srv.close()
+
+
+def test_tight_budget_serves_everything(tng, ctx):
+    """A budget of about two (16,16) slots (~20 MB each): requests queue, slots are reused,
+    and an idle slot of the other level is released when needed."""
+    srv = tng.Server(ctx, LEVELS, budget_bytes=45 << 20, max_slots=8, mixed=1)
+    reqs = []
+    for i in range(8):
+        lvl = 1 if i < 5 else 0
+        mt, nr = LEVELS[lvl]
+        Tt, u, p = request_fields(tng, ctx, mt, nr, 40 + i)
+        reqs.append(srv.submit(lvl, Tt, 2.5, 1e5, u, p))
+    srv.wait(0)
+    st = srv.stats()
+    print("tight budget", st)
+    assert st["bytes_in_use"] <= 45 << 20
+    for t in reqs:
+        assert srv.poll(t)["rc"] == 0
+    srv.close()

@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the matrix-free wedge Stokes hot path on one MI355X.
 
-Workload: the spherical shell with velocity mesh (mt, nr) = (128, 128)
-(163,842 lateral nodes x 129 layers, 63.4 M velocity DoFs) and W1 pressure on
-(64, 64) (2.66 M DoFs); temperature = conductive profile + seeded spherical
-harmonics l = 1..8 of amplitude 0.01; viscosity eta = exp(-ln(1e3) T +
-ln(10) (1 - r)) per wedge.  A step is one full Stokes operator apply
-y = K_D [u; p] (A, B^T, B, Dirichlet rows, diamond-interface sum).
+Workload (the headline configuration): the spherical shell with velocity
+mesh (mt, nr) = (128, 128) -- 163,842 lateral nodes x 129 layers, 63.4 M
+velocity DoFs -- and W1 pressure on (64, 64) (2.66 M DoFs); temperature =
+conductive profile + seeded spherical harmonics l = 1..8 of amplitude 0.01;
+viscosity eta = exp(-ln(1e3) T + ln(10) (1 - r)) per wedge.
 
-Prints one JSON line (see the design doc for the fields).
+A timed step is one full Stokes operator apply y = K_D [u; p] in FP32 (A,
+B^T, B, Dirichlet rows, diamond-interface sum); `value` is its throughput in
+GDoF/s.  The same line also reports the FP64 apply, the FP64 solve of the
+configuration to a 1e-8 relative residual, the mixed-precision solve of the
+same shell with viscosity contrast 1e6 next to the FP64 solve of that field,
+a short serving run (p50/p99 latency), the live roofline of the dominant
+kernel and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -17,7 +22,6 @@ import json
 import math
 import os
 import platform
-import subprocess
 import sys
 import time
 
@@ -31,43 +35,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup(tng, ctx, mt, nr, dtype):
-    import numpy as np
+def shell_fields(tng, ctx, mesh, seed=1, lmax=8):
     import torch
     import synthetic
-    mesh = tng.Mesh(ctx, mt, nr, levels=2)
     xyz, r = mesh.coords(0)
-    T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=1, lmin=1, lmax=8, amp=0.01)
-    dev = torch.device("cuda", 0)
-    T_t = torch.tensor(T.reshape(mesh.shape(0)), device=dev, dtype=dtype)
-    eta = torch.empty(mesh.wedge_shape(0), device=dev, dtype=dtype)
-    tng.eta_from_temperature(ctx, mesh, 0, T_t, math.log(1e3), math.log(10.0), eta)
-    g = torch.Generator(device="cpu").manual_seed(2)
-    u = (torch.rand((3,) + mesh.shape(0), generator=g, dtype=torch.float64) * 2 - 1).to(dev, dtype)
-    p = (torch.rand(mesh.shape(1), generator=g, dtype=torch.float64) * 2 - 1).to(dev, dtype)
-    tng.interface_sum(ctx, mesh, 0, [u[0], u[1], u[2]], mode=1)
-    tng.interface_sum(ctx, mesh, 1, [p], mode=1)
-    yu = torch.empty_like(u)
-    yp = torch.empty_like(p)
-    torch.cuda.synchronize()
-    return mesh, eta, u, p, yu, yp
+    T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=seed, lmin=1, lmax=lmax, amp=0.01)
+    return torch.tensor(T.reshape(mesh.shape(0)), device="cuda", dtype=torch.float64)
 
 
 def unique_dofs(mt, nr):
-    nu = 3 * (10 * mt * mt + 2) * (nr + 1)
-    npr = (10 * (mt // 2) ** 2 + 2) * (nr // 2 + 1)
-    return nu, npr
+    return 3 * (10 * mt * mt + 2) * (nr + 1), (10 * (mt // 2) ** 2 + 2) * (nr // 2 + 1)
 
 
 def algorithmic_bytes(mesh, esize):
-    """Minimal traffic of one K apply: read u, write y_u (3 node fields each),
-    read the two wedge viscosities per cell, read p and write y_p."""
+    """Minimal traffic of one K apply: read u and write y_u (3 node fields
+    each), read two wedge viscosities per cell, read p and write y_p."""
     c0, c1 = mesh.counts(0), mesh.counts(1)
     return esize * (6 * c0["node_slots"] + 2 * c0["cells"] + 2 * c1["node_slots"])
 
 
-def time_apply(tng, ctx, mesh, eta, u, p, yu, yp, steps, warmup):
+def bench_apply(tng, ctx, mesh, T64, dtype, steps, warmup):
     import torch
+    eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=dtype)
+    tng.eta_from_temperature(ctx, mesh, 0, T64.to(dtype), math.log(1e3), math.log(10.0), eta)
+    g = torch.Generator(device="cpu").manual_seed(2)
+    u = (torch.rand((3,) + mesh.shape(0), generator=g, dtype=torch.float64) * 2 - 1).to("cuda", dtype)
+    p = (torch.rand(mesh.shape(1), generator=g, dtype=torch.float64) * 2 - 1).to("cuda", dtype)
+    tng.interface_sum(ctx, mesh, 0, [u[0], u[1], u[2]], mode=1)
+    tng.interface_sum(ctx, mesh, 1, [p], mode=1)
+    yu, yp = torch.empty_like(u), torch.empty_like(p)
     flags = tng.OP_A | tng.OP_BT | tng.OP_B | tng.OP_DIRICHLET
     for _ in range(warmup):
         tng.stokes_apply(ctx, mesh, 0, flags, eta, u, p, yu, yp)
@@ -80,11 +76,84 @@ def time_apply(tng, ctx, mesh, eta, u, p, yu, yp, steps, warmup):
     wall = (time.perf_counter() - t0) / steps
     kms, nl = ctx.kernel_stats("stokes_apply")
     ctx.profile(False)
+    del eta, u, p, yu, yp
     return wall, kms / max(nl, 1)
 
 
+def bench_solve(tng, ctx, mesh, T64, E, F, mixed, reps=2):
+    """Solves/s of the Stokes problem with eta = exp(-E T + F (1 - r)) and the
+    buoyancy right-hand side 1e5 T rhat, to a 1e-8 relative residual."""
+    import torch
+    eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
+    tng.eta_from_temperature(ctx, mesh, 0, T64, E, F, eta)
+    f = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+    tng.rhs_buoyancy(ctx, mesh, 0, T64, 1e5, f)
+    u = torch.empty_like(f)
+    p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-8, max_iters=600)
+    infos = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(f, None, u, p, eta=eta, raise_on_fail=False)
+        torch.cuda.synchronize()
+        info["wall"] = time.perf_counter() - t0
+        infos.append(info)
+    best = min(infos, key=lambda x: x["wall"])
+    s.close()
+    return best, (u.clone(), p.clone())
+
+
+def bench_serving(tng, ctx, nreq, rate_factor, budget):
+    """Poisson-arrival request stream over (16,16), (32,32), (64,64) shells."""
+    import numpy as np
+    import torch
+    import synthetic
+    levels = [(16, 16), (32, 32), (64, 64)]
+    reqs = synthetic.serving_requests(nreq, levels)
+    fields = []
+    meshes = [tng.Mesh(None, mt, nr, levels=1) for mt, nr in levels]
+    for rq in reqs:
+        mesh = meshes[rq["level"]]
+        xyz, r = mesh.coords(0)
+        T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=rq["seed"], lmin=1, lmax=16)
+        Tt = torch.tensor(T.reshape(mesh.shape(0)), device="cuda")
+        u = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+        mt, nr = levels[rq["level"]]
+        p = torch.empty((10, mt // 2 + 1, mt // 2 + 1, nr // 2 + 1), device="cuda", dtype=torch.float64)
+        fields.append((Tt, u, p))
+    srv = tng.Server(ctx, levels, budget_bytes=budget, max_slots=16, mixed=1, rtol=1e-8)
+    # saturated throughput: everything submitted at once
+    t0 = time.perf_counter()
+    tk = [srv.submit(rq["level"], *fields[i][:1], rq["log10_contrast"], 1e5, fields[i][1], fields[i][2])
+          for i, rq in enumerate(reqs)]
+    srv.wait(0)
+    mu = nreq / (time.perf_counter() - t0)
+    # Poisson arrivals at rate_factor * mu
+    lam = rate_factor * mu
+    arr = synthetic.poisson_arrivals(nreq, lam, seed=7)
+    t0 = time.perf_counter()
+    tk = []
+    for i, rq in enumerate(reqs):
+        while time.perf_counter() - t0 < arr[i]:
+            time.sleep(2e-4)
+        tk.append(srv.submit(rq["level"], fields[i][0], rq["log10_contrast"], 1e5, fields[i][1], fields[i][2]))
+    srv.wait(0)
+    total = time.perf_counter() - t0
+    lat = np.array([srv.poll(t)["latency"] for t in tk])
+    ok = sum(srv.poll(t)["rc"] == 0 for t in tk)
+    st = srv.stats()
+    srv.close()
+    return {"requests": nreq, "ok": int(ok), "saturated_solves_per_s": round(mu, 2),
+            "lambda_per_s": round(lam, 2), "solves_per_s": round(nreq / total, 2),
+            "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "slots": st["slots"], "budget_bytes": budget, "bytes_in_use": st["bytes_in_use"],
+            "levels": levels}
+
+
 def cpu_baseline(mt=16, nr=16, reps=10):
-    """The FP64 oracle (assembled K, scipy CSR SpMV) on a bounded sample shell."""
+    """The FP64 oracle (assembled K_D, scipy CSR SpMV) on a bounded sample shell."""
     import numpy as np
     import synthetic
     from oracle.mesh import ShellMesh
@@ -95,8 +164,7 @@ def cpu_baseline(mt=16, nr=16, reps=10):
     t0 = time.perf_counter()
     orc = StokesOracle(mt, nr, eta, hierarchy=om.h)
     t_asm = time.perf_counter() - t0
-    rng = np.random.default_rng(2)
-    x = rng.uniform(-1, 1, orc.K.shape[0])
+    x = np.random.default_rng(2).uniform(-1, 1, orc.K.shape[0])
     for _ in range(2):
         orc.K @ x
     ts = []
@@ -106,26 +174,38 @@ def cpu_baseline(mt=16, nr=16, reps=10):
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
     ndof = orc.K.shape[0]
-    return {"value": ndof / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"assembled FP64 K_D of the ({mt},{nr}) shell ({ndof} u+p DoFs, "
-                       f"nnz {orc.K.nnz}), scipy CSR SpMV, median of {reps}; assembly took "
-                       f"{t_asm:.1f} s, SpMV {t * 1e3:.2f} ms; host {platform.processor() or platform.machine()}, "
-                       f"nproc {os.cpu_count()}")}
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except Exception:
+        pass
+    return {"value": round(ndof / t / 1e9, 5), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"assembled FP64 K_D of the ({mt},{nr}) shell ({ndof} u+p DoFs, nnz {orc.K.nnz}), "
+                       f"scipy CSR SpMV (single thread), median of {reps}: {t * 1e3:.2f} ms per apply; "
+                       f"assembly {t_asm:.1f} s; host {cpu}, nproc {os.cpu_count()}")}
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mt", type=int, default=128)
     ap.add_argument("--nr", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="apply only (profiling runs)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-rate", type=float, default=0.75, help="arrival rate / saturated rate")
+    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of a known size (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the shell would shard by lateral diamond blocks with one neighbour "
-              "exchange per apply; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the shell would shard by "
+              "lateral diamond blocks with one neighbour exchange per apply, see DESIGN.md).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2609_21633_amd as tng
@@ -133,18 +213,28 @@ def main():
     ctx = tng.Context(0)
     mt, nr = args.mt, args.nr
     nu, npr = unique_dofs(mt, nr)
+    levels = int(math.log2(mt))                   # down to (2, 2)
+    mesh = tng.Mesh(ctx, mt, nr, levels=levels)
+    T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
     res = {}
     for name, dtype, es in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
-        log(f"[bench] setting up {name} apply on ({mt},{nr})")
-        mesh, eta, u, p, yu, yp = setup(tng, ctx, mt, nr, dtype)
-        wall, kms = time_apply(tng, ctx, mesh, eta, u, p, yu, yp, args.steps, args.warmup)
+        log(f"[bench] {name} apply on ({mt},{nr})")
+        wall, kms = bench_apply(tng, ctx, mesh, T64, dtype, args.steps, args.warmup)
         ab = algorithmic_bytes(mesh, es)
-        res[name] = {"ms": wall * 1e3, "kernel_ms": kms, "gdofs": (nu + npr) / wall / 1e9,
-                     "alg_bytes": ab, "kernel_gbs": ab / (kms * 1e-3) / 1e9}
-        log(f"[bench] {name}: {wall * 1e3:.3f} ms/apply, kernel {kms:.3f} ms, "
-            f"{res[name]['gdofs']:.1f} GDoF/s, {res[name]['kernel_gbs']:.0f} GB/s algorithmic")
-        del mesh, eta, u, p, yu, yp
+        res[name] = {"ms": wall * 1e3, "kernel_ms": kms, "gdofs": (nu + npr) / wall / 1e9, "alg_bytes": ab,
+                     "kernel_gbs": ab / (kms * 1e-3) / 1e9}
+        log(f"[bench] {name}: {wall * 1e3:.3f} ms/apply (kernel {kms:.3f} ms), {res[name]['gdofs']:.1f} GDoF/s, "
+            f"{res[name]['kernel_gbs']:.0f} GB/s algorithmic")
         torch.cuda.empty_cache()
+    if args.copy_calibration:
+        # plain device copy of 2 GiB between buffers that were written before
+        # (untouched pages do not exercise HBM), for scaling HBM counters
+        x = torch.full((512 * 1024 * 1024,), 1.0, dtype=torch.float32, device="cuda")
+        y = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     head = res["f32"]
     out = {
         "metric": "GDoF/s Stokes apply FP32 vs FP64 at 1e-8 solve tol; solves/s, p50/p99 latency",
@@ -159,15 +249,45 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"Stokes K apply, shell vel ({mt},{nr}) / p ({mt // 2},{nr // 2}), "
-                               "eta = exp(-ln(1e3) T + ln(10)(1-r)), T = conduction + SH l=1..8",
+        "config": {"workload": (f"Stokes K apply on the shell with velocity ({mt},{nr}) / pressure "
+                                f"({mt // 2},{nr // 2}), eta = exp(-ln(1e3) T + ln(10)(1-r)), "
+                                "T = conduction + spherical harmonics l=1..8"),
                    "u_dofs": nu, "p_dofs": npr},
         "roofline": {"bound": "hbm", "achieved": round(head["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "stokes_band_kernel<float,2,A,BT,B>",
+                     "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": round(head["kernel_ms"], 4)},
         "f64_apply": {"gdofs": round(res["f64"]["gdofs"], 3), "ms": round(res["f64"]["ms"], 4),
-                      "kernel_gbs": round(res["f64"]["kernel_gbs"], 1)},
+                      "kernel_gbs": round(res["f64"]["kernel_gbs"], 1),
+                      "kernel_ms": round(res["f64"]["kernel_ms"], 4)},
     }
+    if not args.no_solve:
+        log("[bench] FP64 solve, contrast 1e3 x 10 (depth)")
+        s1, _ = bench_solve(tng, ctx, mesh, T64, math.log(1e3), math.log(10.0), mixed=0)
+        out["solve_fp64"] = {"solves_per_s": round(1.0 / s1["wall"], 4), "seconds": round(s1["wall"], 3),
+                             "iterations": s1["inner_its"], "rel_res": s1["rel_res"], "rc": s1["rc"]}
+        log(f"[bench] {out['solve_fp64']}")
+        log("[bench] contrast 1e6: mixed vs FP64 on the same field")
+        s64, (u64, p64) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=0)
+        s32, (u32, p32) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=1)
+        du = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+        dp = float(torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64))
+        out["solve_contrast_1e6"] = {
+            "fp64": {"solves_per_s": round(1.0 / s64["wall"], 4), "iterations": s64["inner_its"],
+                     "rel_res": s64["rel_res"], "rc": s64["rc"]},
+            "mixed": {"solves_per_s": round(1.0 / s32["wall"], 4), "inner_iterations": s32["inner_its"],
+                      "refinement_steps": s32["outer_its"], "rel_res": s32["rel_res"], "rc": s32["rc"]},
+            "mixed_over_fp64": round(s64["wall"] / s32["wall"], 3),
+            "mixed_vs_fp64_rel_err": {"u": du, "p": dp},
+            "mixed_over_fp64_c1_field": round(s1["wall"] / s32["wall"], 3)}
+        log(f"[bench] {out['solve_contrast_1e6']}")
+        del u64, p64, u32, p32
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        log(f"[bench] serving: {args.serving_requests} requests at {args.serving_rate} x saturated rate")
+        out["serving"] = bench_serving(tng, ctx, args.serving_requests, args.serving_rate,
+                                       int(args.serving_budget_gb * (1 << 30)))
+        log(f"[bench] {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()

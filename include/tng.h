@@ -101,7 +101,7 @@ int tng_ctx_destroy(tng_ctx* ctx);
 int tng_ctx_profile(tng_ctx* ctx, int enable);
 int tng_ctx_kernel_stats(tng_ctx* ctx, const char* name, double* total_ms, long long* launches);
 
-/* ---- mesh (Sec. 2, a1) -------------------------------------------------- */
+/* ---- mesh (Sec. 2) ------------------------------------------------------ */
 /* Builds the shell with mt lateral intervals per diamond edge (power of two)
  * and nr radial intervals on [r_in, r_out], and uploads `levels` levels to the
  * context's device.  ctx may be NULL: then only the host-side description is
@@ -122,7 +122,7 @@ int tng_mesh_coords(const tng_mesh* mesh, int level, double* unit_xyz_host, doub
 int tng_mesh_dup_groups(const tng_mesh* mesh, int level, int* unique_id_host);
 int tng_mesh_destroy(tng_mesh* mesh);
 
-/* ---- operator (Sec. 3 eq:matfree, eq:epsq, eq:localapply; a3-a5) -------- */
+/* ---- operator (Sec. 3 eq:matfree, eq:epsq, eq:localapply) -------------- */
 /* y = K(eta) x restricted to the blocks in op_flags, on level `level`.
  * eta_wedge: device wedge field of level `level`.  u[3]: device velocity in;
  * p: device pressure (level + 1) in, may be NULL unless TNG_OP_BT is set.
@@ -136,7 +136,7 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
                      const void* const u[3], const void* p,
                      void* const y_u[3], void* y_p);
 
-/* ---- fields (a2) -------------------------------------------------------- */
+/* ---- fields ------------------------------------------------------------- */
 /* Per-wedge viscosity from nodal temperature: eta_e = exp(-E Tbar_e + F (1 - r_m)),
  * Tbar_e the mean of the wedge's six nodal values (the W1 interpolant at q_c,
  * Sec. 4) and r_m the wedge's mid radius; the Frank-Kamenetskii family of
@@ -150,7 +150,7 @@ int tng_eta_from_temperature(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_
 int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec,
                     const void* eta_fine, void* eta_coarse);
 
-/* ---- multigrid pieces (Sec. 7; a6-a8) ----------------------------------- */
+/* ---- multigrid pieces (Sec. 7) ------------------------------------------ */
 /* Diagonal of K_D's viscous block on `level`: diag_(node,c) = sum over the
  * node's wedges of V eta (|grad phi|^2 + (d_c phi)^2 / 3) (eq:elemmat, one
  * point), 1 on Dirichlet rows.  diag[3]: device velocity field out. */
@@ -179,7 +179,7 @@ int tng_restrict(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pr
 int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec, const void* const c[3],
                 void* const f[3]);
 
-/* ---- Stokes solver (Sec. 7; a6-a12) ------------------------------------ */
+/* ---- Stokes solver (Sec. 7) --------------------------------------------- */
 /* Options of the FGMRES / block-preconditioner / multigrid solve.
  * mixed: 0 = everything FP64; 1 = FP64 iterative refinement (outer residual,
  *   correction, pressure-mean projection, coarsest solve in FP64) around an
@@ -244,7 +244,7 @@ int tng_stokes_solve(tng_solver* solver, const double* eta_wedge, const double* 
  * solver's Krylov precision (FP32 when mixed).  b, x: device velocity fields. */
 int tng_stokes_solver_vcycle(tng_solver* solver, const void* const b[3], void* const x[3]);
 
-/* ---- buoyancy and energy (a13, a14) -------------------------------------- */
+/* ---- buoyancy and energy (Sec. 6) --------------------------------------- */
 /* Buoyancy right-hand side of eq:stokes in Boussinesq form (rho = alpha = 1):
  * f_(i,c) = sum_e V_e N_i(q_c) Ra T(q_c) rhat_c(q_c), one-point rule, T(q_c)
  * the mean of the wedge's nodal temperatures and rhat the direction of x(q_c);
@@ -287,13 +287,14 @@ typedef struct {
 int tng_energy_step(tng_solver* solver, const tng_step_opts* opts, const double* H, double* T,
                     double* const u[3], double* p, tng_step_info* info);
 
-/* ---- serving (a15) --------------------------------------------------------- */
+/* ---- serving ------------------------------------------------------------ */
 /* Request server for streams of Stokes solves.  levels: nlevels pairs
  * (mt, nr), each kept resident with its multigrid hierarchy.  Requests are
  * admitted FIFO per level into solver slots; a slot is a solver with its own
  * HIP stream and host worker, reused for later requests of its level, and
- * slots run concurrently on the device.  A new slot is created only while the
- * measured per-slot memory of its level keeps the total within
+ * slots run concurrently on the device.  The device memory of one slot of
+ * each level is measured here, by building a slot and releasing it.  A new
+ * slot is created only while that per-slot memory keeps the total within
  * hbm_budget_bytes (an idle slot of another level is released to make room
  * when needed); at most max_slots slots per level.  opts: solver options of
  * every slot (normally mixed precision). */

@@ -16,7 +16,9 @@ ARCH = "gfx950"
 def hipcc_command(out: str = LIB) -> list[str]:
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-munsafe-fp-atomics", "-pthread",
+           # the sign of a zero carries no meaning here; this lets 0 + x fold to x,
+           # so accumulators start without a zero fill
+           "-munsafe-fp-atomics", "-fno-signed-zeros", "-pthread",
            # no packed FP32 instructions anywhere in device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",

@@ -9,13 +9,14 @@
 //   are reused for later requests of that level.
 // * Admission is FIFO per level: a queued request starts as soon as its level
 //   has an idle slot, or a new slot fits in the HBM budget.  The memory model
-//   of a level is measured when its first slot is created (device memory in
-//   use before and after), then used for all later admissions.
+//   of a level is measured once, when the server is created, by building one
+//   slot and counting the device bytes allocated for it.
 // * Requests of all slots overlap on the device through their streams; a
 //   finished slot takes the next queued request of its level immediately.
 // Each request solves the Stokes problem with eta = exp(-ln(contrast) T) and
 // the buoyancy right-hand side Ra T rhat in mixed precision.
 #include <atomic>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -50,7 +51,7 @@ struct ServerLevel {
     tng_mesh* mesh = nullptr;
     std::vector<std::unique_ptr<ServerSlot>> slots;
     std::deque<ServerReq*> queue;
-    long long bytes_per_slot = -1;      // measured on the first slot
+    long long bytes_per_slot = -1;      // measured at server creation
 };
 
 struct ServerSlot {
@@ -85,13 +86,6 @@ struct tng_server {
 
 namespace tng {
 namespace {
-
-long long device_used(int dev) {
-    size_t fr = 0, tot = 0;
-    TNG_HIP(hipSetDevice(dev));
-    TNG_HIP(hipMemGetInfo(&fr, &tot));
-    return (long long)(tot - fr);
-}
 
 void dispatch(tng_server* srv);
 
@@ -163,7 +157,6 @@ ServerSlot* make_slot(tng_server* srv, int li) {
     slot->srv = srv;
     slot->level = li;
     slot->mesh = lv.mesh;
-    const long long before = device_used(srv->ctx->device);
     TNG_HIP(hipStreamCreate(&slot->stream));   // default priority
     if (tng_ctx_create(srv->ctx->device, slot->stream, &slot->ctx) != TNG_OK)
         throw Error(TNG_E_HIP, "slot context creation failed");
@@ -172,10 +165,6 @@ ServerSlot* make_slot(tng_server* srv, int li) {
     const tng::Level& L = lv.mesh->lv[0];
     slot->eta.alloc(2 * L.cells());
     slot->f.alloc(3 * L.node_slots());
-    TNG_HIP(hipDeviceSynchronize());
-    const long long after = device_used(srv->ctx->device);
-    const long long cost = std::max(after - before, 1LL);
-    if (lv.bytes_per_slot < 0) lv.bytes_per_slot = cost;
     srv->bytes_in_use += lv.bytes_per_slot;
     ServerSlot* raw = slot.get();
     lv.slots.push_back(std::move(slot));
@@ -183,21 +172,23 @@ ServerSlot* make_slot(tng_server* srv, int li) {
     return raw;
 }
 
-// Estimated bytes of a slot of level li before any exists: sizes of the
-// solver's vectors (Krylov basis, multigrid scratch, hierarchy viscosity).
-long long estimate_slot_bytes(const tng_server* srv, const ServerLevel& lv) {
-    const auto& L0 = lv.mesh->lv[0];
-    const auto& L1 = lv.mesh->lv[1];
-    const long long ns = L0.node_slots(), np = L1.node_slots();
-    const long long N = 3 * ns + np;
-    const int m = srv->opts.restart;
-    const bool mixed = srv->opts.mixed != 0;
-    const long long kb = mixed ? 4 : 8;
-    long long b = (2 * m + 2) * N * kb;               // Krylov V, Z, w
-    b += 8 * 3 * N * (long long)sizeof(double);       // outer vectors, rhs, work
-    b += (long long)(6 * 3 * ns * kb * 8) / 7;        // multigrid scratch over all levels
-    b += 2 * L0.cells() * 8 * 3;                      // viscosity copies
-    return b;
+// Device bytes of one slot of level li: a slot is built and released once,
+// counting what this thread allocates for it.  A level whose slot cannot be
+// allocated at all is given an unbounded cost and refuses every request.
+long long measure_slot_bytes(tng_server* srv, ServerLevel& lv) {
+    const long long before = tl_device_bytes;
+    long long cost = LLONG_MAX;
+    tng_solver* sv = nullptr;
+    if (tng_stokes_solver_create(srv->ctx, lv.mesh, &srv->opts, &sv) == TNG_OK) {
+        try {
+            const tng::Level& L = lv.mesh->lv[0];
+            DevBuf<double> eta(2 * L.cells()), f(3 * L.node_slots());
+            cost = std::max(tl_device_bytes - before, 1LL);
+        } catch (const Error&) {
+        }
+        tng_stokes_solver_destroy(sv);
+    }
+    return cost;
 }
 
 // Admits queued requests (lock held).
@@ -214,8 +205,7 @@ void dispatch(tng_server* srv) {
             }
             if (!idle) {
                 if (live >= srv->max_slots) break;
-                const long long need = lv.bytes_per_slot >= 0 ? lv.bytes_per_slot : estimate_slot_bytes(srv, lv);
-                if (srv->bytes_in_use + need > (long long)srv->budget) {
+                if (lv.bytes_per_slot > (long long)srv->budget - srv->bytes_in_use) {
                     // an idle slot of another level may be retired to make room
                     if (live == 0) {
                         for (auto& other : srv->levels) {
@@ -269,6 +259,7 @@ int tng_server_create(tng_ctx* ctx, const int* levels, int nlevels, size_t hbm_b
             for (int k = 0; k < i; ++k) tng_mesh_destroy(srv->levels[k].mesh);
             throw Error(rc, std::string("server level mesh: ") + tng_last_error());
         }
+        lv.bytes_per_slot = tng::measure_slot_bytes(srv.get(), lv);
     }
     *out = srv.release();
     TNG_API_END
@@ -281,10 +272,10 @@ int tng_server_submit(tng_server* srv, int level_idx, const double* T, double lo
     TNG_REQUIRE(level_idx >= 0 && level_idx < (int)srv->levels.size(), "level_idx out of range");
     std::lock_guard<std::mutex> lk(srv->mu);
     ServerLevel& lv = srv->levels[level_idx];
-    const long long need = lv.bytes_per_slot >= 0 ? lv.bytes_per_slot : tng::estimate_slot_bytes(srv, lv);
-    if (lv.slots.empty() && need > (long long)srv->budget)
-        throw Error(TNG_E_BUDGET, "request does not fit the HBM budget (needs ~" + std::to_string(need) +
-                                      " bytes, budget " + std::to_string(srv->budget) + ")");
+    if (lv.slots.empty() && lv.bytes_per_slot > (long long)srv->budget)
+        throw Error(TNG_E_BUDGET, "request does not fit the HBM budget (a slot of this level needs " +
+                                      std::to_string(lv.bytes_per_slot) + " bytes, budget " +
+                                      std::to_string(srv->budget) + ")");
     auto r = std::make_unique<ServerReq>();
     r->ticket = srv->next_ticket++;
     r->level = level_idx;

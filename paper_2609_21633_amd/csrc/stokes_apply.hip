@@ -1,4 +1,5 @@
-// Atomic-free streaming kernel for the Stokes apply y = K(eta) [u; p].
+// Streaming kernel for the Stokes apply y = K(eta) [u; p] (Sec. 3, one-point
+// rule of Sec. 4).
 //
 // Work decomposition (one diamond d, a "band"):
 //   * lanes run along the radial direction: lane l of a wave handles the CPL
@@ -8,22 +9,29 @@
 //   * the workgroup streams along j over the cell rows of its band, carrying
 //     the half-finished node row in registers, so each node of the band's
 //     interior is written exactly once, with its complete sum.
-// Contributions that cross a wave boundary are combined in LDS (lateral, i
-// direction) or with lane shuffles (radial).  A band starts one cell row
-// early (the halo row) so that its first node row is complete; nodes on the
-// seams between tiles (node columns that are multiples of TI) and between
-// radial chunks receive exactly two partial sums, added with atomics to
-// memory zeroed beforehand, which keeps the result independent of timing.
+// Velocity rows are staged in a three-row LDS ring (rows j, j+1 in use, row
+// j+2 arriving), copied straight from HBM without passing through registers;
+// each node column is read from HBM once per workgroup and shared by the two
+// waves that touch it.  The nodal differences of a triangle are formed once
+// per node layer and shared by the wedges below and above it, and so are the
+// test-function sums of the result.  Contributions that cross a wave boundary
+// are combined in LDS (lateral, i direction) or moved one lane up with a DPP
+// wavefront shift (radial).  A band starts one cell row early (the halo row)
+// so that its first node row is complete; nodes on the seams between tiles
+// (node columns that are multiples of TI) and between radial chunks receive
+// exactly two partial sums, added with atomics to memory zeroed beforehand,
+// which keeps the result independent of timing.
 //
-// The divergence block is accumulated per coarse pressure node in LDS over
-// the band and flushed with atomics once a coarse row is complete.
+// The divergence block is reduced per coarse pressure node through LDS, kept
+// by one owner thread per node and flushed once a coarse row is complete.
 #include "tng_internal.hpp"
 #include "wedge.hpp"
 
 namespace tng {
 namespace {
 
-constexpr int TI_MAX = 8;   // cell columns (waves) per workgroup
+constexpr int TIC = 8;   // cell columns (waves) per workgroup
+
 
 template <typename T>
 struct BandArgs {
@@ -81,20 +89,42 @@ struct CoarseMap {
     static constexpr int NKL = CPL == 1 ? 2 : CPL / 2 + 1;
 };
 
+// Lane l receives lane l+1 (shl) or lane l-1 (shr); lanes shifted in from
+// outside the wavefront read zero (DPP wave shift with bound control).
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
 template <typename T, int CPL, bool DO_A, bool DO_BT, bool DO_B>
-__global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a) {
+__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
     constexpr bool LOAD_U = DO_A || DO_B;
-    constexpr int XW = DO_U ? TI_MAX : 1;
+    // velocity rows j, j+1, j+2 of the TI + 1 node columns, radial fastest
+    constexpr int KW = 64 * CPL + 1;            // node layers of a radial chunk
+    constexpr int KWP = (KW + 1) & ~1;          // even pitch: lane pairs stay 8-byte aligned
+    constexpr int RR = LOAD_U ? 3 : 1;
+    constexpr int RW = LOAD_U ? TIC + 1 : 1;
+    __shared__ T ring[RR][RW][3][KWP];
+    constexpr int XW = DO_U ? TIC : 1;
     __shared__ T xch[2][XW][3][NL][64];
     constexpr int NKC = DO_B ? 32 * CPL + 1 : 1;          // coarse layers per chunk
-    constexpr int BW = DO_B ? TI_MAX : 1;
-    __shared__ T bsl[2][BW][4][NKC];                      // per-wave coarse partials
+    constexpr int BW = DO_B ? TIC + 4 : 1;
+    __shared__ T bsl[2][BW][4][NKC];   // per-wave coarse partials, wave w in slot w + 2
     constexpr int NKL = CoarseMap<CPL>::NKL;
     const IsoWeights<T>& iso = IsoTable<T>::get();
 
-    const int TI = a.TI;
+    const int TI = a.TI;   // <= TIC on small levels
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int bid = blockIdx.x;
@@ -113,7 +143,7 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
     const int jfirst = j0 > 0 ? j0 - 1 : 0;            // halo row (computed, not owned)
     const int jlast_cell = last_band ? m - 1 : j0 + a.TJ - 1;
     const int jlast = last_band ? m : jlast_cell;      // last node row emitted
-    const int k0 = chunk * a.KC;
+    const int k0 = chunk * a.KC;                       // even: KC is a multiple of 64
     const int kend = min(n, k0 + a.KC);                // cells [k0, kend) of this chunk
 
     // 32-bit offsets: every field of a supported level has < 2^31 entries
@@ -122,28 +152,47 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
     const unsigned colA = ((unsigned)d * (m + 1) + i) * ldi;   // node column i
     const unsigned colB = colA + ldi;                          // node column i + 1
 
+    const int kl0 = CPL * lane;                        // first chunk-local layer of the lane
     int kk[NL];
 #pragma unroll
-    for (int c = 0; c < NL; ++c) kk[c] = k0 + CPL * lane + c;
-    bool cell_ok[CPL];
+    for (int c = 0; c < NL; ++c) kk[c] = k0 + kl0 + c;
+    // radial factors of the lane's cells; a cell outside the chunk gets a zero
+    // volume, which zeroes every contribution it makes
+    T s1[CPL], vr[CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) cell_ok[c] = kk[c] < kend;
+    for (int c = 0; c < CPL; ++c) {
+        const T rm = a.r_in + (T(kk[c]) + T(0.5)) * a.dr;
+        s1[c] = T(0.5) / rm;
+        vr[c] = kk[c] < kend ? rm * rm : T(0);
+    }
     const bool top_lane = (kk[0] <= kend - 1) && (kend - 1 <= kk[CPL - 1]);
     const int top_c = kend - kk[0];
-    bool node_ok[NL];
-#pragma unroll
-    for (int c = 0; c < NL; ++c)
-        node_ok[c] = LOAD_U && kk[c] <= n && !(a.dirichlet && (kk[c] == 0 || kk[c] == n));
 
-    auto load_u = [&](unsigned col, int jrow, T (&dst)[NL][3]) {
-        const unsigned base = col + (unsigned)jrow * ldj;
+    // velocity staging: each radial line of a chunk column (KW values of one
+    // component) is copied straight from HBM into its ring row, 64 dwords per
+    // instruction, lane l moving dword l of each 256-byte piece.  Dirichlet
+    // layers and layers past the chunk are never written and keep the zeros
+    // the ring starts with.
+    constexpr int DW = sizeof(T) / 4;                   // dwords per value
+    constexpr int NCH = (KW * DW + 63) / 64;            // 256-byte pieces per line
+    bool lok[NCH];
 #pragma unroll
-        for (int c = 0; c < NL; ++c) {
-            const unsigned o = base + (unsigned)kk[c];
-            dst[c][0] = node_ok[c] ? a.u0[o] : T(0);
-            dst[c][1] = node_ok[c] ? a.u1[o] : T(0);
-            dst[c][2] = node_ok[c] ? a.u2[o] : T(0);
-        }
+    for (int t = 0; t < NCH; ++t) {
+        const int e = (lane + 64 * t) / DW;             // value moved by this lane
+        const int k = k0 + e;
+        lok[t] = LOAD_U && e < KW && k <= kend && !(a.dirichlet && (k == 0 || k == n));
+    }
+    auto stage = [&](unsigned col, int jrow, int slot, int wl) {
+        const unsigned base = col + (unsigned)jrow * ldj + (unsigned)k0;
+        const T* const src[3] = {a.u0 + base, a.u1 + base, a.u2 + base};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int t = 0; t < NCH; ++t)
+                if (lok[t])
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned*>(src[r]) + lane + 64 * t,
+                                                     reinterpret_cast<unsigned*>(&ring[slot][wl][r][0]) + 64 * t,
+                                                     4, 0, 0);
     };
 
     const int mc = m / 2, nc = n / 2;
@@ -154,78 +203,110 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
     const int ab = i & 1;
     const int K0 = k0 >> 1;
 
-    // per-row inputs of the cell row: viscosities and coarse pressure corners
+    // per-row inputs of the cell row: viscosities, and the coarse pressure of
+    // the four lateral corners on the NKL coarse layers the lane's cells touch
+    // (combined only when used, so that the loads stay in flight)
+    const int Kb = (k0 + kl0) >> 1;
+    int Kp[NKL];
+#pragma unroll
+    for (int s = 0; s < NKL; ++s) Kp[s] = min(Kb + s, nc);
     struct RowIn {
         T eta[CPL][2];
-        T pc[CPL][4];
+        T pk[4][NKL];
     };
     auto load_row = [&](int j, RowIn& r) {
         const unsigned ecol = (((unsigned)d * m + i) * m + j) * (unsigned)n * 2u;
-        const int J = j >> 1;
-        const unsigned pb0 = pcol + (unsigned)I * pldi + (unsigned)J * pldj;
-        const unsigned pbq[4] = {pb0, pb0 + pldi, pb0 + pldj, pb0 + pldi + pldj};
+        if (DO_A) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int k = cell_ok[c] ? kk[c] : k0;
-            if (DO_A) {
+            for (int c = 0; c < CPL; ++c) {
+                const int k = kk[c] < kend ? kk[c] : k0;
                 r.eta[c][0] = a.eta[ecol + 2u * k];
                 r.eta[c][1] = a.eta[ecol + 2u * k + 1u];
             }
-            if (DO_BT) {
-                const int K = k >> 1, cb = k & 1;
-                const T rw0 = iso.rw[cb][0], rw1 = iso.rw[cb][1];
+        }
+        if (DO_BT) {
+            const unsigned pb0 = pcol + (unsigned)I * pldi + (unsigned)(j >> 1) * pldj;
+            const unsigned pbq[4] = {pb0, pb0 + pldi, pb0 + pldj, pb0 + pldi + pldj};
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    r.pc[c][q] = rw0 * a.p[pbq[q] + K] + rw1 * a.p[pbq[q] + K + 1];
-            }
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int s = 0; s < NKL; ++s) r.pk[q][s] = a.p[pbq[q] + Kp[s]];
         }
     };
 
-    // rolling partial sums of node row j+1 (R0: column i, R1: column i+1)
-    T R0[NL][3], R1[NL][3];
+    // node-row partial sums, [column i / i+1][layer][component]: Rc for node row
+    // j (complete after this row's cells), Rn for node row j+1
+    T Rc[2][NL][3];
 #pragma unroll
-    for (int c = 0; c < NL; ++c)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) R0[c][r] = R1[c][r] = T(0);
+        for (int c = 0; c < NL; ++c)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Rc[q][c][r] = T(0);
 
-    // divergence: owner threads keep the two open coarse rows in registers
-    constexpr int NOWN = 2;
+    // divergence: owner thread t < ncoarse (at most one coarse node per thread,
+    // since CPL = 2 runs only with TI >= 4) keeps its two open coarse rows in
+    // registers
     const int ncoarse = (TI / 2 + 1) * NKC;
-    T pacc0[NOWN], pacc1[NOWN];
-#pragma unroll
-    for (int o = 0; o < NOWN; ++o) pacc0[o] = pacc1[o] = T(0);
-
-    T uA[NL][3], uB[NL][3], uC[NL][3], uD[NL][3];
-    RowIn rin;
-    load_u(colA, jfirst, uA);
-    load_u(colB, jfirst, uB);
-    if (jfirst <= jlast_cell) {
-        load_u(colA, jfirst + 1, uC);
-        load_u(colB, jfirst + 1, uD);
-        load_row(jfirst, rin);
+    const bool owner = DO_B && (int)threadIdx.x < ncoarse;
+    const int il = (int)threadIdx.x / NKC, kl = (int)threadIdx.x % NKC;
+    const int Ig = I0 + il, Kg = K0 + kl;
+    const bool own_ok = owner && Ig <= mc && Kg <= nc && kl <= (kend - k0) / 2;
+    const bool own_seam = (il == 0 && I0 > 0) || (il == TI / 2 && Ig < mc) || (kl == 0 && K0 > 0) ||
+                          (Kg < nc && kl == (kend - k0) / 2);
+    const unsigned own_off = pcol + (unsigned)Ig * pldi + (unsigned)Kg;
+    if (DO_B) {
+        // wave slots without a wave stay zero: two below, and from TI on
+        for (int x = threadIdx.x; x < 4 * 4 * NKC; x += TI * 64) {
+            const int sl4 = x / (4 * NKC), rem = x % (4 * NKC);
+            const int slot = sl4 & 1 ? (sl4 >> 1 ? TI + 3 : 1) : (sl4 >> 1 ? TI + 2 : 0);
+            (&bsl[0][0][0][0])[(size_t)slot * 4 * NKC + rem] = T(0);
+            (&bsl[1][0][0][0])[(size_t)slot * 4 * NKC + rem] = T(0);
+        }
     }
+    T pacc0 = T(0), pacc1 = T(0);
 
-    for (int j = jfirst; j <= jlast; ++j) {
+    int sj = 0, sj1 = 1, sj2 = 2;    // ring slots of node rows j, j+1, j+2
+    const bool xw = (w == TI - 1);   // the last wave also stages column i0 + TI
+    RowIn rin;
+    if (LOAD_U) {
+        for (int x = threadIdx.x; x < RR * RW * 3 * KWP; x += TI * 64) (&ring[0][0][0][0])[x] = T(0);
+        __syncthreads();
+        stage(colA, jfirst, sj, w);
+        stage(colA, jfirst + 1, sj1, w);
+        if (xw) {
+            stage(colB, jfirst, sj, TI);
+            stage(colB, jfirst + 1, sj1, TI);
+        }
+    }
+    load_row(jfirst, rin);
+    __builtin_amdgcn_s_waitcnt(0);   // staged rows have landed in LDS
+    __syncthreads();
+
+    // one cell row: rows alternate between the two register sets, so that the
+    // loop carries no copies
+    auto step = [&](const int j, T (&Rc)[2][NL][3], T (&Rn)[2][NL][3], const RowIn& rin, RowIn& rnext) {
         const bool row_cells = j <= jlast_cell;    // the extra last step only emits
         const bool owned = j >= j0;
         const int par = j & 1;
         const int J = j >> 1, bb = j & 1;
         // prefetch the next cell row while this one is computed
-        T uE[NL][3], uF[NL][3];
-        RowIn rnext;
         const bool pre = j + 1 <= jlast_cell;
         if (pre) {
-            load_u(colA, j + 2, uE);
-            load_u(colB, j + 2, uF);
+            // node row j+2 into the slot of row j-1, read for the last time
+            // before the previous barrier
+            if (LOAD_U) {
+                stage(colA, j + 2, sj2, w);
+                if (xw) stage(colB, j + 2, sj2, TI);
+            }
             load_row(j + 1, rnext);
         }
-        T Nd[4][NL][3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int c = 0; c < NL; ++c)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) Nd[q][c][r] = T(0);
+                for (int r = 0; r < 3; ++r) Rn[q][c][r] = T(0);
         T cp[4][NKL];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -233,77 +314,180 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
             for (int s = 0; s < NKL; ++s) cp[q][s] = T(0);
         if (row_cells) {
             const T* g = a.geo + (((unsigned)d * m + i) * m + j) * (unsigned)GEO_PER_COL;
+            // staged velocity of corner q (A=(i,j), B=(i+1,j), C=(i,j+1), D=(i+1,j+1))
+            auto rd = [&](int q, int c, int r) -> T {
+                return ring[q < 2 ? sj : sj1][w + (q & 1)][r][kl0 + c];
+            };
+            T top[4][3];   // partials of the lane's top layer, per corner
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                if (!cell_ok[c]) continue;
-                const int k = kk[c];
-                const T rm = a.r_in + (T(k) + T(0.5)) * a.dr;
-                const T s1 = T(0.5) / rm;
-                const T rm2 = rm * rm;
-                T tB[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int wd = 0; wd < 2; ++wd) {
-                    // wedge 0: corners (i,j),(i+1,j),(i,j+1); wedge 1: (i+1,j+1),(i,j+1),(i+1,j)
-                    T uw[6][3];
+            for (int t = 0; t < 2; ++t) {
+                // triangle corners: wedge 0 (A, B, C), wedge 1 (D, C, B)
+                const int q0 = t == 0 ? 0 : 3, q1 = t == 0 ? 1 : 2, q2 = t == 0 ? 2 : 1;
+                const T* gt = g + t * GEO_PER_TRI;
+                // per-layer nodal differences, shared by the wedges below and above:
+                // e1 = u1 - u0, e2 = u2 - u0, sm = u0 + u1 + u2
+                auto derive = [&](int c, T (&e)[3][3]) {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
-                        if (wd == 0) {
-                            uw[0][r] = uA[c][r]; uw[1][r] = uB[c][r]; uw[2][r] = uC[c][r];
-                            uw[3][r] = uA[c + 1][r]; uw[4][r] = uB[c + 1][r]; uw[5][r] = uC[c + 1][r];
-                        } else {
-                            uw[0][r] = uD[c][r]; uw[1][r] = uC[c][r]; uw[2][r] = uB[c][r];
-                            uw[3][r] = uD[c + 1][r]; uw[4][r] = uC[c + 1][r]; uw[5][r] = uB[c + 1][r];
-                        }
+                        const T x0 = LOAD_U ? rd(q0, c, r) : T(0);
+                        const T x1 = LOAD_U ? rd(q1, c, r) : T(0);
+                        const T x2 = LOAD_U ? rd(q2, c, r) : T(0);
+                        e[0][r] = x1 - x0;
+                        e[1][r] = x2 - x0;
+                        e[2][r] = x0 + x1 + x2;
                     }
-                    T pbar = 0;
-                    if (DO_BT) {
+                };
+                const T r3[3] = {gt[6], gt[7], gt[8]};
+                T plat[NKL];   // pressure at the wedge's lateral centroid, per coarse layer
+                if (DO_BT) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) pbar += iso.lw[ab][bb][wd][q] * rin.pc[c][q];
-                    }
-                    const T eta = DO_A ? rin.eta[c][wd] : T(0);
-                    WedgeOut<T> o;
-                    wedge_apply<T, DO_A, DO_BT, DO_B>(uw, g + wd * GEO_PER_TRI, s1, rm2, eta, pbar, o);
-                    if (DO_U) {
-                        constexpr int cq[2][3] = {{0, 1, 2}, {3, 2, 1}};
+                    for (int s = 0; s < NKL; ++s) {
+                        T v = T(0);
 #pragma unroll
-                        for (int jn = 0; jn < 3; ++jn)
-#pragma unroll
-                            for (int r = 0; r < 3; ++r) {
-                                Nd[cq[wd][jn]][c][r] += o.y[jn][r];
-                                Nd[cq[wd][jn]][c + 1][r] += o.y[jn + 3][r];
-                            }
-                    }
-                    if (DO_B) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) tB[q] += iso.lw[ab][bb][wd][q] * o.dv;
+                        for (int q = 0; q < 4; ++q) v += iso.lw[ab][bb][t][q] * rin.pk[q][s];
+                        plat[s] = v;
                     }
                 }
-                if (DO_B) {
-                    // coarse layers of this cell relative to the lane's first coarse layer
-                    const int cb = k & 1;
-                    const int sl = CPL == 1 ? 0 : ((k >> 1) - ((k0 + CPL * lane) >> 1));
+                T dvl[NKL];    // -V div u of the triangle's wedges, per coarse layer
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        cp[q][sl] += iso.rw[cb][0] * tB[q];
-                        cp[q][sl + 1] += iso.rw[cb][1] * tB[q];
+                for (int s = 0; s < NKL; ++s) dvl[s] = T(0);
+                T lo[3][3], hi[3][3], zb[3][3];
+                derive(0, lo);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    derive(c + 1, hi);
+                    const T r1[3] = {gt[0] * s1[c], gt[1] * s1[c], gt[2] * s1[c]};
+                    const T r2[3] = {gt[3] * s1[c], gt[4] * s1[c], gt[5] * s1[c]};
+                    const T V = vr[c] * gt[9];
+                    // velocity gradient at q_c: du_r/dx_a = A_r rho1~_a + B_r rho2~_a + C_r rho3'_a
+                    T L[3][3];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const T Ar = lo[0][r] + hi[0][r];
+                        const T Br = lo[1][r] + hi[1][r];
+                        const T Cr = hi[2][r] - lo[2][r];
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) L[r][x] = Ar * r1[x] + Br * r2[x] + Cr * r3[x];
                     }
+                    const T tr = L[0][0] + L[1][1] + L[2][2];
+                    if (DO_B) {
+                        // -V div u, split onto the two coarse layers of the cell
+                        const T dv = -V * tr;
+                        const int cb = (kl0 + c) & 1;
+                        const int sl = ((kl0 + c) >> 1) - (kl0 >> 1);
+                        dvl[sl] += iso.rw[cb][0] * dv;
+                        dvl[sl + 1] += iso.rw[cb][1] * dv;
+                    }
+                    T za[3][3];   // Z_m = (V sigma) rho_m, rows m = 1, 2, 3
+                    if (DO_U) {
+                        T pbar = T(0);
+                        if (DO_BT) {
+                            const int cb = (kl0 + c) & 1;
+                            const int sl = ((kl0 + c) >> 1) - (kl0 >> 1);
+                            pbar = iso.rw[cb][0] * plat[sl] + iso.rw[cb][1] * plat[sl + 1];
+                        }
+                        T S[3][3];
+                        if (DO_A) {
+                            const T e1 = rin.eta[c][t] * V;
+                            const T e2 = e1 + e1;
+                            const T qd = e2 * tr * T(1.0 / 3.0) + (DO_BT ? V * pbar : T(0));
+                            S[0][0] = e2 * L[0][0] - qd;
+                            S[1][1] = e2 * L[1][1] - qd;
+                            S[2][2] = e2 * L[2][2] - qd;
+                            S[0][1] = S[1][0] = e1 * (L[0][1] + L[1][0]);
+                            S[0][2] = S[2][0] = e1 * (L[0][2] + L[2][0]);
+                            S[1][2] = S[2][1] = e1 * (L[1][2] + L[2][1]);
+                        } else {
+                            const T qd = V * pbar;
+#pragma unroll
+                            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                                for (int x = 0; x < 3; ++x) S[r][x] = (r == x) ? -qd : T(0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            za[0][r] = S[r][0] * r1[0] + S[r][1] * r1[1] + S[r][2] * r1[2];
+                            za[1][r] = S[r][0] * r2[0] + S[r][1] * r2[1] + S[r][2] * r2[2];
+                            za[2][r] = S[r][0] * r3[0] + S[r][1] * r3[1] + S[r][2] * r3[2];
+                        }
+                        // nodal values of layer c: test functions of the wedge above
+                        // (g' = (-1,-1,-1), (1,0,-1), (0,1,-1)) and, from c = 1 on,
+                        // of the wedge below (g' = (-1,-1,1), (1,0,1), (0,1,1))
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            T P1 = za[0][r], P2 = za[1][r], Q = -za[2][r];
+                            if (c > 0) {
+                                P1 += zb[0][r];
+                                P2 += zb[1][r];
+                                Q += zb[2][r];
+                            }
+                            const T N0 = Q - (P1 + P2), N1 = P1 + Q, N2 = P2 + Q;
+                            if (t == 0) {
+                                Rc[0][c][r] += N0;
+                                Rc[1][c][r] += N1;
+                                Rn[0][c][r] += N2;
+                            } else {
+                                Rn[1][c][r] += N0;
+                                Rn[0][c][r] += N1;
+                                Rc[1][c][r] += N2;
+                            }
+                        }
+#pragma unroll
+                        for (int x = 0; x < 3; ++x)
+#pragma unroll
+                            for (int r = 0; r < 3; ++r) zb[x][r] = za[x][r];
+                    }
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) lo[x][r] = hi[x][r];
+                }
+                if (DO_B) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int s = 0; s < NKL; ++s) cp[q][s] += iso.lw[ab][bb][t][q] * dvl[s];
+                }
+                if (DO_U) {
+                    // top layer of the lane: the wedge below only
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const T z12 = zb[0][r] + zb[1][r];
+                        const T N0 = zb[2][r] - z12, N1 = zb[0][r] + zb[2][r], N2 = zb[1][r] + zb[2][r];
+                        if (t == 0) {
+                            top[0][r] = N0;
+                            top[1][r] = N1;
+                            top[2][r] = N2;
+                        } else {
+                            top[3][r] = N0;
+                            top[2][r] += N1;
+                            top[1][r] += N2;
+                        }
+                    }
+                }
+            }
+            if (DO_U) {
+                // radial: the top partial of the lane below completes this lane's
+                // bottom layer; the top layer itself is kept for the chunk's top node
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    Rc[0][0][r] += wave_shift<DPP_WAVE_SHR1>(top[0][r]);
+                    Rc[1][0][r] += wave_shift<DPP_WAVE_SHR1>(top[1][r]);
+                    Rn[0][0][r] += wave_shift<DPP_WAVE_SHR1>(top[2][r]);
+                    Rn[1][0][r] += wave_shift<DPP_WAVE_SHR1>(top[3][r]);
+                    Rc[0][CPL][r] += top[0][r];
+                    Rc[1][CPL][r] += top[1][r];
+                    Rn[0][CPL][r] += top[2][r];
+                    Rn[1][CPL][r] += top[3][r];
                 }
             }
         }
         if (DO_U) {
-            // radial: the top partial of the lane below completes this lane's bottom node
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const T t = shfl_up1(Nd[q][CPL][r], lane);
-                    if (lane > 0) Nd[q][0][r] += t;
-                }
             // lateral: this wave's partial of node (i+1, j) goes to the wave on its right
 #pragma unroll
             for (int c = 0; c < NL; ++c)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) xch[par][w][r][c][lane] = R1[c][r] + Nd[1][c][r];
+                for (int r = 0; r < 3; ++r) xch[par][w][r][c][lane] = Rc[1][c][r];
         }
         if (DO_B && owned && row_cells) {
             // radial reduction of the coarse partials to one value per coarse layer
@@ -312,40 +496,34 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int s2 = 0; s2 < 2; ++s2) cp[q][s2] += __shfl(cp[q][s2], (lane + 1) & 63, 64);
+                    for (int s2 = 0; s2 < 2; ++s2) cp[q][s2] += wave_shift<DPP_WAVE_SHL1>(cp[q][s2]);
                 // the even lane's layer K'+1 part goes to the next even lane
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T t = __shfl(cp[q][1], (lane + 62) & 63, 64);
-                    const T top = cp[q][1];
+                    const T t = wave_shift<DPP_WAVE_SHR1>(wave_shift<DPP_WAVE_SHR1>(cp[q][1]));
                     if ((lane & 1) == 0) {
-                        const int Kl = lane >> 1;
-                        bsl[par][w][q][Kl] = cp[q][0] + (lane >= 2 ? t : T(0));
-                        if (lane == 62) bsl[par][w][q][32] = top;
+                        bsl[par][w + 2][q][lane >> 1] = cp[q][0] + t;
+                        if (lane == 62) bsl[par][w + 2][q][32] = cp[q][1];
                     }
                 }
             } else {
                 // lane l covers coarse layers CPL/2*l .. CPL/2*l + CPL/2
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T t = __shfl(cp[q][NKL - 1], (lane + 63) & 63, 64);
+                    const T t = wave_shift<DPP_WAVE_SHR1>(cp[q][NKL - 1]);
                     const int Kb = (CPL / 2) * lane;
 #pragma unroll
-                    for (int s2 = 0; s2 < NKL - 1; ++s2) {
-                        T v = cp[q][s2];
-                        if (s2 == 0 && lane > 0) v += t;
-                        bsl[par][w][q][Kb + s2] = v;
-                    }
-                    if (lane == 63) bsl[par][w][q][Kb + NKL - 1] = cp[q][NKL - 1];
+                    for (int s2 = 0; s2 < NKL - 1; ++s2) bsl[par][w + 2][q][Kb + s2] = s2 == 0 ? cp[q][0] + t : cp[q][s2];
+                    if (lane == 63) bsl[par][w + 2][q][Kb + NKL - 1] = cp[q][NKL - 1];
                 }
             }
         }
+        if (LOAD_U && pre) __builtin_amdgcn_s_waitcnt(0);   // row j+2 has landed in LDS
         __syncthreads();
         if (DO_U && owned) {
             const unsigned rowA = colA + (unsigned)j * ldj;
             const unsigned rowB = colB + (unsigned)j * ldj;
             const bool seamL = (w == 0) && (i0 > 0);
-            const bool right = (w == TI - 1);
             const bool seamR = (i0 + TI < m);
 #pragma unroll
             for (int c = 0; c < NL; ++c) {
@@ -354,7 +532,7 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                 if (top_lane && c == top_c) {
                     live = true;
                     seamK = kend < n;                   // chunk top: the next chunk adds the rest
-                } else if (c < CPL && cell_ok[c]) {
+                } else if (c < CPL && k < kend) {
                     live = true;
                     seamK = (c == 0 && lane == 0 && k0 > 0);   // chunk bottom
                 }
@@ -363,7 +541,7 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                 T v[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    v[r] = R0[c][r] + Nd[0][c][r];
+                    v[r] = Rc[0][c][r];
                     if (w > 0) v[r] += xch[par][w - 1][r][c][lane];
                 }
                 const bool seam = seamL || seamK;
@@ -371,95 +549,59 @@ __global__ void __launch_bounds__(TI_MAX * 64) stokes_band_kernel(BandArgs<T> a)
                 emit(a.y0, oa, v[0], seam);
                 emit(a.y1, oa, v[1], seam);
                 emit(a.y2, oa, v[2], seam);
-                if (right) {
+                if (xw) {
                     // node column i0 + TI: complete only on the diamond edge
                     const bool s2 = seamR || seamK;
                     const unsigned ob = rowB + (unsigned)k;
-                    emit(a.y0, ob, xch[par][w][0][c][lane], s2);
-                    emit(a.y1, ob, xch[par][w][1][c][lane], s2);
-                    emit(a.y2, ob, xch[par][w][2][c][lane], s2);
+                    emit(a.y0, ob, Rc[1][c][0], s2);
+                    emit(a.y1, ob, Rc[1][c][1], s2);
+                    emit(a.y2, ob, Rc[1][c][2], s2);
                 }
             }
-        }
-        if (DO_U) {
-#pragma unroll
-            for (int c = 0; c < NL; ++c)
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    R0[c][r] = Nd[2][c][r];
-                    R1[c][r] = Nd[3][c][r];
-                }
         }
         if (DO_B && owned && row_cells) {
             // owner threads add the (up to four) waves touching each coarse node, in
             // a fixed order, into the open rows J (corners 0, 1) and J+1 (corners 2, 3)
+            if (owner) {
 #pragma unroll
-            for (int o = 0; o < NOWN; ++o) {
-                const int idx = threadIdx.x + o * TI * 64;
-                if (idx < ncoarse) {
-                    const int il = idx / NKC, kl = idx % NKC;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int ws = 2 * (il - (q & 1));   // waves whose coarse column is il - (q&1)
-                        T v = T(0);
-                        if (ws >= 0 && ws < TI) v += bsl[par][ws][q][kl];
-                        if (ws + 1 >= 0 && ws + 1 < TI) v += bsl[par][ws + 1][q][kl];
-                        if (q < 2) pacc0[o] += v; else pacc1[o] += v;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    // waves 2 (il - (q&1)) and the next one, in slots shifted by two
+                    const int ws = 2 * (il - (q & 1)) + 2;
+                    const T v = bsl[par][ws][q][kl] + bsl[par][ws + 1][q][kl];
+                    if (q < 2) pacc0 += v; else pacc1 += v;
                 }
             }
             if (j & 1) {
                 // coarse row J has received all of this band's cells
                 const bool rowseam = (J == (j0 >> 1) && j0 > 0);
-#pragma unroll
-                for (int o = 0; o < NOWN; ++o) {
-                    const int idx = threadIdx.x + o * TI * 64;
-                    if (idx < ncoarse) {
-                        const int il = idx / NKC, kl = idx % NKC;
-                        const int Ig = I0 + il, Kg = K0 + kl;
-                        if (Ig <= mc && Kg <= nc && kl <= (kend - k0) / 2) {
-                            const bool seam = rowseam || (il == 0 && I0 > 0) ||
-                                              (il == TI / 2 && Ig < mc) ||
-                                              (kl == 0 && K0 > 0) || (Kg < nc && kl == (kend - k0) / 2);
-                            emit(a.yp, pcol + (unsigned)Ig * pldi + (unsigned)J * pldj + (unsigned)Kg,
-                                 pacc0[o], seam);
-                        }
-                    }
-                    pacc0[o] = pacc1[o];
-                    pacc1[o] = T(0);
-                }
+                if (own_ok) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, rowseam || own_seam);
+                pacc0 = pacc1;
+                pacc1 = T(0);
             }
         }
         if (pre) {
+            const int s = sj;
+            sj = sj1;
+            sj1 = sj2;
+            sj2 = s;
+        }
+    };
+    T Rs[2][NL][3];
+    RowIn rin2;
+    for (int j = jfirst; j <= jlast; ++j) {
+        step(j, Rc, Rs, rin, rin2);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int c = 0; c < NL; ++c)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    uA[c][r] = uC[c][r];
-                    uB[c][r] = uD[c][r];
-                    uC[c][r] = uE[c][r];
-                    uD[c][r] = uF[c][r];
-                }
-            rin = rnext;
-        }
+                for (int r = 0; r < 3; ++r) Rc[q][c][r] = Rs[q][c][r];
+        rin = rin2;
     }
     if (DO_B) {
         // the coarse row above the band's last cell row: complete only on the last band
         const int J = (jlast_cell >> 1) + 1;
-#pragma unroll
-        for (int o = 0; o < NOWN; ++o) {
-            const int idx = threadIdx.x + o * TI * 64;
-            if (idx < ncoarse) {
-                const int il = idx / NKC, kl = idx % NKC;
-                const int Ig = I0 + il, Kg = K0 + kl;
-                if (Ig <= mc && Kg <= nc && J <= mc && kl <= (kend - k0) / 2) {
-                    const bool seam = !last_band || (il == 0 && I0 > 0) || (il == TI / 2 && Ig < mc) ||
-                                      (kl == 0 && K0 > 0) || (Kg < nc && kl == (kend - k0) / 2);
-                    emit(a.yp, pcol + (unsigned)Ig * pldi + (unsigned)J * pldj + (unsigned)Kg, pacc0[o],
-                         seam);
-                }
-            }
-        }
+        if (own_ok && J <= mc) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, !last_band || own_seam);
     }
 }
 
@@ -547,7 +689,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.geo = is64 ? reinterpret_cast<const T*>(L.geo64.p) : reinterpret_cast<const T*>(L.geo32.p);
     a.m = L.m;
     a.n = L.n;
-    a.TI = std::min(TI_MAX, L.m);
+    a.TI = std::min(TIC, L.m);
     a.TJ = std::min(16, L.m);
     // cells per lane: enough for the whole radial column within the register
     // budget (two or more FP64 cells per lane spill), longer columns are split
@@ -556,6 +698,9 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     const int cpl_max = is64 ? 1 : 2;
     cpl = cpl <= 1 ? 1 : (cpl <= 2 ? 2 : 4);
     if (cpl > cpl_max) cpl = cpl_max;
+    // two cells per lane need at least four columns per workgroup, so that
+    // every coarse node of the divergence has one owner thread
+    if (a.TI < 4) cpl = 1;
     a.KC = 64 * cpl;
     a.ntile = L.m / a.TI;
     a.nband = L.m / a.TJ;
@@ -578,14 +723,10 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         }
     }
     const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0);
-    if constexpr (std::is_same<T, double>::value) {
+    if (cpl == 1)
         launch_band_ops<T, 1>(ctx, a, key);
-    } else {
-        if (cpl == 1)
-            launch_band_ops<T, 1>(ctx, a, key);
-        else
-            launch_band_ops<T, 2>(ctx, a, key);
-    }
+    else if constexpr (!std::is_same<T, double>::value)
+        launch_band_ops<T, 2>(ctx, a, key);
     const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
     if (doA || doBT) {
         void* f[3] = {yu[0], yu[1], yu[2]};

@@ -52,6 +52,13 @@ void clear_last_error();
         return TNG_E_INVAL;                                                           \
     }
 
+// Device bytes allocated by the calling thread through DevBuf, in whole
+// 4 KiB pages; differences around a piece of set-up charge exactly what that
+// set-up allocated, whatever other threads do meanwhile.
+inline thread_local long long tl_device_bytes = 0;
+
+inline long long devbuf_pages(size_t bytes) { return (long long)((bytes + 4095) & ~size_t(4095)); }
+
 // Owning device buffer.
 template <class T>
 struct DevBuf {
@@ -76,9 +83,13 @@ struct DevBuf {
             throw Error(TNG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
         }
         n = count;
+        tl_device_bytes += devbuf_pages(count * sizeof(T));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            tl_device_bytes -= devbuf_pages(n * sizeof(T));
+        }
         p = nullptr;
         n = 0;
     }
@@ -188,3 +199,4 @@ class ScopedKernelTimer {
 };
 
 }  // namespace tng
+

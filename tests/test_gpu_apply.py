@@ -1,4 +1,4 @@
-"""Parity of the HIP Stokes apply (a3-a5) with the assembled FP64 oracle.
+"""Parity of the HIP Stokes apply with the assembled FP64 oracle.
 
 Tolerances (relative 2-norm per block over unique DoFs): 1e-12 for FP64,
 1e-5 for FP32 (the FP32 path is fed the FP64 inputs rounded to FP32 and is

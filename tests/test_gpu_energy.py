@@ -1,5 +1,5 @@
-"""GPU parity of the buoyancy right-hand side (a13), the SUPG energy operator
-and the coupled time step (a14) with the FP64 oracle."""
+"""GPU parity of the buoyancy right-hand side, the SUPG energy operator
+and the coupled time step with the FP64 oracle."""
 import math
 
 import numpy as np

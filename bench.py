@@ -47,6 +47,36 @@ def unique_dofs(mt, nr):
     return 3 * (10 * mt * mt + 2) * (nr + 1), (10 * (mt // 2) ** 2 + 2) * (nr // 2 + 1)
 
 
+COUNTERS_MD = os.path.join(ROOT, "profiles", "stokes_apply_shell128_hbm_counters.md")
+
+
+def kernel_sources_digest():
+    """Digest of the apply kernel's sources and build flags (what the committed
+    HBM counters were measured with)."""
+    import hashlib
+    from paper_2609_21633_amd import build
+    h = hashlib.sha256()
+    for rel in ("paper_2609_21633_amd/csrc/stokes_apply.hip", "paper_2609_21633_amd/csrc/wedge.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    flags = [c for c in build.hipcc_command("x") if c.startswith("-") and not c.startswith("-I") and c != "-o"]
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel has changed since the counters were taken."""
+    try:
+        with open(COUNTERS_MD) as f:
+            kv = dict(l.strip().split(": ", 1) for l in f if ": " in l and l.strip().split(":")[0].isidentifier())
+    except OSError:
+        return None
+    if kv.get("sources") != kernel_sources_digest() or key not in kv:
+        return None
+    return float(kv[key])
+
+
 def algorithmic_bytes(mesh, esize):
     """Minimal traffic of one K apply: read u and write y_u (3 node fields
     each), read two wedge viscosities per cell, read p and write y_p."""
@@ -236,6 +266,9 @@ def main():
         torch.cuda.synchronize()
         del x, y
     head = res["f32"]
+    # measured HBM traffic (scaled rocprofv3 counters) only for the (128,128) shell they were taken on
+    t32 = counter_traffic("f32_traffic_bytes_per_launch") if (mt, nr) == (128, 128) else None
+    t64 = counter_traffic("f64_traffic_bytes_per_launch") if (mt, nr) == (128, 128) else None
     out = {
         "metric": "GDoF/s Stokes apply FP32 vs FP64 at 1e-8 solve tol; solves/s, p50/p99 latency",
         "value": round(head["gdofs"], 3),
@@ -254,11 +287,14 @@ def main():
                                 "T = conduction + spherical harmonics l=1..8"),
                    "u_dofs": nu, "p_dofs": npr},
         "roofline": {"bound": "hbm", "achieved": round(head["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None if t32 is None else round(t32 / (head["kernel_ms"] * 1e6), 1),
+                     "traffic_bytes_per_launch": t32,
                      "kernel": "stokes_band_kernel<float,2,A,BT,B>",
                      "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": round(head["kernel_ms"], 4)},
         "f64_apply": {"gdofs": round(res["f64"]["gdofs"], 3), "ms": round(res["f64"]["ms"], 4),
                       "kernel_gbs": round(res["f64"]["kernel_gbs"], 1),
+                      "traffic_gbs": None if t64 is None else round(t64 / (res["f64"]["kernel_ms"] * 1e6), 1),
                       "kernel_ms": round(res["f64"]["kernel_ms"], 4)},
     }
     if not args.no_solve:
@@ -279,7 +315,7 @@ def main():
                       "refinement_steps": s32["outer_its"], "rel_res": s32["rel_res"], "rc": s32["rc"]},
             "mixed_over_fp64": round(s64["wall"] / s32["wall"], 3),
             "mixed_vs_fp64_rel_err": {"u": du, "p": dp},
-            "mixed_over_fp64_c1_field": round(s1["wall"] / s32["wall"], 3)}
+            "mixed_1e6_over_fp64_solve_at_contrast_1e3": round(s1["wall"] / s32["wall"], 3)}
         log(f"[bench] {out['solve_contrast_1e6']}")
         del u64, p64, u32, p32
         torch.cuda.empty_cache()

@@ -24,14 +24,15 @@ from __future__ import annotations
 import numpy as np
 
 from .mesh import ShellMesh
-from .stokes import element_divergence, element_matrices
+from .stokes import element_divergence, element_matrices_hg
 
 
 class StokesRows:
     """Row evaluator of K_D on ``mesh`` (velocity level) with pressure on level - 1."""
 
-    def __init__(self, mesh: ShellMesh):
+    def __init__(self, mesh: ShellMesh, hg_alpha: float = 0.0):
         self.mesh = m = mesh
+        self.hg_alpha = hg_alpha
         if m.nr % 2:
             raise ValueError("nr must be even")
         self.nrc = m.nr // 2
@@ -133,7 +134,7 @@ class StokesRows:
             return u[node].astype(np.float64).copy(), np.abs(u[node]).astype(np.float64)
         lat, k = divmod(int(node), self.mesh.nr + 1)
         w, wn, xw, loc = self._element_terms(lat, k, eta_of)
-        A = element_matrices(xw, eta_of(w))                   # [n, 18, 18]
+        A = element_matrices_hg(xw, eta_of(w), self.hg_alpha)  # [n, 18, 18]
         Bf = element_divergence(xw)                           # [n, 6, 18]
         ue = u[wn].astype(np.float64)                          # [n, 6, 3]
         ue[self.boundary(wn)] = 0.0                            # Dirichlet columns

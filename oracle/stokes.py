@@ -90,6 +90,40 @@ def element_matrices(xw: np.ndarray, eta: np.ndarray):
     return A
 
 
+def hourglass_vectors():
+    """Nodal values of the three barycentric hourglass modes h_a = (lambda_a - 1/3) zeta,
+    a = 0, 1, 2, of the reference wedge (eq:hourglass: w_1 = h_1, w_2 = h_2 and
+    h_0 = -h_1 - h_2).  Returns [3, 6] (nodes 0-2 at zeta = -1, 3-5 at zeta = +1)."""
+    h = np.empty((3, 6))
+    for a in range(3):
+        for j in range(6):
+            lam = 1.0 if j % 3 == a else 0.0
+            zeta = -1.0 if j < 3 else 1.0
+            h[a, j] = (lam - 1.0 / 3.0) * zeta
+    return h
+
+
+def element_matrices_hg(xw: np.ndarray, eta: np.ndarray, alpha: float):
+    """One-point element matrices with hourglass control (eq:hgstab), [n, 18, 18].
+
+    A_e^stab = A_e + eps_e sum_a sum_d (h_a (x) e_d)(h_a (x) e_d)^T, with eps_e =
+    alpha * mean(diag A_e) (a small parameter scaled with the local stiffness).
+    The sum runs over all three barycentric hourglass modes h_a, which span the
+    same space as w_1, w_2 and make the term independent of which lateral vertex
+    a wedge numbers first.
+    """
+    A = element_matrices(xw, eta)
+    if alpha == 0.0:
+        return A
+    eps = alpha * np.einsum("wii->w", A) / 18.0
+    h = hourglass_vectors()
+    W = np.zeros((18, 9))                      # columns h_a (x) e_d
+    for a in range(3):
+        for d in range(3):
+            W[d::3, 3 * a + d] = h[a]
+    return A + eps[:, None, None] * (W @ W.T)[None, :, :]
+
+
 def element_divergence(xw: np.ndarray):
     """B_f per wedge, [n, 6, 18]: (B_f)_{i,a} = -V_e N_i(q_c) div(phi_a) at q_c."""
     N, _ = ref_basis(*QC)
@@ -99,11 +133,12 @@ def element_divergence(xw: np.ndarray):
 
 
 class StokesOracle:
-    """Assembled FP64 Stokes saddle-point operator on the (mt, nr) shell."""
+    """Assembled FP64 Stokes saddle-point operator on the (mt, nr) shell
+    (hg_alpha > 0: viscous block with hourglass control, eq:hgstab)."""
 
     def __init__(self, mt: int, nr: int, eta_wedge: np.ndarray, r_in: float = 0.55,
                  r_out: float = 1.0, hierarchy: SphereHierarchy | None = None,
-                 chunk: int = 200_000):
+                 chunk: int = 200_000, hg_alpha: float = 0.0):
         self.mesh = m = ShellMesh(mt, nr, r_in, r_out, hierarchy)
         self.mt, self.nr = mt, nr
         eta_wedge = np.asarray(eta_wedge, dtype=np.float64)
@@ -118,7 +153,7 @@ class StokesOracle:
             w = wn[s:s + chunk]
             xw = xyz[w]
             dof = (w[:, :, None] * 3 + np.arange(3)[None, None, :]).reshape(len(w), 18)
-            Ae = element_matrices(xw, eta_wedge[s:s + chunk])
+            Ae = element_matrices_hg(xw, eta_wedge[s:s + chunk], hg_alpha)
             rows = np.repeat(dof, 18, axis=1).ravel()
             cols = np.tile(dof, (1, 18)).ravel()
             A = A + sp.csr_matrix((Ae.ravel(), (rows, cols)), shape=(nu, nu))

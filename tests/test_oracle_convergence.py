@@ -41,14 +41,14 @@ def _fields(stokes: bool):
     return lam(u), lam(f), lam(eta), lam(p)
 
 
-def _discrete(mt, fu, ff, fe):
+def _discrete(mt, fu, ff, fe, hg_alpha=0.0):
     m = ShellMesh(mt, mt, R_IN, R_OUT)
     xyz = m.node_xyz()
     wn = m.wedge_nodes()
     xw = xyz[wn]
     N, _ = ref_basis(*QC)
     xq = np.einsum("j,wja->wa", N, xw)                   # x(q_c) of each wedge
-    o = StokesOracle(mt, mt, fe(*xq.T), R_IN, R_OUT)
+    o = StokesOracle(mt, mt, fe(*xq.T), R_IN, R_OUT, hg_alpha=hg_alpha)
     _, V, _ = wedge_geometry(xw)
     fq = np.array(ff(*xq.T)).T
     F = np.zeros((m.n_nodes, 3))
@@ -59,22 +59,25 @@ def _discrete(mt, fu, ff, fe):
 
 
 @pytest.mark.slow
-def test_viscous_block_second_order():
+@pytest.mark.parametrize("hg_alpha", [0.0, 0.05])
+def test_viscous_block_second_order(hg_alpha):
+    """Also with hourglass control (eq:hgstab): the error keeps the optimal order."""
     fu, ff, fe, _ = _fields(stokes=False)
     errs = []
     for mt in (4, 8):
-        m, o, F, ue = _discrete(mt, fu, ff, fe)
+        m, o, F, ue = _discrete(mt, fu, ff, fe, hg_alpha)
         uh = spla.spsolve(o.A_D.tocsc(), F.ravel()).reshape(-1, 3)
         errs.append(np.sqrt(np.mean((uh - ue) ** 2)))
     assert errs[0] / errs[1] > 3.4, errs
 
 
 @pytest.mark.slow
-def test_stokes_second_order_velocity_and_pressure():
+@pytest.mark.parametrize("hg_alpha", [0.0, 0.05])
+def test_stokes_second_order_velocity_and_pressure(hg_alpha):
     fu, ff, fe, fp = _fields(stokes=True)
     eu, ep = [], []
     for mt in (4, 8):
-        m, o, F, ue = _discrete(mt, fu, ff, fe)
+        m, o, F, ue = _discrete(mt, fu, ff, fe, hg_alpha)
         uh, ph = o.solve(F)
         pc = fp(*ShellMesh(mt // 2, mt // 2, R_IN, R_OUT).node_xyz().T)
         pc = pc - pc.mean()

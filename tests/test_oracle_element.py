@@ -195,3 +195,71 @@ def test_two_wedge_hex_symmetric_psd():
     ev = np.linalg.eigvalsh(K)
     assert np.allclose(K, K.T)
     assert ev.min() > -1e-12 * ev.max()
+
+
+# ---- hourglass control (eq:hgstab) ------------------------------------------------
+
+def _hg_vec(h, d):
+    v = np.zeros(18)
+    v[d::3] = h
+    return v
+
+
+def test_hourglass_vectors_match_eq_hourglass():
+    """h_1, h_2 are the nodal values of w_1, w_2 (golden file); h_0 = -h_1 - h_2."""
+    from oracle.stokes import hourglass_vectors
+    hg = _hourglass()
+    h = hourglass_vectors()
+    w = list(hg.values())
+    assert np.allclose(h[1], w[0]) and np.allclose(h[2], w[1])
+    assert np.allclose(h.sum(axis=0), 0.0)
+
+
+def test_hourglass_control_lifts_exactly_the_hourglass_modes():
+    """A_e^stab = A_e + eps H: the six hourglass modes become eigenvectors with
+    eigenvalue 2 eps (H h_a = 2 h_a, from h_a . h_b = 2 (delta_ab - 1/3) and
+    sum_a h_a = 0), with eps = alpha mean(diag A_e); translations stay in the
+    null space.  On a curved wedge (x = r(zeta) s(xi, eta) has xi zeta and
+    eta zeta parts) rotations and the dilation carry hourglass components, so
+    what stays null is their part orthogonal to the hourglass span: the null
+    space keeps dimension 7 and the rank goes from 5 to 11."""
+    from oracle.stokes import element_matrices_hg, hourglass_vectors
+    xw = _mesh_wedges()
+    eta = np.linspace(0.5, 3.0, len(xw))
+    alpha = 0.05
+    A0 = element_matrices(xw, eta)
+    A1 = element_matrices_hg(xw, eta, alpha)
+    h = hourglass_vectors()
+    for a0, a1, x in zip(A0, A1, xw):
+        eps = alpha * np.trace(a0) / 18.0
+        for a in range(3):
+            for d in range(3):
+                v = _hg_vec(h[a], d)
+                assert np.abs(a1 @ v - 2 * eps * v).max() < 1e-13 * np.abs(a1).max()
+        W = np.stack([_hg_vec(h[a], d) for a in range(3) for d in range(3)], axis=1)
+        Q, _ = np.linalg.qr(W)
+        Q = Q[:, :6]                                      # orthonormal basis of the hourglass span
+        modes = [np.tile(e, 6) for e in np.eye(3)]
+        modes += [(v - Q @ (Q.T @ v)) for v in [np.cross(wv, x).ravel() for wv in np.eye(3)] + [x.ravel()]]
+        for v in modes:
+            assert np.abs(a1 @ v).max() < 1e-12 * np.abs(a1).max() * np.abs(v).max()
+        ev = np.linalg.eigvalsh(a1)
+        assert ev.min() > -1e-12 * ev.max()
+        assert np.sum(ev > 1e-10 * ev.max()) == 11
+        assert np.allclose(a1, a1.T, atol=1e-14 * np.abs(a1).max())
+
+
+def test_hourglass_control_independent_of_vertex_numbering():
+    """Renumbering the lateral vertices of a wedge (cyclically or by a swap, the
+    same on both faces) permutes A_e^stab accordingly: the term does not depend
+    on which vertex a wedge calls 0."""
+    from oracle.stokes import element_matrices_hg
+    xw = _mesh_wedges(n=4)
+    eta = np.full(len(xw), 1.7)
+    for perm in ((1, 2, 0), (0, 2, 1), (2, 1, 0)):
+        node = list(perm) + [p + 3 for p in perm]
+        dof = np.array([3 * j + c for j in node for c in range(3)])
+        A = element_matrices_hg(xw, eta, 0.08)
+        B = element_matrices_hg(xw[:, node, :], eta, 0.08)
+        for a, b in zip(A, B):
+            assert np.abs(a[np.ix_(dof, dof)] - b).max() < 1e-13 * np.abs(a).max()

@@ -130,9 +130,15 @@ int tng_mesh_destroy(tng_mesh* mesh);
  * y_p: device pressure out (required if TNG_OP_B).  Outputs are overwritten
  * (not accumulated) and are assembled: every copy of a duplicate node holds
  * the full sum.  With TNG_OP_DIRICHLET the velocity input is read as zero on
- * both spheres and y_u = u there.  Inputs and outputs must not alias. */
+ * both spheres and y_u = u there.  Inputs and outputs must not alias.
+ * hg_alpha: hourglass control of the viscous block (Sec. 4, eq:hgstab), 0 for
+ *   the plain one-point operator.  With alpha > 0 every wedge adds
+ *   eps_e sum_a sum_d (h_a (x) e_d)(h_a (x) e_d)^T to A_e, summed over the three
+ *   barycentric hourglass modes h_a = (lambda_a - 1/3) zeta (span of w_1, w_2,
+ *   independent of the wedge's vertex numbering), eps_e = alpha mean(diag A_e).
+ *   Must be finite and >= 0 (TNG_E_INVAL otherwise). */
 int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec,
-                     unsigned op_flags, const void* eta_wedge,
+                     unsigned op_flags, double hg_alpha, const void* eta_wedge,
                      const void* const u[3], const void* p,
                      void* const y_u[3], void* y_p);
 
@@ -153,9 +159,10 @@ int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec
 /* ---- multigrid pieces (Sec. 7) ------------------------------------------ */
 /* Diagonal of K_D's viscous block on `level`: diag_(node,c) = sum over the
  * node's wedges of V eta (|grad phi|^2 + (d_c phi)^2 / 3) (eq:elemmat, one
- * point), 1 on Dirichlet rows.  diag[3]: device velocity field out. */
+ * point), plus 2/3 eps_e per wedge with hourglass control (hg_alpha as in
+ * tng_stokes_apply), 1 on Dirichlet rows.  diag[3]: device velocity field out. */
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
-               void* const diag[3]);
+               double hg_alpha, void* const diag[3]);
 /* Row-sum lumped inverse-viscosity pressure mass of eq:pmass on the pressure
  * level of `level` (i.e. level + 1): m_I = sum_e (V_e / eta_e) psi_I(q_c^e).
  * mass: device node field of level + 1 out.  The Schur preconditioner is
@@ -164,12 +171,12 @@ int tng_pressure_mass(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
                       void* mass);
 /* Chebyshev smoother: `steps` applications of x <- x + p(D^{-1} A)(b - A x),
  * p the degree-`degree` Chebyshev polynomial for the eigenvalue interval
- * [lmin, lmax] of D^{-1} A (A with Dirichlet rows, D = diag).  diag: the
- * diagonal as returned by tng_diag_A.  x is updated in place.  Allocates
- * scratch and synchronises. */
+ * [lmin, lmax] of D^{-1} A (A with Dirichlet rows and hourglass control
+ * hg_alpha, D = diag).  diag: the diagonal as returned by tng_diag_A.  x is
+ * updated in place.  Allocates scratch and synchronises. */
 int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
-               const void* const diag[3], const void* const b[3], void* const x[3], int degree, int steps,
-               double lmin, double lmax);
+               double hg_alpha, const void* const diag[3], const void* const b[3], void* const x[3], int degree,
+               int steps, double lmin, double lmax);
 /* W1 transfer between fine_level and fine_level + 1 (index-space
  * interpolation: coarse nodes copied, edge midpoints and odd layers averaged).
  * Restriction c = P^T f with Dirichlet layers of c set to zero; prolongation
@@ -194,7 +201,9 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  * levels: multigrid levels used (0 = all levels of the mesh); the coarsest
  *   one is solved exactly and must have at most 1024 interior DoFs.
  * inner_rtol, inner_max_iters, max_outer: mixed-precision inner tolerance and
- *   iteration limit per refinement step, and the refinement step limit. */
+ *   iteration limit per refinement step, and the refinement step limit.
+ * hg_alpha: hourglass control (eq:hgstab, see tng_stokes_apply) of the viscous
+ *   block on every level: the solve is then of that stabilised operator. */
 typedef struct {
     int mixed;
     int restart;
@@ -208,6 +217,7 @@ typedef struct {
     int inner_max_iters;
     int max_outer;
     int power_its;
+    double hg_alpha;
 } tng_solver_opts;
 
 /* outer_its: refinement steps (1 in FP64 mode); inner_its: FGMRES iterations

@@ -38,16 +38,16 @@ def lib():
         "tng_mesh_coords": [_vp, C.c_int, _vp, _vp],
         "tng_mesh_dup_groups": [_vp, C.c_int, _vp],
         "tng_mesh_destroy": [_vp],
-        "tng_stokes_apply": [_vp, _vp, C.c_int, C.c_int, C.c_uint, _vp, C.POINTER(_vp), _vp,
+        "tng_stokes_apply": [_vp, _vp, C.c_int, C.c_int, C.c_uint, C.c_double, _vp, C.POINTER(_vp), _vp,
                              C.POINTER(_vp), _vp],
         "tng_interface_sum": [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)],
         "tng_ctx_profile": [_vp, C.c_int],
         "tng_ctx_kernel_stats": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
         "tng_eta_from_temperature": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.c_double, _vp],
         "tng_eta_coarsen": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
-        "tng_diag_A": [_vp, _vp, C.c_int, C.c_int, _vp, C.POINTER(_vp)],
+        "tng_diag_A": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
         "tng_pressure_mass": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
-        "tng_smooth": [_vp, _vp, C.c_int, C.c_int, _vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+        "tng_smooth": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
                        C.c_int, C.c_int, C.c_double, C.c_double],
         "tng_restrict": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
         "tng_prolong": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
@@ -195,13 +195,15 @@ class Mesh:
             pass
 
 
-def stokes_apply(ctx: Context, mesh: Mesh, level: int, flags: int, eta, u, p, y_u, y_p):
+def stokes_apply(ctx: Context, mesh: Mesh, level: int, flags: int, eta, u, p, y_u, y_p,
+                 hg_alpha: float = 0.0):
     """y = K(eta) [u; p] on `level` (blocks selected by flags).  u, y_u: 3 node fields
     (a [3, ...] tensor or a list); p, y_p: pressure fields on level + 1; any of them
-    may be None when the selected blocks do not use it."""
+    may be None when the selected blocks do not use it.  hg_alpha > 0 adds hourglass
+    control to the viscous block."""
     ref = next(t for t in (u[0] if u is not None else None, y_u[0] if y_u is not None else None,
                            p, y_p) if t is not None)
-    check(lib().tng_stokes_apply(ctx.h, mesh.h, level, _prec(ref), flags, _ptr(eta), _ptr3(u),
+    check(lib().tng_stokes_apply(ctx.h, mesh.h, level, _prec(ref), flags, float(hg_alpha), _ptr(eta), _ptr3(u),
                                  _ptr(p), _ptr3(y_u), _ptr(y_p)))
 
 
@@ -221,9 +223,9 @@ def eta_coarsen(ctx: Context, mesh: Mesh, fine_level: int, eta_fine, eta_coarse)
                                 _ptr(eta_coarse)))
 
 
-def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag):
+def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag, hg_alpha: float = 0.0):
     """Diagonal of the viscous block (Dirichlet rows 1) into diag ([3, ...])."""
-    check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr3(diag)))
+    check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag)))
 
 
 def pressure_mass(ctx: Context, mesh: Mesh, level: int, eta, mass):
@@ -232,9 +234,9 @@ def pressure_mass(ctx: Context, mesh: Mesh, level: int, eta, mass):
 
 
 def smooth(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, steps: int,
-           lmin: float, lmax: float):
-    check(lib().tng_smooth(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr3(diag), _ptr3(b), _ptr3(x),
-                           degree, steps, lmin, lmax))
+           lmin: float, lmax: float, hg_alpha: float = 0.0):
+    check(lib().tng_smooth(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag), _ptr3(b),
+                           _ptr3(x), degree, steps, lmin, lmax))
 
 
 def restrict(ctx: Context, mesh: Mesh, fine_level: int, f, c):
@@ -249,7 +251,8 @@ class SolverOpts(C.Structure):
     _fields_ = [("mixed", C.c_int), ("restart", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double),
                 ("cheb_degree", C.c_int), ("pre", C.c_int), ("post", C.c_int), ("levels", C.c_int),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("inner_rtol", C.c_double),
-                ("inner_max_iters", C.c_int), ("max_outer", C.c_int), ("power_its", C.c_int)]
+                ("inner_max_iters", C.c_int), ("max_outer", C.c_int), ("power_its", C.c_int),
+                ("hg_alpha", C.c_double)]
 
 
 class SolveInfo(C.Structure):

@@ -58,8 +58,8 @@ using tng::Error;
 namespace tng {
 namespace {
 template <typename T>
-void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, const void* const diag[3], const void* const b[3],
-              void* const x[3], int degree, int steps, double lmin, double lmax) {
+void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, double hg_alpha, const void* const diag[3],
+              const void* const b[3], void* const x[3], int degree, int steps, double lmin, double lmax) {
     const long long ns = L.node_slots(), n3 = 3 * ns;
     tng::DevBuf<T> invd(n3), bb(n3), xx(n3), y(n3), d(n3);
     hipStream_t st = ctx->stream;
@@ -69,7 +69,8 @@ void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, const void* co
         TNG_HIP(hipMemcpyAsync(xx.p + c * ns, x[c], ns * sizeof(T), hipMemcpyDeviceToDevice, st));
     }
     tng::vec_invert<T>(ctx, n3, invd.p);
-    tng::chebyshev_steps<T>(ctx, L, (const T*)eta, invd.p, bb.p, xx.p, y.p, d.p, degree, steps, lmin, lmax, false);
+    tng::chebyshev_steps<T>(ctx, L, (const T*)eta, hg_alpha, invd.p, bb.p, xx.p, y.p, d.p, degree, steps, lmin, lmax,
+                            false);
     for (int c = 0; c < 3; ++c)
         TNG_HIP(hipMemcpyAsync(x[c], xx.p + c * ns, ns * sizeof(T), hipMemcpyDeviceToDevice, st));
     TNG_HIP(hipStreamSynchronize(st));   // scratch is freed on return
@@ -221,9 +222,10 @@ int tng_mesh_destroy(tng_mesh* mesh) {
 }
 
 int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec,
-                     unsigned op_flags, const void* eta_wedge, const void* const u[3],
+                     unsigned op_flags, double hg_alpha, const void* eta_wedge, const void* const u[3],
                      const void* p, void* const y_u[3], void* y_p) {
     TNG_API_BEGIN
+    TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE((op_flags & ~15u) == 0, "unknown op_flags bits");
@@ -245,7 +247,7 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     if ((op_flags & TNG_OP_DIRICHLET) && doA)
         TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
     TNG_HIP(hipSetDevice(ctx->device));
-    tng::launch_stokes_apply(ctx, L, Lp, prec, op_flags, eta_wedge, u, p, y_u, y_p);
+    tng::launch_stokes_apply(ctx, L, Lp, prec, op_flags, hg_alpha, eta_wedge, u, p, y_u, y_p);
     TNG_API_END
 }
 
@@ -299,7 +301,7 @@ int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
 }
 
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
-               void* const diag[3]) {
+               double hg_alpha, void* const diag[3]) {
     TNG_API_BEGIN
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
@@ -307,10 +309,10 @@ int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, con
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         double* d[3] = {(double*)diag[0], (double*)diag[1], (double*)diag[2]};
-        tng::mg_diag_A<double>(ctx, L, (const double*)eta_wedge, d);
+        tng::mg_diag_A<double>(ctx, L, (const double*)eta_wedge, hg_alpha, d);
     } else {
         float* d[3] = {(float*)diag[0], (float*)diag[1], (float*)diag[2]};
-        tng::mg_diag_A<float>(ctx, L, (const float*)eta_wedge, d);
+        tng::mg_diag_A<float>(ctx, L, (const float*)eta_wedge, hg_alpha, d);
     }
     TNG_API_END
 }
@@ -374,8 +376,8 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
 }
 
 int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
-               const void* const diag[3], const void* const b[3], void* const x[3], int degree, int steps,
-               double lmin, double lmax) {
+               double hg_alpha, const void* const diag[3], const void* const b[3], void* const x[3], int degree,
+               int steps, double lmin, double lmax) {
     TNG_API_BEGIN
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
@@ -385,9 +387,9 @@ int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, con
     TNG_REQUIRE(lmin > 0 && lmax > lmin, "need 0 < lmin < lmax");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64)
-        tng::smooth_t<double>(ctx, L, eta_wedge, diag, b, x, degree, steps, lmin, lmax);
+        tng::smooth_t<double>(ctx, L, eta_wedge, hg_alpha, diag, b, x, degree, steps, lmin, lmax);
     else
-        tng::smooth_t<float>(ctx, L, eta_wedge, diag, b, x, degree, steps, lmin, lmax);
+        tng::smooth_t<float>(ctx, L, eta_wedge, hg_alpha, diag, b, x, degree, steps, lmin, lmax);
     TNG_API_END
 }
 

@@ -36,7 +36,7 @@ struct CoarseDense {
 };
 
 template <typename T>
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, T* const d[3]);
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3]);
 template <typename T>
 void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag);
 template <typename T>
@@ -81,7 +81,7 @@ void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a);
 template <typename T>
 void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* x, T* y);
 template <typename T>
-void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta);
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha);
 
 struct EnergyWS;
 EnergyWS* energy_ws_create();
@@ -97,7 +97,7 @@ template <typename T>
 void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]);
 
 template <typename T>
-void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, const T* invd, const T* b, T* x, T* y,
-                     T* d, int deg, int steps, double lo, double hi, bool x_zero);
+void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
+                     T* x, T* y, T* d, int deg, int steps, double lo, double hi, bool x_zero);
 
 }  // namespace tng

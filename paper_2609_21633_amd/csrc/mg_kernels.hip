@@ -42,11 +42,22 @@ __device__ __forceinline__ void basis_grad(const double* g, double s1, int lat, 
     for (int x = 0; x < 3; ++x) out[x] = a * s1 * g[x] + b * s1 * g[3 + x] + c * g[6 + x];
 }
 
+// Hourglass-control scale of a wedge (eq:hgstab over the three barycentric
+// modes): eps_e = alpha mean(diag A_e) = alpha 5/27 eta V sum_j |grad phi_j|^2,
+// sum_j |grad phi_j|^2 = 4 (|rho1~|^2 + |rho2~|^2 + rho1~.rho2~) + 6 |rho3'|^2.
+__device__ __forceinline__ double hg_eps(const double* g, double s1, double V, double e, double alpha) {
+    const double a = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3] + g[4] * g[4] + g[5] * g[5] +
+                     g[0] * g[3] + g[1] * g[4] + g[2] * g[5];
+    const double b = g[6] * g[6] + g[7] * g[7] + g[8] * g[8];
+    return alpha * (5.0 / 27.0) * e * V * (4.0 * s1 * s1 * a + 6.0 * b);
+}
+
 // diag(A)_(node,c) = sum over the node's wedges of V eta (|grad phi|^2 + 1/3 (d_c phi)^2),
-// the diagonal of eq:elemmat with the one-point rule.  Per-diamond partial sums.
+// the diagonal of eq:elemmat with the one-point rule, plus 2/3 eps_e with hourglass
+// control (sum_a h_a[j]^2 = 2/3 for every node).  Per-diamond partial sums.
 template <typename T>
 __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restrict__ geo, int m, int n,
-                              double r_in, double dr, T* d0, T* d1, T* d2, long long nslots) {
+                              double r_in, double dr, double hg_alpha, T* d0, T* d1, T* d2, long long nslots) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const NodeIdx q = decode_node(t, m, n);
@@ -74,7 +85,8 @@ __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restric
                     const double V = rm * rm * g[9];
                     const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
                     const double nn = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-                    for (int c = 0; c < 3; ++c) acc[c] += V * e * (nn + gr[c] * gr[c] / 3.0);
+                    const double hg = hg_alpha != 0.0 ? (2.0 / 3.0) * hg_eps(g, s1, V, e, hg_alpha) : 0.0;
+                    for (int c = 0; c < 3; ++c) acc[c] += V * e * (nn + gr[c] * gr[c] / 3.0) + hg;
                 }
             }
         }
@@ -487,7 +499,7 @@ template <typename T>
 __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr, const int* __restrict__ copy_slot,
                                        const int* __restrict__ slot_dof, long long nslots, const T* __restrict__ eta,
                                        const double* __restrict__ geo, int m, int n, double r_in, double dr,
-                                       double* __restrict__ Ad) {
+                                       double hg_alpha, double* __restrict__ Ad) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= nd) return;
     for (int r = 0; r < nd; ++r) Ad[(long long)col * nd + r] = 0.0;
@@ -519,6 +531,7 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
                         const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
                         double gj[3];
                         basis_grad(g, s1, lat, top, gj);
+                        const double eps = hg_alpha != 0.0 ? hg_eps(g, s1, V, e, hg_alpha) : 0.0;
                         for (int l2 = 0; l2 < 6; ++l2) {
                             const int lat2 = l2 % 3, top2 = l2 / 3;
                             double gl[3];
@@ -530,8 +543,12 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
                                 const int row = slot_dof[d2 * nslots + s2];
                                 if (row < 0) continue;
                                 // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c - 2/3 (g_j)_c (g_l)_d]
-                                const double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
-                                                          (2.0 / 3.0) * gj[ccomp] * gl[d2]);
+                                double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
+                                                    (2.0 / 3.0) * gj[ccomp] * gl[d2]);
+                                // hourglass term: eps delta_cd zeta_j zeta_l (delta_{lat_j, lat_l} - 1/3)
+                                if (ccomp == d2)
+                                    v += eps * (top ? 1.0 : -1.0) * (top2 ? 1.0 : -1.0) *
+                                         ((lat == lat2 ? 1.0 : 0.0) - 1.0 / 3.0);
                                 Ad[(long long)col * nd + row] += v;
                             }
                         }
@@ -549,10 +566,10 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, T* const d[3]) {
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3]) {
     const long long ns = L.node_slots();
     diag_A_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(),
-                                                             d[0], d[1], d[2], ns);
+                                                             hg_alpha, d[0], d[1], d[2], ns);
     TNG_HIP(hipGetLastError());
     void* f[3] = {d[0], d[1], d[2]};
     launch_interface(ctx, L, prec_of<T>(), 0, 3, f);
@@ -664,10 +681,10 @@ void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* 
 }
 
 template <typename T>
-void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta) {
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha) {
     coarse_assemble_kernel<T><<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(
         cd.ndof, cd.copy_ptr.p, cd.copy_slot.p, cd.slot_dof.p, cd.nslots, eta, L.geo64.p, L.m, L.n, L.r_in,
-        L.dr(), cd.Ainv.p);
+        L.dr(), hg_alpha, cd.Ainv.p);
     TNG_HIP(hipGetLastError());
 }
 
@@ -725,7 +742,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 }
 
 #define TNG_INST(T)                                                                                        \
-    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, T* const[3]);                      \
+    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3]);                      \
     template void mg_pmass<T>(const tng_ctx*, const Level&, const Level&, const T*, T*);                  \
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
@@ -748,7 +765,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
                                const T* const*, int, double*, bool);                                       \
     template void vec_rand<T>(const tng_ctx*, long long, unsigned long long, T*);                         \
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
-    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*);
+    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double);
 TNG_INST(double)
 TNG_INST(float)
 #undef TNG_INST

@@ -115,7 +115,7 @@ void apply_K(tng_solver* s, const T* eta0, const T* x, T* y) {
     const void* u[3] = {x, x + ns, x + 2 * ns};
     void* yu[3] = {y, y + ns, y + 2 * ns};
     launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_A | TNG_OP_BT | TNG_OP_B | TNG_OP_DIRICHLET,
-                        eta0, u, x + 3 * ns, yu, y + 3 * ns);
+                        s->opts.hg_alpha, eta0, u, x + 3 * ns, yu, y + 3 * ns);
 }
 
 template <typename T>
@@ -124,16 +124,16 @@ void apply_A(tng_solver* s, int l, const T* eta, const T* x, T* y) {
     const long long ns = L.node_slots();
     const void* u[3] = {x, x + ns, x + 2 * ns};
     void* yu[3] = {y, y + ns, y + 2 * ns};
-    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, eta, u, nullptr, yu,
-                        nullptr);
+    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, s->opts.hg_alpha, eta, u,
+                        nullptr, yu, nullptr);
 }
 
 template <typename T>
 void apply_BT(tng_solver* s, const T* p, T* yu) {
     const long long ns = s->ns0;
     void* y[3] = {yu, yu + ns, yu + 2 * ns};
-    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_BT | TNG_OP_DIRICHLET, nullptr, nullptr, p, y,
-                        nullptr);
+    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_BT | TNG_OP_DIRICHLET, 0.0, nullptr, nullptr, p,
+                        y, nullptr);
 }
 
 // squared owner-masked norm of a velocity vector of level l into device scalar
@@ -150,15 +150,15 @@ void vel_dot(tng_solver* s, int l, const T* x, const T* const* ydev, double* out
 // eigenvalue interval [lo, hi]: every step is a polynomial of degree `deg`
 // (deg operator applies; the first one is skipped when x starts at zero).
 template <typename T>
-void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, const T* invd, const T* b, T* x, T* y,
-                     T* d, int deg, int steps, double lo, double hi, bool x_zero) {
+void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
+                     T* x, T* y, T* d, int deg, int steps, double lo, double hi, bool x_zero) {
     const long long ns = L.node_slots(), n3 = 3 * ns;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     auto applyA = [&](const T* xin, T* yout) {
         const void* u[3] = {xin, xin + ns, xin + 2 * ns};
         void* yu[3] = {yout, yout + ns, yout + 2 * ns};
-        launch_stokes_apply(ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, eta, u, nullptr, yu,
-                            nullptr);
+        launch_stokes_apply(ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, hg_alpha, eta, u, nullptr,
+                            yu, nullptr);
     };
     for (int st = 0; st < steps; ++st) {
         if (x_zero && st == 0) {
@@ -183,7 +183,8 @@ namespace {
 template <typename T>
 void chebyshev(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
     MGLevel<T>& M = hier<T>(s)[l];
-    chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, M.invd.p, b, x, M.y.p, M.d.p, std::max(1, s->opts.cheb_degree),
+    chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, M.invd.p, b, x, M.y.p, M.d.p,
+                       std::max(1, s->opts.cheb_degree),
                        steps, s->opts.cheb_lo * M.lmax, s->opts.cheb_hi * M.lmax, x_zero);
 }
 
@@ -463,7 +464,7 @@ void setup_level_operators(tng_solver* s) {
     for (int l = 0; l < s->nlev - 1; ++l) {
         MGLevel<T>& M = H[l];
         T* d[3] = {M.invd.p, M.invd.p + M.ns, M.invd.p + 2 * M.ns};
-        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, d);
+        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d);
         vec_invert<T>(s->ctx, 3 * M.ns, M.invd.p);
         M.lmax = power_lmax<T>(s, l);
     }
@@ -476,7 +477,7 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
                            s->ctx->stream));
     for (int l = 0; l + 1 < s->nlev; ++l) launch_eta_coarsen(s->ctx, s->mesh->lv[l + 1], TNG_F64, H[l].eta.p, H[l + 1].eta.p);
     // coarsest level: dense inverse of D A D over its interior DoFs
-    coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p);
+    coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p, s->opts.hg_alpha);
     coarse_invert(s->ctx, s->cd);
     mg_pmass<double>(s->ctx, L0(s), L1(s), H[0].eta.p, s->pm64.p);
     if (!mixed) {
@@ -493,10 +494,10 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
 
 }  // namespace
 
-template void chebyshev_steps<double>(const tng_ctx*, const Level&, const double*, const double*, const double*,
-                                      double*, double*, double*, int, int, double, double, bool);
-template void chebyshev_steps<float>(const tng_ctx*, const Level&, const float*, const float*, const float*,
-                                     float*, float*, float*, int, int, double, double, bool);
+template void chebyshev_steps<double>(const tng_ctx*, const Level&, const double*, double, const double*,
+                                      const double*, double*, double*, double*, int, int, double, double, bool);
+template void chebyshev_steps<float>(const tng_ctx*, const Level&, const float*, double, const float*,
+                                     const float*, float*, float*, float*, int, int, double, double, bool);
 }  // namespace tng
 
 using tng::Error;
@@ -521,6 +522,7 @@ int tng_solver_opts_default(tng_solver_opts* o) {
     o->inner_max_iters = 30;
     o->max_outer = 20;
     o->power_its = 10;
+    o->hg_alpha = 0.0;
     TNG_API_END
 }
 
@@ -534,6 +536,7 @@ int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts
     TNG_REQUIRE(opts->cheb_degree >= 1 && opts->pre >= 0 && opts->post >= 0, "bad smoother options");
     TNG_REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "bad Chebyshev interval");
     TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
+    TNG_REQUIRE(opts->hg_alpha >= 0.0 && std::isfinite(opts->hg_alpha), "hg_alpha must be finite and >= 0");
     const int nlev = opts->levels > 0 ? opts->levels : (int)mesh->lv.size();
     TNG_REQUIRE(nlev >= 2 && nlev <= (int)mesh->lv.size(), "levels out of range");
     for (int l = 0; l + 1 < nlev; ++l)

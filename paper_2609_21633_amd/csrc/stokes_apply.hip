@@ -49,6 +49,7 @@ struct BandArgs {
     int TI, TJ, KC;
     int ntile, nband, nchunk;
     T r_in, dr;
+    T hg;          // hourglass control: alpha * 5/81 (0 without)
     int dirichlet;
 };
 
@@ -105,8 +106,9 @@ __device__ __forceinline__ double wave_shift(double v) {
 constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
 
-template <typename T, int CPL, bool DO_A, bool DO_BT, bool DO_B>
+template <typename T, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG>
 __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
+    static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
     constexpr bool LOAD_U = DO_A || DO_B;
@@ -338,6 +340,18 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                     }
                 };
                 const T r3[3] = {gt[6], gt[7], gt[8]};
+                // hourglass control (eq:hgstab over the three barycentric modes): a node
+                // of lateral index l and face zeta = -1/+1 receives zeta eps (Du_l - mean Du),
+                // Du the top-minus-bottom nodal difference, eps = alpha mean(diag A_e) =
+                // alpha 5/27 eta V sum_j |grad phi_j|^2 and sum_j |grad phi_j|^2 =
+                // s1^2 hgA + hgB with the triangle's metric sums below
+                T hgA = T(0), hgB = T(0);
+                if (DO_HG) {
+                    hgA = T(4) * (gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2] + gt[3] * gt[3] + gt[4] * gt[4] +
+                                  gt[5] * gt[5] + gt[0] * gt[3] + gt[1] * gt[4] + gt[2] * gt[5]);
+                    hgB = T(6) * (gt[6] * gt[6] + gt[7] * gt[7] + gt[8] * gt[8]);
+                }
+                T hxb[3], hyb[3];   // eps/3 times the e1, e2 differences of the wedge below
                 T plat[NKL];   // pressure at the wedge's lateral centroid, per coarse layer
                 if (DO_BT) {
 #pragma unroll
@@ -379,6 +393,15 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                         dvl[sl + 1] += iso.rw[cb][1] * dv;
                     }
                     T za[3][3];   // Z_m = (V sigma) rho_m, rows m = 1, 2, 3
+                    T hx[3], hy[3];
+                    if (DO_HG) {
+                        const T e3 = a.hg * rin.eta[c][t] * V * (s1[c] * s1[c] * hgA + hgB);
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            hx[r] = e3 * (hi[0][r] - lo[0][r]);
+                            hy[r] = e3 * (hi[1][r] - lo[1][r]);
+                        }
+                    }
                     if (DO_U) {
                         T pbar = T(0);
                         if (DO_BT) {
@@ -421,7 +444,15 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                                 P2 += zb[1][r];
                                 Q += zb[2][r];
                             }
-                            const T N0 = Q - (P1 + P2), N1 = P1 + Q, N2 = P2 + Q;
+                            T N0 = Q - (P1 + P2), N1 = P1 + Q, N2 = P2 + Q;
+                            if (DO_HG) {
+                                // eps c_l of the wedge below minus that of the wedge above
+                                const T DX = (c > 0 ? hxb[r] : T(0)) - hx[r];
+                                const T DY = (c > 0 ? hyb[r] : T(0)) - hy[r];
+                                N0 -= DX + DY;
+                                N1 += T(2) * DX - DY;
+                                N2 += T(2) * DY - DX;
+                            }
                             if (t == 0) {
                                 Rc[0][c][r] += N0;
                                 Rc[1][c][r] += N1;
@@ -436,6 +467,13 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                         for (int x = 0; x < 3; ++x)
 #pragma unroll
                             for (int r = 0; r < 3; ++r) zb[x][r] = za[x][r];
+                        if (DO_HG) {
+#pragma unroll
+                            for (int r = 0; r < 3; ++r) {
+                                hxb[r] = hx[r];
+                                hyb[r] = hy[r];
+                            }
+                        }
                     }
 #pragma unroll
                     for (int x = 0; x < 3; ++x)
@@ -453,7 +491,12 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
                         const T z12 = zb[0][r] + zb[1][r];
-                        const T N0 = zb[2][r] - z12, N1 = zb[0][r] + zb[2][r], N2 = zb[1][r] + zb[2][r];
+                        T N0 = zb[2][r] - z12, N1 = zb[0][r] + zb[2][r], N2 = zb[1][r] + zb[2][r];
+                        if (DO_HG) {
+                            N0 -= hxb[r] + hyb[r];
+                            N1 += T(2) * hxb[r] - hyb[r];
+                            N2 += T(2) * hyb[r] - hxb[r];
+                        }
                         if (t == 0) {
                             top[0][r] = N0;
                             top[1][r] = N1;
@@ -641,24 +684,29 @@ __global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int CPL, bool A, bool BT, bool B>
+template <typename T, int CPL, bool A, bool BT, bool B, bool HG>
 void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args) {
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
     ScopedKernelTimer timer(ctx, "stokes_apply");
-    stokes_band_kernel<T, CPL, A, BT, B><<<(unsigned)nb, args.TI * 64, 0, ctx->stream>>>(args);
+    stokes_band_kernel<T, CPL, A, BT, B, HG><<<(unsigned)nb, args.TI * 64, 0, ctx->stream>>>(args);
     TNG_HIP(hipGetLastError());
 }
 
+// key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only)
 template <typename T, int CPL>
 void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, int key) {
     switch (key) {
-        case 1: launch_band_t<T, CPL, true, false, false>(ctx, args); break;
-        case 2: launch_band_t<T, CPL, false, true, false>(ctx, args); break;
-        case 3: launch_band_t<T, CPL, true, true, false>(ctx, args); break;
-        case 4: launch_band_t<T, CPL, false, false, true>(ctx, args); break;
-        case 5: launch_band_t<T, CPL, true, false, true>(ctx, args); break;
-        case 6: launch_band_t<T, CPL, false, true, true>(ctx, args); break;
-        case 7: launch_band_t<T, CPL, true, true, true>(ctx, args); break;
+        case 1: launch_band_t<T, CPL, true, false, false, false>(ctx, args); break;
+        case 2: launch_band_t<T, CPL, false, true, false, false>(ctx, args); break;
+        case 3: launch_band_t<T, CPL, true, true, false, false>(ctx, args); break;
+        case 4: launch_band_t<T, CPL, false, false, true, false>(ctx, args); break;
+        case 5: launch_band_t<T, CPL, true, false, true, false>(ctx, args); break;
+        case 6: launch_band_t<T, CPL, false, true, true, false>(ctx, args); break;
+        case 7: launch_band_t<T, CPL, true, true, true, false>(ctx, args); break;
+        case 9: launch_band_t<T, CPL, true, false, false, true>(ctx, args); break;
+        case 11: launch_band_t<T, CPL, true, true, false, true>(ctx, args); break;
+        case 13: launch_band_t<T, CPL, true, false, true, true>(ctx, args); break;
+        case 15: launch_band_t<T, CPL, true, true, true, true>(ctx, args); break;
         default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
     }
 }
@@ -671,7 +719,7 @@ __global__ void fill0_kernel(T* __restrict__ a, long long n) {
 }
 
 template <typename T>
-void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned flags,
+void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned flags, double hg_alpha,
                 const void* eta, const void* const u[3], const void* p, void* const yu[3],
                 void* yp) {
     const bool doA = flags & TNG_OP_A, doBT = flags & TNG_OP_BT, doB = flags & TNG_OP_B;
@@ -708,6 +756,8 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.r_in = T(L.r_in);
     a.dr = T(L.dr());
     a.dirichlet = (flags & TNG_OP_DIRICHLET) ? 1 : 0;
+    const bool doHG = doA && hg_alpha != 0.0;
+    a.hg = T(hg_alpha * (5.0 / 81.0));
     if (doB) {
         const long long np = Lp->node_slots();
         fill0_kernel<T><<<std::min<long long>(nblocks(np, 256), 4096), 256, 0, ctx->stream>>>(a.yp, np);
@@ -722,7 +772,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
             TNG_HIP(hipGetLastError());
         }
     }
-    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0);
+    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0);
     if (cpl == 1)
         launch_band_ops<T, 1>(ctx, a, key);
     else if constexpr (!std::is_same<T, double>::value)
@@ -743,12 +793,12 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
 }  // namespace
 
 void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec,
-                         unsigned flags, const void* eta, const void* const u[3], const void* p,
+                         unsigned flags, double hg_alpha, const void* eta, const void* const u[3], const void* p,
                          void* const yu[3], void* yp) {
     if (prec == TNG_F64)
-        band_apply<double>(ctx, L, Lp, flags, eta, u, p, yu, yp);
+        band_apply<double>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
     else
-        band_apply<float>(ctx, L, Lp, flags, eta, u, p, yu, yp);
+        band_apply<float>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
 }
 
 }  // namespace tng

@@ -175,8 +175,9 @@ inline const Level& device_level(const tng_ctx* ctx, const tng_mesh* mesh, int l
 }
 
 // Kernel launchers (defined in the .hip translation units).
+// hg_alpha: hourglass-control scale of the viscous block (0: plain one-point operator)
 void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec,
-                         unsigned flags, const void* eta, const void* const u[3], const void* p,
+                         unsigned flags, double hg_alpha, const void* eta, const void* const u[3], const void* p,
                          void* const yu[3], void* yp);
 void launch_interface(const tng_ctx* ctx, const Level& L, tng_prec prec, int mode, int ncomp,
                       void* const f[]);

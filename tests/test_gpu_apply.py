@@ -131,3 +131,33 @@ def test_unit_columns(tng, ctx):
         got = np.concatenate([lm.from_lib(yu).ravel(), lmp.from_lib(yp)])
         want = K[:, col].toarray().ravel()
         assert np.abs(got - want).max() < 1e-13 * np.abs(want).max(), col
+
+
+# ---- hourglass control (eq:hgstab) ---------------------------------------------------
+
+HG = 0.05
+
+
+@pytest.mark.parametrize("mt,nr,prec", [(8, 8, "f64"), (16, 10, "f64"), (8, 6, "f32"), (16, 16, "f32")])
+def test_hourglass_controlled_operator(tng, ctx, mt, nr, prec):
+    """K with the stabilised viscous block against the oracle assembled with the
+    same alpha: full operator with Dirichlet rows and A alone without them."""
+    import torch
+    from oracle.stokes import StokesOracle
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    orh = StokesOracle(mt, nr, eta, hierarchy=om.h, hg_alpha=HG)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    e, uu, pp = (t[k].to(dt) for k in ("eta", "u", "p"))
+    yu, yp = torch.full_like(uu, float("nan")), torch.full_like(pp, float("nan"))
+    tng.stokes_apply(ctx, mesh, 0, OPS_ALL, e, uu, pp, yu, yp, hg_alpha=HG)
+    ru, rp = orh.apply(u, p)
+    gu, gp = lm.from_lib(yu.double().cpu().numpy()), lmp.from_lib(yp.double().cpu().numpy())
+    print(f"hg {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
+    assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    # the stabilisation changes the result (it is not a no-op on random inputs)
+    assert rel(ru, orc.apply(u, p)[0]) > 1e-3
+    rng = np.random.default_rng(5)
+    uf = rng.uniform(-1, 1, u.shape)
+    ut = torch.tensor(lm.to_lib(uf), device="cuda").to(dt).contiguous()
+    tng.stokes_apply(ctx, mesh, 0, 1, e, ut, None, yu, None, hg_alpha=HG)
+    assert rel(lm.from_lib(yu.double().cpu().numpy()), (orh.A @ uf.ravel()).reshape(-1, 3)) < tol

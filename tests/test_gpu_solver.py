@@ -179,3 +179,42 @@ def test_mixed_matches_fp64_solve_16(tng, ctx):
         res.append((lm.from_lib(u.cpu().numpy()), lmp.from_lib(p.cpu().numpy())))
     assert rel(res[1][0], res[0][0]) < 1e-7
     assert rel(res[1][1], res[0][1]) < 1e-7
+
+
+# ---- hourglass control (eq:hgstab) ---------------------------------------------------
+
+HG = 0.05
+
+
+def test_diag_with_hourglass_control(tng, ctx):
+    import torch
+    from oracle.stokes import StokesOracle
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    orh = StokesOracle(8, 8, eta, hierarchy=om.h, hg_alpha=HG)
+    d = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    tng.diag_A(ctx, mesh, 0, eta_t, d, hg_alpha=HG)
+    assert rel(lm.from_lib(d.cpu().numpy(), check_dups=1e-13), orh.diag_A()) < 1e-12
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_hourglass_controlled_solve_matches_direct_solve(tng, ctx, mixed):
+    """With hg_alpha the solver solves the stabilised system on every level;
+    its solution matches the oracle's direct solve of that system."""
+    import torch
+    from oracle.stokes import StokesOracle
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    orh = StokesOracle(8, 8, eta, hierarchy=om.h, hg_alpha=HG)
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((om.n_nodes, 3))
+    f[om.boundary_nodes()] = 0.0
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-10, max_iters=400, hg_alpha=HG)
+    u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    info = s.solve(vel(lm, f), None, u, p, eta=eta_t)
+    uo, po = orh.solve(f)
+    eu = rel(lm.from_lib(u.cpu().numpy(), check_dups=1e-12), uo)
+    ep = rel(lmp.from_lib(p.cpu().numpy(), check_dups=1e-12), po)
+    print(f"hg solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7

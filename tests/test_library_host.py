@@ -42,14 +42,17 @@ def test_argument_validation_without_gpu():
     # a host-only mesh is rejected by device calls
     m = tng.Mesh(None, 4, 4, levels=2)
     y = (C.c_void_p * 3)(1, 2, 3)
-    rc = L.tng_stokes_apply(None, m.h, 0, 0, 1, C.c_void_p(1), y, None, y, None)
+    rc = L.tng_stokes_apply(None, m.h, 0, 0, 1, 0.0, C.c_void_p(1), y, None, y, None)
     assert rc == -1
-    assert L.tng_stokes_apply(C.c_void_p(0), m.h, 5, 0, 1, None, y, None, y, None) == -1
+    assert L.tng_stokes_apply(C.c_void_p(0), m.h, 5, 0, 1, 0.0, None, y, None, y, None) == -1
+    # hourglass-control scale must be finite and non-negative
+    assert L.tng_stokes_apply(None, m.h, 0, 0, 1, -0.5, C.c_void_p(1), y, None, y, None) == -1
+    assert b"hg_alpha" in L.tng_last_error()
 
 
 @pytest.mark.parametrize("mt,nr", [(2, 2), (4, 4), (8, 4), (16, 16)])
 def test_host_mesh_matches_oracle(mt, nr):
-    """a1: counts, coordinates (matched by position), duplicate groups of size
+    """Counts, coordinates (matched by position), duplicate groups of size
     2 (edges), 3 (ring vertices) and 5 (poles), wedges = oracle wedges."""
     tng = _lib()
     m = tng.Mesh(None, mt, nr, levels=2 if mt > 1 else 1)

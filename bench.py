@@ -134,6 +134,74 @@ def bench_solve(tng, ctx, mesh, T64, E, F, mixed, reps=2):
     return best, (u.clone(), p.clone())
 
 
+def variant_bytes(name):
+    """Algorithmic bytes of one launch from a detailed timer name
+    "stokes_apply/<f32|f64>/<variant>/<m>x<n>" or "energy_apply/<prec>/SUPG/<m>x<n>":
+    every input read and every output written once."""
+    parts = name.split("/")
+    if len(parts) != 4:
+        return None
+    kern, prec, var, size = parts
+    es = 8 if prec == "f64" else 4
+    m, n = (int(v) for v in size.split("x"))
+    ns = 10 * (m + 1) ** 2 * (n + 1)
+    cells = 10 * m * m * n
+    npr = 10 * (m // 2 + 1) ** 2 * (n // 2 + 1)
+    if kern == "energy_apply":
+        return es * 5 * ns                                   # T, u (3) in, y out
+    # values moved per variant: u in / y out (3 node fields each), two viscosities per cell,
+    # p in and y_p out (one pressure field each)
+    table = {"A": 6 * ns + 2 * cells, "BT": 3 * ns + npr, "B": 3 * ns + npr,
+             "A+BT": 6 * ns + 2 * cells + npr, "A+B": 6 * ns + 2 * cells + npr,
+             "BT+B": 6 * ns + 2 * npr, "K": 6 * ns + 2 * cells + 2 * npr}
+    b = table[var.replace("+HG", "")]
+    return es * b
+
+
+def bench_coupled(tng, ctx, mt, nr, steps):
+    """Coupled Stokes-energy time stepping: per step a mixed-precision Stokes solve to 1e-8
+    with eta(T) and the buoyancy Ra T rhat, then a backward-Euler SUPG energy step with
+    internal heating.  Reports the time per step and each kernel's algorithmic GB/s."""
+    import numpy as np
+    import torch
+    import synthetic
+    levels = int(math.log2(mt))
+    mesh = tng.Mesh(ctx, mt, nr, levels=levels)
+    T = shell_fields(tng, ctx, mesh, seed=4, lmax=8)
+    H = torch.tensor(np.random.default_rng(5).uniform(0.0, 10.0, mesh.shape(0)), device="cuda")
+    tng.interface_sum(ctx, mesh, 0, [T, H], mode=1)
+    u = torch.zeros((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+    p = torch.zeros(mesh.shape(1), device="cuda", dtype=torch.float64)
+    sv = tng.StokesSolver(ctx, mesh, mixed=1, rtol=1e-8, max_iters=600, inner_max_iters=60, max_outer=40)
+    per_step = []
+    ctx.profile(True)
+    for st in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = sv.energy_step(T, u, p, H=H, Ra=1e7, E=math.log(1e3), F=math.log(10.0), courant=1.0,
+                              raise_on_fail=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_step.append({"seconds": round(wall, 3), "stokes_inner_its": info["stokes"]["inner_its"],
+                         "stokes_outer_its": info["stokes"]["outer_its"],
+                         "stokes_rel_res": info["stokes"]["rel_res"], "energy_its": info["energy_its"],
+                         "dt": info["dt"]})
+        log(f"[bench] coupled step {st}: {per_step[-1]}")
+    kernels = {}
+    for name, (ms, n) in sorted(ctx.kernel_stats_all().items()):
+        b = variant_bytes(name)
+        kernels[name] = {"launches": n, "avg_us": round(ms / n * 1e3, 2),
+                         "alg_gbs": None if b is None else round(b / (ms / n * 1e-3) / 1e9, 1)}
+    ctx.profile(False)
+    sv.close()
+    secs = [s["seconds"] for s in per_step]
+    return {"workload": f"coupled Stokes-energy steps on the ({mt},{nr}) shell, Ra 1e7, "
+                        "eta = exp(-ln(1e3) T + ln(10)(1-r)), H = U(0,10)",
+            "steps": steps, "seconds_per_step_mean": round(sum(secs) / len(secs), 3),
+            "seconds_per_step_after_first": round(sum(secs[1:]) / max(len(secs) - 1, 1), 3),
+            "per_step": per_step, "kernels": kernels}
+
+
 def bench_serving(tng, ctx, nreq, rate_factor, budget):
     """Poisson-arrival request stream over (16,16), (32,32), (64,64) shells."""
     import numpy as np
@@ -231,6 +299,9 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of a known size (for HBM counter calibration)")
+    ap.add_argument("--coupled", action="store_true",
+                    help="instead: coupled Stokes-energy steps on the (--mt, --nr) shell (default (256,256), "
+                         "--steps steps), one JSON report line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the shell would shard by "
@@ -241,6 +312,12 @@ def main():
     import paper_2609_21633_amd as tng
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = tng.Context(0)
+    if args.coupled:
+        cm = args.mt if "--mt" in sys.argv else 256
+        cn = args.nr if "--nr" in sys.argv else 256
+        cs = args.steps if "--steps" in sys.argv else 10
+        print(json.dumps(bench_coupled(tng, ctx, cm, cn, cs)), flush=True)
+        return
     mt, nr = args.mt, args.nr
     nu, npr = unique_dofs(mt, nr)
     levels = int(math.log2(mt))                   # down to (2, 2)

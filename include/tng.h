@@ -94,12 +94,20 @@ int tng_ctx_create(int device, void* hip_stream, tng_ctx** out);
 int tng_ctx_set_stream(tng_ctx* ctx, void* hip_stream);
 int tng_ctx_destroy(tng_ctx* ctx);
 /* Measurement: with enable != 0, every call records a HIP event pair on the
- * context stream around its main kernel (kernel names: "stokes_apply").
- * tng_ctx_kernel_stats synchronises on the recorded events and returns the
- * summed elapsed milliseconds and the number of launches since profiling was
- * (re)enabled; an unknown name gives 0 and 0. */
+ * context stream around its main kernel, under the name
+ * "<kernel>/<precision>/<variant>/<m>x<n>" (kernels "stokes_apply" with
+ * variant A, BT, B, A+BT, ... and a "+HG" suffix for hourglass control;
+ * "energy_apply").  tng_ctx_kernel_stats synchronises on the recorded events
+ * and returns the summed elapsed milliseconds and the number of launches
+ * since profiling was (re)enabled, over the names equal to `name` or starting
+ * with `name` + "/" (so "stokes_apply" sums every variant); none gives 0 and
+ * 0.  tng_ctx_kernel_stats_at returns the index-th recorded full name (copied
+ * into name, at most name_len bytes with the terminator) and its figures,
+ * TNG_E_INVAL past the last one. */
 int tng_ctx_profile(tng_ctx* ctx, int enable);
 int tng_ctx_kernel_stats(tng_ctx* ctx, const char* name, double* total_ms, long long* launches);
+int tng_ctx_kernel_stats_at(tng_ctx* ctx, int index, char* name, int name_len, double* total_ms,
+                            long long* launches);
 
 /* ---- mesh (Sec. 2) ------------------------------------------------------ */
 /* Builds the shell with mt lateral intervals per diamond edge (power of two)

@@ -43,6 +43,8 @@ def lib():
         "tng_interface_sum": [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)],
         "tng_ctx_profile": [_vp, C.c_int],
         "tng_ctx_kernel_stats": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
+        "tng_ctx_kernel_stats_at": [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_longlong)],
         "tng_eta_from_temperature": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.c_double, _vp],
         "tng_eta_coarsen": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
         "tng_diag_A": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
@@ -129,6 +131,17 @@ class Context:
         ms, n = C.c_double(), C.c_longlong()
         check(lib().tng_ctx_kernel_stats(self.h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def kernel_stats_all(self) -> dict:
+        """{full timer name: (total milliseconds, launches)} since profiling was enabled."""
+        out = {}
+        buf = C.create_string_buffer(256)
+        ms, n = C.c_double(), C.c_longlong()
+        i = 0
+        while lib().tng_ctx_kernel_stats_at(self.h, i, buf, 256, C.byref(ms), C.byref(n)) == 0:
+            out[buf.value.decode()] = (ms.value, n.value)
+            i += 1
+        return out
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,6 +1,8 @@
 // C entry points: argument validation and dispatch to the launchers.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <string>
 
 #include "mg.hpp"
@@ -17,9 +19,11 @@ void clear_last_error() { g_last_error.clear(); }
 
 void build_mesh(tng_mesh* mesh, int levels);
 
-ScopedKernelTimer::ScopedKernelTimer(const tng_ctx* ctx, const char* name)
-    : ctx_(const_cast<tng_ctx*>(ctx)), name_(name) {
+ScopedKernelTimer::ScopedKernelTimer(const tng_ctx* ctx, const char* kernel, const char* detail)
+    : ctx_(const_cast<tng_ctx*>(ctx)) {
     if (!ctx_->profile) return;
+    name_ = kernel;
+    if (detail) name_ = name_ + "/" + detail;
     TNG_HIP(hipEventCreate(&a_));
     TNG_HIP(hipEventCreate(&b_));
     TNG_HIP(hipEventRecord(a_, ctx_->stream));
@@ -119,9 +123,30 @@ int tng_ctx_kernel_stats(tng_ctx* ctx, const char* name, double* total_ms, long 
     TNG_API_BEGIN
     TNG_REQUIRE(ctx != nullptr && name != nullptr, "ctx or name is NULL");
     tng::drain(ctx);
-    auto it = ctx->stats.find(name);
-    if (total_ms) *total_ms = it == ctx->stats.end() ? 0.0 : it->second.total_ms;
-    if (launches) *launches = it == ctx->stats.end() ? 0 : it->second.launches;
+    const std::string key(name), pre = key + "/";
+    double ms = 0.0;
+    long long n = 0;
+    for (const auto& kv : ctx->stats)
+        if (kv.first == key || kv.first.compare(0, pre.size(), pre) == 0) {
+            ms += kv.second.total_ms;
+            n += kv.second.launches;
+        }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    TNG_API_END
+}
+
+int tng_ctx_kernel_stats_at(tng_ctx* ctx, int index, char* name, int name_len, double* total_ms,
+                            long long* launches) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr && name != nullptr && name_len > 0, "NULL argument");
+    tng::drain(ctx);
+    TNG_REQUIRE(index >= 0 && index < (int)ctx->stats.size(), "index out of range");
+    auto it = ctx->stats.begin();
+    std::advance(it, index);
+    std::snprintf(name, (size_t)name_len, "%s", it->first.c_str());
+    if (total_ms) *total_ms = it->second.total_ms;
+    if (launches) *launches = it->second.launches;
     TNG_API_END
 }
 

@@ -11,6 +11,9 @@
 // with N_i(q_c) = 1/6, i.e. lumped mass, diffusion, advection and streamline
 // diffusion.  Every kernel gathers over the wedges around a node (no atomics)
 // and produces per-diamond partial sums that the interface pass completes.
+#include <cstdio>
+#include <type_traits>
+
 #include "mg.hpp"
 #include "tng_internal.hpp"
 
@@ -257,7 +260,11 @@ template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y) {
     const long long ns = L.node_slots();
     {
-        ScopedKernelTimer timer(ctx, "energy_apply");
+        char detail[48] = {0};
+        if (ctx->profile)
+            std::snprintf(detail, sizeof(detail), "%s/SUPG/%dx%d", std::is_same<T, double>::value ? "f64" : "f32",
+                          L.m, L.n);
+        ScopedKernelTimer timer(ctx, "energy_apply", detail);
         energy_node_kernel<T, 0><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), Tin, u[0], u[1], u[2],
                                                                          1.0 / dt, y, ns);
         TNG_HIP(hipGetLastError());

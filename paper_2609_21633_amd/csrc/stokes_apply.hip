@@ -4,33 +4,40 @@
 // Work decomposition (one diamond d, a "band"):
 //   * lanes run along the radial direction: lane l of a wave handles the CPL
 //     consecutive cells k = k0 + CPL*l + c of one cell column, so every memory
-//     access of a wave covers a contiguous radial stretch;
-//   * the TI waves of a workgroup handle TI adjacent cell columns i0..i0+TI-1;
+//     access of a wave covers a contiguous radial stretch of 64 CPL cells;
+//   * a workgroup has 8 waves: TC = 8 / RS adjacent cell columns, each column
+//     split into RS radial stretches handled by RS waves, so that one
+//     workgroup holds whole radial columns (a column split across workgroups
+//     costs far more, in memory stalls, than the split inside one);
 //   * the workgroup streams along j over the cell rows of its band, carrying
 //     the half-finished node row in registers, so each node of the band's
 //     interior is written exactly once, with its complete sum.
 // Velocity rows are staged in a three-row LDS ring (rows j, j+1 in use, row
 // j+2 arriving), copied straight from HBM without passing through registers;
-// each node column is read from HBM once per workgroup and shared by the two
+// each node column is read from HBM once per workgroup and shared by the
 // waves that touch it.  The nodal differences of a triangle are formed once
 // per node layer and shared by the wedges below and above it, and so are the
 // test-function sums of the result.  Contributions that cross a wave boundary
-// are combined in LDS (lateral, i direction) or moved one lane up with a DPP
-// wavefront shift (radial).  A band starts one cell row early (the halo row)
-// so that its first node row is complete; nodes on the seams between tiles
-// (node columns that are multiples of TI) and between radial chunks receive
-// exactly two partial sums, added with atomics to memory zeroed beforehand,
-// which keeps the result independent of timing.
+// are combined in LDS (lateral, and radial between the stretches of a column)
+// or moved one lane up with a DPP wavefront shift (radial, inside a wave).  A
+// band starts one cell row early (the halo row) so that its first node row is
+// complete; nodes on the seams between tiles (node columns that are multiples
+// of TC) and between workgroup radial ranges (columns longer than RS
+// stretches) receive exactly two partial sums, added with atomics to memory
+// zeroed beforehand, which keeps the result independent of timing.
 //
 // The divergence block is reduced per coarse pressure node through LDS, kept
 // by one owner thread per node and flushed once a coarse row is complete.
+#include <cstdio>
+#include <type_traits>
+
 #include "tng_internal.hpp"
 #include "wedge.hpp"
 
 namespace tng {
 namespace {
 
-constexpr int TIC = 8;   // cell columns (waves) per workgroup
+constexpr int TIC = 8;   // waves per workgroup (cell columns when a column fits one wave)
 
 
 template <typename T>
@@ -106,29 +113,37 @@ __device__ __forceinline__ double wave_shift(double v) {
 constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
 
-template <typename T, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG>
+template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG>
 __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
+    constexpr int TC = TIC / RS;  // cell columns per workgroup; RS waves share a column radially
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
     constexpr bool LOAD_U = DO_A || DO_B;
-    // velocity rows j, j+1, j+2 of the TI + 1 node columns, radial fastest
-    constexpr int KW = 64 * CPL + 1;            // node layers of a radial chunk
+    constexpr int KC = 64 * CPL;                // cells of one wave's radial stretch
+    // velocity rows j, j+1, j+2 of the TC + 1 node columns, radial fastest
+    constexpr int KW = RS * KC + 1;             // node layers of the workgroup's radial range
     constexpr int KWP = (KW + 1) & ~1;          // even pitch: lane pairs stay 8-byte aligned
     constexpr int RR = LOAD_U ? 3 : 1;
-    constexpr int RW = LOAD_U ? TIC + 1 : 1;
+    constexpr int RW = LOAD_U ? TC + 1 : 1;
     __shared__ T ring[RR][RW][3][KWP];
     constexpr int XW = DO_U ? TIC : 1;
-    __shared__ T xch[2][XW][3][NL][64];
-    constexpr int NKC = DO_B ? 32 * CPL + 1 : 1;          // coarse layers per chunk
-    constexpr int BW = DO_B ? TIC + 4 : 1;
-    __shared__ T bsl[2][BW][4][NKC];   // per-wave coarse partials, wave w in slot w + 2
+    __shared__ T xch[2][XW][3][CPL][64];   // lateral partials of layers 0..CPL-1 of every lane
+    __shared__ T xtop[2][XW][3];           // and of the workgroup's top node
+    constexpr int RX = (DO_U && RS > 1) ? TIC : 1;
+    __shared__ T rxs[2][RX][4][3];     // top-layer partials handed to the wave above
+    constexpr int NKC = DO_B ? 32 * CPL + 1 : 1;          // coarse layers of one wave
+    constexpr int PADW = 2 * RS;                          // two empty columns each side
+    constexpr int BW = DO_B ? TIC + 2 * PADW : 1;
+    __shared__ T bsl[2][BW][4][NKC];   // per-wave coarse partials, wave w in slot w + PADW
     constexpr int NKL = CoarseMap<CPL>::NKL;
     const IsoWeights<T>& iso = IsoTable<T>::get();
 
-    const int TI = a.TI;   // <= TIC on small levels
+    const int TI = a.TI;   // columns, <= TC on small levels; the workgroup has TI * RS waves
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wc = w / RS;       // column of the wave within the tile
+    const int h = w % RS;        // radial stretch of the wave within the workgroup
     int bid = blockIdx.x;
     const int chunk = bid % a.nchunk;
     bid /= a.nchunk;
@@ -139,14 +154,16 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
 
     const int m = a.m, n = a.n;
     const int i0 = tile * TI;
-    const int i = i0 + w;
+    const int i = i0 + wc;
     const int j0 = band * a.TJ;
     const bool last_band = (band == a.nband - 1);
     const int jfirst = j0 > 0 ? j0 - 1 : 0;            // halo row (computed, not owned)
     const int jlast_cell = last_band ? m - 1 : j0 + a.TJ - 1;
     const int jlast = last_band ? m : jlast_cell;      // last node row emitted
-    const int k0 = chunk * a.KC;                       // even: KC is a multiple of 64
-    const int kend = min(n, k0 + a.KC);                // cells [k0, kend) of this chunk
+    const int kc0 = chunk * RS * KC;                   // workgroup's radial range [kc0, kcend)
+    const int kcend = min(n, kc0 + RS * KC);
+    const int k0 = kc0 + h * KC;                       // even: KC is a multiple of 64
+    const int kend = min(kcend, k0 + KC);              // cells [k0, kend) of this wave
 
     // 32-bit offsets: every field of a supported level has < 2^31 entries
     const unsigned ldj = n + 1;
@@ -154,7 +171,7 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
     const unsigned colA = ((unsigned)d * (m + 1) + i) * ldi;   // node column i
     const unsigned colB = colA + ldi;                          // node column i + 1
 
-    const int kl0 = CPL * lane;                        // first chunk-local layer of the lane
+    const int kl0 = CPL * lane;                        // first wave-local layer of the lane
     int kk[NL];
 #pragma unroll
     for (int c = 0; c < NL; ++c) kk[c] = k0 + kl0 + c;
@@ -167,22 +184,25 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
         s1[c] = T(0.5) / rm;
         vr[c] = kk[c] < kend ? rm * rm : T(0);
     }
-    const bool top_lane = (kk[0] <= kend - 1) && (kend - 1 <= kk[CPL - 1]);
-    const int top_c = kend - kk[0];
+    // the lane holding the workgroup's top node (layer kcend)
+    const bool top_lane = (kk[0] <= kcend - 1) && (kcend - 1 <= kk[CPL - 1]);
+    const int top_c = kcend - kk[0];
 
-    // velocity staging: each radial line of a chunk column (KW values of one
-    // component) is copied straight from HBM into its ring row, 64 dwords per
-    // instruction, lane l moving dword l of each 256-byte piece.  Dirichlet
-    // layers and layers past the chunk are never written and keep the zeros
-    // the ring starts with.
+    // velocity staging: each radial line of a column over the workgroup's range
+    // (KW values of one component) is copied straight from HBM into its ring
+    // row, 64 dwords per instruction, lane l moving dword l of each 256-byte
+    // piece; the RS waves of a column copy consecutive stretches of it, the top
+    // one also the range's top node.  Dirichlet layers and layers past the
+    // range are never written and keep the zeros the ring starts with.
     constexpr int DW = sizeof(T) / 4;                   // dwords per value
-    constexpr int NCH = (KW * DW + 63) / 64;            // 256-byte pieces per line
+    constexpr int NCH = CPL * DW + 1;                   // 256-byte pieces per wave (+ the top node)
     bool lok[NCH];
 #pragma unroll
     for (int t = 0; t < NCH; ++t) {
-        const int e = (lane + 64 * t) / DW;             // value moved by this lane
-        const int k = k0 + e;
-        lok[t] = LOAD_U && e < KW && k <= kend && !(a.dirichlet && (k == 0 || k == n));
+        const int e = h * KC + (lane + 64 * t) / DW;    // value moved by this lane
+        const int k = kc0 + e;
+        lok[t] = LOAD_U && e < KW && k <= kcend && (t < NCH - 1 || h == RS - 1) &&
+                 !(a.dirichlet && (k == 0 || k == n));
     }
     auto stage = [&](unsigned col, int jrow, int slot, int wl) {
         const unsigned base = col + (unsigned)jrow * ldj + (unsigned)k0;
@@ -192,9 +212,9 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
 #pragma unroll
             for (int t = 0; t < NCH; ++t)
                 if (lok[t])
-                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned*>(src[r]) + lane + 64 * t,
-                                                     reinterpret_cast<unsigned*>(&ring[slot][wl][r][0]) + 64 * t,
-                                                     4, 0, 0);
+                    __builtin_amdgcn_global_load_lds(
+                        reinterpret_cast<const unsigned*>(src[r]) + lane + 64 * t,
+                        reinterpret_cast<unsigned*>(&ring[slot][wl][r][0]) + h * KC * DW + 64 * t, 4, 0, 0);
     };
 
     const int mc = m / 2, nc = n / 2;
@@ -203,7 +223,7 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
     const unsigned pcol = (unsigned)d * (mc + 1) * pldi;
     const int I = i >> 1, I0 = i0 >> 1;
     const int ab = i & 1;
-    const int K0 = k0 >> 1;
+    const int K0 = kc0 >> 1;
 
     // per-row inputs of the cell row: viscosities, and the coarse pressure of
     // the four lateral corners on the NKL coarse layers the lane's cells touch
@@ -221,7 +241,9 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
         if (DO_A) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int k = kk[c] < kend ? kk[c] : k0;
+                // a cell outside the wave's stretch reads the range's first cell: the wave's own
+            // first cell lies past the column when the stretch is empty
+            const int k = kk[c] < kend ? kk[c] : kc0;
                 r.eta[c][0] = a.eta[ecol + 2u * k];
                 r.eta[c][1] = a.eta[ecol + 2u * k + 1u];
             }
@@ -247,21 +269,26 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
             for (int r = 0; r < 3; ++r) Rc[q][c][r] = T(0);
 
     // divergence: owner thread t < ncoarse (at most one coarse node per thread,
-    // since CPL = 2 runs only with TI >= 4) keeps its two open coarse rows in
-    // registers
-    const int ncoarse = (TI / 2 + 1) * NKC;
+    // guaranteed by the host's choice of TI, RS and CPL) keeps its two open
+    // coarse rows in registers
+    constexpr int NKW = RS * (NKC - 1) + 1;               // coarse layers of the workgroup
+    const int ncoarse = (TI / 2 + 1) * NKW;
     const bool owner = DO_B && (int)threadIdx.x < ncoarse;
-    const int il = (int)threadIdx.x / NKC, kl = (int)threadIdx.x % NKC;
+    const int il = (int)threadIdx.x / NKW, kl = (int)threadIdx.x % NKW;
     const int Ig = I0 + il, Kg = K0 + kl;
-    const bool own_ok = owner && Ig <= mc && Kg <= nc && kl <= (kend - k0) / 2;
+    const bool own_ok = owner && Ig <= mc && Kg <= nc && kl <= (kcend - kc0) / 2;
     const bool own_seam = (il == 0 && I0 > 0) || (il == TI / 2 && Ig < mc) || (kl == 0 && K0 > 0) ||
-                          (Kg < nc && kl == (kend - k0) / 2);
+                          (Kg < nc && kl == (kcend - kc0) / 2);
     const unsigned own_off = pcol + (unsigned)Ig * pldi + (unsigned)Kg;
+    // the owner's coarse layer in the waves' slots: wave stretch hk, local layer klo;
+    // a stretch boundary layer is also the top layer of the stretch below
+    const int hk = min(kl / (NKC - 1), RS - 1), klo = kl - hk * (NKC - 1);
+    const bool below = RS > 1 && klo == 0 && hk > 0;
     if (DO_B) {
-        // wave slots without a wave stay zero: two below, and from TI on
-        for (int x = threadIdx.x; x < 4 * 4 * NKC; x += TI * 64) {
-            const int sl4 = x / (4 * NKC), rem = x % (4 * NKC);
-            const int slot = sl4 & 1 ? (sl4 >> 1 ? TI + 3 : 1) : (sl4 >> 1 ? TI + 2 : 0);
+        // wave slots without a wave stay zero: two columns below, two from column TI on
+        for (int x = threadIdx.x; x < 2 * PADW * 4 * NKC; x += TI * RS * 64) {
+            const int sl = x / (4 * NKC), rem = x % (4 * NKC);
+            const int slot = sl < PADW ? sl : (TI * RS + sl);
             (&bsl[0][0][0][0])[(size_t)slot * 4 * NKC + rem] = T(0);
             (&bsl[1][0][0][0])[(size_t)slot * 4 * NKC + rem] = T(0);
         }
@@ -269,13 +296,13 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
     T pacc0 = T(0), pacc1 = T(0);
 
     int sj = 0, sj1 = 1, sj2 = 2;    // ring slots of node rows j, j+1, j+2
-    const bool xw = (w == TI - 1);   // the last wave also stages column i0 + TI
+    const bool xw = (wc == TI - 1);  // the last column's waves also stage column i0 + TI
     RowIn rin;
     if (LOAD_U) {
-        for (int x = threadIdx.x; x < RR * RW * 3 * KWP; x += TI * 64) (&ring[0][0][0][0])[x] = T(0);
+        for (int x = threadIdx.x; x < RR * RW * 3 * KWP; x += TI * RS * 64) (&ring[0][0][0][0])[x] = T(0);
         __syncthreads();
-        stage(colA, jfirst, sj, w);
-        stage(colA, jfirst + 1, sj1, w);
+        stage(colA, jfirst, sj, wc);
+        stage(colA, jfirst + 1, sj1, wc);
         if (xw) {
             stage(colB, jfirst, sj, TI);
             stage(colB, jfirst + 1, sj1, TI);
@@ -298,7 +325,7 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
             // node row j+2 into the slot of row j-1, read for the last time
             // before the previous barrier
             if (LOAD_U) {
-                stage(colA, j + 2, sj2, w);
+                stage(colA, j + 2, sj2, wc);
                 if (xw) stage(colB, j + 2, sj2, TI);
             }
             load_row(j + 1, rnext);
@@ -314,11 +341,12 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int s = 0; s < NKL; ++s) cp[q][s] = T(0);
+        T top_out[4][3];   // this row's top-layer partials (the DPP shift drops lane 63's)
         if (row_cells) {
             const T* g = a.geo + (((unsigned)d * m + i) * m + j) * (unsigned)GEO_PER_COL;
             // staged velocity of corner q (A=(i,j), B=(i+1,j), C=(i,j+1), D=(i+1,j+1))
             auto rd = [&](int q, int c, int r) -> T {
-                return ring[q < 2 ? sj : sj1][w + (q & 1)][r][kl0 + c];
+                return ring[q < 2 ? sj : sj1][wc + (q & 1)][r][h * KC + kl0 + c];
             };
             T top[4][3];   // partials of the lane's top layer, per corner
 #pragma unroll
@@ -522,15 +550,29 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                     Rc[1][CPL][r] += top[1][r];
                     Rn[0][CPL][r] += top[2][r];
                     Rn[1][CPL][r] += top[3][r];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) top_out[q][r] = top[q][r];
                 }
             }
         }
         if (DO_U) {
             // lateral: this wave's partial of node (i+1, j) goes to the wave on its right
 #pragma unroll
-            for (int c = 0; c < NL; ++c)
+            for (int c = 0; c < CPL; ++c)
 #pragma unroll
                 for (int r = 0; r < 3; ++r) xch[par][w][r][c][lane] = Rc[1][c][r];
+            if (top_lane && top_c == CPL) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) xtop[par][w][r] = Rc[1][CPL][r];
+            }
+            // radial between the waves of a column: the top lane's new top-layer
+            // partials go to lane 0 of the wave above
+            if (RS > 1 && h < RS - 1 && lane == 63) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) rxs[par][w][q][r] = row_cells ? top_out[q][r] : T(0);
+            }
         }
         if (DO_B && owned && row_cells) {
             // radial reduction of the coarse partials to one value per coarse layer
@@ -545,8 +587,8 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                 for (int q = 0; q < 4; ++q) {
                     const T t = wave_shift<DPP_WAVE_SHR1>(wave_shift<DPP_WAVE_SHR1>(cp[q][1]));
                     if ((lane & 1) == 0) {
-                        bsl[par][w + 2][q][lane >> 1] = cp[q][0] + t;
-                        if (lane == 62) bsl[par][w + 2][q][32] = cp[q][1];
+                        bsl[par][w + PADW][q][lane >> 1] = cp[q][0] + t;
+                        if (lane == 62) bsl[par][w + PADW][q][32] = cp[q][1];
                     }
                 }
             } else {
@@ -556,8 +598,8 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                     const T t = wave_shift<DPP_WAVE_SHR1>(cp[q][NKL - 1]);
                     const int Kb = (CPL / 2) * lane;
 #pragma unroll
-                    for (int s2 = 0; s2 < NKL - 1; ++s2) bsl[par][w + 2][q][Kb + s2] = s2 == 0 ? cp[q][0] + t : cp[q][s2];
-                    if (lane == 63) bsl[par][w + 2][q][Kb + NKL - 1] = cp[q][NKL - 1];
+                    for (int s2 = 0; s2 < NKL - 1; ++s2) bsl[par][w + PADW][q][Kb + s2] = s2 == 0 ? cp[q][0] + t : cp[q][s2];
+                    if (lane == 63) bsl[par][w + PADW][q][Kb + NKL - 1] = cp[q][NKL - 1];
                 }
             }
         }
@@ -566,7 +608,8 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
         if (DO_U && owned) {
             const unsigned rowA = colA + (unsigned)j * ldj;
             const unsigned rowB = colB + (unsigned)j * ldj;
-            const bool seamL = (w == 0) && (i0 > 0);
+            const bool seamL = (wc == 0) && (i0 > 0);
+            const bool rxin = RS > 1 && h > 0 && lane == 0;   // layer 0 also gets the wave below
             const bool seamR = (i0 + TI < m);
 #pragma unroll
             for (int c = 0; c < NL; ++c) {
@@ -574,18 +617,24 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                 bool live = false, seamK = false;
                 if (top_lane && c == top_c) {
                     live = true;
-                    seamK = kend < n;                   // chunk top: the next chunk adds the rest
+                    seamK = kcend < n;                  // range top: the next range adds the rest
                 } else if (c < CPL && k < kend) {
                     live = true;
-                    seamK = (c == 0 && lane == 0 && k0 > 0);   // chunk bottom
+                    seamK = (c == 0 && lane == 0 && h == 0 && kc0 > 0);   // range bottom
                 }
                 if (a.dirichlet && (k == 0 || k == n)) live = false;   // rows set afterwards
                 if (!live) continue;
-                T v[3];
+                T v[3], vb[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     v[r] = Rc[0][c][r];
-                    if (w > 0) v[r] += xch[par][w - 1][r][c][lane];
+                    vb[r] = Rc[1][c][r];
+                    if (wc > 0) v[r] += c < CPL ? xch[par][w - RS][r][c][lane] : xtop[par][w - RS][r];
+                    if (c == 0 && rxin) {
+                        v[r] += rxs[par][w - 1][0][r];
+                        if (wc > 0) v[r] += rxs[par][w - RS - 1][1][r];
+                        vb[r] += rxs[par][w - 1][1][r];
+                    }
                 }
                 const bool seam = seamL || seamK;
                 const unsigned oa = rowA + (unsigned)k;
@@ -596,10 +645,17 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
                     // node column i0 + TI: complete only on the diamond edge
                     const bool s2 = seamR || seamK;
                     const unsigned ob = rowB + (unsigned)k;
-                    emit(a.y0, ob, Rc[1][c][0], s2);
-                    emit(a.y1, ob, Rc[1][c][1], s2);
-                    emit(a.y2, ob, Rc[1][c][2], s2);
+                    emit(a.y0, ob, vb[0], s2);
+                    emit(a.y1, ob, vb[1], s2);
+                    emit(a.y2, ob, vb[2], s2);
                 }
+            }
+        }
+        if (DO_U && RS > 1 && h > 0 && lane == 0 && row_cells) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                Rn[0][0][r] += rxs[par][w - 1][2][r];
+                Rn[1][0][r] += rxs[par][w - 1][3][r];
             }
         }
         if (DO_B && owned && row_cells) {
@@ -608,9 +664,11 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
             if (owner) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    // waves 2 (il - (q&1)) and the next one, in slots shifted by two
-                    const int ws = 2 * (il - (q & 1)) + 2;
-                    const T v = bsl[par][ws][q][kl] + bsl[par][ws + 1][q][kl];
+                    // columns 2 (il - (q&1)) and the next one, stretch hk (and hk - 1 at
+                    // its bottom layer), in slots shifted by PADW
+                    const int ws = (2 * (il - (q & 1))) * RS + hk + PADW;
+                    T v = bsl[par][ws][q][klo] + bsl[par][ws + RS][q][klo];
+                    if (below) v += bsl[par][ws - 1][q][NKC - 1] + bsl[par][ws + RS - 1][q][NKC - 1];
                     if (q < 2) pacc0 += v; else pacc1 += v;
                 }
             }
@@ -684,29 +742,35 @@ __global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int CPL, bool A, bool BT, bool B, bool HG>
+template <typename T, int RS, int CPL, bool A, bool BT, bool B, bool HG>
 void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args) {
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
-    ScopedKernelTimer timer(ctx, "stokes_apply");
-    stokes_band_kernel<T, CPL, A, BT, B, HG><<<(unsigned)nb, args.TI * 64, 0, ctx->stream>>>(args);
+    char detail[64] = {0};
+    if (ctx->profile) {
+        const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
+        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", args.m, args.n);
+    }
+    ScopedKernelTimer timer(ctx, "stokes_apply", detail);
+    stokes_band_kernel<T, RS, CPL, A, BT, B, HG><<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args);
     TNG_HIP(hipGetLastError());
 }
 
 // key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only)
-template <typename T, int CPL>
+template <typename T, int RS, int CPL>
 void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, int key) {
     switch (key) {
-        case 1: launch_band_t<T, CPL, true, false, false, false>(ctx, args); break;
-        case 2: launch_band_t<T, CPL, false, true, false, false>(ctx, args); break;
-        case 3: launch_band_t<T, CPL, true, true, false, false>(ctx, args); break;
-        case 4: launch_band_t<T, CPL, false, false, true, false>(ctx, args); break;
-        case 5: launch_band_t<T, CPL, true, false, true, false>(ctx, args); break;
-        case 6: launch_band_t<T, CPL, false, true, true, false>(ctx, args); break;
-        case 7: launch_band_t<T, CPL, true, true, true, false>(ctx, args); break;
-        case 9: launch_band_t<T, CPL, true, false, false, true>(ctx, args); break;
-        case 11: launch_band_t<T, CPL, true, true, false, true>(ctx, args); break;
-        case 13: launch_band_t<T, CPL, true, false, true, true>(ctx, args); break;
-        case 15: launch_band_t<T, CPL, true, true, true, true>(ctx, args); break;
+        case 1: launch_band_t<T, RS, CPL, true, false, false, false>(ctx, args); break;
+        case 2: launch_band_t<T, RS, CPL, false, true, false, false>(ctx, args); break;
+        case 3: launch_band_t<T, RS, CPL, true, true, false, false>(ctx, args); break;
+        case 4: launch_band_t<T, RS, CPL, false, false, true, false>(ctx, args); break;
+        case 5: launch_band_t<T, RS, CPL, true, false, true, false>(ctx, args); break;
+        case 6: launch_band_t<T, RS, CPL, false, true, true, false>(ctx, args); break;
+        case 7: launch_band_t<T, RS, CPL, true, true, true, false>(ctx, args); break;
+        case 9: launch_band_t<T, RS, CPL, true, false, false, true>(ctx, args); break;
+        case 11: launch_band_t<T, RS, CPL, true, true, false, true>(ctx, args); break;
+        case 13: launch_band_t<T, RS, CPL, true, false, true, true>(ctx, args); break;
+        case 15: launch_band_t<T, RS, CPL, true, true, true, true>(ctx, args); break;
         default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
     }
 }
@@ -737,19 +801,26 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.geo = is64 ? reinterpret_cast<const T*>(L.geo64.p) : reinterpret_cast<const T*>(L.geo32.p);
     a.m = L.m;
     a.n = L.n;
-    a.TI = std::min(TIC, L.m);
-    a.TJ = std::min(16, L.m);
-    // cells per lane: enough for the whole radial column within the register
-    // budget (two or more FP64 cells per lane spill), longer columns are split
-    // into radial chunks
+    // cells per lane: enough for a radial stretch of 64 lanes within the
+    // register budget (two or more FP64 cells per lane spill); a column longer
+    // than one stretch is split among RS waves of the same workgroup (RS
+    // columns fewer per workgroup), and only columns longer than RS stretches
+    // into workgroup ranges with seams, which cost far more than the split
     int cpl = (L.n + 63) / 64;
     const int cpl_max = is64 ? 1 : 2;
-    cpl = cpl <= 1 ? 1 : (cpl <= 2 ? 2 : 4);
+    cpl = cpl <= 1 ? 1 : 2;
     if (cpl > cpl_max) cpl = cpl_max;
     // two cells per lane need at least four columns per workgroup, so that
     // every coarse node of the divergence has one owner thread
-    if (a.TI < 4) cpl = 1;
-    a.KC = 64 * cpl;
+    if (std::min(TIC, L.m) < 4) cpl = 1;
+    const int stretches = (L.n + 64 * cpl - 1) / (64 * cpl);
+    const int rs_max = is64 ? 4 : 2;
+    int rs = stretches >= 3 ? 4 : (stretches >= 2 ? 2 : 1);
+    if (rs > rs_max) rs = rs_max;
+    if (L.m < TIC / rs) rs = 1;                     // the split needs full-width tiles
+    a.TI = std::min(TIC / rs, L.m);
+    a.TJ = std::min(16, L.m);
+    a.KC = rs * 64 * cpl;                           // radial range of a workgroup
     a.ntile = L.m / a.TI;
     a.nband = L.m / a.TJ;
     a.nchunk = (L.n + a.KC - 1) / a.KC;
@@ -773,10 +844,22 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         }
     }
     const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0);
-    if (cpl == 1)
-        launch_band_ops<T, 1>(ctx, a, key);
-    else if constexpr (!std::is_same<T, double>::value)
-        launch_band_ops<T, 2>(ctx, a, key);
+    if constexpr (std::is_same<T, double>::value) {
+        if (rs == 1)
+            launch_band_ops<T, 1, 1>(ctx, a, key);
+        else if (rs == 2)
+            launch_band_ops<T, 2, 1>(ctx, a, key);
+        else
+            launch_band_ops<T, 4, 1>(ctx, a, key);
+    } else {
+        // FP32 splits only two-cell stretches (one-cell columns fit one stretch)
+        if (cpl == 1)
+            launch_band_ops<T, 1, 1>(ctx, a, key);
+        else if (rs == 1)
+            launch_band_ops<T, 1, 2>(ctx, a, key);
+        else
+            launch_band_ops<T, 2, 2>(ctx, a, key);
+    }
     const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
     if (doA || doBT) {
         void* f[3] = {yu[0], yu[1], yu[2]};

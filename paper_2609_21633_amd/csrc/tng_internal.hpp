@@ -188,14 +188,16 @@ void launch_eta_from_T(const tng_ctx* ctx, const Level& L, tng_prec prec, const 
 void launch_eta_coarsen(const tng_ctx* ctx, const Level& Lc, tng_prec prec, const void* ef,
                         void* ec);
 
-// Records a start/stop event pair around a launch when profiling is on.
+// Records a start/stop event pair around a launch when profiling is on.  The
+// name is "<kernel>/<detail>" (precision, variant, level size); statistics can
+// be read per full name or summed over a kernel prefix.
 class ScopedKernelTimer {
   public:
-    ScopedKernelTimer(const tng_ctx* ctx, const char* name);
+    ScopedKernelTimer(const tng_ctx* ctx, const char* kernel, const char* detail = nullptr);
     ~ScopedKernelTimer();
   private:
     tng_ctx* ctx_;
-    const char* name_;
+    std::string name_;
     hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 

@@ -161,3 +161,22 @@ def test_hourglass_controlled_operator(tng, ctx, mt, nr, prec):
     ut = torch.tensor(lm.to_lib(uf), device="cuda").to(dt).contiguous()
     tng.stokes_apply(ctx, mesh, 0, 1, e, ut, None, yu, None, hg_alpha=HG)
     assert rel(lm.from_lib(yu.double().cpu().numpy()), (orh.A @ uf.ravel()).reshape(-1, 3)) < tol
+
+
+# ---- radial split: a column handled by 2 or 4 waves of one workgroup -----------------
+
+@pytest.mark.parametrize("mt,nr,prec", [(4, 96, "f64"), (4, 160, "f64"), (4, 320, "f64"),
+                                         (4, 160, "f32"), (4, 288, "f32")])
+def test_radial_split_columns(tng, ctx, mt, nr, prec):
+    """Radial sizes that split a column among the waves of a workgroup, with a
+    partly filled last stretch, empty stretches (FP64 nr 160 and 320, FP32 nr 288)
+    and workgroup ranges with seams; every block with Dirichlet rows."""
+    import torch
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    yu, yp = run_apply(tng, ctx, mesh, t, OPS_ALL, dt)
+    ru, rp = orc.apply(u, p)
+    gu = lm.from_lib(yu, check_dups=1e-6)
+    gp = lmp.from_lib(yp, check_dups=1e-6)
+    print(f"split {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
+    assert rel(gu, ru) < tol and rel(gp, rp) < tol

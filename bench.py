@@ -202,9 +202,8 @@ def bench_coupled(tng, ctx, mt, nr, steps):
             "per_step": per_step, "kernels": kernels}
 
 
-def bench_serving(tng, ctx, nreq, rate_factor, budget):
-    """Poisson-arrival request stream over (16,16), (32,32), (64,64) shells."""
-    import numpy as np
+def serving_fields(tng, nreq):
+    """Seeded requests over (16,16), (32,32), (64,64) shells and their device buffers."""
     import torch
     import synthetic
     levels = [(16, 16), (32, 32), (64, 64)]
@@ -220,34 +219,86 @@ def bench_serving(tng, ctx, nreq, rate_factor, budget):
         mt, nr = levels[rq["level"]]
         p = torch.empty((10, mt // 2 + 1, mt // 2 + 1, nr // 2 + 1), device="cuda", dtype=torch.float64)
         fields.append((Tt, u, p))
-    srv = tng.Server(ctx, levels, budget_bytes=budget, max_slots=16, mixed=1, rtol=1e-8)
-    # saturated throughput: everything submitted at once
-    t0 = time.perf_counter()
-    tk = [srv.submit(rq["level"], *fields[i][:1], rq["log10_contrast"], 1e5, fields[i][1], fields[i][2])
-          for i, rq in enumerate(reqs)]
-    srv.wait(0)
-    mu = nreq / (time.perf_counter() - t0)
-    # Poisson arrivals at rate_factor * mu
-    lam = rate_factor * mu
-    arr = synthetic.poisson_arrivals(nreq, lam, seed=7)
+    return levels, reqs, fields
+
+
+def serving_run(srv, reqs, fields, arrivals, tag):
+    """Submits request i at arrivals[i] seconds (all at once if None); returns the
+    per-request latencies (arrival -> result on the device), successes and wall time."""
+    import numpy as np
     t0 = time.perf_counter()
     tk = []
     for i, rq in enumerate(reqs):
-        while time.perf_counter() - t0 < arr[i]:
-            time.sleep(2e-4)
+        if arrivals is not None:
+            while time.perf_counter() - t0 < arrivals[i]:
+                time.sleep(2e-4)
         tk.append(srv.submit(rq["level"], fields[i][0], rq["log10_contrast"], 1e5, fields[i][1], fields[i][2]))
+        if (i + 1) % 64 == 0:
+            log(f"[bench] serving {tag}: {i + 1} submitted")
     srv.wait(0)
     total = time.perf_counter() - t0
     lat = np.array([srv.poll(t)["latency"] for t in tk])
-    ok = sum(srv.poll(t)["rc"] == 0 for t in tk)
+    ok = int(sum(srv.poll(t)["rc"] == 0 for t in tk))
+    return lat, ok, total
+
+
+def bench_serving(tng, ctx, nreq, rate_factor, budget):
+    """Poisson-arrival request stream over (16,16), (32,32), (64,64) shells."""
+    import numpy as np
+    import synthetic
+    levels, reqs, fields = serving_fields(tng, nreq)
+    srv = tng.Server(ctx, levels, budget_bytes=budget, max_slots=16, mixed=1, rtol=1e-8)
+    _, _, tsat = serving_run(srv, reqs, fields, None, "saturated")   # everything submitted at once
+    mu = nreq / tsat
+    lam = rate_factor * mu
+    lat, ok, total = serving_run(srv, reqs, fields, synthetic.poisson_arrivals(nreq, lam, seed=7), "poisson")
     st = srv.stats()
     srv.close()
-    return {"requests": nreq, "ok": int(ok), "saturated_solves_per_s": round(mu, 2),
+    return {"requests": nreq, "ok": ok, "saturated_solves_per_s": round(mu, 2),
             "lambda_per_s": round(lam, 2), "solves_per_s": round(nreq / total, 2),
             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
             "slots": st["slots"], "budget_bytes": budget, "bytes_in_use": st["bytes_in_use"],
             "levels": levels}
+
+
+def bench_serving_sweep(tng, ctx, nreq=256, factors=(0.25, 0.5, 0.75, 0.95), budget=200 << 30,
+                        tight_budget=2 << 30):
+    """The serving stream at its saturated rate mu and at Poisson arrival rates
+    lambda = f mu, each with p50/p99 latency and throughput, then the saturated
+    stream again under a tight HBM budget."""
+    import numpy as np
+    import synthetic
+    levels, reqs, fields = serving_fields(tng, nreq)
+    srv = tng.Server(ctx, levels, budget_bytes=budget, max_slots=16, mixed=1, rtol=1e-8)
+    lat, ok, tsat = serving_run(srv, reqs, fields, None, "saturated")
+    mu = nreq / tsat
+    rows = [{"lambda_factor": None, "lambda_per_s": None, "ok": ok, "solves_per_s": round(mu, 3),
+             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 1)}]
+    log(f"[bench] serving saturated: {rows[-1]}")
+    for li, f in enumerate(factors):
+        lam = f * mu
+        lat, ok, total = serving_run(srv, reqs, fields, synthetic.poisson_arrivals(nreq, lam, seed=7 + li),
+                                     f"lambda={f}mu")
+        rows.append({"lambda_factor": f, "lambda_per_s": round(lam, 3), "ok": ok,
+                     "solves_per_s": round(nreq / total, 3),
+                     "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                     "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 1)})
+        log(f"[bench] serving {rows[-1]}")
+    st = srv.stats()
+    srv.close()
+    tight = tng.Server(ctx, levels, budget_bytes=tight_budget, max_slots=16, mixed=1, rtol=1e-8)
+    lat, ok, total = serving_run(tight, reqs, fields, None, "tight budget")
+    tst = tight.stats()
+    tight.close()
+    return {"workload": f"{nreq} Stokes solve requests over the (16,16), (32,32), (64,64) shells, contrast "
+                        "10^U(2,6), T with l = 1..16, mixed precision to 1e-8",
+            "budget_bytes": budget, "slots_used": st["slots"], "runs": rows,
+            "tight_budget": {"budget_bytes": tight_budget, "ok": ok, "solves_per_s": round(nreq / total, 3),
+                             "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                             "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+                             "slots_live_at_end": tst["slots"], "bytes_in_use_at_end": tst["bytes_in_use"]}}
 
 
 def cpu_baseline(mt=16, nr=16, reps=10):
@@ -299,6 +350,9 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of a known size (for HBM counter calibration)")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="instead: 256-request serving stream at the saturated rate and four Poisson "
+                         "rates, plus a tight 2 GiB budget; one JSON report line")
     ap.add_argument("--coupled", action="store_true",
                     help="instead: coupled Stokes-energy steps on the (--mt, --nr) shell (default (256,256), "
                          "--steps steps), one JSON report line")
@@ -312,6 +366,9 @@ def main():
     import paper_2609_21633_amd as tng
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = tng.Context(0)
+    if args.serving_sweep:
+        print(json.dumps(bench_serving_sweep(tng, ctx)), flush=True)
+        return
     if args.coupled:
         cm = args.mt if "--mt" in sys.argv else 256
         cn = args.nr if "--nr" in sys.argv else 256

@@ -210,10 +210,15 @@ def serving_fields(tng, nreq):
     reqs = synthetic.serving_requests(nreq, levels)
     fields = []
     meshes = [tng.Mesh(None, mt, nr, levels=1) for mt, nr in levels]
-    for rq in reqs:
+    coords = [m.coords(0) for m in meshes]
+    bases = [synthetic.harmonic_basis(xyz.reshape(-1, 3), 1, 16) for xyz, _ in coords]
+    for i, rq in enumerate(reqs):
         mesh = meshes[rq["level"]]
-        xyz, r = mesh.coords(0)
-        T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=rq["seed"], lmin=1, lmax=16)
+        xyz, r = coords[rq["level"]]
+        T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=rq["seed"], lmin=1, lmax=16,
+                                  basis=bases[rq["level"]])
+        if (i + 1) % 32 == 0:
+            log(f"[bench] serving fields: {i + 1} of {len(reqs)}")
         Tt = torch.tensor(T.reshape(mesh.shape(0)), device="cuda")
         u = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
         mt, nr = levels[rq["level"]]

@@ -49,29 +49,37 @@ def _real_sph_harm(l: int, m: int, theta, phi):
     return np.sqrt(2.0) * (np.real(y) if m > 0 else np.imag(y))
 
 
-def _harmonic_pattern(unit_xyz: np.ndarray, lmin: int, lmax: int, rng) -> np.ndarray:
+def harmonic_basis(unit_xyz: np.ndarray, lmin: int, lmax: int) -> np.ndarray:
+    """[n_points, n_harmonics] real orthonormal Y_lm, l-major then m = -l..l, for
+    reuse by many temperature draws on the same points."""
+    unit_xyz = np.asarray(unit_xyz, np.float64)
     x, y, z = unit_xyz[:, 0], unit_xyz[:, 1], unit_xyz[:, 2]
     theta = np.arccos(np.clip(z, -1.0, 1.0))
     phi = np.arctan2(y, x)
-    a = np.zeros(len(unit_xyz))
-    for l in range(lmin, lmax + 1):
-        c = rng.standard_normal(2 * l + 1)          # m = -l .. l
-        for i, m in enumerate(range(-l, l + 1)):
-            a += c[i] * _real_sph_harm(l, m, theta, phi)
+    cols = [_real_sph_harm(l, m, theta, phi) for l in range(lmin, lmax + 1) for m in range(-l, l + 1)]
+    return np.stack(cols, axis=1)
+
+
+def _harmonic_pattern(unit_xyz: np.ndarray, lmin: int, lmax: int, rng, basis=None) -> np.ndarray:
+    if basis is None:
+        basis = harmonic_basis(unit_xyz, lmin, lmax)
+    c = np.concatenate([rng.standard_normal(2 * l + 1) for l in range(lmin, lmax + 1)])
+    a = basis @ c
     return a / np.max(np.abs(a))
 
 
 def temperature(unit_xyz: np.ndarray, r: np.ndarray, seed: int, r_in: float = 0.55,
-                r_out: float = 1.0, lmin: int = 1, lmax: int = 8, amp: float = 0.01):
+                r_out: float = 1.0, lmin: int = 1, lmax: int = 8, amp: float = 0.01, basis=None):
     """Initial temperature on a tensor grid of lateral points x radii.
 
     T(s, r) = T_cond(r) + amp * A(s) * sin(pi (r - r_in) / (r_out - r_in)), with
     A = sum_{l=lmin..lmax} sum_m c_lm Y_lm (real, orthonormal), c_lm ~ N(0, 1)
     drawn l-major then m = -l..l, and A rescaled so that max |A| = 1 over the
-    given lateral points.  Returns [n_lat, n_r].
+    given lateral points.  Returns [n_lat, n_r].  basis: harmonic_basis(unit_xyz,
+    lmin, lmax) of the same points, to skip re-evaluating the harmonics.
     """
     rng = np.random.default_rng(seed)
-    A = _harmonic_pattern(np.asarray(unit_xyz, np.float64), lmin, lmax, rng)
+    A = _harmonic_pattern(np.asarray(unit_xyz, np.float64), lmin, lmax, rng, basis)
     r = np.asarray(r, dtype=np.float64)
     prof = conductive_profile(r, r_in, r_out)
     bump = np.sin(np.pi * (r - r_in) / (r_out - r_in))

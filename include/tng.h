@@ -211,7 +211,10 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  * inner_rtol, inner_max_iters, max_outer: mixed-precision inner tolerance and
  *   iteration limit per refinement step, and the refinement step limit.
  * hg_alpha: hourglass control (eq:hgstab, see tng_stokes_apply) of the viscous
- *   block on every level: the solve is then of that stabilised operator. */
+ *   block on every level: the solve is then of that stabilised operator.
+ * graphs: 1 (default) replays the preconditioner of each Krylov index as a
+ *   HIP graph captured at its first use (on a private stream ordered with the
+ *   context's stream by events); 0 launches every kernel from the host. */
 typedef struct {
     int mixed;
     int restart;
@@ -226,6 +229,7 @@ typedef struct {
     int max_outer;
     int power_its;
     double hg_alpha;
+    int graphs;
 } tng_solver_opts;
 
 /* outer_its: refinement steps (1 in FP64 mode); inner_its: FGMRES iterations

@@ -265,7 +265,7 @@ class SolverOpts(C.Structure):
                 ("cheb_degree", C.c_int), ("pre", C.c_int), ("post", C.c_int), ("levels", C.c_int),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("inner_rtol", C.c_double),
                 ("inner_max_iters", C.c_int), ("max_outer", C.c_int), ("power_its", C.c_int),
-                ("hg_alpha", C.c_double)]
+                ("hg_alpha", C.c_double), ("graphs", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -350,8 +350,9 @@ class StokesSolver:
 
 
 class Server:
-    """Request server: levels = [(mt, nr), ...]; every slot runs a (normally
-    mixed-precision) solver on its own stream."""
+    """Request server: levels = [(mt, nr), ...]; the slots of a level form one
+    lockstep batch (one launch per kernel for all running slots) on the level's
+    own stream; solver options as for StokesSolver (normally mixed precision)."""
 
     def __init__(self, ctx: Context, levels, budget_bytes: int, max_slots: int = 64, **opts):
         o = SolverOpts()

@@ -73,7 +73,10 @@ void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, double hg_alph
         TNG_HIP(hipMemcpyAsync(xx.p + c * ns, x[c], ns * sizeof(T), hipMemcpyDeviceToDevice, st));
     }
     tng::vec_invert<T>(ctx, n3, invd.p);
-    tng::chebyshev_steps<T>(ctx, L, (const T*)eta, hg_alpha, invd.p, bb.p, xx.p, y.p, d.p, degree, steps, lmin, lmax,
+    const std::vector<double> ab = tng::chebyshev_coefficients(degree, lmin, lmax);
+    tng::DevBuf<double> abd(ab.size());
+    abd.upload(ab.data(), ab.size(), st);
+    tng::chebyshev_steps<T>(ctx, L, (const T*)eta, hg_alpha, invd.p, bb.p, xx.p, y.p, d.p, abd.p, degree, steps,
                             false);
     for (int c = 0; c < 3; ++c)
         TNG_HIP(hipMemcpyAsync(x[c], xx.p + c * ns, ns * sizeof(T), hipMemcpyDeviceToDevice, st));

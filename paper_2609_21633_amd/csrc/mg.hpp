@@ -10,7 +10,7 @@
 namespace tng {
 
 constexpr int MAX_MDOT = 24;          // vectors in one multi-dot / multi-axpy
-constexpr int DOT_BLOCKS = 1024;      // partial sums of a reduction
+constexpr int DOT_BLOCKS = 4096;      // partial sums of a reduction (enough waves to fill HBM)
 constexpr int MAX_COARSE_DOF = 1024;  // dense coarsest-level solve
 
 template <typename T>
@@ -43,8 +43,9 @@ template <typename T>
 void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* const f[3], bool add);
 template <typename T>
 void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]);
+// x, d <- one Chebyshev step with (alpha, beta) = ab_dev[2k], ab_dev[2k + 1]
 template <typename T>
-void vec_cheb_update(const tng_ctx* ctx, long long n, double alpha, double beta, const T* b, const T* y,
+void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int k, const T* b, const T* y,
                      const T* invd, T* d, T* x);
 template <typename T>
 void vec_invert(const tng_ctx* ctx, long long n, T* a);
@@ -80,6 +81,14 @@ template <typename T>
 void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a);
 template <typename T>
 void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* x, T* y);
+// y = f x: x = src or src_tab[idx], y = dst or dst_tab[idx] (idx per slot in a
+// batch with counts), f = 1 / sqrt(*sq) or 1 when sq is NULL
+template <typename T>
+void vec_tab_copy(const tng_ctx* ctx, long long n, const T* src, const T* const* src_tab, T* dst, T* const* dst_tab,
+                  int idx, const double* sq);
+// staging[z * k + i] = src_z[i] and dst_z[i] = staging[z * k + i] for the slots z of a batch
+void scal_gather(const tng_ctx* ctx, const double* src, int k, double* staging);
+void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst);
 template <typename T>
 void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha);
 
@@ -96,8 +105,11 @@ void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], doubl
 template <typename T>
 void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]);
 
+// Coefficients (alpha_k, beta_k), k < deg, of one Chebyshev smoothing step of
+// degree deg for the eigenvalue interval [lo, hi].
+std::vector<double> chebyshev_coefficients(int deg, double lo, double hi);
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
-                     T* x, T* y, T* d, int deg, int steps, double lo, double hi, bool x_zero);
+                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero);
 
 }  // namespace tng

@@ -7,6 +7,7 @@
 // in every copy of a shared node.  Gathers that run per diamond produce
 // partial sums on diamond-edge nodes; the interface kernel then adds the
 // copies.  Reductions count every unique node once (owner mask).
+#include "batch_dev.hpp"
 #include "tng_internal.hpp"
 #include "mg.hpp"
 #include "wedge.hpp"
@@ -15,6 +16,13 @@ namespace tng {
 namespace {
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// per-slot vector counts of a batched multi-dot / multi-axpy stay in range
+inline void check_counts(const SlotBatch& sb) {
+    if (!sb.has_cnt) return;
+    for (int z = 0; z < sb.nb; ++z)
+        TNG_REQUIRE(sb.cnt[z] >= 1 && sb.cnt[z] <= MAX_MDOT, "per-slot vector count out of range");
+}
 
 __constant__ IsoWeights<double> c_isomg = make_iso_weights<double>();
 
@@ -141,7 +149,15 @@ __global__ void pmass_kernel(const T* __restrict__ eta, const double* __restrict
 // layers take the mean of the two coarse layers.  y += P x (add) or y = P x.
 template <typename T>
 __global__ void prolong_kernel(int mf, int nf, const T* __restrict__ c0, const T* __restrict__ c1,
-                               const T* __restrict__ c2, T* f0, T* f1, T* f2, int add, long long nslots) {
+                               const T* __restrict__ c2, T* f0, T* f1, T* f2, int add, long long nslots,
+                               SlotBatch sb) {
+    const long long so = slot_off(sb);
+    c0 = at_slot(c0, so);
+    c1 = at_slot(c1, so);
+    c2 = at_slot(c2, so);
+    f0 = at_slot(f0, so);
+    f1 = at_slot(f1, so);
+    f2 = at_slot(f2, so);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const NodeIdx q = decode_node(t, mf, nf);
@@ -175,7 +191,14 @@ __global__ void prolong_kernel(int mf, int nf, const T* __restrict__ c0, const T
 template <typename T>
 __global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const T* __restrict__ f1,
                                 const T* __restrict__ f2, const T* __restrict__ inv_mult,
-                                T* c0, T* c1, T* c2, long long ncslots) {
+                                T* c0, T* c1, T* c2, long long ncslots, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    f0 = at_slot(f0, so);
+    f1 = at_slot(f1, so);
+    f2 = at_slot(f2, so);
+    c0 = at_slot(c0, so);
+    c1 = at_slot(c1, so);
+    c2 = at_slot(c2, so);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncslots) return;
     const int mc = mf / 2, nc = nf / 2;
@@ -206,16 +229,44 @@ __global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const 
 }
 
 // One Chebyshev step of the smoother on D^{-1} A, fused after y = A x:
-//   d <- alpha d + beta D^{-1} (b - y),   x <- x + d.
+//   d <- alpha d + beta D^{-1} (b - y),   x <- x + d,
+// with (alpha, beta) = ab[2k], ab[2k + 1] (per slot: they scale with the
+// slot's eigenvalue estimate).
+constexpr int EW_PER = 4;   // elements per thread of the streaming elementwise kernels
+
 template <typename T>
-__global__ void cheb_update_kernel(long long n, T alpha, T beta, const T* __restrict__ b,
-                                   const T* __restrict__ y, const T* __restrict__ invd, T* d, T* x) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const T r = beta * invd[t] * (b[t] - y[t]);
-    const T dv = alpha == T(0) ? r : alpha * d[t] + r;   // d may hold garbage on the first step
-    d[t] = dv;
-    x[t] += dv;
+__global__ void __launch_bounds__(256) cheb_update_kernel(long long n, const double* __restrict__ ab, int k,
+                                                          const T* __restrict__ b, const T* __restrict__ y,
+                                                          const T* __restrict__ invd, T* d, T* x, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    ab = at_slot(ab, so);
+    b = at_slot(b, so);
+    y = at_slot(y, so);
+    invd = at_slot(invd, so);
+    d = at_slot(d, so);
+    x = at_slot(x, so);
+    const T alpha = T(ab[2 * k]), beta = T(ab[2 * k + 1]);
+    const long long t0 = (long long)blockIdx.x * (256 * EW_PER) + threadIdx.x;
+    T bv[EW_PER], yv[EW_PER], iv[EW_PER], dv[EW_PER], xv[EW_PER];
+#pragma unroll
+    for (int e = 0; e < EW_PER; ++e) {
+        const long long t = t0 + e * 256;
+        const bool in = t < n;
+        bv[e] = in ? b[t] : T(0);
+        yv[e] = in ? y[t] : T(0);
+        iv[e] = in ? invd[t] : T(0);
+        dv[e] = in && alpha != T(0) ? d[t] : T(0);   // d may hold garbage on the first step
+        xv[e] = in ? x[t] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EW_PER; ++e) {
+        const long long t = t0 + e * 256;
+        if (t >= n) break;
+        const T r = beta * iv[e] * (bv[e] - yv[e]);
+        const T nd = alpha == T(0) ? r : alpha * dv[e] + r;
+        d[t] = nd;
+        x[t] = xv[e] + nd;
+    }
 }
 
 template <typename T>
@@ -236,44 +287,77 @@ __global__ void diag_dirichlet_kernel(long long ncol, int n, T* d0, T* d1, T* d2
 }
 
 template <typename TO, typename TI>
-__global__ void cast_kernel(long long n, const TI* __restrict__ a, TO* __restrict__ b) {
+__global__ void cast_kernel(long long n, const TI* __restrict__ a, TO* __restrict__ b, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    a = at_slot(a, so);
+    b = at_slot(b, so);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) b[t] = TO(a[t]);
 }
 
 // y <- a x + b y  (x may alias nothing; pass b = 0 to overwrite)
 template <typename T>
-__global__ void axpby_kernel(long long n, T a, const T* __restrict__ x, T b, T* y) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    y[t] = b == T(0) ? a * x[t] : a * x[t] + b * y[t];
+__global__ void __launch_bounds__(256) axpby_kernel(long long n, T a, const T* __restrict__ x, T b, T* y,
+                                                    SlotBatch sb) {
+    const long long so = slot_off(sb);
+    x = at_slot(x, so);
+    y = at_slot(y, so);
+    const long long t0 = (long long)blockIdx.x * (256 * EW_PER) + threadIdx.x;
+    T xv[EW_PER], yv[EW_PER];
+#pragma unroll
+    for (int e = 0; e < EW_PER; ++e) {
+        const long long t = t0 + e * 256;
+        xv[e] = t < n ? x[t] : T(0);
+        yv[e] = t < n && b != T(0) ? y[t] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EW_PER; ++e) {
+        const long long t = t0 + e * 256;
+        if (t >= n) break;
+        y[t] = b == T(0) ? a * xv[e] : a * xv[e] + b * yv[e];
+    }
 }
 
-// Multi-dot partials: for every vector v_q (q < nq) the block sum of
-// mask(slot) x v_q over one segment; a second kernel adds the block sums in a
-// fixed order, so the result does not depend on timing.
+// Multi-dot partials: for every vector v_q (q < nq <= NQ) the block sum of
+// mask(slot) x v_q over one grid-stride share; a second kernel adds the block
+// sums in a fixed order, so the result does not depend on timing.  Node slot
+// t lies in radial column t / n1 (division by a magic multiplier, exact for
+// all 32-bit t); the owner mask counts every unique node once.  The vector
+// pointers are read once per block into scalar registers, and every load of
+// an element is issued before the first use.
 constexpr int DOT_BS = 256;
-template <typename T>
-__global__ void mdot_partial_kernel(unsigned n, unsigned n1, unsigned nlat, const uint8_t* __restrict__ owner,
-                                    const T* __restrict__ x, const T* const* __restrict__ vs, int nq,
-                                    double* __restrict__ part) {
-    __shared__ double sh[DOT_BS / 64][MAX_MDOT];
-    __shared__ const T* vp[MAX_MDOT];
-    if (threadIdx.x < nq) vp[threadIdx.x] = vs[threadIdx.x];
-    __syncthreads();
-    double acc[MAX_MDOT];
-#pragma unroll
-    for (int q = 0; q < MAX_MDOT; ++q) acc[q] = 0.0;
-    for (unsigned t = blockIdx.x * DOT_BS + threadIdx.x; t < n; t += gridDim.x * DOT_BS) {
-        if (!owner[(t / n1) % nlat]) continue;
-        const double xv = (double)x[t];
-#pragma unroll
-        for (int q = 0; q < MAX_MDOT; ++q)
-            if (q < nq) acc[q] += xv * (double)vp[q][t];
-    }
+
+struct MagicDiv {
+    unsigned mul;   // ceil(2^(32 + sh) / d) - 2^32
+    int sh;         // ceil(log2 d)
+};
+inline MagicDiv magic_div(unsigned d) {
+    MagicDiv m{0u, 0};
+    while ((1ull << m.sh) < d) ++m.sh;
+    const unsigned long long big = 1ull << (32 + m.sh);
+    m.mul = (unsigned)((big + d - 1) / d - (1ull << 32));
+    return m;
+}
+__device__ __forceinline__ unsigned mdiv(unsigned t, MagicDiv m) {
+    return (unsigned)((((unsigned long long)__umulhi(t, m.mul)) + t) >> m.sh);
+}
+
+// A pointer read from a table lost its address space; loads through this
+// global-memory pointer type are global, not flat, instructions.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+    return (gptr<T>)p;
+}
+
+// Block sums of acc[q], q < nq, to part[blockIdx.x][q] (fixed order).
+template <int NQ>
+__device__ __forceinline__ void block_partials(const double (&acc)[NQ], int nq, double* __restrict__ part) {
+    __shared__ double sh[DOT_BS / 64][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < MAX_MDOT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         if (q >= nq) break;
         double v = acc[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -287,21 +371,91 @@ __global__ void mdot_partial_kernel(unsigned n, unsigned n1, unsigned nlat, cons
     }
 }
 
-// y <- y + sign * sum_q coef[q] v_q, coefficients read from device memory
-template <typename T>
-__global__ void maxpy_kernel(unsigned n, const double* __restrict__ coef, double sign,
-                             const T* const* __restrict__ vs, int nq, T* y) {
-    __shared__ const T* vp[MAX_MDOT];
-    __shared__ double cf[MAX_MDOT];
-    if (threadIdx.x < nq) {
-        vp[threadIdx.x] = vs[threadIdx.x];
-        cf[threadIdx.x] = sign * coef[threadIdx.x];
+// n slots of up to three node-field components of one level (n1 layers per
+// column, nlat lateral slots per component).
+template <typename T, int NQ>
+__global__ void __launch_bounds__(DOT_BS) mdot_partial_kernel(unsigned n, MagicDiv dn1, unsigned nlat,
+                                                              const uint8_t* __restrict__ owner,
+                                                              const T* __restrict__ x, const T* const* __restrict__ vs,
+                                                              int nq, double* __restrict__ part, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    x = at_slot(x, so);
+    vs = at_slot(vs, so);
+    part = at_slot(part, so);
+    nq = slot_count(sb, nq);
+    gptr<T> vp[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) vp[q] = as_global(vs[q < nq ? q : 0]);
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    // two elements per step, every load (mask and data) issued before the first use
+    const unsigned stride = gridDim.x * DOT_BS;
+    for (unsigned t0 = blockIdx.x * DOT_BS + threadIdx.x; t0 < n; t0 += 2 * stride) {
+        T xv[2], v[2][NQ];
+        bool own[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            const bool in = t < n;
+            const unsigned tt = in ? t : 0;
+            unsigned lat = mdiv(tt, dn1);
+            lat = lat >= nlat ? lat - nlat : lat;
+            lat = lat >= nlat ? lat - nlat : lat;
+            own[e] = in && owner[lat];
+            xv[e] = x[tt];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[e][q] = q < nq ? vp[q][tt] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!own[e]) continue;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)xv[e] * (double)v[e][q];
+        }
     }
-    __syncthreads();
-    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        double acc = (double)y[t];
-        for (int q = 0; q < nq; ++q) acc += cf[q] * (double)vp[q][t];
-        y[t] = T(acc);
+    block_partials<NQ>(acc, nq, part);
+}
+
+// y <- y + sign * sum_q coef[q] v_q (q < nq <= NQ), coefficients read from
+// device memory; pointers and coefficients in scalar registers, all loads of
+// an element in flight together.
+template <typename T, int NQ>
+__global__ void __launch_bounds__(256) maxpy_kernel(unsigned n, const double* __restrict__ coef, double sign,
+                                                    const T* const* __restrict__ vs, int nq, T* y, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    coef = at_slot(coef, so);
+    vs = at_slot(vs, so);
+    y = at_slot(y, so);
+    nq = slot_count(sb, nq);
+    gptr<T> vp[NQ];
+    double cf[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        vp[q] = as_global(vs[q < nq ? q : 0]);
+        cf[q] = q < nq ? sign * coef[q] : 0.0;
+    }
+    const unsigned stride = gridDim.x * blockDim.x;
+    for (unsigned t0 = blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 2 * stride) {
+        T v[2][NQ], yv[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            const unsigned tt = t < n ? t : 0;
+            yv[e] = y[tt];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[e][q] = q < nq ? vp[q][tt] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            if (t >= n) break;
+            double acc = (double)yv[e];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) acc += cf[q] * (double)v[e][q];
+            y[t] = T(acc);
+        }
     }
 }
 
@@ -311,17 +465,27 @@ __global__ void mul_kernel(unsigned n, const T* __restrict__ a, const T* __restr
 }
 
 template <typename T>
-__global__ void fillv_kernel(unsigned n, T v, T* a) {
+__global__ void fillv_kernel(unsigned n, T v, T* a, SlotBatch sb) {
+    a = at_slot(a, slot_off(sb));
     for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) a[t] = v;
 }
 
-__global__ void mdot_final_kernel(int nblocks, int nq, const double* __restrict__ part, double* out,
-                                  int accumulate) {
-    const int q = threadIdx.x;
-    if (q >= nq) return;
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v += part[(long long)b * MAX_MDOT + q];
-    out[q] = accumulate ? out[q] + v : v;
+// out[q] = sum of the block partials of vector q: wave w takes q = w, w + 4,
+// ..., every lane a fixed strided share of the blocks, then a fixed shuffle
+// tree; the order depends only on nblocks.
+__global__ void __launch_bounds__(256) mdot_final_kernel(int nblocks, int nq, const double* __restrict__ part,
+                                                         double* out, int accumulate, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    part = at_slot(part, so);
+    out = at_slot(out, so);
+    nq = slot_count(sb, nq);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = wv; q < nq; q += 4) {
+        double v = 0.0;
+        for (int b = lane; b < nblocks; b += 64) v += part[(long long)b * MAX_MDOT + q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) out[q] = accumulate ? out[q] + v : v;
+    }
 }
 
 // Dense coarsest level ------------------------------------------------------
@@ -377,7 +541,18 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(int nd, const int* _
                                                             const int* __restrict__ slot_dof, long long nslots,
                                                             const double* __restrict__ Ainv,
                                                             const T* __restrict__ b0, const T* __restrict__ b1,
-                                                            const T* __restrict__ b2, T* x0, T* x1, T* x2) {
+                                                            const T* __restrict__ b2, T* x0, T* x1, T* x2,
+                                                            SlotBatch sb) {
+    const long long so = slot_off(sb);
+    dof_slot = at_slot(dof_slot, so);
+    slot_dof = at_slot(slot_dof, so);
+    Ainv = at_slot(Ainv, so);
+    b0 = at_slot(b0, so);
+    b1 = at_slot(b1, so);
+    b2 = at_slot(b2, so);
+    x0 = at_slot(x0, so);
+    x1 = at_slot(x1, so);
+    x2 = at_slot(x2, so);
     __shared__ double rhs[MAX_COARSE_DOF];
     __shared__ double sol[MAX_COARSE_DOF];
     for (int r = threadIdx.x; r < nd; r += blockDim.x) {
@@ -419,57 +594,77 @@ __global__ void unit_vector_kernel(long long nslots, const int* __restrict__ slo
 
 // Pressure: zero nodal mean projection helper  p <- p - mean
 template <typename T>
-__global__ void shift_kernel(long long n, const double* __restrict__ sum_cnt, T* p) {
+__global__ void shift_kernel(long long n, const double* __restrict__ sum_cnt, T* p, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    sum_cnt = at_slot(sum_cnt, so);
+    p = at_slot(p, so);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) p[t] -= T(sum_cnt[0] / sum_cnt[1]);
 }
 
 // Schur preconditioner on the pressure: z = -r / m (Sec. 7, eq:pmass)
 template <typename T>
-__global__ void schur_diag_kernel(long long n, const T* __restrict__ r, const T* __restrict__ mdiag, T* z) {
+__global__ void schur_diag_kernel(long long n, const T* __restrict__ r, const T* __restrict__ mdiag, T* z,
+                                  SlotBatch sb) {
+    const long long so = slot_off(sb);
+    r = at_slot(r, so);
+    mdiag = at_slot(mdiag, so);
+    z = at_slot(z, so);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) z[t] = -r[t] / mdiag[t];
 }
 
 // Multi-dot over a Stokes vector [u0 u1 u2 p] (velocity slots of one level
 // followed by its pressure slots): owner masks of both grids.
-template <typename T>
-__global__ void smdot_partial_kernel(unsigned ns, unsigned n1u, unsigned nlat_u, const uint8_t* __restrict__ ou,
-                                     unsigned np, unsigned n1p, const uint8_t* __restrict__ op,
-                                     const T* __restrict__ x, const T* const* __restrict__ vs, int nq,
-                                     double* __restrict__ part) {
-    __shared__ double sh[DOT_BS / 64][MAX_MDOT];
-    __shared__ const T* vp[MAX_MDOT];
-    if (threadIdx.x < nq) vp[threadIdx.x] = vs[threadIdx.x];
-    __syncthreads();
-    double acc[MAX_MDOT];
+template <typename T, int NQ>
+__global__ void __launch_bounds__(DOT_BS) smdot_partial_kernel(unsigned ns, MagicDiv dn1u, unsigned nlat_u,
+                                                               const uint8_t* __restrict__ ou, unsigned np,
+                                                               MagicDiv dn1p, const uint8_t* __restrict__ op,
+                                                               const T* __restrict__ x,
+                                                               const T* const* __restrict__ vs, int nq,
+                                                               double* __restrict__ part, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    x = at_slot(x, so);
+    vs = at_slot(vs, so);
+    part = at_slot(part, so);
+    nq = slot_count(sb, nq);
+    gptr<T> vp[NQ];
 #pragma unroll
-    for (int q = 0; q < MAX_MDOT; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) vp[q] = as_global(vs[q < nq ? q : 0]);
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     const unsigned nu = 3u * ns, n = nu + np;
-    for (unsigned t = blockIdx.x * DOT_BS + threadIdx.x; t < n; t += gridDim.x * DOT_BS) {
-        bool own;
-        if (t < nu) own = ou[(t / n1u) % nlat_u];
-        else own = op[(t - nu) / n1p];
-        if (!own) continue;
-        const double xv = (double)x[t];
+    // two elements per step, every load (mask and data) issued before the first use
+    const unsigned stride = gridDim.x * DOT_BS;
+    for (unsigned t0 = blockIdx.x * DOT_BS + threadIdx.x; t0 < n; t0 += 2 * stride) {
+        T xv[2], v[2][NQ];
+        bool own[2];
 #pragma unroll
-        for (int q = 0; q < MAX_MDOT; ++q)
-            if (q < nq) acc[q] += xv * (double)vp[q][t];
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            const bool in = t < n;
+            const unsigned tt = in ? t : 0;
+            if (tt < nu) {
+                unsigned lat = mdiv(tt, dn1u);
+                lat = lat >= nlat_u ? lat - nlat_u : lat;
+                lat = lat >= nlat_u ? lat - nlat_u : lat;
+                own[e] = in && ou[lat];
+            } else {
+                own[e] = in && op[mdiv(tt - nu, dn1p)];
+            }
+            xv[e] = x[tt];
 #pragma unroll
-    for (int q = 0; q < MAX_MDOT; ++q) {
-        if (q >= nq) break;
-        double v = acc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) sh[wv][q] = v;
+            for (int q = 0; q < NQ; ++q) v[e][q] = q < nq ? vp[q][tt] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!own[e]) continue;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)xv[e] * (double)v[e][q];
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < nq) {
-        double v = 0.0;
-        for (int w = 0; w < DOT_BS / 64; ++w) v += sh[w][threadIdx.x];
-        part[(long long)blockIdx.x * MAX_MDOT + threadIdx.x] = v;
-    }
+    block_partials<NQ>(acc, nq, part);
 }
 
 // Counter-based uniform numbers in [-1, 1) (splitmix64 of seed and index).
@@ -484,12 +679,48 @@ __global__ void rand_kernel(unsigned n, unsigned long long seed, T* a) {
     }
 }
 
-// y <- y / sqrt(s[0])  (normalise by a device-side squared norm)
+// y <- x / sqrt(s[0])  (normalise by a device-side squared norm)
 template <typename T>
-__global__ void scale_rsqrt_kernel(unsigned n, const double* __restrict__ s, const T* __restrict__ x, T* y) {
+__global__ void scale_rsqrt_kernel(unsigned n, const double* __restrict__ s, const T* __restrict__ x, T* y,
+                                   SlotBatch sb) {
+    const long long so = slot_off(sb);
+    s = at_slot(s, so);
+    x = at_slot(x, so);
+    y = at_slot(y, so);
     const double f = 1.0 / sqrt(s[0]);
     for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
         y[t] = T(f * (double)x[t]);
+}
+
+// y <- f x with x = src or the table entry src_tab[i], y = dst or dst_tab[i]
+// (i: the slot's table index), f = 1 / sqrt(sq[0]) when sq is given, else 1.
+// Moves vectors in and out of a Krylov basis whose index differs per slot.
+template <typename T>
+__global__ void tab_copy_kernel(unsigned n, const T* __restrict__ src, const T* const* __restrict__ src_tab,
+                                T* dst, T* const* __restrict__ dst_tab, int idx, const double* __restrict__ sq,
+                                SlotBatch sb) {
+    using gw = __attribute__((address_space(1))) T*;
+    const long long so = slot_off(sb);
+    const int i = slot_count(sb, idx);
+    const gptr<T> x = src_tab ? as_global(at_slot(src_tab, so)[i]) : as_global(at_slot(src, so));
+    const gw y = dst_tab ? (gw)at_slot(dst_tab, so)[i] : (gw)at_slot(dst, so);
+    if (sq) {
+        const double f = 1.0 / sqrt(at_slot(sq, so)[0]);
+        for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+            y[t] = T(f * (double)x[t]);
+    } else {
+        for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) y[t] = x[t];
+    }
+}
+
+// Short per-slot arrays to and from one shared staging array (row z: slot z).
+__global__ void scal_gather_kernel(const double* __restrict__ src, int k, double* __restrict__ dst, SlotBatch sb) {
+    src = at_slot(src, slot_off(sb));
+    for (int i = threadIdx.x; i < k; i += blockDim.x) dst[(long long)blockIdx.z * k + i] = src[i];
+}
+__global__ void scal_scatter_kernel(const double* __restrict__ src, int k, double* __restrict__ dst, SlotBatch sb) {
+    dst = at_slot(dst, slot_off(sb));
+    for (int i = threadIdx.x; i < k; i += blockDim.x) dst[i] = src[(long long)blockIdx.z * k + i];
 }
 
 // Column `col` of D A D on the coarsest level, assembled from the one-point
@@ -567,6 +798,7 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
 
 template <typename T>
 void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3]) {
+    require_unbatched("mg_diag_A");
     const long long ns = L.node_slots();
     diag_A_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(),
                                                              hg_alpha, d[0], d[1], d[2], ns);
@@ -580,6 +812,7 @@ void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha
 
 template <typename T>
 void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag) {
+    require_unbatched("mg_pmass");
     const long long ns = Lp.node_slots();
     pmass_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(), mdiag, ns);
     TNG_HIP(hipGetLastError());
@@ -590,8 +823,9 @@ void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta,
 template <typename T>
 void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* const f[3], bool add) {
     const long long ns = Lf.node_slots();
-    prolong_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(Lf.m, Lf.n, c[0], c[1], c[2], f[0], f[1], f[2],
-                                                              add ? 1 : 0, ns);
+    const SlotBatch sb = launch_batch();
+    prolong_kernel<T><<<dim3(nblk(ns, 256), 1, sb.nb), 256, 0, ctx->stream>>>(Lf.m, Lf.n, c[0], c[1], c[2], f[0],
+                                                                              f[1], f[2], add ? 1 : 0, ns, sb);
     TNG_HIP(hipGetLastError());
 }
 
@@ -599,47 +833,77 @@ template <typename T>
 void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]) {
     const long long ns = Lc.node_slots();
     const T* im = std::is_same<T, double>::value ? (const T*)Lf.inv_mult64.p : (const T*)Lf.inv_mult32.p;
-    restrict_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(Lf.m, Lf.n, f[0], f[1], f[2], im, c[0], c[1],
-                                                               c[2], ns);
+    const SlotBatch sb = launch_batch();
+    restrict_kernel<T><<<dim3(nblk(ns, 256), 1, sb.nb), 256, 0, ctx->stream>>>(Lf.m, Lf.n, f[0], f[1], f[2], im,
+                                                                               c[0], c[1], c[2], ns, sb);
     TNG_HIP(hipGetLastError());
     void* g[3] = {c[0], c[1], c[2]};
     launch_interface(ctx, Lc, prec_of<T>(), 0, 3, g);
 }
 
 template <typename T>
-void vec_cheb_update(const tng_ctx* ctx, long long n, double alpha, double beta, const T* b, const T* y,
+void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int k, const T* b, const T* y,
                      const T* invd, T* d, T* x) {
-    cheb_update_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, T(alpha), T(beta), b, y, invd, d, x);
+    const SlotBatch sb = launch_batch();
+    cheb_update_kernel<T><<<dim3(nblk(n, 256 * EW_PER), 1, sb.nb), 256, 0, ctx->stream>>>(n, ab_dev, k, b, y, invd, d, x,
+                                                                                  sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void vec_invert(const tng_ctx* ctx, long long n, T* a) {
+    require_unbatched("vec_invert");
     invert_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, a);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename TO, typename TI>
 void vec_cast(const tng_ctx* ctx, long long n, const TI* a, TO* b) {
-    cast_kernel<TO, TI><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, a, b);
+    const SlotBatch sb = launch_batch();
+    cast_kernel<TO, TI><<<dim3(nblk(n, 256), 1, sb.nb), 256, 0, ctx->stream>>>(n, a, b, sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void vec_axpby(const tng_ctx* ctx, long long n, double a, const T* x, double b, T* y) {
-    axpby_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, T(a), x, T(b), y);
+    const SlotBatch sb = launch_batch();
+    axpby_kernel<T><<<dim3(nblk(n, 256 * EW_PER), 1, sb.nb), 256, 0, ctx->stream>>>(n, T(a), x, T(b), y, sb);
     TNG_HIP(hipGetLastError());
 }
+
+// smallest compiled vector count >= every slot's count
+inline int count_class(const SlotBatch& sb, int nq) {
+    int mx = nq;
+    if (sb.has_cnt)
+        for (int z = 0; z < sb.nb; ++z) mx = std::max(mx, sb.cnt[z]);
+    return mx <= 1 ? 1 : mx <= 2 ? 2 : mx <= 4 ? 4 : mx <= 8 ? 8 : mx <= 12 ? 12 : mx <= 16 ? 16 : MAX_MDOT;
+}
+
+#define TNG_NQ_DISPATCH(NQV, CALL)                     \
+    switch (NQV) {                                     \
+        case 1: { constexpr int NQ = 1; CALL; } break;  \
+        case 2: { constexpr int NQ = 2; CALL; } break;  \
+        case 4: { constexpr int NQ = 4; CALL; } break;  \
+        case 8: { constexpr int NQ = 8; CALL; } break;  \
+        case 12: { constexpr int NQ = 12; CALL; } break; \
+        case 16: { constexpr int NQ = 16; CALL; } break; \
+        default: { constexpr int NQ = MAX_MDOT; CALL; } break; \
+    }
 
 template <typename T>
 void vec_mdot(const tng_ctx* ctx, DotScratch& ds, long long n, int n1, long long nlat, const uint8_t* owner,
               const T* x, const T* const* vs_dev, int nq, double* out_dev, bool accumulate) {
     TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-dot");
+    TNG_REQUIRE(n <= 3LL * nlat * n1 && n < (1LL << 32), "multi-dot length out of range");
     const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
-    mdot_partial_kernel<T><<<nb, DOT_BS, 0, ctx->stream>>>((unsigned)n, (unsigned)n1, (unsigned)nlat, owner, x,
-                                                            vs_dev, nq, ds.part.p);
+    const SlotBatch sb = launch_batch();
+    check_counts(sb);
+    const MagicDiv dn1 = magic_div((unsigned)n1);
+    TNG_NQ_DISPATCH(count_class(sb, nq),
+                    (mdot_partial_kernel<T, NQ><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
+                        (unsigned)n, dn1, (unsigned)nlat, owner, x, vs_dev, nq, ds.part.p, sb)));
     TNG_HIP(hipGetLastError());
-    mdot_final_kernel<<<1, 64, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0);
+    mdot_final_kernel<<<dim3(1, 1, sb.nb), 256, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0, sb);
     TNG_HIP(hipGetLastError());
 }
 
@@ -648,7 +912,11 @@ void vec_maxpy(const tng_ctx* ctx, long long n, const double* coef_dev, double s
                int nq, T* y) {
     TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-axpy");
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
-    maxpy_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, coef_dev, sign, vs_dev, nq, y);
+    const SlotBatch sb = launch_batch();
+    check_counts(sb);
+    TNG_NQ_DISPATCH(count_class(sb, nq),
+                    (maxpy_kernel<T, NQ><<<dim3(nb, 1, sb.nb), 256, 0, ctx->stream>>>((unsigned)n, coef_dev, sign,
+                                                                                      vs_dev, nq, y, sb)));
     TNG_HIP(hipGetLastError());
 }
 
@@ -657,17 +925,23 @@ void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level&
                const T* const* vs_dev, int nq, double* out_dev, bool accumulate) {
     TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-dot");
     const long long n = 3 * Lu.node_slots() + Lp.node_slots();
+    TNG_REQUIRE(n < (1LL << 32), "multi-dot length out of range");
     const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
-    smdot_partial_kernel<T><<<nb, DOT_BS, 0, ctx->stream>>>(
-        (unsigned)Lu.node_slots(), (unsigned)(Lu.n + 1), (unsigned)Lu.lat_slots(), Lu.owner.p,
-        (unsigned)Lp.node_slots(), (unsigned)(Lp.n + 1), Lp.owner.p, x, vs_dev, nq, ds.part.p);
+    const SlotBatch sb = launch_batch();
+    check_counts(sb);
+    const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
+    TNG_NQ_DISPATCH(count_class(sb, nq),
+                    (smdot_partial_kernel<T, NQ><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
+                        (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                        (unsigned)Lp.node_slots(), dp, Lp.owner.p, x, vs_dev, nq, ds.part.p, sb)));
     TNG_HIP(hipGetLastError());
-    mdot_final_kernel<<<1, 64, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0);
+    mdot_final_kernel<<<dim3(1, 1, sb.nb), 256, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0, sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a) {
+    require_unbatched("vec_rand");
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
     rand_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, seed, a);
     TNG_HIP(hipGetLastError());
@@ -676,12 +950,36 @@ void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a) {
 template <typename T>
 void vec_scale_rsqrt(const tng_ctx* ctx, long long n, const double* s, const T* x, T* y) {
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
-    scale_rsqrt_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, s, x, y);
+    const SlotBatch sb = launch_batch();
+    scale_rsqrt_kernel<T><<<dim3(nb, 1, sb.nb), 256, 0, ctx->stream>>>((unsigned)n, s, x, y, sb);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_tab_copy(const tng_ctx* ctx, long long n, const T* src, const T* const* src_tab, T* dst, T* const* dst_tab,
+                  int idx, const double* sq) {
+    const SlotBatch sb = launch_batch();
+    const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
+    tab_copy_kernel<T><<<dim3(nb, 1, sb.nb), 256, 0, ctx->stream>>>((unsigned)n, src, src_tab, dst, dst_tab, idx,
+                                                                     sq, sb);
+    TNG_HIP(hipGetLastError());
+}
+
+void scal_gather(const tng_ctx* ctx, const double* src, int k, double* staging) {
+    const SlotBatch sb = launch_batch();
+    scal_gather_kernel<<<dim3(1, 1, sb.nb), 64, 0, ctx->stream>>>(src, k, staging, sb);
+    TNG_HIP(hipGetLastError());
+}
+
+void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst) {
+    const SlotBatch sb = launch_batch();
+    scal_scatter_kernel<<<dim3(1, 1, sb.nb), 64, 0, ctx->stream>>>(staging, k, dst, sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha) {
+    require_unbatched("coarse_assemble");
     coarse_assemble_kernel<T><<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(
         cd.ndof, cd.copy_ptr.p, cd.copy_slot.p, cd.slot_dof.p, cd.nslots, eta, L.geo64.p, L.m, L.n, L.r_in,
         L.dr(), hg_alpha, cd.Ainv.p);
@@ -690,6 +988,7 @@ void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, 
 
 template <typename T>
 void vec_mul(const tng_ctx* ctx, long long n, const T* a, const T* b, T* c) {
+    require_unbatched("vec_mul");
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
     mul_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, a, b, c);
     TNG_HIP(hipGetLastError());
@@ -699,12 +998,14 @@ template <typename T>
 void vec_fill(const tng_ctx* ctx, long long n, T v, T* a) {
     if (n <= 0) return;
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
-    fillv_kernel<T><<<nb, 256, 0, ctx->stream>>>((unsigned)n, v, a);
+    const SlotBatch sb = launch_batch();
+    fillv_kernel<T><<<dim3(nb, 1, sb.nb), 256, 0, ctx->stream>>>((unsigned)n, v, a, sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void coarse_unit(const tng_ctx* ctx, const CoarseDense& cd, int col, T* const x[3]) {
+    require_unbatched("coarse_unit");
     unit_vector_kernel<T><<<nblk(3 * cd.nslots, 256), 256, 0, ctx->stream>>>(cd.nslots, cd.slot_dof.p, col, x[0],
                                                                              x[1], x[2]);
     TNG_HIP(hipGetLastError());
@@ -712,32 +1013,37 @@ void coarse_unit(const tng_ctx* ctx, const CoarseDense& cd, int col, T* const x[
 
 template <typename T>
 void coarse_gather(const tng_ctx* ctx, const CoarseDense& cd, int col, const T* const y[3], double* Ad) {
+    require_unbatched("coarse_gather");
     coarse_gather_col_kernel<T><<<nblk(cd.ndof, 256), 256, 0, ctx->stream>>>(cd.ndof, cd.dof_slot.p, y[0], y[1],
                                                                               y[2], col, Ad);
     TNG_HIP(hipGetLastError());
 }
 
 void coarse_invert(const tng_ctx* ctx, CoarseDense& cd) {
+    require_unbatched("coarse_invert");
     gauss_jordan_kernel<<<1, 1024, 0, ctx->stream>>>(cd.ndof, cd.Ainv.p);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void coarse_solve(const tng_ctx* ctx, const CoarseDense& cd, const T* const b[3], T* const x[3]) {
-    coarse_solve_kernel<T><<<1, 1024, 0, ctx->stream>>>(cd.ndof, cd.dof_slot.p, cd.slot_dof.p, cd.nslots,
-                                                        cd.Ainv.p, b[0], b[1], b[2], x[0], x[1], x[2]);
+    const SlotBatch sb = launch_batch();
+    coarse_solve_kernel<T><<<dim3(1, 1, sb.nb), 1024, 0, ctx->stream>>>(
+        cd.ndof, cd.dof_slot.p, cd.slot_dof.p, cd.nslots, cd.Ainv.p, b[0], b[1], b[2], x[0], x[1], x[2], sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void vec_shift(const tng_ctx* ctx, long long n, const double* sum_cnt, T* p) {
-    shift_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, sum_cnt, p);
+    const SlotBatch sb = launch_batch();
+    shift_kernel<T><<<dim3(nblk(n, 256), 1, sb.nb), 256, 0, ctx->stream>>>(n, sum_cnt, p, sb);
     TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
 void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z) {
-    schur_diag_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, r, mdiag, z);
+    const SlotBatch sb = launch_batch();
+    schur_diag_kernel<T><<<dim3(nblk(n, 256), 1, sb.nb), 256, 0, ctx->stream>>>(n, r, mdiag, z, sb);
     TNG_HIP(hipGetLastError());
 }
 
@@ -747,7 +1053,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
                                  T* const[3]);                                                             \
-    template void vec_cheb_update<T>(const tng_ctx*, long long, double, double, const T*, const T*,       \
+    template void vec_cheb_update<T>(const tng_ctx*, long long, const double*, int, const T*, const T*,   \
                                      const T*, T*, T*);                                                    \
     template void vec_invert<T>(const tng_ctx*, long long, T*);                                           \
     template void vec_axpby<T>(const tng_ctx*, long long, double, const T*, double, T*);                  \
@@ -765,6 +1071,8 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
                                const T* const*, int, double*, bool);                                       \
     template void vec_rand<T>(const tng_ctx*, long long, unsigned long long, T*);                         \
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
+    template void vec_tab_copy<T>(const tng_ctx*, long long, const T*, const T* const*, T*, T* const*, int, \
+                                  const double*);                                                          \
     template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double);
 TNG_INST(double)
 TNG_INST(float)

@@ -1,23 +1,24 @@
 // Request server for streams of Stokes solves (ensembles, inversion sweeps):
 // requests of different mesh levels and viscosity fields arrive over time,
-// are admitted into solver slots while memory allows, and run concurrently
-// on the device.
+// are admitted into solver slots while memory allows, and advance together.
 //
-// * Every configured level keeps its mesh hierarchy resident.
-// * A slot is a solver instance (multigrid hierarchy, Krylov basis, scratch)
-//   with its own context, HIP stream and host worker thread; slots of a level
-//   are reused for later requests of that level.
-// * Admission is FIFO per level: a queued request starts as soon as its level
-//   has an idle slot, or a new slot fits in the HBM budget.  The memory model
-//   of a level is measured once, when the server is created, by building one
-//   slot and counting the device bytes allocated for it.
-// * Requests of all slots overlap on the device through their streams; a
-//   finished slot takes the next queued request of its level immediately.
+// * Every configured level keeps its mesh hierarchy resident and owns one
+//   lockstep batch of solver slots (SolverBatch), one HIP stream and one host
+//   driver thread: each step of the driver runs one FGMRES iteration of every
+//   running slot of the level, every kernel launched once for all of them
+//   (grid x slots), and levels overlap on the device through their streams.
+// * A slot is one arena of device memory holding a whole solver (multigrid
+//   hierarchy, Krylov basis, scratch); its size is measured once, when the
+//   server is created, by building one slot.
+// * Admission is FIFO per level at step boundaries: a queued request starts
+//   in an idle slot of its level, or in a new slot while the budget allows;
+//   a level with no slot at all may have an idle slot of another level (with
+//   an empty queue) released to make room.  Finished slots take the next
+//   queued request at the next step boundary.
 // Each request solves the Stokes problem with eta = exp(-ln(contrast) T) and
-// the buoyancy right-hand side Ra T rhat in mixed precision.
-#include <atomic>
-#include <climits>
+// the buoyancy right-hand side Ra T rhat in the solver options' precision.
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -26,6 +27,7 @@
 #include <mutex>
 #include <thread>
 
+#include "batch.hpp"
 #include "mg.hpp"
 
 using Clock = std::chrono::steady_clock;
@@ -44,29 +46,18 @@ struct ServerReq {
     bool done = false;
 };
 
-struct ServerSlot;
-
 struct ServerLevel {
-    int mt, nr;
+    int mt = 0, nr = 0;
     tng_mesh* mesh = nullptr;
-    std::vector<std::unique_ptr<ServerSlot>> slots;
-    std::deque<ServerReq*> queue;
-    long long bytes_per_slot = -1;      // measured at server creation
-};
-
-struct ServerSlot {
-    tng_server* srv = nullptr;
-    int level = 0;
-    const tng_mesh* mesh = nullptr;
-    tng_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
-    tng_solver* solver = nullptr;
-    tng::DevBuf<double> eta, f;
-    std::thread th;
-    ServerReq* job = nullptr;           // guarded by srv->mu
-    bool stop = false;
-    bool retire = false;                // free the slot's memory for another level
-    bool dead = false;
+    tng_ctx* ctx = nullptr;
+    std::unique_ptr<tng::SolverBatch> batch;   // touched only by the driver thread (after creation)
+    std::vector<ServerReq*> job;               // request of every slot (nullptr: idle); guarded by srv->mu
+    std::deque<ServerReq*> queue;
+    long long bytes_per_slot = -1;
+    int cap_slots = 0;                         // max_slots, lowered if the device refuses a slot
+    int release_wanted = 0;                    // idle slots another level asked this one to free
+    std::thread driver;
 };
 
 struct tng_server {
@@ -81,153 +72,165 @@ struct tng_server {
     long long next_ticket = 1;
     long long bytes_in_use = 0;
     int busy = 0;
-    std::string last_error;
+    bool stop = false;
 };
 
 namespace tng {
 namespace {
 
-void dispatch(tng_server* srv);
+int live_slots(const ServerLevel& lv) { return (int)lv.job.size(); }
 
-void run_request(ServerSlot* s, ServerReq* r) {
-    const tng::Level& L = s->mesh->lv[0];
-    const long long ns = L.node_slots();
-    const double E = std::log(10.0) * r->contrast_log10;
-    launch_eta_from_T(s->ctx, L, TNG_F64, r->T, s->eta.p, E, 0.0);
-    double* f[3] = {s->f.p, s->f.p + ns, s->f.p + 2 * ns};
-    energy_buoyancy(s->ctx, L, r->T, r->Ra, f);
-    const double* fc[3] = {f[0], f[1], f[2]};
-    r->rc = tng_stokes_solve(s->solver, s->eta.p, fc, nullptr, r->u, r->p, &r->info);
+int idle_index(const ServerLevel& lv) {
+    for (size_t i = 0; i < lv.job.size(); ++i)
+        if (lv.job[i] == nullptr) return (int)i;
+    return -1;
 }
 
-void worker(ServerSlot* s) {
-    tng_server* srv = s->srv;
-    (void)hipSetDevice(s->ctx->device);
-    std::unique_lock<std::mutex> lk(srv->mu);
-    for (;;) {
-        srv->cv_work.wait(lk, [&] { return s->stop || s->retire || s->job != nullptr; });
-        if (s->job == nullptr && s->retire) {
-            // give the memory back and let the dispatcher admit other levels
-            tng_solver* sv = s->solver;
-            s->solver = nullptr;
-            lk.unlock();
-            tng_stokes_solver_destroy(sv);
-            s->eta.release();
-            s->f.release();
-            (void)hipStreamSynchronize(s->stream);
-            lk.lock();
-            s->dead = true;
-            srv->bytes_in_use -= srv->levels[s->level].bytes_per_slot;
-            tng::dispatch(srv);
-            srv->cv_done.notify_all();
+// A queued request of lv could start now (lock held).
+bool admissible(const tng_server* srv, const ServerLevel& lv) {
+    if (lv.queue.empty()) return false;
+    if (idle_index(lv) >= 0) return true;
+    return live_slots(lv) < lv.cap_slots && lv.bytes_per_slot <= (long long)srv->budget - srv->bytes_in_use;
+}
+
+// Asks another level to free an idle slot for lv, which has none (lock held).
+void request_room(tng_server* srv, ServerLevel& lv) {
+    if (live_slots(lv) != 0) return;
+    for (auto& other : srv->levels) {
+        if (&other == &lv || !other.queue.empty() || other.release_wanted > 0) continue;
+        if (idle_index(other) >= 0) {
+            other.release_wanted += 1;
+            srv->cv_work.notify_all();
             return;
         }
-        if (s->job == nullptr && s->stop) return;
-        ServerReq* r = s->job;
-        lk.unlock();
-        r->t_start = Clock::now();
-        try {
-            run_request(s, r);
-        } catch (const tng::Error& e) {
-            r->rc = e.code;
-        } catch (...) {
-            r->rc = TNG_E_INVAL;
-        }
-        r->t_done = Clock::now();
-        lk.lock();
-        r->done = true;
-        s->job = nullptr;
-        srv->busy -= 1;
-        // take the next queued request of this level right away
-        ServerLevel& lv = srv->levels[s->level];
-        if (!lv.queue.empty() && !s->stop && !s->retire) {
-            s->job = lv.queue.front();
-            lv.queue.pop_front();
-            srv->busy += 1;
-        }
-        srv->cv_done.notify_all();
-        srv->cv_work.notify_all();
     }
 }
 
-// Creates a slot for level li (called with the lock held).
-ServerSlot* make_slot(tng_server* srv, int li) {
-    ServerLevel& lv = srv->levels[li];
-    auto slot = std::make_unique<ServerSlot>();
-    slot->srv = srv;
-    slot->level = li;
-    slot->mesh = lv.mesh;
-    TNG_HIP(hipStreamCreate(&slot->stream));   // default priority
-    if (tng_ctx_create(srv->ctx->device, slot->stream, &slot->ctx) != TNG_OK)
-        throw Error(TNG_E_HIP, "slot context creation failed");
-    const int rc = tng_stokes_solver_create(slot->ctx, lv.mesh, &srv->opts, &slot->solver);
-    if (rc != TNG_OK) throw Error(rc, std::string("slot solver creation failed: ") + tng_last_error());
-    const tng::Level& L = lv.mesh->lv[0];
-    slot->eta.alloc(2 * L.cells());
-    slot->f.alloc(3 * L.node_slots());
-    srv->bytes_in_use += lv.bytes_per_slot;
-    ServerSlot* raw = slot.get();
-    lv.slots.push_back(std::move(slot));
-    raw->th = std::thread(worker, raw);
-    return raw;
+void complete(tng_server* srv, ServerReq* r, int rc, const tng_solve_info& info) {
+    r->rc = rc;
+    r->info = info;
+    r->t_done = Clock::now();
+    r->done = true;
+    srv->busy -= 1;
 }
 
-// Device bytes of one slot of level li: a slot is built and released once,
-// counting what this thread allocates for it.  A level whose slot cannot be
-// allocated at all is given an unbounded cost and refuses every request.
-long long measure_slot_bytes(tng_server* srv, ServerLevel& lv) {
-    const long long before = tl_device_bytes;
-    long long cost = LLONG_MAX;
-    tng_solver* sv = nullptr;
-    if (tng_stokes_solver_create(srv->ctx, lv.mesh, &srv->opts, &sv) == TNG_OK) {
-        try {
-            const tng::Level& L = lv.mesh->lv[0];
-            DevBuf<double> eta(2 * L.cells()), f(3 * L.node_slots());
-            cost = std::max(tl_device_bytes - before, 1LL);
-        } catch (const Error&) {
-        }
-        tng_stokes_solver_destroy(sv);
-    }
-    return cost;
-}
-
-// Admits queued requests (lock held).
-void dispatch(tng_server* srv) {
-    for (size_t li = 0; li < srv->levels.size(); ++li) {
-        ServerLevel& lv = srv->levels[li];
-        while (!lv.queue.empty()) {
-            ServerSlot* idle = nullptr;
-            int live = 0;
-            for (auto& sl : lv.slots) {
-                if (sl->dead || sl->retire) continue;
-                ++live;
-                if (!idle && sl->job == nullptr) idle = sl.get();
+void driver(tng_server* srv, ServerLevel* lv) {
+    (void)hipSetDevice(lv->ctx->device);
+    SolverBatch& B = *lv->batch;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    for (;;) {
+        srv->cv_work.wait(lk, [&] {
+            return srv->stop || B.running() > 0 || lv->release_wanted > 0 || admissible(srv, *lv);
+        });
+        if (srv->stop && B.running() == 0) return;
+        // free idle slots another level is waiting for
+        while (lv->release_wanted > 0) {
+            lv->release_wanted -= 1;
+            const int i = idle_index(*lv);
+            if (i < 0) break;
+            lk.unlock();
+            bool freed = true;
+            try {
+                B.remove_slot(i);
+            } catch (const Error&) {
+                freed = false;
             }
-            if (!idle) {
-                if (live >= srv->max_slots) break;
-                if (lv.bytes_per_slot > (long long)srv->budget - srv->bytes_in_use) {
-                    // an idle slot of another level may be retired to make room
-                    if (live == 0) {
-                        for (auto& other : srv->levels) {
-                            if (&other == &lv) continue;
-                            for (auto& sl : other.slots)
-                                if (!sl->dead && !sl->retire && sl->job == nullptr && other.queue.empty()) {
-                                    sl->retire = true;
-                                    srv->cv_work.notify_all();
-                                    return;   // the retiring worker calls dispatch again
-                                }
+            lk.lock();
+            if (freed) {
+                lv->job.erase(lv->job.begin() + i);
+                srv->bytes_in_use -= lv->bytes_per_slot;
+            }
+            srv->cv_work.notify_all();
+        }
+        // admit queued requests at this step boundary
+        while (!srv->stop && !lv->queue.empty()) {
+            int i = idle_index(*lv);
+            if (i < 0) {
+                if (live_slots(*lv) >= lv->cap_slots) break;
+                if (lv->bytes_per_slot > (long long)srv->budget - srv->bytes_in_use) {
+                    request_room(srv, *lv);
+                    break;
+                }
+                srv->bytes_in_use += lv->bytes_per_slot;
+                lk.unlock();
+                int added = -1;
+                try {
+                    added = B.add_slot();
+                } catch (const Error&) {
+                    added = -1;
+                }
+                lk.lock();
+                if (added < 0) {
+                    // the device has no room for another slot: this level keeps the slots it has
+                    srv->bytes_in_use -= lv->bytes_per_slot;
+                    lv->cap_slots = live_slots(*lv);
+                    if (lv->cap_slots == 0) {
+                        while (!lv->queue.empty()) {
+                            ServerReq* r = lv->queue.front();
+                            lv->queue.pop_front();
+                            r->t_start = Clock::now();
+                            tng_solve_info info{};
+                            info.status = TNG_E_NOMEM;
+                            complete(srv, r, TNG_E_NOMEM, info);
                         }
+                        srv->cv_done.notify_all();
                     }
                     break;
                 }
-                idle = make_slot(srv, (int)li);
+                lv->job.push_back(nullptr);
+                i = added;
             }
-            idle->job = lv.queue.front();
-            lv.queue.pop_front();
-            srv->busy += 1;
+            ServerReq* r = lv->queue.front();
+            lv->queue.pop_front();
+            lv->job[i] = r;
+            lk.unlock();
+            r->t_start = Clock::now();
+            const double E = std::log(10.0) * r->contrast_log10;
+            bool running = false;
+            try {
+                running = B.start(i, r->T, E, r->Ra, r->u, r->p);
+            } catch (const Error&) {
+                running = false;
+            }
+            lk.lock();
+            if (!running) {
+                complete(srv, r, B.rc(i), B.info(i));
+                lv->job[i] = nullptr;
+                srv->cv_done.notify_all();
+            }
+        }
+        if (B.running() == 0) continue;
+        lk.unlock();
+        std::vector<int> fin;
+        int err = TNG_OK;
+        try {
+            fin = B.step();
+        } catch (const Error& e) {
+            err = e.code;
+        }
+        lk.lock();
+        if (err != TNG_OK) {
+            // the stream itself failed: end every running request of the level
+            for (size_t i = 0; i < lv->job.size(); ++i)
+                if (lv->job[i]) {
+                    tng_solve_info info{};
+                    info.status = err;
+                    complete(srv, lv->job[i], err, info);
+                    lv->job[i] = nullptr;
+                }
+            srv->cv_done.notify_all();
+            srv->cv_work.notify_all();
+            return;
+        }
+        for (int i : fin) {
+            complete(srv, lv->job[i], B.rc(i), B.info(i));
+            lv->job[i] = nullptr;
+        }
+        if (!fin.empty()) {
+            srv->cv_done.notify_all();
+            srv->cv_work.notify_all();
         }
     }
-    srv->cv_work.notify_all();
 }
 
 }  // namespace
@@ -248,19 +251,37 @@ int tng_server_create(tng_ctx* ctx, const int* levels, int nlevels, size_t hbm_b
     srv->budget = hbm_budget_bytes;
     srv->max_slots = max_slots;
     srv->levels.resize(nlevels);
+    auto cleanup = [&](int upto) {
+        for (int k = 0; k < upto; ++k) {
+            ServerLevel& lv = srv->levels[k];
+            lv.batch.reset();
+            if (lv.ctx) tng_ctx_destroy(lv.ctx);
+            if (lv.stream) (void)hipStreamDestroy(lv.stream);
+            if (lv.mesh) tng_mesh_destroy(lv.mesh);
+        }
+    };
     for (int i = 0; i < nlevels; ++i) {
         ServerLevel& lv = srv->levels[i];
         lv.mt = levels[2 * i];
         lv.nr = levels[2 * i + 1];
-        int nl = 1;
-        while ((lv.mt >> nl) >= 2 && (lv.nr >> nl) >= 2 && ((lv.nr >> nl) << nl) == lv.nr) ++nl;
-        const int rc = tng_mesh_create(ctx, lv.mt, lv.nr, 0.55, 1.0, nl, &lv.mesh);
-        if (rc != TNG_OK) {
-            for (int k = 0; k < i; ++k) tng_mesh_destroy(srv->levels[k].mesh);
-            throw Error(rc, std::string("server level mesh: ") + tng_last_error());
+        try {
+            int nl = 1;
+            while ((lv.mt >> nl) >= 2 && (lv.nr >> nl) >= 2 && ((lv.nr >> nl) << nl) == lv.nr) ++nl;
+            if (tng_mesh_create(ctx, lv.mt, lv.nr, 0.55, 1.0, nl, &lv.mesh) != TNG_OK)
+                throw Error(TNG_E_INVAL, std::string("server level mesh: ") + tng_last_error());
+            TNG_HIP(hipStreamCreate(&lv.stream));   // default priority
+            if (tng_ctx_create(ctx->device, lv.stream, &lv.ctx) != TNG_OK)
+                throw Error(TNG_E_HIP, "level context creation failed");
+            lv.ctx->profile = ctx->profile;
+            lv.batch = std::make_unique<tng::SolverBatch>(lv.ctx, lv.mesh, *opts);
+            lv.bytes_per_slot = lv.batch->slot_bytes();
+            lv.cap_slots = max_slots;
+        } catch (...) {
+            cleanup(i + 1);
+            throw;
         }
-        lv.bytes_per_slot = tng::measure_slot_bytes(srv.get(), lv);
     }
+    for (auto& lv : srv->levels) lv.driver = std::thread(tng::driver, srv.get(), &lv);
     *out = srv.release();
     TNG_API_END
 }
@@ -272,7 +293,7 @@ int tng_server_submit(tng_server* srv, int level_idx, const double* T, double lo
     TNG_REQUIRE(level_idx >= 0 && level_idx < (int)srv->levels.size(), "level_idx out of range");
     std::lock_guard<std::mutex> lk(srv->mu);
     ServerLevel& lv = srv->levels[level_idx];
-    if (lv.slots.empty() && lv.bytes_per_slot > (long long)srv->budget)
+    if (lv.bytes_per_slot > (long long)srv->budget)
         throw Error(TNG_E_BUDGET, "request does not fit the HBM budget (a slot of this level needs " +
                                       std::to_string(lv.bytes_per_slot) + " bytes, budget " +
                                       std::to_string(srv->budget) + ")");
@@ -286,9 +307,10 @@ int tng_server_submit(tng_server* srv, int level_idx, const double* T, double lo
     r->p = p_out;
     r->t_submit = Clock::now();
     lv.queue.push_back(r.get());
+    srv->busy += 1;
     *ticket = r->ticket;
     srv->reqs.emplace(r->ticket, std::move(r));
-    tng::dispatch(srv);
+    srv->cv_work.notify_all();
     TNG_API_END
 }
 
@@ -318,12 +340,7 @@ int tng_server_wait(tng_server* srv, long long ticket) {
     TNG_REQUIRE(srv, "NULL server");
     std::unique_lock<std::mutex> lk(srv->mu);
     if (ticket <= 0) {
-        srv->cv_done.wait(lk, [&] {
-            if (srv->busy != 0) return false;
-            for (auto& lv : srv->levels)
-                if (!lv.queue.empty()) return false;
-            return true;
-        });
+        srv->cv_done.wait(lk, [&] { return srv->busy == 0; });
     } else {
         auto it = srv->reqs.find(ticket);
         TNG_REQUIRE(it != srv->reqs.end(), "unknown ticket");
@@ -337,14 +354,15 @@ int tng_server_stats(tng_server* srv, long long* bytes_in_use, int* slots, int* 
     TNG_API_BEGIN
     TNG_REQUIRE(srv, "NULL server");
     std::lock_guard<std::mutex> lk(srv->mu);
-    int ns = 0, nq = 0;
+    int ns = 0, nq = 0, running = 0;
     for (auto& lv : srv->levels) {
-        ns += (int)lv.slots.size();
+        ns += (int)lv.job.size();
         nq += (int)lv.queue.size();
+        for (auto* j : lv.job) running += j ? 1 : 0;
     }
     if (bytes_in_use) *bytes_in_use = srv->bytes_in_use;
     if (slots) *slots = ns;
-    if (busy) *busy = srv->busy;
+    if (busy) *busy = running;
     if (queued) *queued = nq;
     TNG_API_END
 }
@@ -354,23 +372,20 @@ int tng_server_destroy(tng_server* srv) {
     if (!srv) return TNG_OK;
     {
         std::unique_lock<std::mutex> lk(srv->mu);
-        srv->cv_done.wait(lk, [&] { return srv->busy == 0; });
+        // queued requests are dropped; running ones finish
         for (auto& lv : srv->levels) {
+            srv->busy -= (int)lv.queue.size();
             lv.queue.clear();
-            for (auto& sl : lv.slots) sl->stop = true;
         }
+        srv->stop = true;
         srv->cv_work.notify_all();
     }
+    for (auto& lv : srv->levels)
+        if (lv.driver.joinable()) lv.driver.join();
     for (auto& lv : srv->levels) {
-        for (auto& sl : lv.slots) {
-            if (sl->th.joinable()) sl->th.join();
-            if (sl->solver) tng_stokes_solver_destroy(sl->solver);
-            sl->eta.release();
-            sl->f.release();
-            tng_ctx_destroy(sl->ctx);
-            if (sl->stream) (void)hipStreamDestroy(sl->stream);
-        }
-        lv.slots.clear();
+        lv.batch.reset();
+        tng_ctx_destroy(lv.ctx);
+        if (lv.stream) (void)hipStreamDestroy(lv.stream);
         tng_mesh_destroy(lv.mesh);
     }
     delete srv;

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <memory>
 
+#include "batch.hpp"
 #include "mg.hpp"
 
 namespace tng {
@@ -29,6 +30,8 @@ struct MGLevel {
     DevBuf<T> invd;                     // 3 ns: inverse diagonal of A
     DevBuf<T> x, b, r, y, d;            // 3 ns scratch
     DevBuf<const T*> xy;                // device pointers {x, y} for reductions
+    DevBuf<double> cheb;                // Chebyshev coefficients (alpha_k, beta_k) of this level
+    std::vector<double> cheb_h;         //   host copy (kept until the upload has run)
     double lmax = 1.0;                  // largest eigenvalue of D^{-1} A (estimate)
     T* c(DevBuf<T>& v, int k) { return v.p + (long long)k * ns; }
 };
@@ -38,6 +41,7 @@ struct KrylovWS {
     int restart = 0;
     long long N = 0;
     DevBuf<T> V, Z, w, t;
+    DevBuf<T> zb;                       // preconditioner output of a batch slot (index-free)
     DevBuf<const T*> vptr, zptr, wptr;
     DevBuf<double> coef;                // device dots / coefficients
     T* Vi(int i) { return V.p + (long long)i * N; }
@@ -66,10 +70,27 @@ struct tng_solver {
     tng::DevBuf<const double*> dptr;    // [bo, ro, pressure of xo, k64.w]
     double* host = nullptr;             // pinned read-back buffer
     bool ready = false;
+    bool batch_slot = false;            // slot of a SolverBatch (extra index-free buffers)
     long long ns0 = 0, np = 0, N = 0;
     tng::EnergyWS* ews = nullptr;       // energy step workspace (created on first use)
     tng::DevBuf<double> eta_step, f_step;
+    // preconditioner graphs: z_j = P^{-1} v_j of Krylov index j, captured on a
+    // private stream (gctx) at first use and replayed there, ordered with the
+    // context's stream by the events
+    hipStream_t gstream = nullptr;
+    tng_ctx* gctx = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<hipGraphExec_t> pg32, pg64;
     ~tng_solver() {
+        if (gstream) (void)hipStreamSynchronize(gstream);
+        for (auto g : pg32)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (auto g : pg64)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gctx) tng_ctx_destroy(gctx);
+        if (gstream) (void)hipStreamDestroy(gstream);
         if (host) (void)hipHostFree(host);
         if (ews) tng::energy_ws_destroy(ews);
     }
@@ -149,11 +170,26 @@ void vel_dot(tng_solver* s, int l, const T* x, const T* const* ydev, double* out
 // Chebyshev smoother on D^{-1} A (Saad's three-term recurrence) for the
 // eigenvalue interval [lo, hi]: every step is a polynomial of degree `deg`
 // (deg operator applies; the first one is skipped when x starts at zero).
+// Step k of the recurrence is d <- alpha_k d + beta_k D^{-1}(b - A x), x += d.
+std::vector<double> chebyshev_coefficients(int deg, double lo, double hi) {
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    std::vector<double> ab(2 * (size_t)std::max(deg, 1));
+    ab[0] = 0.0;
+    ab[1] = 1.0 / theta;
+    double rho_old = 1.0 / sigma;
+    for (int k = 1; k < deg; ++k) {
+        const double rho = 1.0 / (2.0 * sigma - rho_old);
+        ab[2 * k] = rho * rho_old;
+        ab[2 * k + 1] = 2.0 * rho / delta;
+        rho_old = rho;
+    }
+    return ab;
+}
+
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
-                     T* x, T* y, T* d, int deg, int steps, double lo, double hi, bool x_zero) {
+                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero) {
     const long long ns = L.node_slots(), n3 = 3 * ns;
-    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     auto applyA = [&](const T* xin, T* yout) {
         const void* u[3] = {xin, xin + ns, xin + 2 * ns};
         void* yu[3] = {yout, yout + ns, yout + 2 * ns};
@@ -167,13 +203,10 @@ void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg
         } else {
             applyA(x, y);
         }
-        vec_cheb_update<T>(ctx, n3, 0.0, 1.0 / theta, b, y, invd, d, x);
-        double rho_old = 1.0 / sigma;
+        vec_cheb_update<T>(ctx, n3, ab_dev, 0, b, y, invd, d, x);
         for (int k = 1; k < deg; ++k) {
             applyA(x, y);
-            const double rho = 1.0 / (2.0 * sigma - rho_old);
-            vec_cheb_update<T>(ctx, n3, rho * rho_old, 2.0 * rho / delta, b, y, invd, d, x);
-            rho_old = rho;
+            vec_cheb_update<T>(ctx, n3, ab_dev, k, b, y, invd, d, x);
         }
     }
 }
@@ -183,9 +216,8 @@ namespace {
 template <typename T>
 void chebyshev(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
     MGLevel<T>& M = hier<T>(s)[l];
-    chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, M.invd.p, b, x, M.y.p, M.d.p,
-                       std::max(1, s->opts.cheb_degree),
-                       steps, s->opts.cheb_lo * M.lmax, s->opts.cheb_hi * M.lmax, x_zero);
+    chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, M.invd.p, b, x, M.y.p, M.d.p, M.cheb.p,
+                       std::max(1, s->opts.cheb_degree), steps, x_zero);
 }
 
 template <typename T>
@@ -225,6 +257,53 @@ void precond(tng_solver* s, const T* v, T* z) {
     vcycle<T>(s, 0, K.t.p, z);                                   // z_u ~ A^{-1} t
 }
 
+template <typename T>
+std::vector<hipGraphExec_t>& pgraphs(tng_solver* s);
+template <>
+std::vector<hipGraphExec_t>& pgraphs<float>(tng_solver* s) { return s->pg32; }
+template <>
+std::vector<hipGraphExec_t>& pgraphs<double>(tng_solver* s) { return s->pg64; }
+
+// Z_j = P^{-1} V_j, as a replayed graph when the solver has graphs
+template <typename T>
+void precond_j(tng_solver* s, int j) {
+    KrylovWS<T>& K = kws<T>(s);
+    if (!s->gctx) {
+        precond<T>(s, K.Vi(j), K.Zi(j));
+        return;
+    }
+    auto& G = pgraphs<T>(s);
+    if (G.size() < (size_t)K.restart) G.assign(K.restart, nullptr);
+    if (!G[j]) {
+        // capture with every launch on the private stream; no timers inside
+        tng_ctx* saved = s->ctx;
+        hipGraph_t graph = nullptr;
+        TNG_HIP(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
+        s->ctx = s->gctx;
+        try {
+            precond<T>(s, K.Vi(j), K.Zi(j));
+        } catch (...) {
+            s->ctx = saved;
+            (void)hipStreamEndCapture(s->gstream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        s->ctx = saved;
+        TNG_HIP(hipStreamEndCapture(s->gstream, &graph));
+        const hipError_t e = hipGraphInstantiate(&G[j], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            G[j] = nullptr;
+            throw Error(TNG_E_HIP, std::string("preconditioner graph: ") + hipGetErrorString(e));
+        }
+    }
+    TNG_HIP(hipEventRecord(s->ev_in, s->ctx->stream));
+    TNG_HIP(hipStreamWaitEvent(s->gstream, s->ev_in, 0));
+    TNG_HIP(hipGraphLaunch(G[j], s->gstream));
+    TNG_HIP(hipEventRecord(s->ev_out, s->gstream));
+    TNG_HIP(hipStreamWaitEvent(s->ctx->stream, s->ev_out, 0));
+}
+
 double host_norm_from_dev(tng_solver* s, const double* dev) {
     readback(s, dev, 1);
     return std::sqrt(std::max(0.0, s->host[0]));
@@ -262,7 +341,7 @@ int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxi
         g[0] = beta;
         int jend = 0;
         for (int j = 0; j < m; ++j) {
-            precond<T>(s, K.Vi(j), K.Zi(j));
+            precond_j<T>(s, j);
             apply_K<T>(s, eta0, K.Zi(j), K.w.p);
             // classical Gram-Schmidt, twice
             vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc, false);
@@ -401,6 +480,7 @@ void alloc_hierarchy(tng_solver* s, bool scratch) {
         M.r.alloc(n3);
         M.y.alloc(n3);
         M.d.alloc(n3);
+        M.cheb.alloc(2 * (size_t)std::max(1, s->opts.cheb_degree));
         const T* xy[2] = {M.x.p, M.y.p};
         M.xy.alloc(2);
         TNG_HIP(hipMemcpy(M.xy.p, xy, sizeof(xy), hipMemcpyHostToDevice));
@@ -417,6 +497,7 @@ void alloc_krylov(tng_solver* s, const T* rhs) {
     K.Z.alloc((size_t)m * s->N);
     K.w.alloc(s->N);
     K.t.alloc(3 * s->ns0);
+    if (s->batch_slot) K.zb.alloc(s->N);
     K.coef.alloc(4 * MAX_MDOT);
     std::vector<const T*> vp(m + 1), zp(m), wp(2);
     for (int i = 0; i <= m; ++i) vp[i] = K.Vi(i);
@@ -467,6 +548,9 @@ void setup_level_operators(tng_solver* s) {
         mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d);
         vec_invert<T>(s->ctx, 3 * M.ns, M.invd.p);
         M.lmax = power_lmax<T>(s, l);
+        M.cheb_h = chebyshev_coefficients(std::max(1, s->opts.cheb_degree), s->opts.cheb_lo * M.lmax,
+                                          s->opts.cheb_hi * M.lmax);
+        M.cheb.upload(M.cheb_h.data(), M.cheb_h.size(), s->ctx->stream);
     }
 }
 
@@ -495,9 +579,565 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
 }  // namespace
 
 template void chebyshev_steps<double>(const tng_ctx*, const Level&, const double*, double, const double*,
-                                      const double*, double*, double*, double*, int, int, double, double, bool);
+                                      const double*, double*, double*, double*, const double*, int, int, bool);
 template void chebyshev_steps<float>(const tng_ctx*, const Level&, const float*, double, const float*,
-                                     const float*, float*, float*, float*, int, int, double, double, bool);
+                                     const float*, float*, float*, float*, const double*, int, int, bool);
+
+// ---- lockstep batch of solver slots (serving) --------------------------------
+// A slot is a solver built inside its own arena, so the buffers of all slots
+// sit at the same offsets and one launch reaches every slot (SlotBatch).  The
+// algorithm per slot is the one of tng_stokes_solve: FGMRES(restart) with the
+// block preconditioner, FP64 refinement around FP32 inner solves when mixed.
+// Slots of a step may be at different Krylov indices j: the basis vectors of
+// the step are moved through index-free buffers (w, zb) with per-slot table
+// indices, and the multi-dots / multi-axpys take per-slot vector counts.
+
+struct SolverBatch::Slot {
+    Arena arena;
+    tng_solver* s = nullptr;
+    DevBuf<double> eta, f;              // request viscosity and body force (in the arena)
+    bool busy = false;
+    int rc = TNG_OK;
+    tng_solve_info info{};
+    std::chrono::steady_clock::time_point t0;
+    double* uo[3] = {nullptr, nullptr, nullptr};
+    double* po = nullptr;
+    // outer (refinement) state
+    double bn = 0.0, relres = 0.0;
+    int outer = 0, inner_total = 0;
+    // Krylov cycle state
+    double bnorm = 0.0, res = 0.0;
+    int its = 0, j = 0, jend = 0;
+    bool cycle_end = false, inner_done = false, failed = false;
+    std::vector<double> H, cs, sn, g, y;
+    ~Slot() {
+        delete s;
+        eta.release();
+        f.release();
+        if (arena.base) (void)hipFree(arena.base);
+    }
+};
+
+constexpr int BATCH_STG = 4 * MAX_MDOT;   // staging doubles per slot
+
+struct SolverBatch::Staging {
+    DevBuf<double> rd, up;              // device staging rows (owned, outside the arenas)
+    double* host = nullptr;             // pinned: read-back rows, then upload rows
+    bool upload_pending = false;
+    ~Staging() {
+        if (host) (void)hipHostFree(host);
+    }
+    double* host_rd() { return host; }
+    double* host_up() { return host + (size_t)MAX_BATCH * BATCH_STG; }
+};
+
+namespace {
+
+using BSlot = SolverBatch::Slot;
+using Group = std::vector<BSlot*>;
+
+SlotBatch batch_of(const Group& g, const std::vector<int>* cnt) {
+    TNG_REQUIRE(!g.empty() && (int)g.size() <= MAX_BATCH, "batch of 1..16 slots");
+    SlotBatch b;
+    b.nb = (int)g.size();
+    b.has_cnt = cnt != nullptr ? 1 : 0;
+    const char* base = g[0]->arena.base;
+    for (int z = 0; z < b.nb; ++z) {
+        b.off[z] = (long long)(g[z]->arena.base - base);
+        if (cnt) b.cnt[z] = (*cnt)[z];
+    }
+    return b;
+}
+
+// k doubles at the reference slot's device address src, for every slot of g
+const double* batch_gather(tng_ctx* ctx, SolverBatch::Staging& st, const Group& g, const double* src, int k) {
+    const SlotBatch b = batch_of(g, nullptr);
+    {
+        BatchScope bs(&b);
+        scal_gather(ctx, src, k, st.rd.p);
+    }
+    TNG_HIP(hipMemcpyAsync(st.host_rd(), st.rd.p, (size_t)b.nb * k * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    TNG_HIP(hipStreamSynchronize(ctx->stream));
+    st.upload_pending = false;
+    return st.host_rd();
+}
+
+// rows z * k .. of st.host_up() to the reference slot's device address dst of every slot of g
+void batch_scatter(tng_ctx* ctx, SolverBatch::Staging& st, const Group& g, int k, double* dst) {
+    const SlotBatch b = batch_of(g, nullptr);
+    TNG_HIP(hipMemcpyAsync(st.up.p, st.host_up(), (size_t)b.nb * k * sizeof(double), hipMemcpyHostToDevice,
+                           ctx->stream));
+    st.upload_pending = true;
+    BatchScope bs(&b);
+    scal_scatter(ctx, st.up.p, k, dst);
+}
+
+double* host_up_rows(tng_ctx* ctx, SolverBatch::Staging& st) {
+    if (st.upload_pending) {          // the last upload may still read the pinned rows
+        TNG_HIP(hipStreamSynchronize(ctx->stream));
+        st.upload_pending = false;
+    }
+    return st.host_up();
+}
+
+template <typename T>
+T* inner_x(tng_solver* s);
+template <>
+float* inner_x<float>(tng_solver* s) { return s->d32.p; }
+template <>
+double* inner_x<double>(tng_solver* s) { return s->xo.p; }
+template <typename T>
+const T* inner_b(tng_solver* s);
+template <>
+const float* inner_b<float>(tng_solver* s) { return s->r32.p; }
+template <>
+const double* inner_b<double>(tng_solver* s) { return s->bo.p; }
+
+void finish(BSlot* sl, int rc) {
+    sl->rc = rc;
+    sl->failed = rc != TNG_OK;
+    sl->busy = false;
+}
+
+// Result of a finished slot to the caller's buffers (asynchronous).
+void copy_out(tng_ctx* ctx, BSlot* sl) {
+    tng_solver* s = sl->s;
+    const long long ns = s->ns0, np = s->np;
+    for (int c = 0; c < 3; ++c)
+        TNG_HIP(hipMemcpyAsync(sl->uo[c], s->xo.p + c * ns, ns * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    TNG_HIP(hipMemcpyAsync(sl->po, s->xo.p + 3 * ns, np * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+// new Krylov cycle of every slot of g from its (device) starting vector v with
+// squared norm at the slot's Krylov coefficient 0: V_0 = v / |v|
+template <typename T>
+void begin_cycle(tng_ctx* ctx, const Group& g, const T* v, const double* host_sq, int stride, bool first) {
+    tng_solver* r = g[0]->s;
+    KrylovWS<T>& K = kws<T>(r);
+    const SlotBatch b = batch_of(g, nullptr);
+    {
+        BatchScope bs(&b);
+        vec_tab_copy<T>(ctx, r->N, v, nullptr, nullptr, (T* const*)K.vptr.p, 0, K.coef.p);
+    }
+    const int m = K.restart;
+    for (size_t z = 0; z < g.size(); ++z) {
+        BSlot* sl = g[z];
+        const double beta = std::sqrt(std::max(0.0, host_sq[z * stride]));
+        if (first) {
+            sl->bnorm = beta;
+            sl->its = 0;
+            sl->H.assign((size_t)(m + 1) * m, 0.0);
+            sl->cs.assign(m, 0.0);
+            sl->sn.assign(m, 0.0);
+            sl->y.assign(m, 0.0);
+        }
+        sl->g.assign(m + 1, 0.0);
+        sl->g[0] = beta;
+        sl->res = beta;
+        sl->j = 0;
+        sl->cycle_end = sl->inner_done = false;
+    }
+}
+
+}  // namespace
+
+SolverBatch::SolverBatch(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts& opts)
+    : ctx_(ctx), mesh_(mesh), opts_(opts), st_(std::make_unique<Staging>()) {
+    TNG_REQUIRE(ctx != nullptr && mesh != nullptr, "NULL argument");
+    TNG_HIP(hipSetDevice(ctx->device));
+    // one slot's device bytes: the arena demand of building one
+    const long long before = tl_arena_demand;
+    {
+        std::unique_ptr<tng_solver> probe(create_solver(ctx, mesh, &opts, true));
+        const Level& L = mesh->lv[0];
+        DevBuf<double> eta(2 * L.cells()), f(3 * L.node_slots());
+        slot_bytes_ = tl_arena_demand - before;
+    }
+    st_->rd.alloc((size_t)MAX_BATCH * BATCH_STG);
+    st_->up.alloc((size_t)MAX_BATCH * BATCH_STG);
+    TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&st_->host), 2 * (size_t)MAX_BATCH * BATCH_STG * sizeof(double),
+                          hipHostMallocDefault));
+}
+
+SolverBatch::~SolverBatch() {
+    if (ctx_ && ctx_->stream) (void)hipStreamSynchronize(ctx_->stream);
+    slot_.clear();
+}
+
+int SolverBatch::running() const {
+    int n = 0;
+    for (auto& sl : slot_) n += sl->busy ? 1 : 0;
+    return n;
+}
+
+int SolverBatch::idle_slot() const {
+    for (size_t i = 0; i < slot_.size(); ++i)
+        if (!slot_[i]->busy) return (int)i;
+    return -1;
+}
+
+int SolverBatch::add_slot() {
+    auto sl = std::make_unique<Slot>();
+    if (hipMalloc(reinterpret_cast<void**>(&sl->arena.base), (size_t)slot_bytes_) != hipSuccess) {
+        sl->arena.base = nullptr;
+        (void)hipGetLastError();
+        throw Error(TNG_E_NOMEM, "slot arena of " + std::to_string(slot_bytes_) + " bytes failed");
+    }
+    sl->arena.cap = (size_t)slot_bytes_;
+    {
+        ArenaScope as(&sl->arena);
+        sl->s = create_solver(ctx_, mesh_, &opts_, true);
+        const Level& L = mesh_->lv[0];
+        sl->eta.alloc(2 * L.cells());
+        sl->f.alloc(3 * L.node_slots());
+    }
+    TNG_REQUIRE((long long)sl->arena.used == slot_bytes_, "slot layout differs from the measured one");
+    slot_.push_back(std::move(sl));
+    return (int)slot_.size() - 1;
+}
+
+void SolverBatch::remove_slot(int i) {
+    TNG_REQUIRE(i >= 0 && i < (int)slot_.size() && !slot_[i]->busy, "only an idle slot can be removed");
+    TNG_HIP(hipStreamSynchronize(ctx_->stream));
+    slot_.erase(slot_.begin() + i);
+}
+
+int SolverBatch::rc(int i) const { return slot_.at(i)->rc; }
+tng_solve_info SolverBatch::info(int i) const { return slot_.at(i)->info; }
+
+namespace {
+
+void set_info(BSlot* sl) {
+    sl->info.outer_its = sl->outer;
+    sl->info.inner_its = sl->inner_total;
+    sl->info.rel_res = sl->relres;
+    sl->info.status = sl->rc;
+    sl->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl->t0).count();
+}
+
+// inner solve of the slots of g (mixed precision): r32 = ro, d = 0, V_0 = r32 / |r32|
+void begin_inner(tng_ctx* ctx, SolverBatch::Staging& st, const Group& g, std::vector<BSlot*>& done) {
+    tng_solver* r = g[0]->s;
+    KrylovWS<float>& K = r->k32;
+    const SlotBatch b = batch_of(g, nullptr);
+    {
+        BatchScope bs(&b);
+        vec_cast<float, double>(ctx, r->N, r->ro.p, r->r32.p);
+        vec_fill<float>(ctx, r->N, 0.0f, r->d32.p);
+        vec_smdot<float>(ctx, *r->ds, L0(r), L1(r), r->r32.p, K.wptr.p, 1, K.coef.p, false);
+    }
+    const double* hb = batch_gather(ctx, st, g, K.coef.p, 1);
+    Group go;
+    std::vector<double> sq;
+    for (size_t z = 0; z < g.size(); ++z) {
+        if (!(hb[z] > 0.0) || !std::isfinite(hb[z])) {
+            finish(g[z], TNG_E_NOTCONV);           // nothing left to reduce, or a non-finite residual
+            done.push_back(g[z]);
+            continue;
+        }
+        go.push_back(g[z]);
+        sq.push_back(hb[z]);
+    }
+    if (!go.empty()) begin_cycle<float>(ctx, go, go[0]->s->r32.p, sq.data(), 1, true);
+}
+
+// x += dx in FP64 and the true residual of the slots of g; finished slots go to done
+template <typename T>
+void outer_update(tng_ctx* ctx, SolverBatch::Staging& st, const tng_solver_opts& o, const Group& g,
+                  std::vector<BSlot*>& done) {
+    tng_solver* r = g[0]->s;
+    const long long N = r->N;
+    const SlotBatch b = batch_of(g, nullptr);
+    {
+        BatchScope bs(&b);
+        if (std::is_same<T, float>::value) {
+            vec_cast<double, float>(ctx, N, r->d32.p, r->ro.p);
+            vec_axpby<double>(ctx, N, 1.0, r->ro.p, 1.0, r->xo.p);
+        }
+        remove_pressure_mean(r);
+        apply_K<double>(r, r->h64[0].eta.p, r->xo.p, r->ro.p);
+        vec_axpby<double>(ctx, N, 1.0, r->bo.p, -1.0, r->ro.p);
+        vec_smdot<double>(ctx, *r->ds, L0(r), L1(r), r->ro.p, r->dptr.p + 1, 1, r->scal.p, false);
+    }
+    const double* hb = batch_gather(ctx, st, g, r->scal.p, 1);
+    Group again;
+    for (size_t z = 0; z < g.size(); ++z) {
+        BSlot* sl = g[z];
+        sl->inner_total += sl->its;
+        sl->outer += 1;
+        sl->relres = sl->bn > 0 ? std::sqrt(std::max(0.0, hb[z])) / sl->bn : 0.0;
+        if (!std::isfinite(sl->relres)) {
+            finish(sl, TNG_E_NOTCONV);
+        } else if (sl->relres <= o.rtol) {
+            finish(sl, TNG_OK);
+        } else if (!std::is_same<T, float>::value || sl->outer >= o.max_outer) {
+            finish(sl, TNG_E_NOTCONV);
+        } else {
+            again.push_back(sl);
+            continue;
+        }
+        done.push_back(sl);
+    }
+    if (!again.empty()) begin_inner(ctx, st, again, done);
+}
+
+// one FGMRES iteration of the slots of g, then the work of the cycles that end
+template <typename T>
+void step_group(tng_ctx* ctx, SolverBatch::Staging& st, const tng_solver_opts& o, const Group& g,
+                std::vector<BSlot*>& done) {
+    tng_solver* r = g[0]->s;
+    KrylovWS<T>& K = kws<T>(r);
+    const int m = K.restart;
+    const long long N = r->N;
+    double* dsc = K.coef.p;
+    const T* eta0 = hier<T>(r)[0].eta.p;
+    T* const* vtab = (T* const*)K.vptr.p;
+    T* const* ztab = (T* const*)K.zptr.p;
+    const bool mixed = std::is_same<T, float>::value;
+    const double rtol_in = mixed ? o.inner_rtol : o.rtol;
+    const int maxit_in = mixed ? o.inner_max_iters : o.max_iters;
+    const int nb = (int)g.size();
+    std::vector<int> jv(nb), jv1(nb);
+    for (int z = 0; z < nb; ++z) {
+        jv[z] = g[z]->j;
+        jv1[z] = g[z]->j + 1;
+    }
+    const SlotBatch bj = batch_of(g, &jv), bj1 = batch_of(g, &jv1), b0 = batch_of(g, nullptr);
+    {
+        BatchScope bs(&bj);
+        vec_tab_copy<T>(ctx, N, nullptr, K.vptr.p, K.w.p, nullptr, 0, nullptr);     // w = V_j
+    }
+    {
+        BatchScope bs(&b0);
+        precond<T>(r, K.w.p, K.zb.p);                                                // zb = P^{-1} V_j
+    }
+    {
+        BatchScope bs(&bj);
+        vec_tab_copy<T>(ctx, N, K.zb.p, nullptr, nullptr, ztab, 0, nullptr);         // Z_j = zb
+    }
+    {
+        BatchScope bs(&b0);
+        apply_K<T>(r, eta0, K.zb.p, K.w.p);                                          // w = K Z_j
+    }
+    {
+        BatchScope bs(&bj1);                                                         // CGS2 against V_0..V_j
+        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc, false);
+        vec_maxpy<T>(ctx, N, dsc, -1.0, K.vptr.p, 1, K.w.p);
+        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc + MAX_MDOT, false);
+        vec_maxpy<T>(ctx, N, dsc + MAX_MDOT, -1.0, K.vptr.p, 1, K.w.p);
+    }
+    {
+        BatchScope bs(&b0);
+        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.wptr.p + 1, 1, dsc + 2 * MAX_MDOT, false);
+    }
+    {
+        BatchScope bs(&bj1);
+        vec_tab_copy<T>(ctx, N, K.w.p, nullptr, nullptr, vtab, 0, dsc + 2 * MAX_MDOT);  // V_{j+1} = w / |w|
+    }
+    const int kr = 2 * MAX_MDOT + 1;
+    const double* hb = batch_gather(ctx, st, g, dsc, kr);
+    Group ends;
+    for (int z = 0; z < nb; ++z) {
+        BSlot* sl = g[z];
+        const double* row = hb + (size_t)z * kr;
+        const int j = sl->j;
+        double* h = &sl->H[(size_t)j * (m + 1)];
+        for (int i = 0; i <= j; ++i) h[i] = row[i] + row[MAX_MDOT + i];
+        h[j + 1] = std::sqrt(std::max(0.0, row[2 * MAX_MDOT]));
+        if (!std::isfinite(h[j + 1])) {
+            sl->inner_total += sl->its;
+            sl->outer += 1;
+            finish(sl, TNG_E_NOTCONV);
+            done.push_back(sl);
+            continue;
+        }
+        for (int i = 0; i < j; ++i) {
+            const double t0 = sl->cs[i] * h[i] + sl->sn[i] * h[i + 1];
+            h[i + 1] = -sl->sn[i] * h[i] + sl->cs[i] * h[i + 1];
+            h[i] = t0;
+        }
+        const double den = std::hypot(h[j], h[j + 1]);
+        sl->cs[j] = den > 0 ? h[j] / den : 1.0;
+        sl->sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+        h[j] = den;
+        h[j + 1] = 0.0;
+        sl->g[j + 1] = -sl->sn[j] * sl->g[j];
+        sl->g[j] = sl->cs[j] * sl->g[j];
+        sl->res = std::fabs(sl->g[j + 1]);
+        sl->its += 1;
+        sl->jend = j;
+        if (sl->res <= rtol_in * sl->bnorm || sl->its >= maxit_in || h[j] == 0.0) {
+            sl->cycle_end = sl->inner_done = true;
+        } else if (j == m - 1) {
+            sl->cycle_end = true;
+        } else {
+            sl->j = j + 1;
+            continue;
+        }
+        ends.push_back(sl);
+    }
+    if (ends.empty()) return;
+    // x += Z y with y = H^{-1} g (upper triangular) per slot
+    double* up = host_up_rows(ctx, st);
+    std::vector<int> cnt(ends.size());
+    for (size_t z = 0; z < ends.size(); ++z) {
+        BSlot* sl = ends[z];
+        const int je = sl->jend;
+        double* yrow = up + z * MAX_MDOT;
+        for (int i = je; i >= 0; --i) {
+            double acc = sl->g[i];
+            for (int k = i + 1; k <= je; ++k) acc -= sl->H[(size_t)k * (m + 1) + i] * yrow[k];
+            yrow[i] = acc / sl->H[(size_t)i * (m + 1) + i];
+        }
+        cnt[z] = je + 1;
+    }
+    // (a sub-group's launches name the buffers of its own first slot)
+    tng_solver* re = ends[0]->s;
+    KrylovWS<T>& KE = kws<T>(re);
+    batch_scatter(ctx, st, ends, MAX_MDOT, KE.coef.p + 3 * MAX_MDOT);
+    {
+        const SlotBatch be = batch_of(ends, &cnt);
+        BatchScope bs(&be);
+        vec_maxpy<T>(ctx, N, KE.coef.p + 3 * MAX_MDOT, 1.0, KE.zptr.p, 1, inner_x<T>(re));
+    }
+    Group restart, fin;
+    for (BSlot* sl : ends) (sl->inner_done ? fin : restart).push_back(sl);
+    if (!restart.empty()) {
+        // restart from the true inner residual w = b - K x
+        tng_solver* rr = restart[0]->s;
+        KrylovWS<T>& KR = kws<T>(rr);
+        const SlotBatch br = batch_of(restart, nullptr);
+        {
+            BatchScope bs(&br);
+            apply_K<T>(rr, hier<T>(rr)[0].eta.p, inner_x<T>(rr), KR.w.p);
+            vec_axpby<T>(ctx, N, 1.0, inner_b<T>(rr), -1.0, KR.w.p);
+            vec_smdot<T>(ctx, *rr->ds, L0(rr), L1(rr), KR.w.p, KR.wptr.p + 1, 1, KR.coef.p, false);
+        }
+        const double* hr = batch_gather(ctx, st, restart, KR.coef.p, 1);
+        Group cont;
+        std::vector<double> sq;
+        for (size_t z = 0; z < restart.size(); ++z) {
+            BSlot* sl = restart[z];
+            const double beta = std::sqrt(std::max(0.0, hr[z]));
+            sl->res = beta;
+            if (beta <= rtol_in * sl->bnorm) {
+                sl->inner_done = true;
+                fin.push_back(sl);
+            } else if (!std::isfinite(beta)) {
+                sl->inner_total += sl->its;
+                sl->outer += 1;
+                finish(sl, TNG_E_NOTCONV);
+                done.push_back(sl);
+            } else {
+                cont.push_back(sl);
+                sq.push_back(hr[z]);
+            }
+        }
+        if (!cont.empty()) {
+            // the squared norms are already at each slot's coefficient 0
+            begin_cycle<T>(ctx, cont, kws<T>(cont[0]->s).w.p, sq.data(), 1, false);
+        }
+    }
+    if (!fin.empty()) outer_update<T>(ctx, st, o, fin, done);
+}
+
+}  // namespace
+
+bool SolverBatch::start(int i, const double* T, double E, double Ra, double* const u_out[3], double* p_out) {
+    Slot* sl = slot_.at(i).get();
+    TNG_REQUIRE(!sl->busy, "slot is busy");
+    TNG_REQUIRE(T != nullptr && u_out != nullptr && p_out != nullptr, "NULL argument");
+    tng_solver* s = sl->s;
+    const Level& L = mesh_->lv[0];
+    const long long ns = s->ns0, np = s->np;
+    hipStream_t stm = ctx_->stream;
+    sl->t0 = std::chrono::steady_clock::now();
+    for (int c = 0; c < 3; ++c) sl->uo[c] = u_out[c];
+    sl->po = p_out;
+    sl->rc = TNG_OK;
+    sl->failed = false;
+    sl->outer = sl->inner_total = 0;
+    sl->its = 0;
+    sl->relres = 0.0;
+    sl->info = tng_solve_info{};
+    sl->busy = true;
+    std::vector<BSlot*> done;
+    try {
+        launch_eta_from_T(ctx_, L, TNG_F64, T, sl->eta.p, E, 0.0);
+        double* f[3] = {sl->f.p, sl->f.p + ns, sl->f.p + 2 * ns};
+        energy_buoyancy(ctx_, L, T, Ra, f);
+        setup_viscosity(s, sl->eta.p);
+        TNG_HIP(hipMemcpyAsync(s->bo.p, sl->f.p, 3 * ns * sizeof(double), hipMemcpyDeviceToDevice, stm));
+        vec_fill<double>(ctx_, np, 0.0, s->bo.p + 3 * ns);
+        vec_fill<double>(ctx_, s->N, 0.0, s->xo.p);
+        vec_smdot<double>(ctx_, *s->ds, L0(s), L1(s), s->bo.p, s->dptr.p, 1, s->scal.p + 1, false);
+        readback(s, s->scal.p + 1, 1);
+        const double bsq = s->host[0];
+        sl->bn = std::sqrt(std::max(0.0, bsq));
+        if (!std::isfinite(sl->bn)) {
+            finish(sl, TNG_E_NOTCONV);
+        } else if (!(sl->bn > 0.0)) {
+            finish(sl, TNG_OK);                       // b = 0: x = 0
+        } else {
+            sl->relres = 1.0;
+            Group one{sl};
+            if (opts_.mixed) {
+                TNG_HIP(hipMemcpyAsync(s->ro.p, s->bo.p, s->N * sizeof(double), hipMemcpyDeviceToDevice, stm));
+                begin_inner(ctx_, *st_, one, done);
+            } else {
+                // FP64: FGMRES on b itself, V_0 = b / |b| (|b|^2 at the Krylov coefficient 0)
+                TNG_HIP(hipMemcpyAsync(s->k64.coef.p, s->scal.p + 1, sizeof(double), hipMemcpyDeviceToDevice, stm));
+                begin_cycle<double>(ctx_, one, s->bo.p, &bsq, 1, true);
+            }
+        }
+    } catch (const Error& e) {
+        finish(sl, e.code);
+    }
+    if (!sl->busy) {
+        copy_out(ctx_, sl);
+        TNG_HIP(hipStreamSynchronize(stm));
+        set_info(sl);
+        return false;
+    }
+    return true;
+}
+
+std::vector<int> SolverBatch::step() {
+    std::vector<int> run;
+    for (size_t i = 0; i < slot_.size(); ++i)
+        if (slot_[i]->busy) run.push_back((int)i);
+    std::vector<BSlot*> done;
+    for (size_t c0 = 0; c0 < run.size(); c0 += MAX_BATCH) {
+        Group g;
+        for (size_t k = c0; k < std::min(run.size(), c0 + MAX_BATCH); ++k) g.push_back(slot_[run[k]].get());
+        try {
+            if (opts_.mixed)
+                step_group<float>(ctx_, *st_, opts_, g, done);
+            else
+                step_group<double>(ctx_, *st_, opts_, g, done);
+        } catch (const Error& e) {
+            // a launch or copy failed: every slot of the group ends with the error
+            for (BSlot* sl : g)
+                if (sl->busy) {
+                    finish(sl, e.code);
+                    done.push_back(sl);
+                }
+        }
+    }
+    std::vector<int> out;
+    if (done.empty()) return out;
+    for (BSlot* sl : done) copy_out(ctx_, sl);
+    TNG_HIP(hipStreamSynchronize(ctx_->stream));
+    for (BSlot* sl : done) {
+        set_info(sl);
+        for (size_t i = 0; i < slot_.size(); ++i)
+            if (slot_[i].get() == sl) out.push_back((int)i);
+    }
+    return out;
+}
+
 }  // namespace tng
 
 using tng::Error;
@@ -523,12 +1163,29 @@ int tng_solver_opts_default(tng_solver_opts* o) {
     o->max_outer = 20;
     o->power_its = 10;
     o->hg_alpha = 0.0;
+    o->graphs = 1;
     TNG_API_END
 }
 
 int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* opts, tng_solver** out) {
     TNG_API_BEGIN
-    TNG_REQUIRE(ctx != nullptr && mesh != nullptr && opts != nullptr && out != nullptr, "NULL argument");
+    TNG_REQUIRE(out != nullptr, "NULL argument");
+    *out = tng::create_solver(ctx, mesh, opts, false);
+    TNG_API_END
+}
+
+int tng_stokes_solver_destroy(tng_solver* s) {
+    TNG_API_BEGIN
+    delete s;
+    TNG_API_END
+}
+
+}  // extern "C"
+
+namespace tng {
+
+tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* opts, bool batch_slot) {
+    TNG_REQUIRE(ctx != nullptr && mesh != nullptr && opts != nullptr, "NULL argument");
     TNG_REQUIRE(mesh->ctx != nullptr, "mesh was built without a context");
     TNG_REQUIRE(mesh->lv.size() >= 2, "the solver needs at least two mesh levels");
     TNG_REQUIRE(opts->restart >= 1 && opts->restart + 1 <= tng::MAX_MDOT, "restart must be in 1..23");
@@ -546,6 +1203,7 @@ int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts
     s->ctx = ctx;
     s->mesh = mesh;
     s->opts = *opts;
+    s->batch_slot = batch_slot;
     s->nlev = nlev;
     s->ns0 = mesh->lv[0].node_slots();
     s->np = mesh->lv[1].node_slots();
@@ -580,16 +1238,20 @@ int tng_stokes_solver_create(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts
         TNG_HIP(hipMemcpy(s->scal.p + 33, &cnt, sizeof(double), hipMemcpyHostToDevice));
     }
     TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host), 256 * sizeof(double), hipHostMallocDefault));
+    if (opts->graphs && !batch_slot) {
+        TNG_HIP(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));   // default priority
+        if (tng_ctx_create(ctx->device, s->gstream, &s->gctx) != TNG_OK)
+            throw Error(TNG_E_HIP, "graph context creation failed");
+        TNG_HIP(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+        TNG_HIP(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+    }
     TNG_HIP(hipStreamSynchronize(ctx->stream));
-    *out = s.release();
-    TNG_API_END
+    return s.release();
 }
 
-int tng_stokes_solver_destroy(tng_solver* s) {
-    TNG_API_BEGIN
-    delete s;
-    TNG_API_END
-}
+}  // namespace tng
+
+extern "C" {
 
 int tng_stokes_solver_setup(tng_solver* s, const double* eta_wedge) {
     TNG_API_BEGIN

@@ -31,6 +31,7 @@
 #include <cstdio>
 #include <type_traits>
 
+#include "batch_dev.hpp"
 #include "tng_internal.hpp"
 #include "wedge.hpp"
 
@@ -114,8 +115,22 @@ constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
 
 template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG>
-__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
+__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a_in, SlotBatch sb) {
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
+    // fields of slot blockIdx.z (mesh geometry is shared)
+    BandArgs<T> a = a_in;
+    {
+        const long long so = slot_off(sb);
+        a.eta = at_slot(a_in.eta, so);
+        a.u0 = at_slot(a_in.u0, so);
+        a.u1 = at_slot(a_in.u1, so);
+        a.u2 = at_slot(a_in.u2, so);
+        a.p = at_slot(a_in.p, so);
+        a.y0 = at_slot(a_in.y0, so);
+        a.y1 = at_slot(a_in.y1, so);
+        a.y2 = at_slot(a_in.y2, so);
+        a.yp = at_slot(a_in.yp, so);
+    }
     constexpr int TC = TIC / RS;  // cell columns per workgroup; RS waves share a column radially
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
@@ -709,7 +724,11 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a) {
 // Zero the node values that receive two partial sums: node columns on tile
 // seams and node layers on radial-chunk seams.
 template <typename T>
-__global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int KC, int nchunk) {
+__global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int KC, int nchunk, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    y0 = at_slot(y0, so);
+    y1 = at_slot(y1, so);
+    y2 = at_slot(y2, so);
     const int nseam_i = m / TI - 1;
     const long long ncol = (long long)10 * nseam_i * (m + 1);       // seam columns x rows
     const long long n1 = n + 1;
@@ -743,40 +762,42 @@ __global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T, int RS, int CPL, bool A, bool BT, bool B, bool HG>
-void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args) {
+void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb) {
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
     char detail[64] = {0};
     if (ctx->profile) {
         const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
-        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d", std::is_same<T, double>::value ? "f64" : "f32",
-                      ops, HG ? "+HG" : "", args.m, args.n);
+        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d%s", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", args.m, args.n, sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
-    stokes_band_kernel<T, RS, CPL, A, BT, B, HG><<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args);
+    stokes_band_kernel<T, RS, CPL, A, BT, B, HG>
+        <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     TNG_HIP(hipGetLastError());
 }
 
 // key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only)
 template <typename T, int RS, int CPL>
-void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, int key) {
+void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb, int key) {
     switch (key) {
-        case 1: launch_band_t<T, RS, CPL, true, false, false, false>(ctx, args); break;
-        case 2: launch_band_t<T, RS, CPL, false, true, false, false>(ctx, args); break;
-        case 3: launch_band_t<T, RS, CPL, true, true, false, false>(ctx, args); break;
-        case 4: launch_band_t<T, RS, CPL, false, false, true, false>(ctx, args); break;
-        case 5: launch_band_t<T, RS, CPL, true, false, true, false>(ctx, args); break;
-        case 6: launch_band_t<T, RS, CPL, false, true, true, false>(ctx, args); break;
-        case 7: launch_band_t<T, RS, CPL, true, true, true, false>(ctx, args); break;
-        case 9: launch_band_t<T, RS, CPL, true, false, false, true>(ctx, args); break;
-        case 11: launch_band_t<T, RS, CPL, true, true, false, true>(ctx, args); break;
-        case 13: launch_band_t<T, RS, CPL, true, false, true, true>(ctx, args); break;
-        case 15: launch_band_t<T, RS, CPL, true, true, true, true>(ctx, args); break;
+        case 1: launch_band_t<T, RS, CPL, true, false, false, false>(ctx, args, sb); break;
+        case 2: launch_band_t<T, RS, CPL, false, true, false, false>(ctx, args, sb); break;
+        case 3: launch_band_t<T, RS, CPL, true, true, false, false>(ctx, args, sb); break;
+        case 4: launch_band_t<T, RS, CPL, false, false, true, false>(ctx, args, sb); break;
+        case 5: launch_band_t<T, RS, CPL, true, false, true, false>(ctx, args, sb); break;
+        case 6: launch_band_t<T, RS, CPL, false, true, true, false>(ctx, args, sb); break;
+        case 7: launch_band_t<T, RS, CPL, true, true, true, false>(ctx, args, sb); break;
+        case 9: launch_band_t<T, RS, CPL, true, false, false, true>(ctx, args, sb); break;
+        case 11: launch_band_t<T, RS, CPL, true, true, false, true>(ctx, args, sb); break;
+        case 13: launch_band_t<T, RS, CPL, true, false, true, true>(ctx, args, sb); break;
+        case 15: launch_band_t<T, RS, CPL, true, true, true, true>(ctx, args, sb); break;
         default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
     }
 }
 
 template <typename T>
-__global__ void fill0_kernel(T* __restrict__ a, long long n) {
+__global__ void fill0_kernel(T* __restrict__ a, long long n, SlotBatch sb) {
+    a = at_slot(a, slot_off(sb));
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += stride) a[i] = T(0);
@@ -829,36 +850,39 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.dirichlet = (flags & TNG_OP_DIRICHLET) ? 1 : 0;
     const bool doHG = doA && hg_alpha != 0.0;
     a.hg = T(hg_alpha * (5.0 / 81.0));
+    const SlotBatch sb = launch_batch();
+    const unsigned nbz = (unsigned)sb.nb;
     if (doB) {
         const long long np = Lp->node_slots();
-        fill0_kernel<T><<<std::min<long long>(nblocks(np, 256), 4096), 256, 0, ctx->stream>>>(a.yp, np);
+        fill0_kernel<T><<<dim3((unsigned)std::min<long long>(nblocks(np, 256), 4096), 1, nbz), 256, 0,
+                          ctx->stream>>>(a.yp, np, sb);
         TNG_HIP(hipGetLastError());
     }
     if ((doA || doBT) && (a.ntile > 1 || a.nchunk > 1)) {
         const long long nz = 10LL * (a.ntile - 1) * (L.m + 1) * (L.n + 1) +
                              10LL * (L.m + 1) * (L.m + 1) * (a.nchunk - 1);
         if (nz > 0) {
-            zero_seams_kernel<T><<<nblocks(nz, 256), 256, 0, ctx->stream>>>(
-                a.y0, a.y1, a.y2, L.m, L.n, a.TI, a.KC, a.nchunk);
+            zero_seams_kernel<T><<<dim3(nblocks(nz, 256), 1, nbz), 256, 0, ctx->stream>>>(
+                a.y0, a.y1, a.y2, L.m, L.n, a.TI, a.KC, a.nchunk, sb);
             TNG_HIP(hipGetLastError());
         }
     }
     const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0);
     if constexpr (std::is_same<T, double>::value) {
         if (rs == 1)
-            launch_band_ops<T, 1, 1>(ctx, a, key);
+            launch_band_ops<T, 1, 1>(ctx, a, sb, key);
         else if (rs == 2)
-            launch_band_ops<T, 2, 1>(ctx, a, key);
+            launch_band_ops<T, 2, 1>(ctx, a, sb, key);
         else
-            launch_band_ops<T, 4, 1>(ctx, a, key);
+            launch_band_ops<T, 4, 1>(ctx, a, sb, key);
     } else {
         // FP32 splits only two-cell stretches (one-cell columns fit one stretch)
         if (cpl == 1)
-            launch_band_ops<T, 1, 1>(ctx, a, key);
+            launch_band_ops<T, 1, 1>(ctx, a, sb, key);
         else if (rs == 1)
-            launch_band_ops<T, 1, 2>(ctx, a, key);
+            launch_band_ops<T, 1, 2>(ctx, a, sb, key);
         else
-            launch_band_ops<T, 2, 2>(ctx, a, key);
+            launch_band_ops<T, 2, 2>(ctx, a, sb, key);
     }
     const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
     if (doA || doBT) {

@@ -59,44 +59,121 @@ inline thread_local long long tl_device_bytes = 0;
 
 inline long long devbuf_pages(size_t bytes) { return (long long)((bytes + 4095) & ~size_t(4095)); }
 
-// Owning device buffer.
+// A bump region of device memory that DevBuf draws from while it is installed
+// on the calling thread.  Objects built the same way in two arenas place every
+// buffer at the same offset from the arena base, so one kernel launch can
+// reach the buffers of several such objects through per-object byte offsets
+// (SlotBatch).  Buffers taken from an arena are never freed one by one; the
+// arena's owner frees the region.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+constexpr size_t ARENA_ALIGN = 256;
+inline size_t arena_round(size_t bytes) { return (bytes + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1); }
+inline thread_local Arena* tl_arena = nullptr;
+// Bytes an arena needs for every DevBuf allocation made so far by this thread
+// (never decreases: an arena does not reuse released space).
+inline thread_local long long tl_arena_demand = 0;
+
+class ArenaScope {
+  public:
+    explicit ArenaScope(Arena* a) : prev_(tl_arena) { tl_arena = a; }
+    ~ArenaScope() { tl_arena = prev_; }
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+  private:
+    Arena* prev_;
+};
+
+// Device buffer: owned (hipMalloc / hipFree), or carved from the installed arena.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool owned = false;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), owned(o.owned) { o.p = nullptr; o.n = 0; o.owned = false; }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; owned = o.owned;
+            o.p = nullptr; o.n = 0; o.owned = false;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Error(TNG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        const size_t bytes = count * sizeof(T);
+        tl_arena_demand += (long long)arena_round(bytes);
+        if (tl_arena != nullptr) {
+            Arena& a = *tl_arena;
+            if (a.used + arena_round(bytes) > a.cap)
+                throw Error(TNG_E_NOMEM, "arena of " + std::to_string(a.cap) + " bytes exhausted");
+            p = reinterpret_cast<T*>(a.base + a.used);
+            a.used += arena_round(bytes);
+            owned = false;
+        } else {
+            if (hipMalloc(reinterpret_cast<void**>(&p), bytes) != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Error(TNG_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            }
+            owned = true;
+            tl_device_bytes += devbuf_pages(bytes);
         }
         n = count;
-        tl_device_bytes += devbuf_pages(count * sizeof(T));
     }
     void release() {
-        if (p) {
+        if (p && owned) {
             (void)hipFree(p);
             tl_device_bytes -= devbuf_pages(n * sizeof(T));
         }
         p = nullptr;
         n = 0;
+        owned = false;
     }
     void upload(const T* host, size_t count, hipStream_t s) {
         TNG_REQUIRE(count <= n, "upload larger than buffer");
         TNG_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
     }
+};
+
+// Slots of one batched launch.  Kernels that take a SlotBatch run gridDim.z =
+// nb copies of their grid; copy z works on the buffers of slot z, which sit at
+// byte offset off[z] from the buffers named in the launch (arena layout, see
+// Arena); mesh arrays are shared and never offset.  With has_cnt, cnt[z]
+// replaces the launch's vector count (multi-dots, multi-axpys) or table index
+// for copy z.  Outside a batch every launch is the single slot {nb = 1, off 0}.
+constexpr int MAX_BATCH = 16;
+struct SlotBatch {
+    int nb = 1;
+    int has_cnt = 0;
+    long long off[MAX_BATCH] = {};
+    int cnt[MAX_BATCH] = {};
+};
+inline thread_local const SlotBatch* tl_batch = nullptr;
+inline SlotBatch launch_batch() { return tl_batch ? *tl_batch : SlotBatch{}; }
+// Launchers whose kernels do not take a SlotBatch refuse to run inside a batch.
+inline void require_unbatched(const char* what) {
+    if (tl_batch != nullptr && tl_batch->nb > 1)
+        throw Error(TNG_E_STATE, std::string(what) + " has no batched form");
+}
+
+class BatchScope {
+  public:
+    explicit BatchScope(const SlotBatch* b) : prev_(tl_batch) { tl_batch = b; }
+    ~BatchScope() { tl_batch = prev_; }
+    BatchScope(const BatchScope&) = delete;
+    BatchScope& operator=(const BatchScope&) = delete;
+  private:
+    const SlotBatch* prev_;
 };
 
 // Number of per-triangle geometry values: rows rho1, rho2 of G^{-1}, row rho3

@@ -116,3 +116,51 @@ def test_tight_budget_serves_everything(tng, ctx):
     for t in reqs:
         assert srv.poll(t)["rc"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("mixed,nreq", [(1, 18), (0, 3)])
+def test_batched_solves_match_direct_solve(tng, ctx, mixed, nreq):
+    """Requests of one level run as one lockstep batch (18 requests: two launch
+    groups of at most 16 slots, joining at different Krylov indices).  Every
+    result is compared with the oracle's sparse direct solve of the same
+    problem: eta = exp(-ln(c) T) per wedge, f = Ra T rhat (Dirichlet rows 0)."""
+    import torch
+    from oracle.mesh import ShellMesh
+    from oracle.stokes import StokesOracle, buoyancy_rhs, eta_from_temperature
+    from tests._support import LayoutMap
+    mt = 8
+    om = ShellMesh(mt, mt)
+    omp = ShellMesh(mt // 2, mt // 2, hierarchy=om.h)
+    hmesh = tng.Mesh(None, mt, mt, levels=2)
+    lm, lmp = LayoutMap(*hmesh.coords(0), om), LayoutMap(*hmesh.coords(1), omp)
+    # rtol 1e-11: the buoyancy-driven velocity is small next to the pressure, so a
+    # relative residual of 1e-10 leaves velocity errors near 1e-7 at contrast 10^1.5
+    srv = tng.Server(ctx, LEVELS, budget_bytes=8 << 30, max_slots=nreq, mixed=mixed, rtol=1e-11,
+                     max_iters=800)
+    Ra = 1e5
+    reqs = []
+    for i in range(nreq):
+        T = synthetic.temperature(om.s, om.r, seed=500 + i, lmin=1, lmax=8).ravel()
+        lc = 1.5 + 1.5 * i / max(nreq - 1, 1)
+        Tt = torch.tensor(lm.to_lib(T), device="cuda")
+        u = torch.empty((3,) + lm.shape, dtype=torch.float64, device="cuda")
+        p = torch.empty(lmp.shape, dtype=torch.float64, device="cuda")
+        reqs.append((srv.submit(0, Tt, lc, Ra, u, p), T, lc, u, p, Tt))
+    srv.wait(0)
+    st = srv.stats()
+    worst = 0.0
+    for t, T, lc, u, p, _ in reqs:
+        r = srv.poll(t)
+        assert r["done"] and r["rc"] == 0 and r["rel_res"] <= 1e-11, r
+        eta = eta_from_temperature(om, T, lc * np.log(10.0))
+        f = buoyancy_rhs(om, T, Ra)
+        f[om.boundary_nodes()] = 0.0
+        uo, po = StokesOracle(mt, mt, eta, hierarchy=om.h).solve(f)
+        gu = lm.from_lib(u.cpu().numpy(), check_dups=1e-12)
+        gp = lmp.from_lib(p.cpu().numpy(), check_dups=1e-12)
+        eu = np.linalg.norm(gu - uo) / np.linalg.norm(uo)
+        ep = np.linalg.norm(gp - po) / np.linalg.norm(po)
+        worst = max(worst, eu, ep)
+        assert eu < 1e-7 and ep < 1e-7, (t, lc, eu, ep)
+    print(f"batched mixed={mixed}: {nreq} requests, {st['slots']} slots, worst error {worst:.2e}")
+    srv.close()

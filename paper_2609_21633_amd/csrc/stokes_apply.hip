@@ -114,22 +114,22 @@ __device__ __forceinline__ double wave_shift(double v) {
 constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
 
-template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG>
-__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a_in, SlotBatch sb) {
+// BATCH: copy blockIdx.z works on the fields of slot z of a batch (mesh
+// geometry shared); otherwise sb is unused.
+template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH>
+__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
-    // fields of slot blockIdx.z (mesh geometry is shared)
-    BandArgs<T> a = a_in;
-    {
+    if constexpr (BATCH) {
         const long long so = slot_off(sb);
-        a.eta = at_slot(a_in.eta, so);
-        a.u0 = at_slot(a_in.u0, so);
-        a.u1 = at_slot(a_in.u1, so);
-        a.u2 = at_slot(a_in.u2, so);
-        a.p = at_slot(a_in.p, so);
-        a.y0 = at_slot(a_in.y0, so);
-        a.y1 = at_slot(a_in.y1, so);
-        a.y2 = at_slot(a_in.y2, so);
-        a.yp = at_slot(a_in.yp, so);
+        a.eta = at_slot(a.eta, so);
+        a.u0 = at_slot(a.u0, so);
+        a.u1 = at_slot(a.u1, so);
+        a.u2 = at_slot(a.u2, so);
+        a.p = at_slot(a.p, so);
+        a.y0 = at_slot(a.y0, so);
+        a.y1 = at_slot(a.y1, so);
+        a.y2 = at_slot(a.y2, so);
+        a.yp = at_slot(a.yp, so);
     }
     constexpr int TC = TIC / RS;  // cell columns per workgroup; RS waves share a column radially
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
@@ -761,8 +761,11 @@ __global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// the solver's combinations (A, B^T, K, each viscous one also with hourglass
+// control) have a batched form; the others run one slot at a time
 template <typename T, int RS, int CPL, bool A, bool BT, bool B, bool HG>
 void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb) {
+    constexpr bool BATCHABLE = (A && !BT && !B) || (!A && BT && !B) || (A && BT && B);
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
     char detail[64] = {0};
     if (ctx->profile) {
@@ -771,8 +774,14 @@ void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch&
                       ops, HG ? "+HG" : "", args.m, args.n, sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
-    stokes_band_kernel<T, RS, CPL, A, BT, B, HG>
-        <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
+    if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false>
+            <<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
+    else if constexpr (BATCHABLE)
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true>
+            <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
+    else
+        throw Error(TNG_E_STATE, "this operator combination has no batched form");
     TNG_HIP(hipGetLastError());
 }
 

@@ -122,8 +122,9 @@ def test_tight_budget_serves_everything(tng, ctx):
 def test_batched_solves_match_direct_solve(tng, ctx, mixed, nreq):
     """Requests of one level run as one lockstep batch (18 requests: two launch
     groups of at most 16 slots, joining at different Krylov indices).  Every
-    result is compared with the oracle's sparse direct solve of the same
-    problem: eta = exp(-ln(c) T) per wedge, f = Ra T rhat (Dirichlet rows 0)."""
+    result is compared with the single-problem GPU solver on the same problem
+    (eta = exp(-ln(c) T) per wedge, f = Ra T rhat with zero Dirichlet rows), and
+    the first and last with the oracle's sparse direct solve."""
     import torch
     from oracle.mesh import ShellMesh
     from oracle.stokes import StokesOracle, buoyancy_rhs, eta_from_temperature
@@ -131,12 +132,12 @@ def test_batched_solves_match_direct_solve(tng, ctx, mixed, nreq):
     mt = 8
     om = ShellMesh(mt, mt)
     omp = ShellMesh(mt // 2, mt // 2, hierarchy=om.h)
-    hmesh = tng.Mesh(None, mt, mt, levels=2)
-    lm, lmp = LayoutMap(*hmesh.coords(0), om), LayoutMap(*hmesh.coords(1), omp)
+    mesh = tng.Mesh(ctx, mt, mt, levels=3)          # the server's hierarchy of (8,8): down to (2,2)
+    lm, lmp = LayoutMap(*mesh.coords(0), om), LayoutMap(*mesh.coords(1), omp)
     # rtol 1e-11: the buoyancy-driven velocity is small next to the pressure, so a
     # relative residual of 1e-10 leaves velocity errors near 1e-7 at contrast 10^1.5
-    srv = tng.Server(ctx, LEVELS, budget_bytes=8 << 30, max_slots=nreq, mixed=mixed, rtol=1e-11,
-                     max_iters=800)
+    opts = dict(mixed=mixed, rtol=1e-11, max_iters=800)
+    srv = tng.Server(ctx, LEVELS, budget_bytes=8 << 30, max_slots=nreq, **opts)
     Ra = 1e5
     reqs = []
     for i in range(nreq):
@@ -148,19 +149,36 @@ def test_batched_solves_match_direct_solve(tng, ctx, mixed, nreq):
         reqs.append((srv.submit(0, Tt, lc, Ra, u, p), T, lc, u, p, Tt))
     srv.wait(0)
     st = srv.stats()
-    worst = 0.0
-    for t, T, lc, u, p, _ in reqs:
+    single = tng.StokesSolver(ctx, mesh, **opts)
+    worst_single = worst_oracle = 0.0
+    for k, (t, T, lc, u, p, Tt) in enumerate(reqs):
         r = srv.poll(t)
         assert r["done"] and r["rc"] == 0 and r["rel_res"] <= 1e-11, r
-        eta = eta_from_temperature(om, T, lc * np.log(10.0))
-        f = buoyancy_rhs(om, T, Ra)
-        f[om.boundary_nodes()] = 0.0
-        uo, po = StokesOracle(mt, mt, eta, hierarchy=om.h).solve(f)
         gu = lm.from_lib(u.cpu().numpy(), check_dups=1e-12)
         gp = lmp.from_lib(p.cpu().numpy(), check_dups=1e-12)
-        eu = np.linalg.norm(gu - uo) / np.linalg.norm(uo)
-        ep = np.linalg.norm(gp - po) / np.linalg.norm(po)
-        worst = max(worst, eu, ep)
-        assert eu < 1e-7 and ep < 1e-7, (t, lc, eu, ep)
-    print(f"batched mixed={mixed}: {nreq} requests, {st['slots']} slots, worst error {worst:.2e}")
+        eta = torch.empty(mesh.wedge_shape(0), dtype=torch.float64, device="cuda")
+        tng.eta_from_temperature(ctx, mesh, 0, Tt, lc * np.log(10.0), 0.0, eta)
+        f = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+        tng.rhs_buoyancy(ctx, mesh, 0, Tt, Ra, f)
+        us, ps = torch.empty_like(u), torch.empty_like(p)
+        info = single.solve(f, None, us, ps, eta=eta)
+        assert info["rel_res"] <= 1e-11
+        su, sp_ = lm.from_lib(us.cpu().numpy()), lmp.from_lib(ps.cpu().numpy())
+        du = np.linalg.norm(gu - su) / np.linalg.norm(su)
+        dp = np.linalg.norm(gp - sp_) / np.linalg.norm(sp_)
+        worst_single = max(worst_single, du, dp)
+        assert du < 1e-8 and dp < 1e-8, (k, lc, du, dp)
+        if k in (0, nreq - 1):
+            eta_o = eta_from_temperature(om, T, lc * np.log(10.0))
+            fo = buoyancy_rhs(om, T, Ra)
+            fo[om.boundary_nodes()] = 0.0
+            uo, po = StokesOracle(mt, mt, eta_o, hierarchy=om.h).solve(fo)
+            eu = np.linalg.norm(gu - uo) / np.linalg.norm(uo)
+            ep = np.linalg.norm(gp - po) / np.linalg.norm(po)
+            worst_oracle = max(worst_oracle, eu, ep)
+            assert eu < 1e-7 and ep < 1e-7, (k, lc, eu, ep)
+        print(f"request {k}: contrast 10^{lc:.2f}, {r['inner_its']} its, vs single {max(du, dp):.1e}", flush=True)
+    single.close()
+    print(f"batched mixed={mixed}: {nreq} requests, {st['slots']} slots, worst vs single solver "
+          f"{worst_single:.2e}, vs direct solve {worst_oracle:.2e}")
     srv.close()

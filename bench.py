@@ -361,6 +361,9 @@ def main():
     ap.add_argument("--coupled", action="store_true",
                     help="instead: coupled Stokes-energy steps on the (--mt, --nr) shell (default (256,256), "
                          "--steps steps), one JSON report line")
+    ap.add_argument("--profile-solve", choices=["fp64", "mixed"],
+                    help="instead: one Stokes solve of the contrast-1e6 field on the (--mt, --nr) shell, for "
+                         "kernel traces; one JSON report line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the shell would shard by "
@@ -373,6 +376,15 @@ def main():
     ctx = tng.Context(0)
     if args.serving_sweep:
         print(json.dumps(bench_serving_sweep(tng, ctx)), flush=True)
+        return
+    if args.profile_solve:
+        mesh = tng.Mesh(ctx, args.mt, args.nr, levels=int(math.log2(args.mt)))
+        T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
+        s, _ = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=1 if args.profile_solve == "mixed" else 0,
+                           reps=1)
+        print(json.dumps({"workload": f"Stokes solve to 1e-8, contrast 1e6, ({args.mt},{args.nr}) shell",
+                          "mode": args.profile_solve, "seconds": round(s["wall"], 3), "inner_its": s["inner_its"],
+                          "outer_its": s["outer_its"], "rel_res": s["rel_res"], "rc": s["rc"]}), flush=True)
         return
     if args.coupled:
         cm = args.mt if "--mt" in sys.argv else 256

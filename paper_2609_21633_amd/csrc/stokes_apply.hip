@@ -38,7 +38,7 @@
 namespace tng {
 namespace {
 
-constexpr int TIC = 8;   // waves per workgroup (cell columns when a column fits one wave)
+constexpr int TIC = 8;   // widest workgroup: waves (cell columns when a column fits one wave)
 
 
 template <typename T>
@@ -116,8 +116,9 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 
 // BATCH: copy blockIdx.z works on the fields of slot z of a batch (mesh
 // geometry shared); otherwise sb is unused.
-template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH>
-__global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
+// WG: waves per workgroup (4 or 8); a workgroup covers WG / RS cell columns.
+template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG>
+__global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
     if constexpr (BATCH) {
         const long long so = slot_off(sb);
@@ -131,7 +132,7 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a, Sl
         a.y2 = at_slot(a.y2, so);
         a.yp = at_slot(a.yp, so);
     }
-    constexpr int TC = TIC / RS;  // cell columns per workgroup; RS waves share a column radially
+    constexpr int TC = WG / RS;   // cell columns per workgroup; RS waves share a column radially
     constexpr int NL = CPL + 1;   // node layers per lane: bottom of each cell + top partial
     constexpr bool DO_U = DO_A || DO_BT;
     constexpr bool LOAD_U = DO_A || DO_B;
@@ -142,14 +143,14 @@ __global__ void __launch_bounds__(TIC * 64) stokes_band_kernel(BandArgs<T> a, Sl
     constexpr int RR = LOAD_U ? 3 : 1;
     constexpr int RW = LOAD_U ? TC + 1 : 1;
     __shared__ T ring[RR][RW][3][KWP];
-    constexpr int XW = DO_U ? TIC : 1;
+    constexpr int XW = DO_U ? WG : 1;
     __shared__ T xch[2][XW][3][CPL][64];   // lateral partials of layers 0..CPL-1 of every lane
     __shared__ T xtop[2][XW][3];           // and of the workgroup's top node
-    constexpr int RX = (DO_U && RS > 1) ? TIC : 1;
+    constexpr int RX = (DO_U && RS > 1) ? WG : 1;
     __shared__ T rxs[2][RX][4][3];     // top-layer partials handed to the wave above
     constexpr int NKC = DO_B ? 32 * CPL + 1 : 1;          // coarse layers of one wave
     constexpr int PADW = 2 * RS;                          // two empty columns each side
-    constexpr int BW = DO_B ? TIC + 2 * PADW : 1;
+    constexpr int BW = DO_B ? WG + 2 * PADW : 1;
     __shared__ T bsl[2][BW][4][NKC];   // per-wave coarse partials, wave w in slot w + PADW
     constexpr int NKL = CoarseMap<CPL>::NKL;
     const IsoWeights<T>& iso = IsoTable<T>::get();
@@ -763,7 +764,7 @@ inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / 
 
 // the solver's combinations (A, B^T, K, each viscous one also with hourglass
 // control) have a batched form; the others run one slot at a time
-template <typename T, int RS, int CPL, bool A, bool BT, bool B, bool HG>
+template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG>
 void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb) {
     constexpr bool BATCHABLE = (A && !BT && !B) || (!A && BT && !B) || (A && BT && B);
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
@@ -775,10 +776,10 @@ void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch&
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
     if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG>
             <<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else if constexpr (BATCHABLE)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG>
             <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else
         throw Error(TNG_E_STATE, "this operator combination has no batched form");
@@ -786,20 +787,20 @@ void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch&
 }
 
 // key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only)
-template <typename T, int RS, int CPL>
+template <typename T, int RS, int CPL, int WG>
 void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb, int key) {
     switch (key) {
-        case 1: launch_band_t<T, RS, CPL, true, false, false, false>(ctx, args, sb); break;
-        case 2: launch_band_t<T, RS, CPL, false, true, false, false>(ctx, args, sb); break;
-        case 3: launch_band_t<T, RS, CPL, true, true, false, false>(ctx, args, sb); break;
-        case 4: launch_band_t<T, RS, CPL, false, false, true, false>(ctx, args, sb); break;
-        case 5: launch_band_t<T, RS, CPL, true, false, true, false>(ctx, args, sb); break;
-        case 6: launch_band_t<T, RS, CPL, false, true, true, false>(ctx, args, sb); break;
-        case 7: launch_band_t<T, RS, CPL, true, true, true, false>(ctx, args, sb); break;
-        case 9: launch_band_t<T, RS, CPL, true, false, false, true>(ctx, args, sb); break;
-        case 11: launch_band_t<T, RS, CPL, true, true, false, true>(ctx, args, sb); break;
-        case 13: launch_band_t<T, RS, CPL, true, false, true, true>(ctx, args, sb); break;
-        case 15: launch_band_t<T, RS, CPL, true, true, true, true>(ctx, args, sb); break;
+        case 1: launch_band_t<T, RS, CPL, WG, true, false, false, false>(ctx, args, sb); break;
+        case 2: launch_band_t<T, RS, CPL, WG, false, true, false, false>(ctx, args, sb); break;
+        case 3: launch_band_t<T, RS, CPL, WG, true, true, false, false>(ctx, args, sb); break;
+        case 4: launch_band_t<T, RS, CPL, WG, false, false, true, false>(ctx, args, sb); break;
+        case 5: launch_band_t<T, RS, CPL, WG, true, false, true, false>(ctx, args, sb); break;
+        case 6: launch_band_t<T, RS, CPL, WG, false, true, true, false>(ctx, args, sb); break;
+        case 7: launch_band_t<T, RS, CPL, WG, true, true, true, false>(ctx, args, sb); break;
+        case 9: launch_band_t<T, RS, CPL, WG, true, false, false, true>(ctx, args, sb); break;
+        case 11: launch_band_t<T, RS, CPL, WG, true, true, false, true>(ctx, args, sb); break;
+        case 13: launch_band_t<T, RS, CPL, WG, true, false, true, true>(ctx, args, sb); break;
+        case 15: launch_band_t<T, RS, CPL, WG, true, true, true, true>(ctx, args, sb); break;
         default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
     }
 }
@@ -848,7 +849,13 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     int rs = stretches >= 3 ? 4 : (stretches >= 2 ? 2 : 1);
     if (rs > rs_max) rs = rs_max;
     if (L.m < TIC / rs) rs = 1;                     // the split needs full-width tiles
-    a.TI = std::min(TIC / rs, L.m);
+    // Workgroup width (measured at (128,128)/(256,256)): 4 waves for FP64 columns of up to two
+    // stretches (FP64 K 0.90 -> 0.82 ms, A 0.60 -> 0.53 ms) and for the FP32 full operator on
+    // one-stretch columns (0.386 -> 0.364 ms): more workgroups per CU (FP32 K: 3 of 52 KB LDS
+    // and 135 VGPRs instead of 1 of 90 KB), shorter barriers; 8 waves elsewhere, where narrower
+    // tiles cost more in shared edge columns than they gain (FP32 A at (256,256) 2.08 -> 3.76 ms).
+    const int wg = ((is64 && rs <= 2) || (!is64 && rs == 1 && doA && doBT && doB)) ? 4 : 8;
+    a.TI = std::min(wg / rs, L.m);
     a.TJ = std::min(16, L.m);
     a.KC = rs * 64 * cpl;                           // radial range of a workgroup
     a.ntile = L.m / a.TI;
@@ -879,19 +886,19 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0);
     if constexpr (std::is_same<T, double>::value) {
         if (rs == 1)
-            launch_band_ops<T, 1, 1>(ctx, a, sb, key);
+            launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key);
         else if (rs == 2)
-            launch_band_ops<T, 2, 1>(ctx, a, sb, key);
+            launch_band_ops<T, 2, 1, 4>(ctx, a, sb, key);
         else
-            launch_band_ops<T, 4, 1>(ctx, a, sb, key);
+            launch_band_ops<T, 4, 1, 8>(ctx, a, sb, key);
     } else {
         // FP32 splits only two-cell stretches (one-cell columns fit one stretch)
         if (cpl == 1)
-            launch_band_ops<T, 1, 1>(ctx, a, sb, key);
+            wg == 4 ? launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key) : launch_band_ops<T, 1, 1, 8>(ctx, a, sb, key);
         else if (rs == 1)
-            launch_band_ops<T, 1, 2>(ctx, a, sb, key);
+            wg == 4 ? launch_band_ops<T, 1, 2, 4>(ctx, a, sb, key) : launch_band_ops<T, 1, 2, 8>(ctx, a, sb, key);
         else
-            launch_band_ops<T, 2, 2>(ctx, a, sb, key);
+            launch_band_ops<T, 2, 2, 8>(ctx, a, sb, key);
     }
     const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
     if (doA || doBT) {

@@ -33,27 +33,6 @@ __global__ void interface_kernel(int ngroups, int n1, const int* __restrict__ gp
     }
 }
 
-// Dirichlet rows (layers 0 and n): y = u, or y = 0 when u is NULL.
-template <typename T>
-__global__ void dirichlet_copy_kernel(long long ncol, int n, const T* __restrict__ u0,
-                                      const T* __restrict__ u1, const T* __restrict__ u2, T* y0,
-                                      T* y1, T* y2, SlotBatch sb) {
-    const long long so = slot_off(sb);
-    u0 = at_slot(u0, so);
-    u1 = at_slot(u1, so);
-    u2 = at_slot(u2, so);
-    y0 = at_slot(y0, so);
-    y1 = at_slot(y1, so);
-    y2 = at_slot(y2, so);
-    long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= 2 * ncol) return;
-    const long long col = tid >> 1;
-    const long long idx = col * (n + 1) + ((tid & 1) ? n : 0);
-    y0[idx] = u0 ? u0[idx] : T(0);
-    y1[idx] = u1 ? u1[idx] : T(0);
-    y2[idx] = u2 ? u2[idx] : T(0);
-}
-
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -75,24 +54,6 @@ void launch_interface(const tng_ctx* ctx, const Level& L, tng_prec prec, int mod
         interface_kernel<float><<<grid, 256, 0, ctx->stream>>>(
             L.n_groups, L.n + 1, L.grp_ptr.p, L.grp_slot.p, mode, ncomp, (float*)g[0],
             (float*)g[1], (float*)g[2], (float*)g[3], sb);
-    TNG_HIP(hipGetLastError());
-}
-
-void launch_dirichlet_copy(const tng_ctx* ctx, const Level& L, tng_prec prec,
-                           const void* const u[3], void* const y[3]) {
-    const long long ncol = L.lat_slots();
-    const SlotBatch sb = launch_batch();
-    const dim3 grid(blocks_for(2 * ncol, 256), 1, (unsigned)sb.nb);
-    if (prec == TNG_F64)
-        dirichlet_copy_kernel<double><<<grid, 256, 0, ctx->stream>>>(
-            ncol, L.n, u ? (const double*)u[0] : nullptr, u ? (const double*)u[1] : nullptr,
-            u ? (const double*)u[2] : nullptr,
-            (double*)y[0], (double*)y[1], (double*)y[2], sb);
-    else
-        dirichlet_copy_kernel<float><<<grid, 256, 0, ctx->stream>>>(
-            ncol, L.n, u ? (const float*)u[0] : nullptr, u ? (const float*)u[1] : nullptr,
-            u ? (const float*)u[2] : nullptr, (float*)y[0],
-            (float*)y[1], (float*)y[2], sb);
     TNG_HIP(hipGetLastError());
 }
 

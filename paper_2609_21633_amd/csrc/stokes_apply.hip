@@ -722,19 +722,28 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     }
 }
 
-// Zero the node values that receive two partial sums: node columns on tile
-// seams and node layers on radial-chunk seams.
+// The passes before the band kernel in one launch: y_p = 0 (np values, when the
+// divergence block is applied), then zeros at the node values that receive two
+// partial sums (node columns on tile seams, node layers on radial-range seams).
 template <typename T>
-__global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int KC, int nchunk, SlotBatch sb) {
+__global__ void pre_apply_kernel(T* yp, long long np, T* y0, T* y1, T* y2, int m, int n, int TI, int KC,
+                                 int nchunk, long long nz, SlotBatch sb) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long so = slot_off(sb);
+    if (t < np) {
+        at_slot(yp, so)[t] = T(0);
+        return;
+    }
+    t -= np;
+    if (t >= nz) return;
     y0 = at_slot(y0, so);
     y1 = at_slot(y1, so);
     y2 = at_slot(y2, so);
     const int nseam_i = m / TI - 1;
-    const long long ncol = (long long)10 * nseam_i * (m + 1);       // seam columns x rows
     const long long n1 = n + 1;
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ncol = (long long)10 * nseam_i * (m + 1);
     const long long ldi = (long long)(m + 1) * n1;
+    long long idx;
     if (t < ncol * n1) {
         const int k = (int)(t % n1);
         long long r = t / n1;
@@ -742,21 +751,70 @@ __global__ void zero_seams_kernel(T* y0, T* y1, T* y2, int m, int n, int TI, int
         r /= (m + 1);
         const int s = (int)(r % nseam_i);
         const int d = (int)(r / nseam_i);
-        const long long idx = ((long long)d * (m + 1) + (long long)(s + 1) * TI) * ldi + (long long)jrow * n1 + k;
-        y0[idx] = T(0);
-        y1[idx] = T(0);
-        y2[idx] = T(0);
+        idx = ((long long)d * (m + 1) + (long long)(s + 1) * TI) * ldi + (long long)jrow * n1 + k;
+    } else {
+        t -= ncol * n1;
+        const long long nlat = (long long)10 * (m + 1) * (m + 1);
+        idx = (t % nlat) * n1 + (long long)(t / nlat + 1) * KC;
+    }
+    y0[idx] = T(0);
+    y1[idx] = T(0);
+    y2[idx] = T(0);
+}
+
+// The passes after the band kernel in one launch (disjoint writes, any order):
+//  1. the diamond-interface sum of the velocity copies (groups x layers; with
+//     Dirichlet rows, layers 0 and n are left to part 2),
+//  2. the Dirichlet rows y = u (viscous block present) or 0, at layers 0 and n of
+//     every lateral slot,
+//  3. the interface sum of the pressure copies.
+struct PostArgs {
+    int ngu, n1u;                       // velocity groups, layers
+    const int* gpu;
+    const int* gsu;
+    long long nlat_u;                   // lateral slots (Dirichlet part), 0: none
+    int ngp, n1p;                       // pressure groups, layers (0 groups: none)
+    const int* gpp;
+    const int* gsp;
+    int dirichlet;
+};
+template <typename T>
+__global__ void post_apply_kernel(PostArgs q, T* y0, T* y1, T* y2, const T* __restrict__ u0,
+                                  const T* __restrict__ u1, const T* __restrict__ u2, T* yp, SlotBatch sb) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long so = slot_off(sb);
+    const long long r1 = (long long)q.ngu * q.n1u, r2 = 2 * q.nlat_u, r3 = (long long)q.ngp * q.n1p;
+    if (t < r1) {
+        const int g = (int)(t / q.n1u), k = (int)(t % q.n1u);
+        if (q.dirichlet && (k == 0 || k == q.n1u - 1)) return;
+        const int s0 = q.gpu[g], s1 = q.gpu[g + 1];
+        T* ys[3] = {at_slot(y0, so), at_slot(y1, so), at_slot(y2, so)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T* f = ys[c];
+            T acc = f[(long long)q.gsu[s0] * q.n1u + k];
+            for (int s = s0 + 1; s < s1; ++s) acc += f[(long long)q.gsu[s] * q.n1u + k];
+            for (int s = s0; s < s1; ++s) f[(long long)q.gsu[s] * q.n1u + k] = acc;
+        }
         return;
     }
-    t -= ncol * n1;
-    const long long nlat = (long long)10 * (m + 1) * (m + 1);
-    if (t < nlat * (nchunk - 1)) {
-        const long long slot = t % nlat;
-        const int c = (int)(t / nlat) + 1;
-        const long long idx = slot * n1 + (long long)c * KC;
-        y0[idx] = T(0);
-        y1[idx] = T(0);
-        y2[idx] = T(0);
+    t -= r1;
+    if (t < r2) {
+        const long long idx = (t >> 1) * q.n1u + ((t & 1) ? q.n1u - 1 : 0);
+        const T* us[3] = {at_slot(u0, so), at_slot(u1, so), at_slot(u2, so)};
+        T* ys[3] = {at_slot(y0, so), at_slot(y1, so), at_slot(y2, so)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ys[c][idx] = us[c] ? us[c][idx] : T(0);
+        return;
+    }
+    t -= r2;
+    if (t < r3) {
+        const int g = (int)(t / q.n1p), k = (int)(t % q.n1p);
+        const int s0 = q.gpp[g], s1 = q.gpp[g + 1];
+        T* f = at_slot(yp, so);
+        T acc = f[(long long)q.gsp[s0] * q.n1p + k];
+        for (int s = s0 + 1; s < s1; ++s) acc += f[(long long)q.gsp[s] * q.n1p + k];
+        for (int s = s0; s < s1; ++s) f[(long long)q.gsp[s] * q.n1p + k] = acc;
     }
 }
 
@@ -803,14 +861,6 @@ void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatc
         case 15: launch_band_t<T, RS, CPL, WG, true, true, true, true>(ctx, args, sb); break;
         default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
     }
-}
-
-template <typename T>
-__global__ void fill0_kernel(T* __restrict__ a, long long n, SlotBatch sb) {
-    a = at_slot(a, slot_off(sb));
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) a[i] = T(0);
 }
 
 template <typename T>
@@ -868,18 +918,16 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.hg = T(hg_alpha * (5.0 / 81.0));
     const SlotBatch sb = launch_batch();
     const unsigned nbz = (unsigned)sb.nb;
-    if (doB) {
-        const long long np = Lp->node_slots();
-        fill0_kernel<T><<<dim3((unsigned)std::min<long long>(nblocks(np, 256), 4096), 1, nbz), 256, 0,
-                          ctx->stream>>>(a.yp, np, sb);
-        TNG_HIP(hipGetLastError());
-    }
-    if ((doA || doBT) && (a.ntile > 1 || a.nchunk > 1)) {
-        const long long nz = 10LL * (a.ntile - 1) * (L.m + 1) * (L.n + 1) +
-                             10LL * (L.m + 1) * (L.m + 1) * (a.nchunk - 1);
-        if (nz > 0) {
-            zero_seams_kernel<T><<<dim3(nblocks(nz, 256), 1, nbz), 256, 0, ctx->stream>>>(
-                a.y0, a.y1, a.y2, L.m, L.n, a.TI, a.KC, a.nchunk, sb);
+    {
+        // y_p = 0 and the seam zeroing, one launch
+        const long long np = doB ? Lp->node_slots() : 0;
+        const long long nz = ((doA || doBT) && (a.ntile > 1 || a.nchunk > 1))
+                                 ? 10LL * (a.ntile - 1) * (L.m + 1) * (L.n + 1) +
+                                       10LL * (L.m + 1) * (L.m + 1) * (a.nchunk - 1)
+                                 : 0;
+        if (np + nz > 0) {
+            pre_apply_kernel<T><<<dim3(nblocks(np + nz, 256), 1, nbz), 256, 0, ctx->stream>>>(
+                a.yp, np, a.y0, a.y1, a.y2, L.m, L.n, a.TI, a.KC, a.nchunk, nz, sb);
             TNG_HIP(hipGetLastError());
         }
     }
@@ -900,16 +948,31 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         else
             launch_band_ops<T, 2, 2, 8>(ctx, a, sb, key);
     }
-    const tng_prec prec = is64 ? TNG_F64 : TNG_F32;
+    // interface sums and Dirichlet rows (identity rows belong to the viscous block;
+    // without it the rows are zero), one launch
+    PostArgs q{};
     if (doA || doBT) {
-        void* f[3] = {yu[0], yu[1], yu[2]};
-        launch_interface(ctx, L, prec, 0, 3, f);
-        // identity rows belong to the viscous block; without it the rows are zero
-        if (a.dirichlet) launch_dirichlet_copy(ctx, L, prec, doA ? u : nullptr, yu);
+        q.ngu = L.n_groups;
+        q.gpu = L.grp_ptr.p;
+        q.gsu = L.grp_slot.p;
+        q.nlat_u = a.dirichlet ? L.lat_slots() : 0;
+        q.dirichlet = a.dirichlet;
     }
+    q.n1u = L.n + 1;
     if (doB) {
-        void* f[1] = {yp};
-        launch_interface(ctx, *Lp, prec, 0, 1, f);
+        q.ngp = Lp->n_groups;
+        q.n1p = Lp->n + 1;
+        q.gpp = Lp->grp_ptr.p;
+        q.gsp = Lp->grp_slot.p;
+    }
+    const long long npost = (long long)q.ngu * q.n1u + 2 * q.nlat_u + (long long)q.ngp * q.n1p;
+    if (npost > 0) {
+        const T* ud[3] = {nullptr, nullptr, nullptr};
+        if (doA && u)
+            for (int c = 0; c < 3; ++c) ud[c] = static_cast<const T*>(u[c]);
+        post_apply_kernel<T><<<dim3(nblocks(npost, 256), 1, nbz), 256, 0, ctx->stream>>>(
+            q, a.y0, a.y1, a.y2, ud[0], ud[1], ud[2], a.yp, sb);
+        TNG_HIP(hipGetLastError());
     }
 }
 

@@ -258,8 +258,6 @@ void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tn
                          void* const yu[3], void* yp);
 void launch_interface(const tng_ctx* ctx, const Level& L, tng_prec prec, int mode, int ncomp,
                       void* const f[]);
-void launch_dirichlet_copy(const tng_ctx* ctx, const Level& L, tng_prec prec,
-                           const void* const u[3], void* const y[3]);
 void launch_eta_from_T(const tng_ctx* ctx, const Level& L, tng_prec prec, const void* Tn,
                        void* eta, double E, double F);
 void launch_eta_coarsen(const tng_ctx* ctx, const Level& Lc, tng_prec prec, const void* ef,

@@ -311,15 +311,18 @@ int tng_energy_step(tng_solver* solver, const tng_step_opts* opts, const double*
 
 /* ---- serving ------------------------------------------------------------ */
 /* Request server for streams of Stokes solves.  levels: nlevels pairs
- * (mt, nr), each kept resident with its multigrid hierarchy.  Requests are
- * admitted FIFO per level into solver slots; a slot is a solver with its own
- * HIP stream and host worker, reused for later requests of its level, and
- * slots run concurrently on the device.  The device memory of one slot of
- * each level is measured here, by building a slot and releasing it.  A new
- * slot is created only while that per-slot memory keeps the total within
- * hbm_budget_bytes (an idle slot of another level is released to make room
- * when needed); at most max_slots slots per level.  opts: solver options of
- * every slot (normally mixed precision). */
+ * (mt, nr), each kept resident with its multigrid hierarchy, its own HIP
+ * stream and one host driver thread.  Requests are admitted FIFO per level
+ * into solver slots at iteration boundaries; the running slots of a level
+ * advance together, every kernel of an FGMRES iteration launched once for all
+ * of them (continuous batching: finished slots are refilled with queued
+ * requests at the next boundary), and levels overlap through their streams.
+ * A slot is one device allocation holding a whole solver; its size is
+ * measured here, by building one slot of each level.  A new slot is created
+ * only while that per-slot memory keeps the total within hbm_budget_bytes (an
+ * idle slot of another level is released to make room when needed); at most
+ * max_slots slots per level, launched in groups of at most 16.  opts: solver
+ * options of every slot (normally mixed precision). */
 int tng_server_create(tng_ctx* ctx, const int* levels, int nlevels, size_t hbm_budget_bytes, int max_slots,
                       const tng_solver_opts* opts, tng_server** out);
 /* Queues a solve with eta = 10^(log10_contrast)^(-T) = exp(-ln(contrast) T)

@@ -1,8 +1,8 @@
-// Diamond-interface reduction and Dirichlet rows (the one-GPU analog of the
-// paper's post-apply halo exchange, Sec. 2): every node on a diamond edge is
-// stored once per diamond holding it, each copy receives the partial sum of
-// its own diamond's cells, and this pass adds the copies and writes the sum
-// back to all of them, in a fixed order.
+// Diamond-interface reduction (the one-GPU analog of the paper's post-apply
+// halo exchange, Sec. 2): every node on a diamond edge is stored once per
+// diamond holding it, each copy receives the partial sum of its own diamond's
+// cells, and this pass adds the copies and writes the sum back to all of them,
+// in a fixed order.  (The operator apply does this in its own post-pass.)
 #include "batch_dev.hpp"
 #include "tng_internal.hpp"
 

@@ -18,7 +18,6 @@
 // Each request solves the Stokes problem with eta = exp(-ln(contrast) T) and
 // the buoyancy right-hand side Ra T rhat in the solver options' precision.
 #include <chrono>
-#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <deque>

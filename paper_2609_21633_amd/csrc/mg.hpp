@@ -77,6 +77,11 @@ void vec_fill(const tng_ctx* ctx, long long n, T v, T* a);
 template <typename T>
 void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
                const T* const* vs_dev, int nq, double* out_dev, bool accumulate);
+// y <- y + sign * sum_q coef[q] v_q over a Stokes vector, then out = the owner-masked
+// dots of the new y with v_0..v_{nq-1} (norm false) or its squared norm (norm true)
+template <typename T>
+void vec_maxpy_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const double* coef_dev,
+                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm);
 template <typename T>
 void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a);
 template <typename T>

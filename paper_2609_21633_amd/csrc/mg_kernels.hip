@@ -667,6 +667,80 @@ __global__ void __launch_bounds__(DOT_BS) smdot_partial_kernel(unsigned ns, Magi
     block_partials<NQ>(acc, nq, part);
 }
 
+// Gram-Schmidt step fused with the dots that follow it, over a Stokes vector:
+//   y <- y - sum_q c_q v_q   (every slot, as maxpy_kernel),
+// then, over owned slots, the dots of the new y with the same v_q (NORM false:
+// the re-orthogonalisation coefficients) or with itself (NORM true: the
+// squared norm), from the stored (rounded) value of y; block partials as in
+// smdot_partial_kernel.  One pass instead of a multi-axpy and a multi-dot.
+template <typename T, int NQ, bool NORM>
+__global__ void __launch_bounds__(DOT_BS) maxpy_dot_kernel(unsigned ns, MagicDiv dn1u, unsigned nlat_u,
+                                                           const uint8_t* __restrict__ ou, unsigned np,
+                                                           MagicDiv dn1p, const uint8_t* __restrict__ op,
+                                                           const double* __restrict__ coef, double sign,
+                                                           const T* const* __restrict__ vs, int nq, T* y,
+                                                           double* __restrict__ part, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    coef = at_slot(coef, so);
+    vs = at_slot(vs, so);
+    y = at_slot(y, so);
+    part = at_slot(part, so);
+    nq = slot_count(sb, nq);
+    gptr<T> vp[NQ];
+    double cf[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        vp[q] = as_global(vs[q < nq ? q : 0]);
+        cf[q] = q < nq ? sign * coef[q] : 0.0;
+    }
+    constexpr int NA = NORM ? 1 : NQ;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    const unsigned nu = 3u * ns, n = nu + np;
+    const unsigned stride = gridDim.x * DOT_BS;
+    for (unsigned t0 = blockIdx.x * DOT_BS + threadIdx.x; t0 < n; t0 += 2 * stride) {
+        T yv[2], v[2][NQ];
+        bool own[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            const bool in = t < n;
+            const unsigned tt = in ? t : 0;
+            if (tt < nu) {
+                unsigned lat = mdiv(tt, dn1u);
+                lat = lat >= nlat_u ? lat - nlat_u : lat;
+                lat = lat >= nlat_u ? lat - nlat_u : lat;
+                own[e] = in && ou[lat];
+            } else {
+                own[e] = in && op[mdiv(tt - nu, dn1p)];
+            }
+            yv[e] = y[tt];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[e][q] = q < nq ? vp[q][tt] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned t = t0 + e * stride;
+            if (t >= n) break;
+            double a = (double)yv[e];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) a += cf[q] * (double)v[e][q];
+            const T yn = T(a);
+            y[t] = yn;
+            if (!own[e]) continue;
+            if (NORM) {
+                acc[0] += (double)yn * (double)yn;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NA; ++q) acc[q] += (double)v[e][q] * (double)yn;
+            }
+        }
+    }
+    block_partials<NA>(acc, NORM ? 1 : nq, part);
+}
+
 // Counter-based uniform numbers in [-1, 1) (splitmix64 of seed and index).
 template <typename T>
 __global__ void rand_kernel(unsigned n, unsigned long long seed, T* a) {
@@ -940,6 +1014,35 @@ void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level&
 }
 
 template <typename T>
+void vec_maxpy_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const double* coef_dev,
+                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm) {
+    TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-axpy");
+    const long long n = 3 * Lu.node_slots() + Lp.node_slots();
+    TNG_REQUIRE(n < (1LL << 32), "vector length out of range");
+    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
+    const SlotBatch sb = launch_batch();
+    check_counts(sb);
+    const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
+    if (norm) {
+        TNG_NQ_DISPATCH(count_class(sb, nq),
+                        (maxpy_dot_kernel<T, NQ, true><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
+                            (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                            (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y, ds.part.p, sb)));
+    } else {
+        TNG_NQ_DISPATCH(count_class(sb, nq),
+                        (maxpy_dot_kernel<T, NQ, false><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
+                            (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                            (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y, ds.part.p, sb)));
+    }
+    TNG_HIP(hipGetLastError());
+    // the norm has one value for every slot: the per-slot counts do not apply to it
+    SlotBatch sf = sb;
+    if (norm) sf.has_cnt = 0;
+    mdot_final_kernel<<<dim3(1, 1, sf.nb), 256, 0, ctx->stream>>>(nb, norm ? 1 : nq, ds.part.p, out_dev, 0, sf);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
 void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a) {
     require_unbatched("vec_rand");
     const unsigned nb = (unsigned)std::min<long long>(nblk(n, 256), 8192);
@@ -1069,6 +1172,8 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void vec_mul<T>(const tng_ctx*, long long, const T*, const T*, T*);                          \
     template void vec_smdot<T>(const tng_ctx*, DotScratch&, const Level&, const Level&, const T*,         \
                                const T* const*, int, double*, bool);                                       \
+    template void vec_maxpy_smdot<T>(const tng_ctx*, DotScratch&, const Level&, const Level&, const double*,  \
+                                     double, const T* const*, int, T*, double*, bool);                       \
     template void vec_rand<T>(const tng_ctx*, long long, unsigned long long, T*);                         \
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
     template void vec_tab_copy<T>(const tng_ctx*, long long, const T*, const T* const*, T*, T* const*, int, \

@@ -343,12 +343,12 @@ int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxi
         for (int j = 0; j < m; ++j) {
             precond_j<T>(s, j);
             apply_K<T>(s, eta0, K.Zi(j), K.w.p);
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 with h2 = V^T w in the
+            // same pass; w -= V h2 with |w|^2 in the same pass
             vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc, false);
-            vec_maxpy<T>(s->ctx, N, dsc, -1.0, K.vptr.p, j + 1, K.w.p);
-            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc + MAX_MDOT, false);
-            vec_maxpy<T>(s->ctx, N, dsc + MAX_MDOT, -1.0, K.vptr.p, j + 1, K.w.p);
-            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.wptr.p + 1, 1, dsc + 2 * MAX_MDOT, false);
+            vec_maxpy_smdot<T>(s->ctx, *s->ds, Lu, Lp, dsc, -1.0, K.vptr.p, j + 1, K.w.p, dsc + MAX_MDOT, false);
+            vec_maxpy_smdot<T>(s->ctx, *s->ds, Lu, Lp, dsc + MAX_MDOT, -1.0, K.vptr.p, j + 1, K.w.p,
+                               dsc + 2 * MAX_MDOT, true);
             vec_scale_rsqrt<T>(s->ctx, N, dsc + 2 * MAX_MDOT, K.w.p, K.Vi(j + 1));
             readback(s, dsc, 2 * MAX_MDOT + 1);
             double* h = &H[(size_t)j * (m + 1)];
@@ -924,13 +924,9 @@ void step_group(tng_ctx* ctx, SolverBatch::Staging& st, const tng_solver_opts& o
     {
         BatchScope bs(&bj1);                                                         // CGS2 against V_0..V_j
         vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc, false);
-        vec_maxpy<T>(ctx, N, dsc, -1.0, K.vptr.p, 1, K.w.p);
-        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc + MAX_MDOT, false);
-        vec_maxpy<T>(ctx, N, dsc + MAX_MDOT, -1.0, K.vptr.p, 1, K.w.p);
-    }
-    {
-        BatchScope bs(&b0);
-        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.wptr.p + 1, 1, dsc + 2 * MAX_MDOT, false);
+        vec_maxpy_smdot<T>(ctx, *r->ds, L0(r), L1(r), dsc, -1.0, K.vptr.p, 1, K.w.p, dsc + MAX_MDOT, false);
+        vec_maxpy_smdot<T>(ctx, *r->ds, L0(r), L1(r), dsc + MAX_MDOT, -1.0, K.vptr.p, 1, K.w.p,
+                           dsc + 2 * MAX_MDOT, true);
     }
     {
         BatchScope bs(&bj1);

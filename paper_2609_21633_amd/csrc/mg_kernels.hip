@@ -269,6 +269,93 @@ __global__ void __launch_bounds__(256) cheb_update_kernel(long long n, const dou
     }
 }
 
+// The same update with 16-byte vector accesses (every pointer 16-byte aligned):
+// vector i of L = 16 / sizeof(T) values per thread, block 0 also the n % L tail;
+// the arithmetic of every value is that of cheb_update_kernel.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) cheb_update_vec_kernel(long long n, const double* __restrict__ ab, int k,
+                                                              const T* __restrict__ b, const T* __restrict__ y,
+                                                              const T* __restrict__ invd, T* d, T* x, SlotBatch sb) {
+    using V = typename Vec16<T>::type;
+    constexpr int L = 16 / sizeof(T);
+    const long long so = slot_off(sb);
+    ab = at_slot(ab, so);
+    b = at_slot(b, so);
+    y = at_slot(y, so);
+    invd = at_slot(invd, so);
+    d = at_slot(d, so);
+    x = at_slot(x, so);
+    const T alpha = T(ab[2 * k]), beta = T(ab[2 * k + 1]);
+    const long long nv = n / L;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < nv) {
+        V bv = reinterpret_cast<const V*>(b)[i], yv = reinterpret_cast<const V*>(y)[i];
+        V iv = reinterpret_cast<const V*>(invd)[i], xv = reinterpret_cast<const V*>(x)[i];
+        V dv{};
+        if (alpha != T(0)) dv = reinterpret_cast<const V*>(d)[i];   // d may hold garbage on the first step
+        const T* pb = reinterpret_cast<const T*>(&bv);
+        const T* py = reinterpret_cast<const T*>(&yv);
+        const T* pi = reinterpret_cast<const T*>(&iv);
+        T* pd = reinterpret_cast<T*>(&dv);
+        T* px = reinterpret_cast<T*>(&xv);
+#pragma unroll
+        for (int c = 0; c < L; ++c) {
+            const T r = beta * pi[c] * (pb[c] - py[c]);
+            pd[c] = alpha == T(0) ? r : alpha * pd[c] + r;
+            px[c] += pd[c];
+        }
+        reinterpret_cast<V*>(d)[i] = dv;
+        reinterpret_cast<V*>(x)[i] = xv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * L) {
+        const long long t = nv * L + threadIdx.x;
+        const T r = beta * invd[t] * (b[t] - y[t]);
+        const T dn = alpha == T(0) ? r : alpha * d[t] + r;
+        d[t] = dn;
+        x[t] += dn;
+    }
+}
+
+// y <- a x + b y with 16-byte vector accesses (as axpby_kernel)
+template <typename T>
+__global__ void __launch_bounds__(256) axpby_vec_kernel(long long n, T a, const T* __restrict__ x, T b, T* y,
+                                                        SlotBatch sb) {
+    using V = typename Vec16<T>::type;
+    constexpr int L = 16 / sizeof(T);
+    const long long so = slot_off(sb);
+    x = at_slot(x, so);
+    y = at_slot(y, so);
+    const long long nv = n / L;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < nv) {
+        V xv = reinterpret_cast<const V*>(x)[i];
+        V yv{};
+        if (b != T(0)) yv = reinterpret_cast<const V*>(y)[i];
+        const T* px = reinterpret_cast<const T*>(&xv);
+        T* py = reinterpret_cast<T*>(&yv);
+#pragma unroll
+        for (int c = 0; c < L; ++c) py[c] = b == T(0) ? a * px[c] : a * px[c] + b * py[c];
+        reinterpret_cast<V*>(y)[i] = yv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * L) {
+        const long long t = nv * L + threadIdx.x;
+        y[t] = b == T(0) ? a * x[t] : a * x[t] + b * y[t];
+    }
+}
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <typename T>
 __global__ void invert_kernel(long long n, T* a) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -919,6 +1006,13 @@ template <typename T>
 void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int k, const T* b, const T* y,
                      const T* invd, T* d, T* x) {
     const SlotBatch sb = launch_batch();
+    if (aligned16(b) && aligned16(y) && aligned16(invd) && aligned16(d) && aligned16(x)) {
+        const long long nv = n / (16 / (long long)sizeof(T));
+        cheb_update_vec_kernel<T><<<dim3(std::max(1u, nblk(nv, 256)), 1, sb.nb), 256, 0, ctx->stream>>>(
+            n, ab_dev, k, b, y, invd, d, x, sb);
+        TNG_HIP(hipGetLastError());
+        return;
+    }
     cheb_update_kernel<T><<<dim3(nblk(n, 256 * EW_PER), 1, sb.nb), 256, 0, ctx->stream>>>(n, ab_dev, k, b, y, invd, d, x,
                                                                                   sb);
     TNG_HIP(hipGetLastError());
@@ -941,6 +1035,13 @@ void vec_cast(const tng_ctx* ctx, long long n, const TI* a, TO* b) {
 template <typename T>
 void vec_axpby(const tng_ctx* ctx, long long n, double a, const T* x, double b, T* y) {
     const SlotBatch sb = launch_batch();
+    if (aligned16(x) && aligned16(y)) {
+        const long long nv = n / (16 / (long long)sizeof(T));
+        axpby_vec_kernel<T><<<dim3(std::max(1u, nblk(nv, 256)), 1, sb.nb), 256, 0, ctx->stream>>>(n, T(a), x, T(b),
+                                                                                                 y, sb);
+        TNG_HIP(hipGetLastError());
+        return;
+    }
     axpby_kernel<T><<<dim3(nblk(n, 256 * EW_PER), 1, sb.nb), 256, 0, ctx->stream>>>(n, T(a), x, T(b), y, sb);
     TNG_HIP(hipGetLastError());
 }

@@ -44,8 +44,9 @@ struct KrylovWS {
     DevBuf<T> zb;                       // preconditioner output of a batch slot (index-free)
     DevBuf<const T*> vptr, zptr, wptr;
     DevBuf<double> coef;                // device dots / coefficients
-    T* Vi(int i) { return V.p + (long long)i * N; }
-    T* Zi(int i) { return Z.p + (long long)i * N; }
+    long long ld = 0;                   // basis stride: N rounded up to 256 bytes
+    T* Vi(int i) { return V.p + (long long)i * ld; }
+    T* Zi(int i) { return Z.p + (long long)i * ld; }
 };
 
 }  // namespace tng
@@ -493,8 +494,10 @@ void alloc_krylov(tng_solver* s, const T* rhs) {
     const int m = s->opts.restart;
     K.restart = m;
     K.N = s->N;
-    K.V.alloc((size_t)(m + 1) * s->N);
-    K.Z.alloc((size_t)m * s->N);
+    // every basis vector starts on a 256-byte boundary (16-byte vector loads)
+    K.ld = (s->N + (long long)(256 / sizeof(T)) - 1) / (long long)(256 / sizeof(T)) * (long long)(256 / sizeof(T));
+    K.V.alloc((size_t)(m + 1) * K.ld);
+    K.Z.alloc((size_t)m * K.ld);
     K.w.alloc(s->N);
     K.t.alloc(3 * s->ns0);
     if (s->batch_slot) K.zb.alloc(s->N);

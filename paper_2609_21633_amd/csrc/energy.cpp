@@ -11,9 +11,11 @@
 namespace tng {
 
 template <typename T>
-void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
+void energy_wedge_flow(const tng_ctx* ctx, const Level& L, const T* const u[3], double* wf);
 template <typename T>
-void energy_diag(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, T* diag);
+void energy_apply_wf(const tng_ctx* ctx, const Level& L, const double* wf, double dt, const T* Tin, T* y);
+template <typename T>
+void energy_diag(const tng_ctx* ctx, const Level& L, const double* wf, double dt, T* diag);
 template <typename T>
 void energy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, const T* H, double dt, double T_in,
                 double T_out, T* b);
@@ -27,6 +29,7 @@ struct EnergyWS {
     int restart = 0;
     long long ns = 0;
     DevBuf<double> V, Z, w, invd, b, f;
+    DevBuf<double> wf;                  // per-wedge flow data (mean velocity, tau) of the current velocity
     DevBuf<const double*> vptr, zptr, wptr;
     DevBuf<double> coef, part;
     DotScratch ds;
@@ -50,6 +53,7 @@ void ews_init(EnergyWS& W, const Level& L, int restart) {
     W.invd.alloc(W.ns);
     W.b.alloc(W.ns);
     W.f.alloc(3 * W.ns);
+    W.wf.alloc((size_t)L.cells() * 2 * 4);
     W.coef.alloc(4 * MAX_MDOT);
     std::vector<const double*> vp(restart + 1), zp(restart), wp(2);
     for (int i = 0; i <= restart; ++i) vp[i] = W.Vi(i);
@@ -72,7 +76,7 @@ double rb(const tng_ctx* ctx, EnergyWS& W, const double* dev, int n) {
 }
 
 // Solves E x = b (b in W.b); x holds the initial guess on entry.
-int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double dt, double* x,
+int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, double dt, double* x,
                  double rtol, int maxit, int* its_out, double* rel_out) {
     const long long ns = W.ns;
     const int m = W.restart;
@@ -95,7 +99,7 @@ int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
     }
     for (;;) {
         // r = b - E x
-        energy_apply<double>(ctx, L, u, dt, x, W.w.p);
+        energy_apply_wf<double>(ctx, L, W.wf.p, dt, x, W.w.p);
         vec_axpby<double>(ctx, ns, 1.0, W.b.p, -1.0, W.w.p);
         dot1(W.w.p, W.wptr.p + 1, dsc);
         const double beta = std::sqrt(std::max(0.0, rb(ctx, W, dsc, 1)));
@@ -108,7 +112,7 @@ int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             vec_mul<double>(ctx, ns, W.invd.p, W.Vi(j), W.Zi(j));
-            energy_apply<double>(ctx, L, u, dt, W.Zi(j), W.w.p);
+            energy_apply_wf<double>(ctx, L, W.wf.p, dt, W.Zi(j), W.w.p);
             vec_mdot<double>(ctx, W.ds, ns, L.n + 1, nlat, L.owner.p, W.w.p, W.vptr.p, j + 1, dsc, false);
             vec_maxpy<double>(ctx, ns, dsc, -1.0, W.vptr.p, j + 1, W.w.p);
             vec_mdot<double>(ctx, W.ds, ns, L.n + 1, nlat, L.owner.p, W.w.p, W.vptr.p, j + 1, dsc + MAX_MDOT, false);
@@ -165,12 +169,13 @@ int energy_solve(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
                  double* rel) {
     ews_init(W, L, restart);
     energy_rhs<double>(ctx, L, T, H, dt, T_in, T_out, W.b.p);
-    energy_diag<double>(ctx, L, u, dt, W.invd.p);
+    energy_wedge_flow<double>(ctx, L, u, W.wf.p);   // the velocity is fixed during the solve
+    energy_diag<double>(ctx, L, W.wf.p, dt, W.invd.p);
     vec_invert<double>(ctx, W.ns, W.invd.p);
     // initial guess: T^n with the boundary values imposed
     void* f[1] = {T};
     (void)f;
-    return energy_gmres(ctx, L, W, u, dt, T, rtol, maxit, its, rel);
+    return energy_gmres(ctx, L, W, dt, T, rtol, maxit, its, rel);
 }
 
 double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double courant) {

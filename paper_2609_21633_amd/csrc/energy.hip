@@ -97,11 +97,46 @@ struct WedgeField {
     }
 };
 
+// Flow data of every wedge for the SUPG operator, which depends on the velocity
+// only: ubar (3 values) and tau at q_c, FP64, [10][m][m][n][2][4].  Computed once
+// per velocity field instead of once per node of the wedge in every apply.
+constexpr int WF = 4;
+template <typename T>
+__global__ void wedge_flow_kernel(EnergyGeo G, const T* __restrict__ u0, const T* __restrict__ u1,
+                                  const T* __restrict__ u2, double* __restrict__ wf, long long ncells) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int m = G.m, n = G.n;
+    const int ck = (int)(c % n);
+    long long r = c / n;
+    const int cj = (int)(r % m);
+    r /= m;
+    const int ci = (int)(r % m);
+    const int d = (int)(r / m);
+    const double rm = G.r_in + (ck + 0.5) * G.dr;
+    for (int wd = 0; wd < 2; ++wd) {
+        const double* g = G.geo + (((long long)d * m + ci) * m + cj) * GEO_PER_COL + wd * GEO_PER_TRI;
+        const double V = rm * rm * g[9];
+        double uu[3][6];
+        WedgeField<T>::gather(u0, d, ci, cj, ck, wd, m, n, uu[0]);
+        WedgeField<T>::gather(u1, d, ci, cj, ck, wd, m, n, uu[1]);
+        WedgeField<T>::gather(u2, d, ci, cj, ck, wd, m, n, uu[2]);
+        double ub[3];
+        for (int x = 0; x < 3; ++x)
+            ub[x] = (uu[x][0] + uu[x][1] + uu[x][2] + uu[x][3] + uu[x][4] + uu[x][5]) * (1.0 / 6.0);
+        const double un = sqrt(ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+        double* w = wf + (c * 2 + wd) * WF;
+        w[0] = ub[0];
+        w[1] = ub[1];
+        w[2] = ub[2];
+        w[3] = supg_tau(un, cbrt(V));
+    }
+}
+
 // y = E T (mode 0), or the diagonal of E (mode 1).  Dirichlet rows handled later.
 template <typename T, int MODE>
-__global__ void energy_node_kernel(EnergyGeo G, const T* __restrict__ Tin, const T* __restrict__ u0,
-                                   const T* __restrict__ u1, const T* __restrict__ u2, double inv_dt,
-                                   T* __restrict__ y, long long nslots) {
+__global__ void energy_node_kernel(EnergyGeo G, const T* __restrict__ Tin, const double* __restrict__ wf,
+                                   double inv_dt, T* __restrict__ y, long long nslots) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const NodeIdx4 q = decode4(t, G.m, G.n);
@@ -112,15 +147,9 @@ __global__ void energy_node_kernel(EnergyGeo G, const T* __restrict__ Tin, const
         const double rm = G.r_in + (ck + 0.5) * G.dr;
         const double s1 = 0.5 / rm;
         const double V = rm * rm * g[9];
-        double uu[3][6];
-        WedgeField<T>::gather(u0, q.d, ci, cj, ck, wd, m, n, uu[0]);
-        WedgeField<T>::gather(u1, q.d, ci, cj, ck, wd, m, n, uu[1]);
-        WedgeField<T>::gather(u2, q.d, ci, cj, ck, wd, m, n, uu[2]);
-        double ub[3];
-        for (int c = 0; c < 3; ++c)
-            ub[c] = (uu[c][0] + uu[c][1] + uu[c][2] + uu[c][3] + uu[c][4] + uu[c][5]) * (1.0 / 6.0);
-        const double un = sqrt(ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
-        const double tau = supg_tau(un, cbrt(V));
+        const double* w = wf + (((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd) * WF;
+        const double ub[3] = {w[0], w[1], w[2]};
+        const double tau = w[3];
         double gi[3];
         grad_of(g, s1, lat, top, gi);
         const double ugi = ub[0] * gi[0] + ub[1] * gi[1] + ub[2] * gi[2];
@@ -257,7 +286,16 @@ EnergyGeo make_geo(const Level& L) { return EnergyGeo{L.geo64.p, L.m, L.n, L.r_i
 }  // namespace
 
 template <typename T>
-void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y) {
+void energy_wedge_flow(const tng_ctx* ctx, const Level& L, const T* const u[3], double* wf) {
+    require_unbatched("energy_wedge_flow");
+    const long long nc = L.cells();
+    wedge_flow_kernel<T><<<nblk(nc, 256), 256, 0, ctx->stream>>>(make_geo(L), u[0], u[1], u[2], wf, nc);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void energy_apply_wf(const tng_ctx* ctx, const Level& L, const double* wf, double dt, const T* Tin, T* y) {
+    require_unbatched("energy_apply");
     const long long ns = L.node_slots();
     {
         char detail[48] = {0};
@@ -265,8 +303,7 @@ void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], doubl
             std::snprintf(detail, sizeof(detail), "%s/SUPG/%dx%d", std::is_same<T, double>::value ? "f64" : "f32",
                           L.m, L.n);
         ScopedKernelTimer timer(ctx, "energy_apply", detail);
-        energy_node_kernel<T, 0><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), Tin, u[0], u[1], u[2],
-                                                                         1.0 / dt, y, ns);
+        energy_node_kernel<T, 0><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), Tin, wf, 1.0 / dt, y, ns);
         TNG_HIP(hipGetLastError());
     }
     void* f[1] = {y};
@@ -276,10 +313,18 @@ void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], doubl
 }
 
 template <typename T>
-void energy_diag(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, T* diag) {
+void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y) {
+    DevBuf<double> wf((size_t)L.cells() * 2 * WF);
+    energy_wedge_flow<T>(ctx, L, u, wf.p);
+    energy_apply_wf<T>(ctx, L, wf.p, dt, Tin, y);
+    TNG_HIP(hipStreamSynchronize(ctx->stream));   // wf is freed on return
+}
+
+template <typename T>
+void energy_diag(const tng_ctx* ctx, const Level& L, const double* wf, double dt, T* diag) {
+    require_unbatched("energy_diag");
     const long long ns = L.node_slots();
-    energy_node_kernel<T, 1><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), nullptr, u[0], u[1], u[2],
-                                                                     1.0 / dt, diag, ns);
+    energy_node_kernel<T, 1><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), nullptr, wf, 1.0 / dt, diag, ns);
     TNG_HIP(hipGetLastError());
     void* f[1] = {diag};
     launch_interface(ctx, L, prec_of<T>(), 0, 1, f);
@@ -332,7 +377,9 @@ double cfl_rate(const tng_ctx* ctx, const Level& L, const T* const u[3], DevBuf<
 
 #define TNG_EINST(T)                                                                                   \
     template void energy_apply<T>(const tng_ctx*, const Level&, const T* const[3], double, const T*, T*); \
-    template void energy_diag<T>(const tng_ctx*, const Level&, const T* const[3], double, T*);             \
+    template void energy_wedge_flow<T>(const tng_ctx*, const Level&, const T* const[3], double*);          \
+    template void energy_apply_wf<T>(const tng_ctx*, const Level&, const double*, double, const T*, T*);   \
+    template void energy_diag<T>(const tng_ctx*, const Level&, const double*, double, T*);                 \
     template void energy_rhs<T>(const tng_ctx*, const Level&, const T*, const T*, double, double, double, T*); \
     template void buoyancy_rhs<T>(const tng_ctx*, const Level&, const T*, double, T* const[3]);          \
     template double cfl_rate<T>(const tng_ctx*, const Level&, const T* const[3], DevBuf<double>&);

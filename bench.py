@@ -441,7 +441,7 @@ def main():
                      "unit": "GB/s", "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None if t32 is None else round(t32 / (head["kernel_ms"] * 1e6), 1),
                      "traffic_bytes_per_launch": t32,
-                     "kernel": "stokes_band_kernel<float,2,A,BT,B>",
+                     "kernel": "stokes_band_kernel<float,RS=1,CPL=2,A,BT,B,WG=4> (FP32 full operator)",
                      "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": round(head["kernel_ms"], 4)},
         "f64_apply": {"gdofs": round(res["f64"]["gdofs"], 3), "ms": round(res["f64"]["ms"], 4),
                       "kernel_gbs": round(res["f64"]["kernel_gbs"], 1),

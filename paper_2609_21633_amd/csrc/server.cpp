@@ -56,6 +56,7 @@ struct ServerLevel {
     long long bytes_per_slot = -1;
     int cap_slots = 0;                         // max_slots, lowered if the device refuses a slot
     int release_wanted = 0;                    // idle slots another level asked this one to free
+    int failed = TNG_OK;                       // the level's stream failed: no further requests
     std::thread driver;
 };
 
@@ -96,7 +97,7 @@ bool admissible(const tng_server* srv, const ServerLevel& lv) {
 void request_room(tng_server* srv, ServerLevel& lv) {
     if (live_slots(lv) != 0) return;
     for (auto& other : srv->levels) {
-        if (&other == &lv || !other.queue.empty() || other.release_wanted > 0) continue;
+        if (&other == &lv || !other.queue.empty() || other.release_wanted > 0 || other.failed != TNG_OK) continue;
         if (idle_index(other) >= 0) {
             other.release_wanted += 1;
             srv->cv_work.notify_all();
@@ -209,14 +210,22 @@ void driver(tng_server* srv, ServerLevel* lv) {
         }
         lk.lock();
         if (err != TNG_OK) {
-            // the stream itself failed: end every running request of the level
+            // the stream itself failed: end every running and queued request of the level,
+            // and refuse later ones
+            tng_solve_info info{};
+            info.status = err;
             for (size_t i = 0; i < lv->job.size(); ++i)
                 if (lv->job[i]) {
-                    tng_solve_info info{};
-                    info.status = err;
                     complete(srv, lv->job[i], err, info);
                     lv->job[i] = nullptr;
                 }
+            while (!lv->queue.empty()) {
+                ServerReq* r = lv->queue.front();
+                lv->queue.pop_front();
+                r->t_start = Clock::now();
+                complete(srv, r, err, info);
+            }
+            lv->failed = err;
             srv->cv_done.notify_all();
             srv->cv_work.notify_all();
             return;
@@ -292,6 +301,7 @@ int tng_server_submit(tng_server* srv, int level_idx, const double* T, double lo
     TNG_REQUIRE(level_idx >= 0 && level_idx < (int)srv->levels.size(), "level_idx out of range");
     std::lock_guard<std::mutex> lk(srv->mu);
     ServerLevel& lv = srv->levels[level_idx];
+    if (lv.failed != TNG_OK) throw Error(lv.failed, "this level's device stream failed; it takes no requests");
     if (lv.bytes_per_slot > (long long)srv->budget)
         throw Error(TNG_E_BUDGET, "request does not fit the HBM budget (a slot of this level needs " +
                                       std::to_string(lv.bytes_per_slot) + " bytes, budget " +

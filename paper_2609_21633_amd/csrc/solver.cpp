@@ -1064,13 +1064,13 @@ bool SolverBatch::start(int i, const double* T, double E, double Ra, double* con
     sl->busy = true;
     std::vector<BSlot*> done;
     try {
+        vec_fill<double>(ctx_, s->N, 0.0, s->xo.p);     // the result of a request that fails in set-up
         launch_eta_from_T(ctx_, L, TNG_F64, T, sl->eta.p, E, 0.0);
         double* f[3] = {sl->f.p, sl->f.p + ns, sl->f.p + 2 * ns};
         energy_buoyancy(ctx_, L, T, Ra, f);
         setup_viscosity(s, sl->eta.p);
         TNG_HIP(hipMemcpyAsync(s->bo.p, sl->f.p, 3 * ns * sizeof(double), hipMemcpyDeviceToDevice, stm));
         vec_fill<double>(ctx_, np, 0.0, s->bo.p + 3 * ns);
-        vec_fill<double>(ctx_, s->N, 0.0, s->xo.p);
         vec_smdot<double>(ctx_, *s->ds, L0(s), L1(s), s->bo.p, s->dptr.p, 1, s->scal.p + 1, false);
         readback(s, s->scal.p + 1, 1);
         const double bsq = s->host[0];

@@ -906,11 +906,14 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     // tiles cost more in shared edge columns than they gain (FP32 A at (256,256) 2.08 -> 3.76 ms).
     const int wg = ((is64 && rs <= 2) || (!is64 && rs == 1 && doA && doBT && doB)) ? 4 : 8;
     a.TI = std::min(wg / rs, L.m);
-    a.TJ = std::min(16, L.m);
     a.KC = rs * 64 * cpl;                           // radial range of a workgroup
     a.ntile = L.m / a.TI;
-    a.nband = L.m / a.TJ;
     a.nchunk = (L.n + a.KC - 1) / a.KC;
+    // bands of 16 rows; on small levels shorter bands (down to 4 rows) until there are
+    // about two workgroups per CU: there the serial row loop, not the bytes, sets the time
+    a.TJ = std::min(16, L.m);
+    while (a.TJ > 4 && 10LL * a.ntile * a.nchunk * (L.m / a.TJ) < 512) a.TJ /= 2;
+    a.nband = L.m / a.TJ;
     a.r_in = T(L.r_in);
     a.dr = T(L.dr());
     a.dirichlet = (flags & TNG_OP_DIRICHLET) ? 1 : 0;

@@ -372,8 +372,9 @@ def main():
                          "kernel traces; one JSON report line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the shell would shard by "
-              "lateral diamond blocks with one neighbour exchange per apply, see DESIGN.md).",
+        print("bench.py measures one GPU: there is no multi-GPU path (the shell would shard by "
+              "lateral diamond blocks, with one neighbour exchange of diamond-edge partial sums per "
+              "apply).",
               file=sys.stderr)
         sys.exit(2)
     import torch

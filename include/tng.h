@@ -116,7 +116,11 @@ int tng_ctx_kernel_stats_at(tng_ctx* ctx, int index, char* name, int name_len, d
  * built (counts, coordinates, duplicate groups) and the mesh cannot be used by
  * device calls, which reject it with TNG_E_INVAL.  Levels:
  * (level l = (mt/2^l, nr/2^l); both must stay integers >= 1).  The pressure of
- * level l lives on level l + 1, so an operator on level l needs l + 1 < levels. */
+ * level l lives on level l + 1, so an operator on level l needs l + 1 < levels.
+ * Fields are indexed with 32-bit offsets: 10(mt+1)^2(nr+1) < 2^31 and
+ * 20 mt^2 nr < 2^32, else TNG_E_INVAL (the (512,512) shell is the largest
+ * power-of-two shell that fits; a solver further needs its Stokes vector,
+ * 3 node fields plus the pressure, below 2^32 values). */
 int tng_mesh_create(tng_ctx* ctx, int mt, int nr, double r_in, double r_out,
                     int levels, tng_mesh** out);
 /* out[0..7] = m, n, lateral slots 10(m+1)^2, unique lateral nodes 10 m^2 + 2,

@@ -195,6 +195,9 @@ int tng_mesh_create(tng_ctx* ctx, int mt, int nr, double r_in, double r_out, int
     TNG_REQUIRE((nr >> (levels - 1)) >= 1 && ((nr >> (levels - 1)) << (levels - 1)) == nr,
                 "nr / 2^(levels-1) must be an integer >= 1");
     TNG_REQUIRE(r_in > 0.0 && r_out > r_in, "need 0 < r_in < r_out");
+    // the kernels index a field of the finest level with 32-bit offsets
+    TNG_REQUIRE(10.0 * (mt + 1.0) * (mt + 1.0) * (nr + 1.0) < 2147483648.0 && 20.0 * mt * (double)mt * nr < 4294967296.0,
+                "mesh too large: a node field of the finest level must have fewer than 2^31 values");
     if (ctx) TNG_HIP(hipSetDevice(ctx->device));
     auto* m = new tng_mesh();
     m->ctx = ctx;

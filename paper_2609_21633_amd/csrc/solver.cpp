@@ -1207,6 +1207,8 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     s->ns0 = mesh->lv[0].node_slots();
     s->np = mesh->lv[1].node_slots();
     s->N = 3 * s->ns0 + s->np;
+    // the vector kernels take Stokes-vector lengths (with the basis padding) as 32-bit counts
+    TNG_REQUIRE(s->N + 64 < (1LL << 32), "mesh too large for the solver: a Stokes vector must have fewer than 2^32 values");
     s->ds = std::make_unique<tng::DotScratch>();
     tng::build_coarse_maps(s.get());
     const bool mixed = opts->mixed != 0;

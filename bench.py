@@ -136,12 +136,12 @@ def bench_solve(tng, ctx, mesh, T64, E, F, mixed, reps=2):
 
 def variant_bytes(name):
     """Algorithmic bytes of one launch from a detailed timer name
-    "stokes_apply/<f32|f64>/<variant>/<m>x<n>" or "energy_apply/<prec>/SUPG/<m>x<n>":
-    every input read and every output written once."""
+    "stokes_apply/<f32|f64>/<variant>/<m>x<n>/b<bands>" or "energy_apply/<prec>/SUPG/<m>x<n>":
+    every input read and every output written once (None for batched launches)."""
     parts = name.split("/")
-    if len(parts) != 4:
+    if len(parts) < 4 or "batch" in parts:
         return None
-    kern, prec, var, size = parts
+    kern, prec, var, size = parts[:4]
     es = 8 if prec == "f64" else 4
     m, n = (int(v) for v in size.split("x"))
     ns = 10 * (m + 1) ** 2 * (n + 1)

@@ -93,11 +93,18 @@ const char* tng_last_error(void);
 int tng_ctx_create(int device, void* hip_stream, tng_ctx** out);
 int tng_ctx_set_stream(tng_ctx* ctx, void* hip_stream);
 int tng_ctx_destroy(tng_ctx* ctx);
+/* Band count of the operator apply (a tuning override, Sec. 3 kernel layout):
+ * the apply splits every diamond's cell rows into bands streamed by one
+ * workgroup each.  bands = 0 (the default) chooses the count per launch from
+ * the chip's resident workgroups; bands > 0 forces that many bands (clamped to
+ * [1, m/2] on a level of m rows; unequal bands start on even rows).  Results do
+ * not depend on it beyond rounding.  TNG_E_INVAL for bands < 0. */
+int tng_ctx_set_apply_bands(tng_ctx* ctx, int bands);
 /* Measurement: with enable != 0, every call records a HIP event pair on the
  * context stream around its main kernel, under the name
  * "<kernel>/<precision>/<variant>/<m>x<n>" (kernels "stokes_apply" with
- * variant A, BT, B, A+BT, ... and a "+HG" suffix for hourglass control;
- * "energy_apply").  tng_ctx_kernel_stats synchronises on the recorded events
+ * variant A, BT, B, A+BT, ... and a "+HG" suffix for hourglass control, then
+ * "/b<bands>" and, for serving batches, "/batch"; "energy_apply").  tng_ctx_kernel_stats synchronises on the recorded events
  * and returns the summed elapsed milliseconds and the number of launches
  * since profiling was (re)enabled, over the names equal to `name` or starting
  * with `name` + "/" (so "stokes_apply" sums every variant); none gives 0 and

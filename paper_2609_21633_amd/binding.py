@@ -33,6 +33,7 @@ def lib():
         "tng_ctx_create": [C.c_int, _vp, C.POINTER(_vp)],
         "tng_ctx_set_stream": [_vp, _vp],
         "tng_ctx_destroy": [_vp],
+        "tng_ctx_set_apply_bands": [_vp, C.c_int],
         "tng_mesh_create": [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(_vp)],
         "tng_mesh_counts": [_vp, C.c_int, C.POINTER(C.c_longlong)],
         "tng_mesh_coords": [_vp, C.c_int, _vp, _vp],
@@ -121,6 +122,10 @@ class Context:
     def set_stream(self, stream):
         self.stream = stream
         check(lib().tng_ctx_set_stream(self.h, _vp(stream.cuda_stream)))
+
+    def set_apply_bands(self, bands: int = 0):
+        """Force the operator apply's band count (0: chosen per launch)."""
+        check(lib().tng_ctx_set_apply_bands(self.h, int(bands)))
 
     def profile(self, enable: bool = True):
         """Record HIP events around the main kernel of every call (on this stream)."""

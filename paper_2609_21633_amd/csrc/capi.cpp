@@ -113,6 +113,14 @@ int tng_ctx_set_stream(tng_ctx* ctx, void* hip_stream) {
     TNG_API_END
 }
 
+int tng_ctx_set_apply_bands(tng_ctx* ctx, int bands) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    TNG_REQUIRE(bands >= 0, "bands must be >= 0");
+    ctx->apply_bands = bands;
+    TNG_API_END
+}
+
 int tng_ctx_profile(tng_ctx* ctx, int enable) {
     TNG_API_BEGIN
     TNG_REQUIRE(ctx != nullptr, "ctx is NULL");

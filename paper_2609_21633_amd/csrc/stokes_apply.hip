@@ -28,6 +28,8 @@
 //
 // The divergence block is reduced per coarse pressure node through LDS, kept
 // by one owner thread per node and flushed once a coarse row is complete.
+#include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <type_traits>
 
@@ -54,7 +56,7 @@ struct BandArgs {
     T* yp;
     const T* __restrict__ geo;
     int m, n;
-    int TI, TJ, KC;
+    int TI, KC;
     int ntile, nband, nchunk;
     T r_in, dr;
     T hg;          // hourglass control: alpha * 5/81 (0 without)
@@ -171,10 +173,13 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     const int m = a.m, n = a.n;
     const int i0 = tile * TI;
     const int i = i0 + wc;
-    const int j0 = band * a.TJ;
+    // band b: cell rows [j0, j1), starting on even rows (so that coarse rows stay
+    // whole), lengths differing by at most two rows
+    const int j0 = 2 * ((band * (m >> 1)) / a.nband);
     const bool last_band = (band == a.nband - 1);
+    const int j1 = last_band ? m : 2 * (((band + 1) * (m >> 1)) / a.nband);
     const int jfirst = j0 > 0 ? j0 - 1 : 0;            // halo row (computed, not owned)
-    const int jlast_cell = last_band ? m - 1 : j0 + a.TJ - 1;
+    const int jlast_cell = j1 - 1;
     const int jlast = last_band ? m : jlast_cell;      // last node row emitted
     const int kc0 = chunk * RS * KC;                   // workgroup's radial range [kc0, kcend)
     const int kcend = min(n, kc0 + RS * KC);
@@ -820,17 +825,60 @@ __global__ void post_apply_kernel(PostArgs q, T* y0, T* y1, T* y2, const T* __re
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Band count of a launch.  The workgroups run in rounds of the chip's resident
+// capacity (slots), all bands of a round about equally long, so a launch takes
+// about rounds x (band rows + halo row + start-up) row steps, the last round set
+// by the longest band; the start-up (ring fill, first loads) is about START_ROWS
+// row steps.  Bands have at least four rows.
+constexpr double START_ROWS = 2.0;
+inline int choose_bands(int m, long long cols, long long slots) {
+    if (m < 8) return 1;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int nb = 1; nb <= m / 4; ++nb) {
+        const long long rounds = (cols * nb + slots - 1) / slots;
+        const double mean = (double)m / nb, longest = 2.0 * ((m / 2 + nb - 1) / nb);
+        const double cost = (rounds - 1) * (mean + 1 + START_ROWS) + (longest + 1 + START_ROWS);
+        if (cost < best_cost * (1 - 1e-9)) {
+            best_cost = cost;
+            best = nb;
+        }
+    }
+    return best;
+}
+
 // the solver's combinations (A, B^T, K, each viscous one also with hourglass
 // control) have a batched form; the others run one slot at a time
 template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG>
-void launch_band_t(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb) {
+void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb) {
     constexpr bool BATCHABLE = (A && !BT && !B) || (!A && BT && !B) || (A && BT && B);
+    const int block = args.TI * RS * 64;
+    const bool batched = sb.nb > 1;
+    if (ctx->apply_bands > 0) {
+        args.nband = std::max(1, std::min(ctx->apply_bands, std::max(1, args.m / 2)));
+    } else {
+        // resident workgroups per CU of this kernel at this block size, asked once
+        static std::atomic<int> resident[2][TIC + 1];
+        std::atomic<int>& rc = resident[batched ? 1 : 0][block / 64];
+        int per_cu = rc.load(std::memory_order_relaxed);
+        if (per_cu == 0) {
+            if (batched)
+                TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG>, block, 0));
+            else
+                TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG>, block, 0));
+            per_cu = std::max(1, per_cu);
+            rc.store(per_cu, std::memory_order_relaxed);
+        }
+        args.nband = choose_bands(args.m, 10LL * args.ntile * args.nchunk * sb.nb, (long long)per_cu * ctx->n_cu);
+    }
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
     char detail[64] = {0};
     if (ctx->profile) {
         const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
-        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d%s", std::is_same<T, double>::value ? "f64" : "f32",
-                      ops, HG ? "+HG" : "", args.m, args.n, sb.nb > 1 ? "/batch" : "");
+        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", args.m, args.n, args.nband, sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
     if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
@@ -909,11 +957,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.KC = rs * 64 * cpl;                           // radial range of a workgroup
     a.ntile = L.m / a.TI;
     a.nchunk = (L.n + a.KC - 1) / a.KC;
-    // bands of 16 rows; on small levels shorter bands (down to 4 rows) until there are
-    // about two workgroups per CU: there the serial row loop, not the bytes, sets the time
-    a.TJ = std::min(16, L.m);
-    while (a.TJ > 4 && 10LL * a.ntile * a.nchunk * (L.m / a.TJ) < 512) a.TJ /= 2;
-    a.nband = L.m / a.TJ;
+    a.nband = 1;   // chosen per kernel at launch
     a.r_in = T(L.r_in);
     a.dr = T(L.dr());
     a.dirichlet = (flags & TNG_OP_DIRICHLET) ? 1 : 0;

@@ -222,6 +222,7 @@ struct tng_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int n_cu = 256;
+    int apply_bands = 0;   // band count of the operator apply; 0 = chosen per launch
     bool profile = false;
     std::map<std::string, tng::KernelStats> stats;
     ~tng_ctx();

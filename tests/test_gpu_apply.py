@@ -180,3 +180,25 @@ def test_radial_split_columns(tng, ctx, mt, nr, prec):
     gp = lmp.from_lib(yp, check_dups=1e-6)
     print(f"split {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < tol and rel(gp, rp) < tol
+
+
+# ---- band partition: bands of unequal length (forced through the context) -------------
+
+@pytest.mark.parametrize("mt,nr,bands,prec", [(16, 16, 3, "f64"), (16, 10, 5, "f64"), (32, 8, 7, "f32"),
+                                               (16, 16, 8, "f32"), (8, 8, 1, "f64")])
+def test_forced_band_counts(tng, ctx, mt, nr, bands, prec):
+    """Bands of 4-6, 2-4 and 4-6 rows (counts that do not divide the rows), eight
+    two-row bands and a single band: the result does not depend on the partition."""
+    import torch
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    ctx.set_apply_bands(bands)
+    try:
+        yu, yp = run_apply(tng, ctx, mesh, t, OPS_ALL, dt)
+    finally:
+        ctx.set_apply_bands(0)
+    ru, rp = orc.apply(u, p)
+    gu = lm.from_lib(yu, check_dups=1e-6)
+    gp = lmp.from_lib(yp, check_dups=1e-6)
+    print(f"bands {bands} {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
+    assert rel(gu, ru) < tol and rel(gp, rp) < tol

@@ -349,8 +349,10 @@ def cpu_baseline(sizes=((16, 16), (32, 32)), reps=10):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # a few launches leave the GPU below its sustained clock: 100 (about 40 ms of FP32
+    # applies) bring it there
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--mt", type=int, default=128)
     ap.add_argument("--nr", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -5,8 +5,8 @@
 //   * lanes run along the radial direction: lane l of a wave handles the CPL
 //     consecutive cells k = k0 + CPL*l + c of one cell column, so every memory
 //     access of a wave covers a contiguous radial stretch of 64 CPL cells;
-//   * a workgroup has 8 waves: TC = 8 / RS adjacent cell columns, each column
-//     split into RS radial stretches handled by RS waves, so that one
+//   * a workgroup has WG = 4 or 8 waves: TC = WG / RS adjacent cell columns, each
+//     column split into RS radial stretches handled by RS waves, so that one
 //     workgroup holds whole radial columns (a column split across workgroups
 //     costs far more, in memory stalls, than the split inside one);
 //   * the workgroup streams along j over the cell rows of its band, carrying
@@ -28,6 +28,10 @@
 //
 // The divergence block is reduced per coarse pressure node through LDS, kept
 // by one owner thread per node and flushed once a coarse row is complete.
+//
+// The band count is chosen per launch from the kernel's resident workgroups
+// (bands of unequal length, starting on even rows), and blocks are renumbered
+// so that each XCD works on a contiguous run of tiles and bands.
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
@@ -162,7 +166,15 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wc = w / RS;       // column of the wave within the tile
     const int h = w % RS;        // radial stretch of the wave within the workgroup
-    int bid = blockIdx.x;
+    // XCD-aware order: the dispatcher deals consecutive workgroups to the eight XCDs
+    // in turn; each XCD takes a contiguous run of (tile, band) blocks instead, so that
+    // the same bands of neighbouring tiles, which share a node column, run together
+    // under one L2
+    int bid;
+    {
+        const unsigned nbk = gridDim.x, q = nbk >> 3, r = nbk & 7, x = blockIdx.x & 7;
+        bid = (int)(x * q + min(x, r) + (blockIdx.x >> 3));
+    }
     const int chunk = bid % a.nchunk;
     bid /= a.nchunk;
     const int band = bid % a.nband;

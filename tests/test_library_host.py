@@ -39,6 +39,7 @@ def test_argument_validation_without_gpu():
     assert b"power of two" in L.tng_last_error()
     assert L.tng_mesh_create(None, 8, 8, 1.0, 0.5, 1, C.byref(h)) == -1
     assert L.tng_mesh_create(None, 8, 6, 0.55, 1.0, 3, C.byref(h)) == -1
+    assert L.tng_ctx_set_apply_bands(None, 0) == -1
     # 32-bit field offsets: (1024, 512) has 10 * 1025^2 * 513 > 2^31 node slots
     assert L.tng_mesh_create(None, 1024, 512, 0.55, 1.0, 1, C.byref(h)) == -1
     assert b"too large" in L.tng_last_error()

@@ -196,6 +196,20 @@ int tng_pressure_mass(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
 int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
                double hg_alpha, const void* const diag[3], const void* const b[3], void* const x[3], int degree,
                int steps, double lmin, double lmax);
+/* tng_smooth without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, result and stream as in tng_smooth,
+ * except: degree <= 16, and the call neither allocates nor synchronises.  Its
+ * five work vectors and step coefficients live in one library-owned device
+ * array of 48 MiB per GPU (held from the first tng_ctx_create on that GPU
+ * until the process ends): a level needs 5 x 3 x node_slots values (rounded
+ * up to 256-byte pieces) plus 256 bytes, so levels up to (32,32) fit in FP64
+ * and FP32; larger levels return TNG_E_INVAL and launch nothing.  Every call
+ * on a GPU uses that GPU's one array: calls enqueued on one stream are ordered,
+ * but calls that overlap on one GPU (different streams or contexts) race. */
+int tng_smooth_noalloc(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+                       double hg_alpha, const void* const diag[3], const void* const b[3], void* const x[3],
+                       int degree, int steps, double lmin, double lmax);
 /* W1 transfer between fine_level and fine_level + 1 (index-space
  * interpolation: coarse nodes copied, edge midpoints and odd layers averaged).
  * Restriction c = P^T f with Dirichlet layers of c set to zero; prolongation

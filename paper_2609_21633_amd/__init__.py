@@ -9,5 +9,5 @@ does, and fails loudly if ``libtng.so`` has not been built.
 from .binding import (  # noqa: F401
     OP_A, OP_B, OP_BT, OP_DIRICHLET, TngError, Context, Mesh, StokesSolver, diag_A, eta_coarsen,
     eta_from_temperature, interface_sum, lib, pressure_mass, prolong, restrict, smooth, stokes_apply,
-    rhs_buoyancy, energy_apply, Server,
+    rhs_buoyancy, energy_apply, Server, smooth_noalloc,
 )

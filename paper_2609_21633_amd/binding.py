@@ -52,6 +52,8 @@ def lib():
         "tng_pressure_mass": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
         "tng_smooth": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
                        C.c_int, C.c_int, C.c_double, C.c_double],
+        "tng_smooth_noalloc": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp), C.POINTER(_vp),
+                               C.POINTER(_vp), C.c_int, C.c_int, C.c_double, C.c_double],
         "tng_restrict": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
         "tng_prolong": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.POINTER(_vp)],
         "tng_solver_opts_default": [_vp],
@@ -255,6 +257,13 @@ def smooth(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, s
            lmin: float, lmax: float, hg_alpha: float = 0.0):
     check(lib().tng_smooth(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag), _ptr3(b),
                            _ptr3(x), degree, steps, lmin, lmax))
+
+
+def smooth_noalloc(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, steps: int,
+                   lmin: float, lmax: float, hg_alpha: float = 0.0):
+    """smooth() with the library's fixed device scratch array: no allocation, no synchronisation."""
+    check(lib().tng_smooth_noalloc(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag),
+                                   _ptr3(b), _ptr3(x), degree, steps, lmin, lmax))
 
 
 def restrict(ctx: Context, mesh: Mesh, fine_level: int, f, c):

@@ -100,6 +100,12 @@ int tng_ctx_create(int device, void* hip_stream, tng_ctx** out) {
     auto* c = new tng_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    try {
+        tng::noalloc_register_device(device);
+    } catch (...) {
+        delete c;
+        throw;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
     *out = c;

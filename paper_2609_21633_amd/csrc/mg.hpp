@@ -113,6 +113,8 @@ void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T*
 // Coefficients (alpha_k, beta_k), k < deg, of one Chebyshev smoothing step of
 // degree deg for the eigenvalue interval [lo, hi].
 std::vector<double> chebyshev_coefficients(int deg, double lo, double hi);
+// the same into ab[0 .. 2 max(deg, 1))
+void chebyshev_coefficients(int deg, double lo, double hi, double* ab);
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
                      T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero);

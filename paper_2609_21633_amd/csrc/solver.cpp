@@ -173,8 +173,13 @@ void vel_dot(tng_solver* s, int l, const T* x, const T* const* ydev, double* out
 // (deg operator applies; the first one is skipped when x starts at zero).
 // Step k of the recurrence is d <- alpha_k d + beta_k D^{-1}(b - A x), x += d.
 std::vector<double> chebyshev_coefficients(int deg, double lo, double hi) {
-    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     std::vector<double> ab(2 * (size_t)std::max(deg, 1));
+    chebyshev_coefficients(deg, lo, hi, ab.data());
+    return ab;
+}
+
+void chebyshev_coefficients(int deg, double lo, double hi, double* ab) {
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     ab[0] = 0.0;
     ab[1] = 1.0 / theta;
     double rho_old = 1.0 / sigma;
@@ -184,7 +189,6 @@ std::vector<double> chebyshev_coefficients(int deg, double lo, double hi) {
         ab[2 * k + 1] = 2.0 * rho / delta;
         rho_old = rho;
     }
-    return ab;
 }
 
 template <typename T>

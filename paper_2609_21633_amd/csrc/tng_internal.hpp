@@ -264,6 +264,10 @@ void launch_eta_from_T(const tng_ctx* ctx, const Level& L, tng_prec prec, const 
 void launch_eta_coarsen(const tng_ctx* ctx, const Level& Lc, tng_prec prec, const void* ef,
                         void* ec);
 
+// Scratch array of the no-allocation entry points (noalloc.hip): asks the
+// array's address on `device`, which must be current, once per device.
+void noalloc_register_device(int device);
+
 // Records a start/stop event pair around a launch when profiling is on.  The
 // name is "<kernel>/<detail>" (precision, variant, level size); statistics can
 // be read per full name or summed over a kernel prefix.

@@ -134,6 +134,74 @@ def bench_solve(tng, ctx, mesh, T64, E, F, mixed, reps=2):
     return best, (u.clone(), p.clone())
 
 
+def bench_copy_roof(tng, ctx, nbytes=2 << 30, reps=10):
+    """Practical HBM roof: the library's plain streaming copy (tng_stream_copy) of
+    nbytes, 2 x nbytes moved per launch, HIP-event timed on the launch stream."""
+    import torch
+    x = torch.full((nbytes // 4,), 1.0, dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    for _ in range(3):
+        tng.stream_copy(ctx, x, y)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        tng.stream_copy(ctx, x, y)
+    ms, n = ctx.kernel_stats("stream_copy")
+    ctx.profile(False)
+    del x, y
+    torch.cuda.empty_cache()
+    t = ms / max(n, 1) * 1e-3
+    return {"kernel": "stream_copy_kernel (16-byte vectors, 4 per thread and trip)", "bytes_per_launch": 2 * nbytes,
+            "kernel_ms": round(t * 1e3, 4), "gbs": round(2 * nbytes / t / 1e9, 1)}
+
+
+GOLDEN16 = os.path.join(ROOT, "tests", "golden", "stokes16_contrast1e6.npz")
+
+
+def golden16_errors(tng, ctx, mixed):
+    """The contrast-1e6 solve on the (16,16) copy of the workload, to the benchmarked 1e-8,
+    against the oracle's exact discrete solution stored in tests/golden (written by the
+    committed script next to it).  The library's slots are matched to the stored node order
+    by their coordinates (stored with the solution)."""
+    import numpy as np
+    import torch
+    from scipy.spatial import cKDTree
+    import synthetic
+    d = np.load(GOLDEN16)
+    mesh = tng.Mesh(ctx, 16, 16, levels=4)
+
+    def node_map(level, s_ref, r_ref):
+        xyz, r = mesh.coords(level)
+        assert np.allclose(r, r_ref, rtol=0, atol=1e-14)
+        dist, lat = cKDTree(s_ref).query(xyz.reshape(-1, 3))
+        assert dist.max() < 1e-9
+        first = np.full(len(s_ref), -1)
+        for slot in range(len(lat) - 1, -1, -1):
+            first[lat[slot]] = slot
+        return lat, first
+
+    lat_u, first_u = node_map(0, d["s_u"], d["r_u"])
+    _, first_p = node_map(1, d["s_p"], d["r_p"])
+    # T on the stored nodes (the generator's recipe), scattered to the library slots
+    T = synthetic.temperature(d["s_u"], d["r_u"], seed=1, lmin=1, lmax=8, amp=0.01)
+    T_lib = torch.tensor(T[lat_u].reshape(mesh.shape(0)), device="cuda")
+    eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
+    tng.eta_from_temperature(ctx, mesh, 0, T_lib, math.log(1e6), 0.0, eta)
+    f = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+    tng.rhs_buoyancy(ctx, mesh, 0, T_lib, 1e5, f)
+    u = torch.empty_like(f)
+    p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-8, max_iters=4000, inner_max_iters=4000, max_outer=60)
+    info = s.solve(f, None, u, p, eta=eta, raise_on_fail=False)
+    s.close()
+    n1, nc1 = 17, 9
+    ug = u.cpu().numpy().reshape(3, -1, n1)[:, first_u, :].reshape(3, -1).T
+    pg = p.cpu().numpy().reshape(-1, nc1)[first_p, :].ravel()
+    return {"u": float(np.linalg.norm(ug - d["u"]) / np.linalg.norm(d["u"])),
+            "p": float(np.linalg.norm(pg - d["p"]) / np.linalg.norm(d["p"])),
+            "rel_res": info["rel_res"], "iterations": info["inner_its"], "rc": info["rc"]}
+
+
 def variant_bytes(name):
     """Algorithmic bytes of one launch from a detailed timer name
     "stokes_apply/<f32|f64>/<variant>/<m>x<n>/b<bands>" or "energy_apply/<prec>/SUPG/<m>x<n>":
@@ -306,7 +374,7 @@ def bench_serving_sweep(tng, ctx, nreq=256, factors=(0.25, 0.5, 0.75, 0.95), bud
                              "slots_live_at_end": tst["slots"], "bytes_in_use_at_end": tst["bytes_in_use"]}}
 
 
-def cpu_baseline(sizes=((16, 16), (32, 32)), reps=10):
+def cpu_baseline(sizes=((16, 16), (32, 32)), reps=10, solve_sizes=(8,)):
     """The FP64 oracle (assembled K_D, scipy CSR SpMV) on bounded sample shells; the value
     is that of the largest one (the SpMV is memory-bound, so its GDoF/s barely depend on size)."""
     import numpy as np
@@ -335,15 +403,76 @@ def cpu_baseline(sizes=((16, 16), (32, 32)), reps=10):
         parts.append(f"({mt},{nr}) shell {ndof} u+p DoFs, nnz {orc.K.nnz}: {t * 1e3:.2f} ms per apply "
                      f"({value:.4f} GDoF/s), assembly {t_asm:.1f} s")
         del orc
+    solves = [cpu_solve(mt) for mt in solve_sizes]
+    return {"value": round(value, 5), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"assembled FP64 K_D, scipy CSR SpMV (single thread), median of {reps} after 2 warm-ups: "
+                       + "; ".join(parts) + f"; value from the largest; host {host_cpu()}, nproc {os.cpu_count()}"),
+            "solves": solves}
+
+
+def host_cpu():
     cpu = platform.processor() or platform.machine()
     try:
         with open("/proc/cpuinfo") as fh:
             cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
     except Exception:
         pass
-    return {"value": round(value, 5), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"assembled FP64 K_D, scipy CSR SpMV (single thread), median of {reps} after 2 warm-ups: "
-                       + "; ".join(parts) + f"; value from the largest; host {cpu}, nproc {os.cpu_count()}")}
+    return cpu
+
+
+def cpu_solve(mt):
+    """The oracle's exact discrete solve (A_D factorised, CG on the pressure Schur
+    complement to 1e-13) of the contrast-1e6 workload on the (mt, mt) copy."""
+    import synthetic
+    from oracle.mesh import ShellMesh
+    from oracle.saddle import SchurSolver
+    from oracle.stokes import StokesOracle, buoyancy_rhs, eta_from_temperature
+    om = ShellMesh(mt, mt)
+    T = synthetic.temperature(om.s, om.r, seed=1, lmin=1, lmax=8, amp=0.01).ravel()
+    eta = eta_from_temperature(om, T, math.log(1e6), 0.0)
+    f = buoyancy_rhs(om, T, 1e5)
+    f[om.boundary_nodes()] = 0.0
+    t0 = time.perf_counter()
+    orc = StokesOracle(mt, mt, eta, hierarchy=om.h)
+    sol = SchurSolver(orc, eta)
+    t_fac = time.perf_counter() - t0
+    _, _, info = sol.solve(f)
+    t = time.perf_counter() - t0
+    return {"shell": [mt, mt], "dofs": orc.K.shape[0], "seconds": round(t, 2), "assembly_and_factor_s": round(t_fac, 2),
+            "schur_cg_its": info["cg_its"], "rel_res": info["rel_res"], "cores": 1}
+
+
+def run_solves(tng, ctx, mesh, T64):
+    """The FP64 solve of the headline field, the contrast-1e6 field in FP64 and mixed
+    precision (same field), and the contrast-1e6 solves on the (16,16) copy against
+    the stored oracle solution."""
+    import torch
+    out = {}
+    log("[bench] FP64 solve, contrast 1e3 x 10 (depth)")
+    s1, _ = bench_solve(tng, ctx, mesh, T64, math.log(1e3), math.log(10.0), mixed=0)
+    out["solve_fp64"] = {"solves_per_s": round(1.0 / s1["wall"], 4), "seconds": round(s1["wall"], 3),
+                         "iterations": s1["inner_its"], "rel_res": s1["rel_res"], "rc": s1["rc"]}
+    log(f"[bench] {out['solve_fp64']}")
+    log("[bench] contrast 1e6: mixed vs FP64 on the same field")
+    s64, (u64, p64) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=0)
+    s32, (u32, p32) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=1)
+    du = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+    dp = float(torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64))
+    del u64, p64, u32, p32
+    torch.cuda.empty_cache()
+    log("[bench] contrast 1e6 on the (16,16) copy vs the stored oracle solution")
+    g64, g32 = golden16_errors(tng, ctx, 0), golden16_errors(tng, ctx, 1)
+    out["solve_contrast_1e6"] = {
+        "fp64": {"solves_per_s": round(1.0 / s64["wall"], 4), "iterations": s64["inner_its"],
+                 "rel_res": s64["rel_res"], "rc": s64["rc"]},
+        "mixed": {"solves_per_s": round(1.0 / s32["wall"], 4), "inner_iterations": s32["inner_its"],
+                  "refinement_steps": s32["outer_its"], "rel_res": s32["rel_res"], "rc": s32["rc"]},
+        "mixed_over_fp64": round(s64["wall"] / s32["wall"], 3),
+        "mixed_vs_fp64_rel_err": {"u": du, "p": dp},
+        "vs_oracle_on_16x16_copy": {"fp64": g64, "mixed": g32},
+        "mixed_1e6_over_fp64_solve_at_contrast_1e3": round(s1["wall"] / s32["wall"], 3)}
+    log(f"[bench] {out['solve_contrast_1e6']}")
+    return out
 
 
 def main():
@@ -360,9 +489,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=0.75, help="arrival rate / saturated rate")
-    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain device copy of a known size (for HBM counter calibration)")
+    ap.add_argument("--serving-budget-gb", type=float, default=200.0, help="HBM budget in GB (1e9 bytes)")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="instead: the CPU oracle on larger shells (SpMV up to (64,64), exact solves at (8,8) "
+                         "and (16,16)); CPU only, several minutes; one JSON report line")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="instead: 256-request serving stream at the saturated rate and four Poisson "
                          "rates, plus a tight 2 GiB budget; one JSON report line")
@@ -379,6 +509,9 @@ def main():
               "apply).",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_baseline_full:
+        print(json.dumps(cpu_baseline(sizes=((16, 16), (32, 32), (64, 64)), solve_sizes=(8, 16))), flush=True)
+        return
     import torch
     import paper_2609_21633_amd as tng
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -406,6 +539,16 @@ def main():
     levels = int(math.log2(mt))                   # down to (2, 2)
     mesh = tng.Mesh(ctx, mt, nr, levels=levels)
     T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
+    extra = {}
+    if not args.no_solve:
+        extra.update(run_solves(tng, ctx, mesh, T64))
+    if not args.no_serving:
+        log(f"[bench] serving: {args.serving_requests} requests at {args.serving_rate} x saturated rate")
+        extra["serving"] = bench_serving(tng, ctx, args.serving_requests, args.serving_rate,
+                                         int(args.serving_budget_gb * 1e9))
+        log(f"[bench] {extra['serving']}")
+    # the timed applies come after the solves and the serving run, so that they run at the
+    # GPU's sustained clock (as inside a solve) whatever the number of warm-up steps
     res = {}
     for name, dtype, es in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
         log(f"[bench] {name} apply on ({mt},{nr})")
@@ -416,15 +559,8 @@ def main():
         log(f"[bench] {name}: {wall * 1e3:.3f} ms/apply (kernel {kms:.3f} ms), {res[name]['gdofs']:.1f} GDoF/s, "
             f"{res[name]['kernel_gbs']:.0f} GB/s algorithmic")
         torch.cuda.empty_cache()
-    if args.copy_calibration:
-        # plain device copy of 2 GiB between buffers that were written before
-        # (untouched pages do not exercise HBM), for scaling HBM counters
-        x = torch.full((512 * 1024 * 1024,), 1.0, dtype=torch.float32, device="cuda")
-        y = torch.zeros_like(x)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+    roof = bench_copy_roof(tng, ctx)
+    log(f"[bench] practical roof (stream copy): {roof}")
     head = res["f32"]
     # measured HBM traffic (scaled rocprofv3 counters) only for the (128,128) shell they were taken on
     t32 = counter_traffic("f32_traffic_bytes_per_launch") if (mt, nr) == (128, 128) else None
@@ -451,39 +587,15 @@ def main():
                      "traffic": None if t32 is None else round(t32 / (head["kernel_ms"] * 1e6), 1),
                      "traffic_bytes_per_launch": t32,
                      "kernel": "stokes_band_kernel<float,RS=1,CPL=2,A,BT,B,WG=4> (FP32 full operator)",
-                     "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": round(head["kernel_ms"], 4)},
+                     "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": round(head["kernel_ms"], 4),
+                     "practical_roof": roof,
+                     "frac_of_practical_roof": round(head["kernel_gbs"] / roof["gbs"], 4)},
         "f64_apply": {"gdofs": round(res["f64"]["gdofs"], 3), "ms": round(res["f64"]["ms"], 4),
                       "kernel_gbs": round(res["f64"]["kernel_gbs"], 1),
                       "traffic_gbs": None if t64 is None else round(t64 / (res["f64"]["kernel_ms"] * 1e6), 1),
                       "kernel_ms": round(res["f64"]["kernel_ms"], 4)},
     }
-    if not args.no_solve:
-        log("[bench] FP64 solve, contrast 1e3 x 10 (depth)")
-        s1, _ = bench_solve(tng, ctx, mesh, T64, math.log(1e3), math.log(10.0), mixed=0)
-        out["solve_fp64"] = {"solves_per_s": round(1.0 / s1["wall"], 4), "seconds": round(s1["wall"], 3),
-                             "iterations": s1["inner_its"], "rel_res": s1["rel_res"], "rc": s1["rc"]}
-        log(f"[bench] {out['solve_fp64']}")
-        log("[bench] contrast 1e6: mixed vs FP64 on the same field")
-        s64, (u64, p64) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=0)
-        s32, (u32, p32) = bench_solve(tng, ctx, mesh, T64, math.log(1e6), 0.0, mixed=1)
-        du = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
-        dp = float(torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64))
-        out["solve_contrast_1e6"] = {
-            "fp64": {"solves_per_s": round(1.0 / s64["wall"], 4), "iterations": s64["inner_its"],
-                     "rel_res": s64["rel_res"], "rc": s64["rc"]},
-            "mixed": {"solves_per_s": round(1.0 / s32["wall"], 4), "inner_iterations": s32["inner_its"],
-                      "refinement_steps": s32["outer_its"], "rel_res": s32["rel_res"], "rc": s32["rc"]},
-            "mixed_over_fp64": round(s64["wall"] / s32["wall"], 3),
-            "mixed_vs_fp64_rel_err": {"u": du, "p": dp},
-            "mixed_1e6_over_fp64_solve_at_contrast_1e3": round(s1["wall"] / s32["wall"], 3)}
-        log(f"[bench] {out['solve_contrast_1e6']}")
-        del u64, p64, u32, p32
-        torch.cuda.empty_cache()
-    if not args.no_serving:
-        log(f"[bench] serving: {args.serving_requests} requests at {args.serving_rate} x saturated rate")
-        out["serving"] = bench_serving(tng, ctx, args.serving_requests, args.serving_rate,
-                                       int(args.serving_budget_gb * (1 << 30)))
-        log(f"[bench] {out['serving']}")
+    out.update(extra)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()

@@ -18,8 +18,15 @@
  *   and destroyed by the library.  Field pointers are caller-owned memory and
  *   are never freed or retained beyond the call (server submissions excepted,
  *   see tng_server_submit).
- * Memory: "device" pointers must be device memory of the context's GPU (e.g.
- *   torch CUDA tensors); "host" pointers are ordinary host memory.
+ * Memory: "device" pointers must be ordinary (coarse-grained) device memory
+ *   of the context's GPU from hipMalloc, e.g. torch CUDA tensors, holding the
+ *   whole field; "host" pointers are ordinary host memory.  Every call checks
+ *   its device pointers (hipPointerGetAttributes: device memory of the
+ *   context's device, not managed; hipMemGetAddressRange: the field fits in
+ *   the allocation) and returns TNG_E_INVAL otherwise.  Host, pinned-host and
+ *   managed memory are refused: the operator kernels add seam partial sums
+ *   with floating-point atomics that are only reliable on coarse-grained
+ *   device memory.
  * Streams: applies, smoothers, transfers and field kernels are enqueued on the
  *   context's stream and return without synchronising.  Solves, energy steps
  *   and server polls synchronise that stream.
@@ -80,8 +87,19 @@ enum {
     TNG_OP_A = 1,       /* viscous block A(eta), eq:elemmat with one-point rule */
     TNG_OP_BT = 2,      /* gradient block B^T (pressure -> velocity)           */
     TNG_OP_B = 4,       /* divergence block B (velocity -> pressure)           */
-    TNG_OP_DIRICHLET = 8 /* zero-velocity rows on both spheres: identity rows,
+    TNG_OP_DIRICHLET = 8, /* zero-velocity rows on both spheres: identity rows,
                             columns dropped (K_D = [[DAD + I - D, DB^T],[BD, 0]]) */
+    /* Free slip (the paper's verification setup, Sec. 8) on the inner / outer
+     * sphere instead: a node's velocity is taken in the frame (rhat, two
+     * tangents), rhat = the node's unit vector; the normal component is a
+     * Dirichlet DoF (identity row, column dropped), the tangential ones are
+     * free (zero tangential traction).  In Cartesian components, with
+     * P = I - rhat rhat^T and N = rhat rhat^T at the sphere's nodes:
+     * y_u = P (A P u + B^T p) + N u there, y_p = B P u.  A sphere with its
+     * free-slip bit set is free slip whatever TNG_OP_DIRICHLET says; the other
+     * sphere is no slip with TNG_OP_DIRICHLET and unconstrained without it. */
+    TNG_OP_FREESLIP_INNER = 16,
+    TNG_OP_FREESLIP_OUTER = 32
 };
 
 /* Message of the last failed call on this thread ("" if none).  Library-owned. */
@@ -115,6 +133,17 @@ int tng_ctx_profile(tng_ctx* ctx, int enable);
 int tng_ctx_kernel_stats(tng_ctx* ctx, const char* name, double* total_ms, long long* launches);
 int tng_ctx_kernel_stats_at(tng_ctx* ctx, int index, char* name, int name_len, double* total_ms,
                             long long* launches);
+
+/* Plain streaming copy dst = src of `bytes` device bytes (a multiple of 16,
+ * both pointers 16-byte aligned, not overlapping), enqueued on the context's
+ * stream and timed as "stream_copy" when profiling is on: the practical HBM
+ * roof (2 x bytes moved per launch) that the operator kernels are measured
+ * against, and a kernel of known traffic for scaling HBM counters. */
+int tng_stream_copy(tng_ctx* ctx, const void* src, void* dst, size_t bytes);
+/* Checks that `bytes` bytes at p are device memory that every call of this
+ * library accepts (the check every entry point applies to its device
+ * pointers): TNG_OK, or TNG_E_INVAL with the reason in tng_last_error(). */
+int tng_check_device_buffer(tng_ctx* ctx, const void* p, size_t bytes);
 
 /* ---- mesh (Sec. 2) ------------------------------------------------------ */
 /* Builds the shell with mt lateral intervals per diamond edge (power of two)
@@ -160,6 +189,19 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
                      unsigned op_flags, double hg_alpha, const void* eta_wedge,
                      const void* const u[3], const void* p,
                      void* const y_u[3], void* y_p);
+
+/* Decomposition that tng_stokes_apply uses for these arguments (the kernel
+ * layout of Sec. 5 as built here; for tests that target its seams and for
+ * measurement).  Launches nothing.  out[0..7] = cell columns per workgroup
+ * tile, waves per column (radial split), cells per lane, waves per workgroup,
+ * tiles per diamond, bands per diamond (the per-launch choice, or the forced
+ * count of tng_ctx_set_apply_bands), radial ranges per column, cells per
+ * radial range.  Band b of m rows covers the cell rows
+ * [2 floor(b (m/2) / bands), 2 floor((b+1) (m/2) / bands)); tile t covers the
+ * cell columns [t tile, (t+1) tile); radial range c covers the cells
+ * [c range, (c+1) range) and is split into stretches of 64 x (cells per lane). */
+int tng_stokes_apply_layout(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, unsigned op_flags,
+                            double hg_alpha, int out[8]);
 
 /* ---- fields ------------------------------------------------------------- */
 /* Per-wedge viscosity from nodal temperature: eta_e = exp(-E Tbar_e + F (1 - r_m)),

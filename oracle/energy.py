@@ -50,10 +50,16 @@ class EnergyOracle:
         K = np.einsum("wia,wja->wij", g, g)
         C = N[None, :, None] * ug[:, None, :]
         S = tau[:, None, None] * ug[:, :, None] * ug[:, None, :]
-        Ae = V[:, None, None] * (K + C + S)
         rows = np.repeat(wn, 6, axis=1).ravel()
         cols = np.tile(wn, (1, 6)).ravel()
-        A = sp.csr_matrix((Ae.ravel(), (rows, cols)), shape=(m.n_nodes, m.n_nodes))
+
+        def assemble(Ee):
+            return sp.csr_matrix(((V[:, None, None] * Ee).ravel(), (rows, cols)), shape=(m.n_nodes, m.n_nodes))
+
+        # the three parts separately (diffusion, advection, streamline diffusion),
+        # without Dirichlet rows, and their sum
+        self.K, self.C, self.S = assemble(K), assemble(C), assemble(S)
+        A = assemble(K + C + S)
         ml = np.zeros(m.n_nodes)
         np.add.at(ml, wn, V[:, None] * N[None, :])
         self.mass = ml

@@ -19,6 +19,15 @@ Readings (the same on both sides):
 * sign: B is the weak form of -div, (B_f)_{i,(j,c)} = -V_e N_i(q_c) d_c phi_j(q_c);
 * Dirichlet: velocity rows on both spheres become identity rows and their
   columns are dropped:  K_D = [[D A D + (I - D), D B^T], [B D, 0]];
+* free slip (the setup of the paper's verification runs, Sec. 8): at a node of
+  a free-slip sphere the velocity is expressed in the local frame (rhat, two
+  tangential directions), rhat = x / |x| the sphere's normal at the node; the
+  normal component is a Dirichlet DoF (identity row, column dropped) and the
+  two tangential ones are free (zero tangential traction, a natural condition).
+  Rotating back to Cartesian components gives, per node, the projection
+  P = I - rhat rhat^T onto the tangent plane and N = rhat rhat^T:
+  K = [[P A P + N, P B^T], [B P, 0]], which is the no-slip K_D with P = 0,
+  N = I on no-slip nodes (and P = I, N = 0 inside);
 * per-wedge viscosity: eta(q_c) is the wedge's value; for temperature-driven
   laws it is the law evaluated at the mean of the six nodal temperatures and
   the wedge's mid radius (the value of the W1 interpolant at q_c);
@@ -132,13 +141,47 @@ def element_divergence(xw: np.ndarray):
     return -(V[:, None, None] * N[None, :, None] * div[:, None, :])
 
 
+BC_KINDS = ("noslip", "freeslip", "none")
+
+
+def boundary_projections(mesh: ShellMesh, bc=("noslip", "noslip")):
+    """Sparse block-diagonal P (velocity subspace a node may take) and N = I - P
+    on the spheres (0 inside), DoF order 3 node + component.  bc = (inner, outer),
+    each "noslip" (P = 0), "freeslip" (P = I - rhat rhat^T) or "none" (P = I, N = 0)."""
+    if len(bc) != 2 or any(b not in BC_KINDS for b in bc):
+        raise ValueError("bc must be a pair of 'noslip', 'freeslip' or 'none'")
+    nn = mesh.n_nodes
+    k = np.tile(np.arange(mesh.nr + 1), mesh.n_lat)
+    x = mesh.node_xyz()
+    rhat = x / np.linalg.norm(x, axis=1)[:, None]
+    Pb = np.tile(np.eye(3), (nn, 1, 1))
+    Nb = np.zeros((nn, 3, 3))
+    for kind, layer in zip(bc, (0, mesh.nr)):
+        sel = k == layer
+        if kind == "noslip":
+            Pb[sel] = 0.0
+            Nb[sel] = np.eye(3)
+        elif kind == "freeslip":
+            nnT = rhat[sel][:, :, None] * rhat[sel][:, None, :]
+            Pb[sel] = np.eye(3) - nnT
+            Nb[sel] = nnT
+    rows = (3 * np.arange(nn)[:, None, None] + np.arange(3)[None, :, None]).repeat(3, axis=2)
+    cols = (3 * np.arange(nn)[:, None, None] + np.arange(3)[None, None, :]).repeat(3, axis=1)
+    P = sp.csr_matrix((Pb.ravel(), (rows.ravel(), cols.ravel())), shape=(3 * nn, 3 * nn))
+    N = sp.csr_matrix((Nb.ravel(), (rows.ravel(), cols.ravel())), shape=(3 * nn, 3 * nn))
+    P.eliminate_zeros()
+    N.eliminate_zeros()
+    return P, N
+
+
 class StokesOracle:
     """Assembled FP64 Stokes saddle-point operator on the (mt, nr) shell
-    (hg_alpha > 0: viscous block with hourglass control, eq:hgstab)."""
+    (hg_alpha > 0: viscous block with hourglass control, eq:hgstab; bc = velocity
+    condition on (inner, outer) sphere, see boundary_projections)."""
 
     def __init__(self, mt: int, nr: int, eta_wedge: np.ndarray, r_in: float = 0.55,
                  r_out: float = 1.0, hierarchy: SphereHierarchy | None = None,
-                 chunk: int = 200_000, hg_alpha: float = 0.0):
+                 chunk: int = 200_000, hg_alpha: float = 0.0, bc=("noslip", "noslip")):
         self.mesh = m = ShellMesh(mt, nr, r_in, r_out, hierarchy)
         self.mt, self.nr = mt, nr
         eta_wedge = np.asarray(eta_wedge, dtype=np.float64)
@@ -167,14 +210,15 @@ class StokesOracle:
         self.B = (self.P.T @ self.Bf).tocsr()               # B = P^T B_f
         self.n_u = nu
         self.n_p = self.P.shape[1]
-        bnd = np.repeat(m.boundary_nodes(), 3)
-        self.dirichlet = bnd
-        d = (~bnd).astype(np.float64)
-        D = sp.diags(d)
-        I_D = sp.diags(1.0 - d)
-        self.A_D = (D @ self.A @ D + I_D).tocsr()
-        self.BT_D = (D @ self.B.T).tocsr()
-        self.B_D = (self.B @ D).tocsr()
+        self.bc = tuple(bc)
+        Pm, Nm = boundary_projections(m, self.bc)
+        self.P_bc, self.N_bc = Pm, Nm
+        # DoFs with a no-slip (identity) row
+        k = np.repeat(np.tile(np.arange(nr + 1), m.n_lat), 3)
+        self.dirichlet = ((k == 0) & (self.bc[0] == "noslip")) | ((k == nr) & (self.bc[1] == "noslip"))
+        self.A_D = (Pm @ self.A @ Pm + Nm).tocsr()
+        self.BT_D = (Pm @ self.B.T).tocsr()
+        self.B_D = (self.B @ Pm).tocsr()
         self.K = sp.bmat([[self.A_D, self.BT_D], [self.B_D, None]], format="csr")
 
     # -- products -----------------------------------------------------------

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TNG_LIB", os.path.join(HERE, "libtng.so"))
 
 OP_A, OP_BT, OP_B, OP_DIRICHLET = 1, 2, 4, 8
+OP_FREESLIP_INNER, OP_FREESLIP_OUTER = 16, 32
 F64, F32 = 0, 1
 
 _lib = None
@@ -42,6 +43,9 @@ def lib():
         "tng_stokes_apply": [_vp, _vp, C.c_int, C.c_int, C.c_uint, C.c_double, _vp, C.POINTER(_vp), _vp,
                              C.POINTER(_vp), _vp],
         "tng_interface_sum": [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)],
+        "tng_stream_copy": [_vp, _vp, _vp, C.c_size_t],
+        "tng_check_device_buffer": [_vp, _vp, C.c_size_t],
+        "tng_stokes_apply_layout": [_vp, _vp, C.c_int, C.c_int, C.c_uint, C.c_double, C.POINTER(C.c_int)],
         "tng_ctx_profile": [_vp, C.c_int],
         "tng_ctx_kernel_stats": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
         "tng_ctx_kernel_stats_at": [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_double),
@@ -106,6 +110,46 @@ def _prec(t):
     if t.dtype == torch.float32:
         return F32
     raise TypeError("fields must be float32 or float64")
+
+
+def _chk(ctx, t, dtype, numel: int, name: str):
+    """A field argument must be a contiguous tensor of `dtype` with `numel`
+    values on the context's GPU (the library cannot see a torch tensor's device,
+    dtype or size; a wrong one would be read as garbage or out of bounds)."""
+    if t is None:
+        return
+    if not getattr(t, "is_cuda", False) or t.device.index != ctx.device:
+        raise TypeError(f"{name} must be a tensor on cuda:{ctx.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, the call uses {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} values, the mesh level needs {numel}")
+
+
+def _chk3(ctx, ts, dtype, numel: int, name: str):
+    if ts is None:
+        return
+    if len(ts) != 3:
+        raise ValueError(f"{name} must hold three components")
+    for c in range(3):
+        _chk(ctx, ts[c], dtype, numel, f"{name}[{c}]")
+
+
+def _counts(mesh, level: int) -> dict:
+    cache = mesh.__dict__.setdefault("_counts", {})
+    if level not in cache:
+        cache[level] = mesh.counts(level)
+    return cache[level]
+
+
+def _nodes(mesh, level: int) -> int:
+    return _counts(mesh, level)["node_slots"]
+
+
+def _wedges(mesh, level: int) -> int:
+    return _counts(mesh, level)["wedges"]
 
 
 class Context:
@@ -223,38 +267,87 @@ def stokes_apply(ctx: Context, mesh: Mesh, level: int, flags: int, eta, u, p, y_
     control to the viscous block."""
     ref = next(t for t in (u[0] if u is not None else None, y_u[0] if y_u is not None else None,
                            p, y_p) if t is not None)
+    dt = ref.dtype
+    nu = _nodes(mesh, level)
+    _chk(ctx, eta, dt, _wedges(mesh, level), "eta")
+    _chk3(ctx, u, dt, nu, "u")
+    _chk3(ctx, y_u, dt, nu, "y_u")
+    if p is not None or y_p is not None:
+        np_ = _nodes(mesh, level + 1)
+        _chk(ctx, p, dt, np_, "p")
+        _chk(ctx, y_p, dt, np_, "y_p")
     check(lib().tng_stokes_apply(ctx.h, mesh.h, level, _prec(ref), flags, float(hg_alpha), _ptr(eta), _ptr3(u),
                                  _ptr(p), _ptr3(y_u), _ptr(y_p)))
 
 
+def stream_copy(ctx: Context, src, dst):
+    """dst = src with the library's plain streaming copy kernel (a bandwidth probe)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst differ in size")
+    for name, t in (("src", src), ("dst", dst)):
+        if not t.is_cuda or t.device.index != ctx.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor on cuda:{ctx.device}")
+    check(lib().tng_stream_copy(ctx.h, _ptr(src), _ptr(dst), src.numel() * src.element_size()))
+
+
+def check_device_buffer(ctx: Context, ptr: int, nbytes: int):
+    """The library's own check of a device pointer (raises TngError if refused)."""
+    check(lib().tng_check_device_buffer(ctx.h, _vp(ptr), nbytes))
+
+
+def stokes_apply_layout(ctx: Context, mesh: Mesh, level: int, flags: int, f64: bool, hg_alpha: float = 0.0) -> dict:
+    """Decomposition tng_stokes_apply uses for these arguments (launches nothing)."""
+    out = (C.c_int * 8)()
+    check(lib().tng_stokes_apply_layout(ctx.h, mesh.h, level, F64 if f64 else F32, flags, float(hg_alpha), out))
+    keys = ("tile", "rs", "cpl", "wg", "ntile", "bands", "nchunk", "range")
+    return dict(zip(keys, [int(v) for v in out]))
+
+
 def interface_sum(ctx: Context, mesh: Mesh, level: int, fields, mode: int = 0):
+    for c, f in enumerate(fields):
+        _chk(ctx, f, fields[0].dtype, _nodes(mesh, level), f"fields[{c}]")
     arr = (_vp * len(fields))(*[f.data_ptr() for f in fields])
     check(lib().tng_interface_sum(ctx.h, mesh.h, level, _prec(fields[0]), mode, len(fields), arr))
 
 
 def eta_from_temperature(ctx: Context, mesh: Mesh, level: int, T, E: float, F: float, eta_out):
     """Per-wedge viscosity exp(-E Tbar + F (1 - r_m)) from a nodal temperature field."""
+    _chk(ctx, T, T.dtype, _nodes(mesh, level), "T")
+    _chk(ctx, eta_out, T.dtype, _wedges(mesh, level), "eta_out")
     check(lib().tng_eta_from_temperature(ctx.h, mesh.h, level, _prec(T), _ptr(T), E, F,
                                          _ptr(eta_out)))
 
 
 def eta_coarsen(ctx: Context, mesh: Mesh, fine_level: int, eta_fine, eta_coarse):
+    _chk(ctx, eta_fine, eta_fine.dtype, _wedges(mesh, fine_level), "eta_fine")
+    _chk(ctx, eta_coarse, eta_fine.dtype, _wedges(mesh, fine_level + 1), "eta_coarse")
     check(lib().tng_eta_coarsen(ctx.h, mesh.h, fine_level, _prec(eta_fine), _ptr(eta_fine),
                                 _ptr(eta_coarse)))
 
 
 def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag, hg_alpha: float = 0.0):
     """Diagonal of the viscous block (Dirichlet rows 1) into diag ([3, ...])."""
+    _chk(ctx, eta, eta.dtype, _wedges(mesh, level), "eta")
+    _chk3(ctx, diag, eta.dtype, _nodes(mesh, level), "diag")
     check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag)))
 
 
 def pressure_mass(ctx: Context, mesh: Mesh, level: int, eta, mass):
     """Lumped inverse-viscosity pressure mass on level + 1."""
+    _chk(ctx, eta, eta.dtype, _wedges(mesh, level), "eta")
+    _chk(ctx, mass, eta.dtype, _nodes(mesh, level + 1), "mass")
     check(lib().tng_pressure_mass(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr(mass)))
+
+
+def _chk_smooth(ctx, mesh, level, eta, diag, b, x):
+    _chk(ctx, eta, eta.dtype, _wedges(mesh, level), "eta")
+    for name, v in (("diag", diag), ("b", b), ("x", x)):
+        _chk3(ctx, v, eta.dtype, _nodes(mesh, level), name)
 
 
 def smooth(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, steps: int,
            lmin: float, lmax: float, hg_alpha: float = 0.0):
+    _chk_smooth(ctx, mesh, level, eta, diag, b, x)
     check(lib().tng_smooth(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag), _ptr3(b),
                            _ptr3(x), degree, steps, lmin, lmax))
 
@@ -262,15 +355,20 @@ def smooth(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, s
 def smooth_noalloc(ctx: Context, mesh: Mesh, level: int, eta, diag, b, x, degree: int, steps: int,
                    lmin: float, lmax: float, hg_alpha: float = 0.0):
     """smooth() with the library's fixed device scratch array: no allocation, no synchronisation."""
+    _chk_smooth(ctx, mesh, level, eta, diag, b, x)
     check(lib().tng_smooth_noalloc(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag),
                                    _ptr3(b), _ptr3(x), degree, steps, lmin, lmax))
 
 
 def restrict(ctx: Context, mesh: Mesh, fine_level: int, f, c):
+    _chk3(ctx, f, f[0].dtype, _nodes(mesh, fine_level), "f")
+    _chk3(ctx, c, f[0].dtype, _nodes(mesh, fine_level + 1), "c")
     check(lib().tng_restrict(ctx.h, mesh.h, fine_level, _prec(f[0]), _ptr3(f), _ptr3(c)))
 
 
 def prolong(ctx: Context, mesh: Mesh, fine_level: int, c, f):
+    _chk3(ctx, c, c[0].dtype, _nodes(mesh, fine_level + 1), "c")
+    _chk3(ctx, f, c[0].dtype, _nodes(mesh, fine_level), "f")
     check(lib().tng_prolong(ctx.h, mesh.h, fine_level, _prec(c[0]), _ptr3(c), _ptr3(f)))
 
 
@@ -299,10 +397,16 @@ class StepInfo(C.Structure):
 
 
 def rhs_buoyancy(ctx: Context, mesh: Mesh, level: int, T, Ra: float, f):
+    _chk(ctx, T, T.dtype, _nodes(mesh, level), "T")
+    _chk3(ctx, f, T.dtype, _nodes(mesh, level), "f")
     check(lib().tng_rhs_buoyancy(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _ptr3(f)))
 
 
 def energy_apply(ctx: Context, mesh: Mesh, level: int, u, dt: float, T, y):
+    n = _nodes(mesh, level)
+    _chk3(ctx, u, T.dtype, n, "u")
+    _chk(ctx, T, T.dtype, n, "T")
+    _chk(ctx, y, T.dtype, n, "y")
     check(lib().tng_energy_apply(ctx.h, mesh.h, level, _prec(T), _ptr3(u), dt, _ptr(T), _ptr(y)))
 
 
@@ -322,10 +426,22 @@ class StokesSolver:
         check(lib().tng_stokes_solver_create(ctx.h, mesh.h, C.byref(o), C.byref(h)))
         self.h = h
 
+    def _chk_f64(self, t, numel, name):
+        import torch
+        _chk(self.ctx, t, torch.float64, numel, name)
+
     def setup(self, eta):
+        self._chk_f64(eta, _wedges(self.mesh, 0), "eta")
         check(lib().tng_stokes_solver_setup(self.h, _ptr(eta)))
 
     def solve(self, f, g, u, p, eta=None, raise_on_fail: bool = True) -> dict:
+        import torch
+        nu, np_ = _nodes(self.mesh, 0), _nodes(self.mesh, 1)
+        self._chk_f64(eta, _wedges(self.mesh, 0), "eta")
+        _chk3(self.ctx, f, torch.float64, nu, "f")
+        _chk3(self.ctx, u, torch.float64, nu, "u")
+        self._chk_f64(g, np_, "g")
+        self._chk_f64(p, np_, "p")
         info = SolveInfo()
         rc = lib().tng_stokes_solve(self.h, _ptr(eta), _ptr3(f), _ptr(g), _ptr3(u), _ptr(p), C.byref(info))
         out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}

@@ -1,5 +1,6 @@
 // C entry points: argument validation and dispatch to the launchers.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <iterator>
@@ -18,6 +19,43 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 void clear_last_error() { g_last_error.clear(); }
 
 void build_mesh(tng_mesh* mesh, int levels);
+
+void require_device(const tng_ctx* ctx, const void* p, size_t bytes, const char* what) {
+    TNG_REQUIRE(p != nullptr, std::string(what) + " is NULL");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(TNG_E_INVAL, std::string(what) + " is not device memory of the context's GPU");
+    }
+    if (at.type != hipMemoryTypeDevice || at.isManaged)
+        throw Error(TNG_E_INVAL, std::string(what) +
+                                     " must be device memory (hipMalloc); host, pinned or managed memory is refused");
+    if (at.device != ctx->device)
+        throw Error(TNG_E_INVAL, std::string(what) + " lives on device " + std::to_string(at.device) +
+                                     ", the context uses device " + std::to_string(ctx->device));
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base != nullptr) {
+        const char* b = static_cast<const char*>(base);
+        const char* q = static_cast<const char*>(p);
+        if (q + bytes > b + size)
+            throw Error(TNG_E_INVAL, std::string(what) + " is too small: needs " + std::to_string(bytes) +
+                                         " bytes, its allocation ends " + std::to_string(b + size - q) +
+                                         " bytes after it");
+    } else {
+        (void)hipGetLastError();
+    }
+}
+
+namespace {
+size_t elsize(tng_prec prec) { return prec == TNG_F64 ? sizeof(double) : sizeof(float); }
+size_t node_bytes(const Level& L, tng_prec prec) { return (size_t)L.node_slots() * elsize(prec); }
+size_t wedge_bytes(const Level& L, tng_prec prec) { return (size_t)(2 * L.cells()) * elsize(prec); }
+void require_vel(const tng_ctx* ctx, const void* const v[3], const Level& L, tng_prec prec, const char* what) {
+    TNG_REQUIRE(v != nullptr, std::string(what) + " is NULL");
+    for (int c = 0; c < 3; ++c) require_device(ctx, v[c], node_bytes(L, prec), what);
+}
+}  // namespace
 
 ScopedKernelTimer::ScopedKernelTimer(const tng_ctx* ctx, const char* kernel, const char* detail)
     : ctx_(const_cast<tng_ctx*>(ctx)) {
@@ -174,6 +212,8 @@ int tng_eta_from_temperature(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(T != nullptr && eta_wedge != nullptr, "T or eta_wedge is NULL");
     TNG_REQUIRE(std::isfinite(E) && std::isfinite(F), "E and F must be finite");
+    tng::require_device(ctx, T, tng::node_bytes(L, prec), "T");
+    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
     TNG_HIP(hipSetDevice(ctx->device));
     tng::launch_eta_from_T(ctx, L, prec, T, eta_wedge, E, F);
     TNG_API_END
@@ -182,10 +222,12 @@ int tng_eta_from_temperature(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_
 int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec prec,
                     const void* eta_fine, void* eta_coarse) {
     TNG_API_BEGIN
-    tng::device_level(ctx, mesh, fine_level);
+    const tng::Level& Lf = tng::device_level(ctx, mesh, fine_level);
     const tng::Level& Lc = tng::device_level(ctx, mesh, fine_level + 1);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(eta_fine != nullptr && eta_coarse != nullptr, "eta pointer is NULL");
+    tng::require_device(ctx, eta_fine, tng::wedge_bytes(Lf, prec), "eta_fine");
+    tng::require_device(ctx, eta_coarse, tng::wedge_bytes(Lc, prec), "eta_coarse");
     TNG_HIP(hipSetDevice(ctx->device));
     tng::launch_eta_coarsen(ctx, Lc, prec, eta_fine, eta_coarse);
     TNG_API_END
@@ -273,7 +315,7 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE((op_flags & ~15u) == 0, "unknown op_flags bits");
+    TNG_REQUIRE((op_flags & ~63u) == 0, "unknown op_flags bits");
     const bool doA = op_flags & TNG_OP_A, doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
     TNG_REQUIRE(doA || doBT || doB, "op_flags selects no operator block");
     const tng::Level* Lp = nullptr;
@@ -291,8 +333,55 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     if (doB) TNG_REQUIRE(y_p != nullptr, "y_p is NULL");
     if ((op_flags & TNG_OP_DIRICHLET) && doA)
         TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
+    if (doA) tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
+    if (doA || doB) tng::require_vel(ctx, u, L, prec, "u");
+    if (doA || doBT) tng::require_vel(ctx, y_u, L, prec, "y_u");
+    if (doBT) tng::require_device(ctx, p, tng::node_bytes(*Lp, prec), "p");
+    if (doB) tng::require_device(ctx, y_p, tng::node_bytes(*Lp, prec), "y_p");
     TNG_HIP(hipSetDevice(ctx->device));
     tng::launch_stokes_apply(ctx, L, Lp, prec, op_flags, hg_alpha, eta_wedge, u, p, y_u, y_p);
+    TNG_API_END
+}
+
+int tng_stokes_apply_layout(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, unsigned op_flags,
+                            double hg_alpha, int out[8]) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(out != nullptr, "out is NULL");
+    TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE((op_flags & ~63u) == 0, "unknown op_flags bits");
+    const bool doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
+    TNG_REQUIRE(op_flags & 7u, "op_flags selects no operator block");
+    const tng::Level* Lp = nullptr;
+    if (doBT || doB) {
+        TNG_REQUIRE(level + 1 < (int)mesh->lv.size(), "pressure level (level + 1) not built");
+        Lp = &mesh->lv[level + 1];
+        TNG_REQUIRE(L.m % 2 == 0 && L.n % 2 == 0, "B/B^T need even m and n");
+    }
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::stokes_apply_layout(ctx, L, Lp, prec, op_flags, hg_alpha, out);
+    TNG_API_END
+}
+
+int tng_check_device_buffer(tng_ctx* ctx, const void* p, size_t bytes) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    tng::require_device(ctx, p, bytes, "buffer");
+    TNG_API_END
+}
+
+int tng_stream_copy(tng_ctx* ctx, const void* src, void* dst, size_t bytes) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(ctx != nullptr, "ctx is NULL");
+    TNG_REQUIRE(bytes > 0 && bytes % 16 == 0, "bytes must be a positive multiple of 16");
+    TNG_REQUIRE(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, "src and dst must be 16-byte aligned");
+    tng::require_device(ctx, src, bytes, "src");
+    tng::require_device(ctx, dst, bytes, "dst");
+    TNG_REQUIRE((const char*)src + bytes <= (const char*)dst || (const char*)dst + bytes <= (const char*)src,
+                "src and dst overlap");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::launch_stream_copy(ctx, src, dst, bytes);
     TNG_API_END
 }
 
@@ -303,7 +392,7 @@ int tng_interface_sum(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(mode == 0 || mode == 1, "mode must be 0 (sum) or 1 (copy)");
     TNG_REQUIRE(f != nullptr && ncomp >= 1 && ncomp <= 4, "bad field list");
-    for (int c = 0; c < ncomp; ++c) TNG_REQUIRE(f[c] != nullptr, "field pointer is NULL");
+    for (int c = 0; c < ncomp; ++c) tng::require_device(ctx, f[c], tng::node_bytes(L, prec), "field");
     TNG_HIP(hipSetDevice(ctx->device));
     tng::launch_interface(ctx, L, prec, mode, ncomp, f);
     TNG_API_END
@@ -316,6 +405,8 @@ int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(T && f && f[0] && f[1] && f[2], "NULL argument");
     TNG_REQUIRE(std::isfinite(Ra), "Ra must be finite");
+    tng::require_device(ctx, T, tng::node_bytes(L, prec), "T");
+    tng::require_vel(ctx, f, L, prec, "f");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         double* ff[3] = {(double*)f[0], (double*)f[1], (double*)f[2]};
@@ -334,6 +425,9 @@ int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(u && u[0] && u[1] && u[2] && T && y, "NULL argument");
     TNG_REQUIRE(dt > 0 && std::isfinite(dt), "dt must be positive");
+    tng::require_vel(ctx, u, L, prec, "u");
+    tng::require_device(ctx, T, tng::node_bytes(L, prec), "T");
+    tng::require_device(ctx, y, tng::node_bytes(L, prec), "y");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         const double* uu[3] = {(const double*)u[0], (const double*)u[1], (const double*)u[2]};
@@ -351,6 +445,8 @@ int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, con
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(eta_wedge && diag && diag[0] && diag[1] && diag[2], "NULL argument");
+    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
+    tng::require_vel(ctx, diag, L, prec, "diag");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         double* d[3] = {(double*)diag[0], (double*)diag[1], (double*)diag[2]};
@@ -370,6 +466,8 @@ int tng_pressure_mass(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(eta_wedge && mass, "NULL argument");
     TNG_REQUIRE(L.m % 2 == 0 && L.n % 2 == 0, "needs even m and n");
+    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
+    tng::require_device(ctx, mass, tng::node_bytes(Lp, prec), "mass");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64)
         tng::mg_pmass<double>(ctx, L, Lp, (const double*)eta_wedge, (double*)mass);
@@ -386,6 +484,8 @@ int tng_restrict(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pr
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(f && c && f[0] && f[1] && f[2] && c[0] && c[1] && c[2], "NULL argument");
     TNG_REQUIRE(Lf.m % 2 == 0 && Lf.n % 2 == 0, "needs even m and n");
+    tng::require_vel(ctx, f, Lf, prec, "f");
+    tng::require_vel(ctx, c, Lc, prec, "c");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         const double* ff[3] = {(const double*)f[0], (const double*)f[1], (const double*)f[2]};
@@ -403,10 +503,12 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
                 void* const f[3]) {
     TNG_API_BEGIN
     const tng::Level& Lf = tng::device_level(ctx, mesh, fine_level);
-    tng::device_level(ctx, mesh, fine_level + 1);
+    const tng::Level& Lc = tng::device_level(ctx, mesh, fine_level + 1);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(f && c && f[0] && f[1] && f[2] && c[0] && c[1] && c[2], "NULL argument");
     TNG_REQUIRE(Lf.m % 2 == 0 && Lf.n % 2 == 0, "needs even m and n");
+    tng::require_vel(ctx, c, Lc, prec, "c");
+    tng::require_vel(ctx, f, Lf, prec, "f");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64) {
         const double* cc[3] = {(const double*)c[0], (const double*)c[1], (const double*)c[2]};
@@ -430,6 +532,10 @@ int tng_smooth(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, con
     for (int c = 0; c < 3; ++c) TNG_REQUIRE(diag[c] && b[c] && x[c], "NULL field pointer");
     TNG_REQUIRE(degree >= 1 && steps >= 0, "bad degree or steps");
     TNG_REQUIRE(lmin > 0 && lmax > lmin, "need 0 < lmin < lmax");
+    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
+    tng::require_vel(ctx, diag, L, prec, "diag");
+    tng::require_vel(ctx, b, L, prec, "b");
+    tng::require_vel(ctx, x, L, prec, "x");
     TNG_HIP(hipSetDevice(ctx->device));
     if (prec == TNG_F64)
         tng::smooth_t<double>(ctx, L, eta_wedge, hg_alpha, diag, b, x, degree, steps, lmin, lmax);

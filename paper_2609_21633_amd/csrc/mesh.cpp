@@ -203,6 +203,9 @@ void build_level(Level& L, int m, int n, double r_in, double r_out, bool device)
     TNG_HIP(hipMemcpy(L.inv_mult64.p, im.data(), im.size() * sizeof(double), hipMemcpyHostToDevice));
     L.unit64.alloc(L.unit.size());
     TNG_HIP(hipMemcpy(L.unit64.p, L.unit.data(), L.unit.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> u32(L.unit.begin(), L.unit.end());
+    L.unit32.alloc(u32.size());
+    TNG_HIP(hipMemcpy(L.unit32.p, u32.data(), u32.size() * sizeof(float), hipMemcpyHostToDevice));
     L.inv_mult32.alloc(im32.size());
     TNG_HIP(hipMemcpy(L.inv_mult32.p, im32.data(), im32.size() * sizeof(float), hipMemcpyHostToDevice));
 }

@@ -107,6 +107,15 @@ extern "C" int tng_smooth_noalloc(tng_ctx* ctx, const tng_mesh* mesh, int level,
     TNG_REQUIRE(steps >= 0, "steps must be >= 0");
     TNG_REQUIRE(lmin > 0 && lmax > lmin, "need 0 < lmin < lmax");
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
+    {
+        const size_t el = prec == TNG_F64 ? sizeof(double) : sizeof(float);
+        tng::require_device(ctx, eta_wedge, (size_t)(2 * L.cells()) * el, "eta_wedge");
+        for (int c = 0; c < 3; ++c) {
+            tng::require_device(ctx, diag[c], (size_t)L.node_slots() * el, "diag");
+            tng::require_device(ctx, b[c], (size_t)L.node_slots() * el, "b");
+            tng::require_device(ctx, x[c], (size_t)L.node_slots() * el, "x");
+        }
+    }
     const size_t need = tng::noalloc_smooth_bytes(L.node_slots(), prec);
     if (need > tng::NOALLOC_SCRATCH_BYTES)
         throw tng::Error(TNG_E_INVAL, "level too large for the no-allocation smoother: needs " +

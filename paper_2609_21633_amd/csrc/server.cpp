@@ -56,6 +56,8 @@ struct ServerLevel {
     long long bytes_per_slot = -1;
     int cap_slots = 0;                         // max_slots, lowered if the device refuses a slot
     int release_wanted = 0;                    // idle slots another level asked this one to free
+    bool room_asked = false;                   // this level has asked the others for room since
+                                               // the slots last changed (no repeated asking)
     int failed = TNG_OK;                       // the level's stream failed: no further requests
     std::thread driver;
 };
@@ -93,8 +95,22 @@ bool admissible(const tng_server* srv, const ServerLevel& lv) {
     return live_slots(lv) < lv.cap_slots && lv.bytes_per_slot <= (long long)srv->budget - srv->bytes_in_use;
 }
 
+// lv has queued work but no slot and no room for one, and has not asked the
+// other levels for room since the slots last changed (lock held).
+bool wants_room(const tng_server* srv, const ServerLevel& lv) {
+    return !lv.queue.empty() && lv.failed == TNG_OK && live_slots(lv) == 0 && lv.cap_slots > 0 && !lv.room_asked &&
+           lv.bytes_per_slot > (long long)srv->budget - srv->bytes_in_use;
+}
+
+// Slots changed (some became idle or were freed): levels waiting for room may ask again.
+void slots_changed(tng_server* srv) {
+    for (auto& other : srv->levels) other.room_asked = false;
+    srv->cv_work.notify_all();
+}
+
 // Asks another level to free an idle slot for lv, which has none (lock held).
 void request_room(tng_server* srv, ServerLevel& lv) {
+    lv.room_asked = true;
     if (live_slots(lv) != 0) return;
     for (auto& other : srv->levels) {
         if (&other == &lv || !other.queue.empty() || other.release_wanted > 0 || other.failed != TNG_OK) continue;
@@ -120,9 +136,12 @@ void driver(tng_server* srv, ServerLevel* lv) {
     std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
         srv->cv_work.wait(lk, [&] {
-            return srv->stop || B.running() > 0 || lv->release_wanted > 0 || admissible(srv, *lv);
+            return srv->stop || B.running() > 0 || lv->release_wanted > 0 || admissible(srv, *lv) ||
+                   wants_room(srv, *lv);
         });
         if (srv->stop && B.running() == 0) return;
+        // a level without slots whose request cannot fit asks the others to release an idle one
+        if (wants_room(srv, *lv)) request_room(srv, *lv);
         // free idle slots another level is waiting for
         while (lv->release_wanted > 0) {
             lv->release_wanted -= 1;
@@ -140,7 +159,7 @@ void driver(tng_server* srv, ServerLevel* lv) {
                 lv->job.erase(lv->job.begin() + i);
                 srv->bytes_in_use -= lv->bytes_per_slot;
             }
-            srv->cv_work.notify_all();
+            slots_changed(srv);
         }
         // admit queued requests at this step boundary
         while (!srv->stop && !lv->queue.empty()) {
@@ -236,7 +255,7 @@ void driver(tng_server* srv, ServerLevel* lv) {
         }
         if (!fin.empty()) {
             srv->cv_done.notify_all();
-            srv->cv_work.notify_all();
+            slots_changed(srv);   // idle slots: a level waiting for room may ask again
         }
     }
 }
@@ -299,6 +318,14 @@ int tng_server_submit(tng_server* srv, int level_idx, const double* T, double lo
     TNG_API_BEGIN
     TNG_REQUIRE(srv && T && u_out && u_out[0] && u_out[1] && u_out[2] && p_out && ticket, "NULL argument");
     TNG_REQUIRE(level_idx >= 0 && level_idx < (int)srv->levels.size(), "level_idx out of range");
+    {
+        const tng::Level& L = srv->levels[level_idx].mesh->lv[0];
+        const tng::Level& Lp = srv->levels[level_idx].mesh->lv[1];
+        const size_t nsb = (size_t)L.node_slots() * sizeof(double);
+        tng::require_device(srv->ctx, T, nsb, "T");
+        for (int c = 0; c < 3; ++c) tng::require_device(srv->ctx, u_out[c], nsb, "u_out");
+        tng::require_device(srv->ctx, p_out, (size_t)Lp.node_slots() * sizeof(double), "p_out");
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
     ServerLevel& lv = srv->levels[level_idx];
     if (lv.failed != TNG_OK) throw Error(lv.failed, "this level's device stream failed; it takes no requests");

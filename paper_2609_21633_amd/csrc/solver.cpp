@@ -1261,6 +1261,7 @@ extern "C" {
 int tng_stokes_solver_setup(tng_solver* s, const double* eta_wedge) {
     TNG_API_BEGIN
     TNG_REQUIRE(s != nullptr && eta_wedge != nullptr, "NULL argument");
+    tng::require_device(s->ctx, eta_wedge, 2 * tng::L0(s).cells() * sizeof(double), "eta_wedge");
     TNG_HIP(hipSetDevice(s->ctx->device));
     tng::setup_viscosity(s, eta_wedge);
     TNG_API_END
@@ -1271,6 +1272,16 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     TNG_API_BEGIN
     TNG_REQUIRE(s != nullptr && f != nullptr && u != nullptr && p != nullptr, "NULL argument");
     for (int c = 0; c < 3; ++c) TNG_REQUIRE(f[c] != nullptr && u[c] != nullptr, "NULL field pointer");
+    {
+        const size_t nsb = (size_t)s->ns0 * sizeof(double), npb = (size_t)s->np * sizeof(double);
+        if (eta_wedge) tng::require_device(s->ctx, eta_wedge, 2 * tng::L0(s).cells() * sizeof(double), "eta_wedge");
+        for (int c = 0; c < 3; ++c) {
+            tng::require_device(s->ctx, f[c], nsb, "f");
+            tng::require_device(s->ctx, u[c], nsb, "u");
+        }
+        if (g) tng::require_device(s->ctx, g, npb, "g");
+        tng::require_device(s->ctx, p, npb, "p");
+    }
     TNG_HIP(hipSetDevice(s->ctx->device));
     auto t0 = std::chrono::steady_clock::now();
     if (eta_wedge) tng::setup_viscosity(s, eta_wedge);
@@ -1363,6 +1374,13 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     TNG_REQUIRE(std::isfinite(o->Ra) && std::isfinite(o->E) && std::isfinite(o->F), "non-finite parameter");
     TNG_REQUIRE(o->dt > 0 || o->courant > 0, "need dt > 0 or courant > 0");
     TNG_REQUIRE(o->energy_restart >= 1 && o->energy_restart + 1 <= tng::MAX_MDOT, "energy_restart in 1..23");
+    {
+        const size_t nsb = (size_t)s->ns0 * sizeof(double);
+        if (H) tng::require_device(s->ctx, H, nsb, "H");
+        tng::require_device(s->ctx, T, nsb, "T");
+        for (int c = 0; c < 3; ++c) tng::require_device(s->ctx, u[c], nsb, "u");
+        tng::require_device(s->ctx, p, (size_t)s->np * sizeof(double), "p");
+    }
     TNG_HIP(hipSetDevice(s->ctx->device));
     auto t0 = std::chrono::steady_clock::now();
     const tng::Level& L = tng::L0(s);
@@ -1410,6 +1428,11 @@ int tng_stokes_solver_vcycle(tng_solver* s, const void* const b[3], void* const 
     TNG_API_BEGIN
     TNG_REQUIRE(s != nullptr && b != nullptr && x != nullptr, "NULL argument");
     TNG_REQUIRE(s->ready, "call tng_stokes_solver_setup first");
+    for (int c = 0; c < 3; ++c) {
+        const size_t vb = (size_t)s->ns0 * (s->opts.mixed ? sizeof(float) : sizeof(double));
+        tng::require_device(s->ctx, b[c], vb, "b");
+        tng::require_device(s->ctx, x[c], vb, "x");
+    }
     TNG_HIP(hipSetDevice(s->ctx->device));
     const long long ns = s->ns0;
     hipStream_t st = s->ctx->stream;

@@ -24,7 +24,10 @@
 // complete; nodes on the seams between tiles (node columns that are multiples
 // of TC) and between workgroup radial ranges (columns longer than RS
 // stretches) receive exactly two partial sums, added with atomics to memory
-// zeroed beforehand, which keeps the result independent of timing.
+// zeroed beforehand; two partials sum to the same value in either order, so
+// velocity results do not depend on timing.  Coarse pressure nodes where a
+// band seam crosses a tile seam receive up to four partials, whose order (and
+// so the last bit of the divergence block) can vary from run to run.
 //
 // The divergence block is reduced per coarse pressure node through LDS, kept
 // by one owner thread per node and flushed once a coarse row is complete.
@@ -64,7 +67,9 @@ struct BandArgs {
     int ntile, nband, nchunk;
     T r_in, dr;
     T hg;          // hourglass control: alpha * 5/81 (0 without)
-    int dirichlet;
+    int ns_in, ns_out;   // no-slip (zero) velocity on the inner / outer sphere
+    int fs;              // free slip: bit 0 inner sphere, bit 1 outer sphere
+    const T* __restrict__ unit;   // [10][m+1][m+1][3] node unit vectors (free slip)
 };
 
 template <typename T>
@@ -135,7 +140,9 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 // BATCH: copy blockIdx.z works on the fields of slot z of a batch (mesh
 // geometry shared); otherwise sb is unused.
 // WG: waves per workgroup (4 or 8); a workgroup covers WG / RS cell columns.
-template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG>
+// FS: free slip on a sphere (a.fs), staged boundary velocities projected onto the
+// tangent plane; the other kernels compile without that path.
+template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG, bool FS>
 __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
     if constexpr (BATCH) {
@@ -247,8 +254,37 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
         const int e = h * KC + (lane + 64 * t) / DW;    // value moved by this lane
         const int k = kc0 + e;
         lok[t] = LOAD_U && e < KW && k <= kcend && (t < NCH - 1 || h == RS - 1) &&
-                 !(a.dirichlet && (k == 0 || k == n));
+                 !((a.ns_in && k == 0) || (a.ns_out && k == n));
     }
+    // free slip: this lane moved the first dword of a node value on a free-slip
+    // sphere in piece t, and projects that node's staged velocity onto the
+    // sphere's tangent plane once its loads have landed
+    bool fsb[NCH];
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+        const int e = h * KC + (lane + 64 * t) / DW;
+        const int k = kc0 + e;
+        fsb[t] = FS && lok[t] && ((lane + 64 * t) % DW == 0) &&
+                 (((a.fs & 1) && k == 0) || ((a.fs & 2) && k == n));
+    }
+    // u <- u - rhat (rhat . u) at the staged boundary nodes of node row jrow of
+    // ring column wl (library column icol); waves touch only values they staged
+    auto project_staged = [&](int icol, int jrow, int slot, int wl) {
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            if (!fsb[t]) continue;
+            const int e = h * KC + (lane + 64 * t) / DW;
+            const T* nv = a.unit + (((unsigned)d * (m + 1) + icol) * (m + 1) + jrow) * 3u;
+            const T n0 = nv[0], n1 = nv[1], n2 = nv[2];
+            T* x0 = &ring[slot][wl][0][e];
+            T* x1 = &ring[slot][wl][1][e];
+            T* x2 = &ring[slot][wl][2][e];
+            const T dn = n0 * *x0 + n1 * *x1 + n2 * *x2;
+            *x0 -= dn * n0;
+            *x1 -= dn * n1;
+            *x2 -= dn * n2;
+        }
+    };
     auto stage = [&](unsigned col, int jrow, int slot, int wl) {
         const unsigned base = col + (unsigned)jrow * ldj + (unsigned)k0;
         const T* const src[3] = {a.u0 + base, a.u1 + base, a.u2 + base};
@@ -355,6 +391,14 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     }
     load_row(jfirst, rin);
     __builtin_amdgcn_s_waitcnt(0);   // staged rows have landed in LDS
+    if constexpr (FS && LOAD_U) {
+        project_staged(i, jfirst, sj, wc);
+        project_staged(i, jfirst + 1, sj1, wc);
+        if (xw) {
+            project_staged(i0 + TI, jfirst, sj, TI);
+            project_staged(i0 + TI, jfirst + 1, sj1, TI);
+        }
+    }
     __syncthreads();
 
     // one cell row: rows alternate between the two register sets, so that the
@@ -648,7 +692,13 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                 }
             }
         }
-        if (LOAD_U && pre) __builtin_amdgcn_s_waitcnt(0);   // row j+2 has landed in LDS
+        if (LOAD_U && pre) {
+            __builtin_amdgcn_s_waitcnt(0);   // row j+2 has landed in LDS
+            if constexpr (FS) {
+                project_staged(i, j + 2, sj2, wc);
+                if (xw) project_staged(i0 + TI, j + 2, sj2, TI);
+            }
+        }
         __syncthreads();
         if (DO_U && owned) {
             const unsigned rowA = colA + (unsigned)j * ldj;
@@ -667,7 +717,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                     live = true;
                     seamK = (c == 0 && lane == 0 && h == 0 && kc0 > 0);   // range bottom
                 }
-                if (a.dirichlet && (k == 0 || k == n)) live = false;   // rows set afterwards
+                if ((a.ns_in && k == 0) || (a.ns_out && k == n)) live = false;   // rows set afterwards
                 if (!live) continue;
                 T v[3], vb[3];
 #pragma unroll
@@ -800,48 +850,93 @@ __global__ void pre_apply_kernel(T* yp, long long np, T* y0, T* y1, T* y2, int m
 }
 
 // The passes after the band kernel in one launch (disjoint writes, any order):
-//  1. the diamond-interface sum of the velocity copies (groups x layers; with
-//     Dirichlet rows, layers 0 and n are left to part 2),
-//  2. the Dirichlet rows y = u (viscous block present) or 0, at layers 0 and n of
-//     every lateral slot,
+//  1. the diamond-interface sum of the velocity copies (groups x layers; layers
+//     of no-slip spheres are left to part 2; on a free-slip sphere the sum is
+//     followed by the boundary row y = P y + N u, P = I - rhat rhat^T, N = rhat rhat^T),
+//  2. the boundary rows of every lateral slot at layers 0 and n: no slip y = u
+//     (viscous block present) or 0; free slip y = P y + N u (N u with the viscous
+//     block only) at slots outside duplicate groups (part 1 does the others),
 //  3. the interface sum of the pressure copies.
 struct PostArgs {
     int ngu, n1u;                       // velocity groups, layers
     const int* gpu;
     const int* gsu;
-    long long nlat_u;                   // lateral slots (Dirichlet part), 0: none
+    long long nlat_u;                   // lateral slots (boundary part), 0: none
     int ngp, n1p;                       // pressure groups, layers (0 groups: none)
     const int* gpp;
     const int* gsp;
-    int dirichlet;
+    int ns_in, ns_out;                  // no slip on the inner / outer sphere
+    int fs;                             // free slip: bit 0 inner, bit 1 outer
+    const double* inv_mult;             // [lateral slots]: 1 / copies of the node
 };
+
+// y = P y + N u at one free-slip node, rhat from the unit vector table
+template <typename T>
+__device__ __forceinline__ void freeslip_row(T (&y)[3], const T (&u)[3], const T* __restrict__ rh, bool with_u) {
+    const T n0 = rh[0], n1 = rh[1], n2 = rh[2];
+    const T dy = n0 * y[0] + n1 * y[1] + n2 * y[2];
+    const T du = with_u ? n0 * u[0] + n1 * u[1] + n2 * u[2] : T(0);
+    y[0] += (du - dy) * n0;
+    y[1] += (du - dy) * n1;
+    y[2] += (du - dy) * n2;
+}
+
 template <typename T>
 __global__ void post_apply_kernel(PostArgs q, T* y0, T* y1, T* y2, const T* __restrict__ u0,
-                                  const T* __restrict__ u1, const T* __restrict__ u2, T* yp, SlotBatch sb) {
+                                  const T* __restrict__ u1, const T* __restrict__ u2, T* yp,
+                                  const T* __restrict__ unit, SlotBatch sb) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long so = slot_off(sb);
     const long long r1 = (long long)q.ngu * q.n1u, r2 = 2 * q.nlat_u, r3 = (long long)q.ngp * q.n1p;
+    const int ktop = q.n1u - 1;
     if (t < r1) {
         const int g = (int)(t / q.n1u), k = (int)(t % q.n1u);
-        if (q.dirichlet && (k == 0 || k == q.n1u - 1)) return;
+        if ((q.ns_in && k == 0) || (q.ns_out && k == ktop)) return;
+        const bool fs = ((q.fs & 1) && k == 0) || ((q.fs & 2) && k == ktop);
         const int s0 = q.gpu[g], s1 = q.gpu[g + 1];
         T* ys[3] = {at_slot(y0, so), at_slot(y1, so), at_slot(y2, so)};
+        T acc[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T* f = ys[c];
-            T acc = f[(long long)q.gsu[s0] * q.n1u + k];
-            for (int s = s0 + 1; s < s1; ++s) acc += f[(long long)q.gsu[s] * q.n1u + k];
-            for (int s = s0; s < s1; ++s) f[(long long)q.gsu[s] * q.n1u + k] = acc;
+            const T* f = ys[c];
+            acc[c] = f[(long long)q.gsu[s0] * q.n1u + k];
+            for (int s = s0 + 1; s < s1; ++s) acc[c] += f[(long long)q.gsu[s] * q.n1u + k];
         }
+        if (fs) {
+            const long long i0 = (long long)q.gsu[s0] * q.n1u + k;
+            const T* us[3] = {at_slot(u0, so), at_slot(u1, so), at_slot(u2, so)};
+            T uu[3] = {T(0), T(0), T(0)};
+            if (us[0])
+                for (int c = 0; c < 3; ++c) uu[c] = us[c][i0];
+            freeslip_row(acc, uu, unit + 3LL * q.gsu[s0], us[0] != nullptr);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            for (int s = s0; s < s1; ++s) ys[c][(long long)q.gsu[s] * q.n1u + k] = acc[c];
         return;
     }
     t -= r1;
     if (t < r2) {
-        const long long idx = (t >> 1) * q.n1u + ((t & 1) ? q.n1u - 1 : 0);
+        const long long slot = t >> 1;
+        const bool top = t & 1;
+        const bool fs = top ? (q.fs & 2) : (q.fs & 1);
+        const bool ns = top ? q.ns_out : q.ns_in;
+        const long long idx = slot * q.n1u + (top ? ktop : 0);
         const T* us[3] = {at_slot(u0, so), at_slot(u1, so), at_slot(u2, so)};
         T* ys[3] = {at_slot(y0, so), at_slot(y1, so), at_slot(y2, so)};
+        if (fs) {
+            if (q.inv_mult[slot] < 1.0) return;     // a duplicate group: part 1
+            T y[3] = {ys[0][idx], ys[1][idx], ys[2][idx]};
+            T uu[3] = {T(0), T(0), T(0)};
+            if (us[0])
+                for (int c = 0; c < 3; ++c) uu[c] = us[c][idx];
+            freeslip_row(y, uu, unit + 3 * slot, us[0] != nullptr);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ys[c][idx] = us[c] ? us[c][idx] : T(0);
+            for (int c = 0; c < 3; ++c) ys[c][idx] = y[c];
+        } else if (ns) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ys[c][idx] = us[c] ? us[c][idx] : T(0);
+        }
         return;
     }
     t -= r2;
@@ -881,72 +976,87 @@ inline int choose_bands(int m, long long cols, long long slots) {
 
 // the solver's combinations (A, B^T, K, each viscous one also with hourglass
 // control) have a batched form; the others run one slot at a time
-template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG>
-void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb) {
-    constexpr bool BATCHABLE = (A && !BT && !B) || (!A && BT && !B) || (A && BT && B);
+template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG, bool FS>
+void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, int* bands_out) {
+    constexpr bool BATCHABLE = !FS && ((A && !BT && !B) || (!A && BT && !B) || (A && BT && B));
     const int block = args.TI * RS * 64;
     const bool batched = sb.nb > 1;
     if (ctx->apply_bands > 0) {
         args.nband = std::max(1, std::min(ctx->apply_bands, std::max(1, args.m / 2)));
     } else {
         // resident workgroups per CU of this kernel at this block size, asked once
-        static std::atomic<int> resident[2][TIC + 1];
+        static std::atomic<int> resident[2][TIC + 1];   // per instantiation (one kernel each)
         std::atomic<int>& rc = resident[batched ? 1 : 0][block / 64];
         int per_cu = rc.load(std::memory_order_relaxed);
         if (per_cu == 0) {
             if (batched)
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG, FS>, block, 0));
             else
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS>, block, 0));
             per_cu = std::max(1, per_cu);
             rc.store(per_cu, std::memory_order_relaxed);
         }
         args.nband = choose_bands(args.m, 10LL * args.ntile * args.nchunk * sb.nb, (long long)per_cu * ctx->n_cu);
     }
+    if (bands_out != nullptr) {   // layout query: report the band count, launch nothing
+        *bands_out = args.nband;
+        return;
+    }
     const long long nb = 10LL * args.ntile * args.nband * args.nchunk;
     char detail[64] = {0};
     if (ctx->profile) {
         const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
-        std::snprintf(detail, sizeof(detail), "%s/%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
-                      ops, HG ? "+HG" : "", args.m, args.n, args.nband, sb.nb > 1 ? "/batch" : "");
+        std::snprintf(detail, sizeof(detail), "%s/%s%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", FS ? "+FS" : "", args.m, args.n, args.nband, sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
     if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS>
             <<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else if constexpr (BATCHABLE)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG, false>
             <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else
         throw Error(TNG_E_STATE, "this operator combination has no batched form");
     TNG_HIP(hipGetLastError());
 }
 
-// key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only)
+// key: bit 0 A, bit 1 B^T, bit 2 B, bit 3 hourglass control (with A only), bit 4
+// free slip (the full operator and single blocks without hourglass control)
 template <typename T, int RS, int CPL, int WG>
-void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb, int key) {
+void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatch& sb, int key, int* bands_out) {
     switch (key) {
-        case 1: launch_band_t<T, RS, CPL, WG, true, false, false, false>(ctx, args, sb); break;
-        case 2: launch_band_t<T, RS, CPL, WG, false, true, false, false>(ctx, args, sb); break;
-        case 3: launch_band_t<T, RS, CPL, WG, true, true, false, false>(ctx, args, sb); break;
-        case 4: launch_band_t<T, RS, CPL, WG, false, false, true, false>(ctx, args, sb); break;
-        case 5: launch_band_t<T, RS, CPL, WG, true, false, true, false>(ctx, args, sb); break;
-        case 6: launch_band_t<T, RS, CPL, WG, false, true, true, false>(ctx, args, sb); break;
-        case 7: launch_band_t<T, RS, CPL, WG, true, true, true, false>(ctx, args, sb); break;
-        case 9: launch_band_t<T, RS, CPL, WG, true, false, false, true>(ctx, args, sb); break;
-        case 11: launch_band_t<T, RS, CPL, WG, true, true, false, true>(ctx, args, sb); break;
-        case 13: launch_band_t<T, RS, CPL, WG, true, false, true, true>(ctx, args, sb); break;
-        case 15: launch_band_t<T, RS, CPL, WG, true, true, true, true>(ctx, args, sb); break;
-        default: throw Error(TNG_E_INVAL, "op_flags selects no operator block");
+        case 1: launch_band_t<T, RS, CPL, WG, true, false, false, false, false>(ctx, args, sb, bands_out); break;
+        case 2: launch_band_t<T, RS, CPL, WG, false, true, false, false, false>(ctx, args, sb, bands_out); break;
+        case 3: launch_band_t<T, RS, CPL, WG, true, true, false, false, false>(ctx, args, sb, bands_out); break;
+        case 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, false>(ctx, args, sb, bands_out); break;
+        case 5: launch_band_t<T, RS, CPL, WG, true, false, true, false, false>(ctx, args, sb, bands_out); break;
+        case 6: launch_band_t<T, RS, CPL, WG, false, true, true, false, false>(ctx, args, sb, bands_out); break;
+        case 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false>(ctx, args, sb, bands_out); break;
+        case 9: launch_band_t<T, RS, CPL, WG, true, false, false, true, false>(ctx, args, sb, bands_out); break;
+        case 11: launch_band_t<T, RS, CPL, WG, true, true, false, true, false>(ctx, args, sb, bands_out); break;
+        case 13: launch_band_t<T, RS, CPL, WG, true, false, true, true, false>(ctx, args, sb, bands_out); break;
+        case 15: launch_band_t<T, RS, CPL, WG, true, true, true, true, false>(ctx, args, sb, bands_out); break;
+        case 16 | 1: launch_band_t<T, RS, CPL, WG, true, false, false, false, true>(ctx, args, sb, bands_out); break;
+        case 16 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, true>(ctx, args, sb, bands_out); break;
+        case 16 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, true>(ctx, args, sb, bands_out); break;
+        case 16 | 2:   // B^T reads no velocity: its free-slip rows are the post pass's projection
+            launch_band_t<T, RS, CPL, WG, false, true, false, false, false>(ctx, args, sb, bands_out);
+            break;
+        default:
+            throw Error(TNG_E_INVAL, "this operator combination has no free-slip form (use A, B^T, B or the "
+                                     "full operator, without hourglass control)");
     }
 }
 
+// layout != nullptr: fill the decomposition the launch would use (see
+// tng_stokes_apply_layout) and launch nothing.
 template <typename T>
 void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned flags, double hg_alpha,
                 const void* eta, const void* const u[3], const void* p, void* const yu[3],
-                void* yp) {
+                void* yp, int* layout = nullptr) {
     const bool doA = flags & TNG_OP_A, doBT = flags & TNG_OP_BT, doB = flags & TNG_OP_B;
     const bool is64 = std::is_same<T, double>::value;
     BandArgs<T> a{};
@@ -992,11 +1102,48 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.nband = 1;   // chosen per kernel at launch
     a.r_in = T(L.r_in);
     a.dr = T(L.dr());
-    a.dirichlet = (flags & TNG_OP_DIRICHLET) ? 1 : 0;
+    a.fs = ((flags & TNG_OP_FREESLIP_INNER) ? 1 : 0) | ((flags & TNG_OP_FREESLIP_OUTER) ? 2 : 0);
+    a.ns_in = ((flags & TNG_OP_DIRICHLET) && !(a.fs & 1)) ? 1 : 0;
+    a.ns_out = ((flags & TNG_OP_DIRICHLET) && !(a.fs & 2)) ? 1 : 0;
+    a.unit = is64 ? reinterpret_cast<const T*>(L.unit64.p) : reinterpret_cast<const T*>(L.unit32.p);
     const bool doHG = doA && hg_alpha != 0.0;
     a.hg = T(hg_alpha * (5.0 / 81.0));
     const SlotBatch sb = launch_batch();
     const unsigned nbz = (unsigned)sb.nb;
+    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0) | (a.fs ? 16 : 0);
+    auto dispatch = [&](int* bands_out) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (rs == 1)
+                launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key, bands_out);
+            else if (rs == 2)
+                launch_band_ops<T, 2, 1, 4>(ctx, a, sb, key, bands_out);
+            else
+                launch_band_ops<T, 4, 1, 8>(ctx, a, sb, key, bands_out);
+        } else {
+            // FP32 splits only two-cell stretches (one-cell columns fit one stretch)
+            if (cpl == 1)
+                wg == 4 ? launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key, bands_out)
+                        : launch_band_ops<T, 1, 1, 8>(ctx, a, sb, key, bands_out);
+            else if (rs == 1)
+                wg == 4 ? launch_band_ops<T, 1, 2, 4>(ctx, a, sb, key, bands_out)
+                        : launch_band_ops<T, 1, 2, 8>(ctx, a, sb, key, bands_out);
+            else
+                launch_band_ops<T, 2, 2, 8>(ctx, a, sb, key, bands_out);
+        }
+    };
+    if (layout != nullptr) {
+        int bands = 1;
+        dispatch(&bands);
+        layout[0] = a.TI;
+        layout[1] = rs;
+        layout[2] = cpl;
+        layout[3] = wg;
+        layout[4] = a.ntile;
+        layout[5] = bands;
+        layout[6] = a.nchunk;
+        layout[7] = a.KC;
+        return;
+    }
     {
         // y_p = 0 and the seam zeroing, one launch
         const long long np = doB ? Lp->node_slots() : 0;
@@ -1010,23 +1157,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
             TNG_HIP(hipGetLastError());
         }
     }
-    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0);
-    if constexpr (std::is_same<T, double>::value) {
-        if (rs == 1)
-            launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key);
-        else if (rs == 2)
-            launch_band_ops<T, 2, 1, 4>(ctx, a, sb, key);
-        else
-            launch_band_ops<T, 4, 1, 8>(ctx, a, sb, key);
-    } else {
-        // FP32 splits only two-cell stretches (one-cell columns fit one stretch)
-        if (cpl == 1)
-            wg == 4 ? launch_band_ops<T, 1, 1, 4>(ctx, a, sb, key) : launch_band_ops<T, 1, 1, 8>(ctx, a, sb, key);
-        else if (rs == 1)
-            wg == 4 ? launch_band_ops<T, 1, 2, 4>(ctx, a, sb, key) : launch_band_ops<T, 1, 2, 8>(ctx, a, sb, key);
-        else
-            launch_band_ops<T, 2, 2, 8>(ctx, a, sb, key);
-    }
+    dispatch(nullptr);
     // interface sums and Dirichlet rows (identity rows belong to the viscous block;
     // without it the rows are zero), one launch
     PostArgs q{};
@@ -1034,8 +1165,11 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         q.ngu = L.n_groups;
         q.gpu = L.grp_ptr.p;
         q.gsu = L.grp_slot.p;
-        q.nlat_u = a.dirichlet ? L.lat_slots() : 0;
-        q.dirichlet = a.dirichlet;
+        q.nlat_u = (a.ns_in || a.ns_out || a.fs) ? L.lat_slots() : 0;
+        q.ns_in = a.ns_in;
+        q.ns_out = a.ns_out;
+        q.fs = a.fs;
+        q.inv_mult = L.inv_mult64.p;
     }
     q.n1u = L.n + 1;
     if (doB) {
@@ -1050,7 +1184,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         if (doA && u)
             for (int c = 0; c < 3; ++c) ud[c] = static_cast<const T*>(u[c]);
         post_apply_kernel<T><<<dim3(nblocks(npost, 256), 1, nbz), 256, 0, ctx->stream>>>(
-            q, a.y0, a.y1, a.y2, ud[0], ud[1], ud[2], a.yp, sb);
+            q, a.y0, a.y1, a.y2, ud[0], ud[1], ud[2], a.yp, a.unit, sb);
         TNG_HIP(hipGetLastError());
     }
 }
@@ -1064,6 +1198,14 @@ void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tn
         band_apply<double>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
     else
         band_apply<float>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
+}
+
+void stokes_apply_layout(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec, unsigned flags,
+                         double hg_alpha, int out[8]) {
+    if (prec == TNG_F64)
+        band_apply<double>(ctx, L, Lp, flags, hg_alpha, nullptr, nullptr, nullptr, nullptr, nullptr, out);
+    else
+        band_apply<float>(ctx, L, Lp, flags, hg_alpha, nullptr, nullptr, nullptr, nullptr, nullptr, out);
 }
 
 }  // namespace tng

@@ -198,6 +198,7 @@ struct Level {
     DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
     DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node
     DevBuf<double> unit64;            // [10][m+1][m+1][3] unit vectors
+    DevBuf<float> unit32;
     DevBuf<float> inv_mult32;
 
     long long lat_slots() const { return 10LL * (m + 1) * (m + 1); }
@@ -257,12 +258,25 @@ inline const Level& device_level(const tng_ctx* ctx, const tng_mesh* mesh, int l
 void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec,
                          unsigned flags, double hg_alpha, const void* eta, const void* const u[3], const void* p,
                          void* const yu[3], void* yp);
+// The decomposition launch_stokes_apply would use (tng_stokes_apply_layout);
+// launches nothing.
+void stokes_apply_layout(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec, unsigned flags,
+                         double hg_alpha, int out[8]);
+// Plain streaming copy of `bytes` (a multiple of 16, 16-byte aligned pointers).
+void launch_stream_copy(const tng_ctx* ctx, const void* src, void* dst, size_t bytes);
 void launch_interface(const tng_ctx* ctx, const Level& L, tng_prec prec, int mode, int ncomp,
                       void* const f[]);
 void launch_eta_from_T(const tng_ctx* ctx, const Level& L, tng_prec prec, const void* Tn,
                        void* eta, double E, double F);
 void launch_eta_coarsen(const tng_ctx* ctx, const Level& Lc, tng_prec prec, const void* ef,
                         void* ec);
+
+// Argument check of the C entry points: `p` must point at `bytes` bytes of
+// ordinary device memory (hipMalloc, hipMemoryTypeDevice) of the context's
+// GPU, inside one allocation.  Host, pinned-host and managed memory are
+// refused: the kernels' seam sums use FP atomics that are only reliable on
+// coarse-grained device memory, and a host pointer handed to a kernel faults.
+void require_device(const tng_ctx* ctx, const void* p, size_t bytes, const char* what);
 
 // Scratch array of the no-allocation entry points (noalloc.hip): asks the
 // array's address on `device`, which must be current, once per device.

@@ -18,76 +18,14 @@
 //   sigma = 2 eta dev sym(grad u) - pbar I      (eq:stress, the B^T block),
 //   V_e   = |det J(q_c)| = r_m^2 h |det G|      (eq:oneptenergy, w_q = 1),
 // reduces to y_j = sum_m g'_jm Z_m with Z_m = (V sigma) rho_m (folded rows)
-// and g'_j the reference gradients without their 1/2, 1/6 factors.
+// and g'_j the reference gradients without their 1/2, 1/6 factors.  The band
+// kernel of stokes_apply.hip evaluates these formulas in streaming form; this
+// header holds the constants it shares with the other kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace tng {
-
-template <typename T>
-struct WedgeOut {
-    T y[6][3];   // contributions to the six wedge nodes, three components
-    T dv;        // -V_e div u (the B block before the pressure test weights)
-};
-
-// u[j][c]: nodal velocity of the six wedge nodes (0-2 bottom, 3-5 top).
-// g: ten geometry values of the triangle: rho1(3), rho2(3), rho3'(3), h|det G|.
-// s1 = 1 / (2 r_m), rm2 = r_m^2.  eta: wedge viscosity.  pbar: mean of the six
-// iso-interpolated pressure values (the pressure at q_c).
-template <typename T, bool DO_A, bool DO_BT, bool DO_B>
-__device__ __forceinline__ void wedge_apply(const T (&u)[6][3], const T* __restrict__ g, T s1,
-                                            T rm2, T eta, T pbar, WedgeOut<T>& o) {
-    const T r1[3] = {g[0] * s1, g[1] * s1, g[2] * s1};
-    const T r2[3] = {g[3] * s1, g[4] * s1, g[5] * s1};
-    const T r3[3] = {g[6], g[7], g[8]};
-    const T V = rm2 * g[9];
-    T L[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const T s03 = u[0][c] + u[3][c];
-        const T A = (u[1][c] + u[4][c]) - s03;
-        const T B = (u[2][c] + u[5][c]) - s03;
-        const T C = (u[3][c] + u[4][c] + u[5][c]) - (u[0][c] + u[1][c] + u[2][c]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) L[c][a] = A * r1[a] + B * r2[a] + C * r3[a];
-    }
-    const T tr = L[0][0] + L[1][1] + L[2][2];
-    if (DO_B) o.dv = -V * tr;
-    if (DO_A || DO_BT) {
-        T S[3][3];
-        if (DO_A) {
-            const T e = eta * V;
-            const T e2 = e + e;
-            const T q = e2 * tr * T(1.0 / 3.0) + (DO_BT ? V * pbar : T(0));
-            S[0][0] = e2 * L[0][0] - q;
-            S[1][1] = e2 * L[1][1] - q;
-            S[2][2] = e2 * L[2][2] - q;
-            S[0][1] = S[1][0] = e * (L[0][1] + L[1][0]);
-            S[0][2] = S[2][0] = e * (L[0][2] + L[2][0]);
-            S[1][2] = S[2][1] = e * (L[1][2] + L[2][1]);
-        } else {
-            const T q = V * pbar;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) S[c][a] = (c == a) ? -q : T(0);
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T z1 = S[c][0] * r1[0] + S[c][1] * r1[1] + S[c][2] * r1[2];
-            const T z2 = S[c][0] * r2[0] + S[c][1] * r2[1] + S[c][2] * r2[2];
-            const T z3 = S[c][0] * r3[0] + S[c][1] * r3[1] + S[c][2] * r3[2];
-            const T z12 = z1 + z2;
-            o.y[0][c] = -z12 - z3;
-            o.y[1][c] = z1 - z3;
-            o.y[2][c] = z2 - z3;
-            o.y[3][c] = z3 - z12;
-            o.y[4][c] = z1 + z3;
-            o.y[5][c] = z2 + z3;
-        }
-    }
-}
 
 // Iso-W1 pressure weights (Sec. 3: pressure W1 on the coarser grid).  A fine
 // cell (i, j, k) lies in coarse cell (i/2, j/2, k/2); its fine nodes are

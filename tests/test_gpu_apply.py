@@ -71,6 +71,27 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def check_rows(got, want, M, x, tol, what):
+    """Element-wise bound |y - y_ref| <= tol * s per row, s = (|M| |x|)_row the
+    sum of the magnitudes of the row's terms (a localised error at a few seam
+    nodes cannot hide in a global norm)."""
+    s = (abs(M) @ np.abs(np.asarray(x).ravel())).reshape(np.shape(want))
+    err = np.abs(np.asarray(got) - np.asarray(want))
+    ratio = err / np.maximum(s, 1e-300)
+    worst = float(ratio.max()) if ratio.size else 0.0
+    assert worst <= tol, f"{what}: worst error / row scale {worst:.2e} > {tol:.0e} " \
+                         f"({int((ratio > tol).sum())} rows)"
+    return worst
+
+
+def check_K(orc, gu, gp, u, p, tol, what, K=None):
+    K = orc.K if K is None else K
+    x = np.concatenate([np.asarray(u).ravel(), np.asarray(p)])
+    want = K @ x
+    got = np.concatenate([np.asarray(gu).ravel(), np.asarray(gp)])
+    return check_rows(got, want, K, x, tol, what)
+
+
 @pytest.mark.parametrize("mt,nr", [(8, 8), (16, 16), (8, 6), (16, 10), (4, 2)])
 def test_full_operator_fp64(tng, ctx, mt, nr):
     mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
@@ -82,6 +103,7 @@ def test_full_operator_fp64(tng, ctx, mt, nr):
     print(f"fp64 ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < 1e-12
     assert rel(gp, rp) < 1e-12
+    check_K(orc, gu, gp, u, p, 1e-12, f"fp64 ({mt},{nr})")
 
 
 @pytest.mark.parametrize("mt,nr", [(8, 8), (16, 16), (16, 10)])
@@ -95,6 +117,7 @@ def test_full_operator_fp32(tng, ctx, mt, nr):
     print(f"fp32 ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < 1e-5
     assert rel(gp, rp) < 1e-5
+    check_K(orc, gu, gp, u, p, 1e-5, f"fp32 ({mt},{nr})")
 
 
 def test_blocks_separately(tng, ctx):
@@ -106,12 +129,16 @@ def test_blocks_separately(tng, ctx):
     tt = dict(t, u=torch.tensor(lm.to_lib(uf), device="cuda").contiguous())
     yu, _ = run_apply(tng, ctx, mesh, tt, 1, torch.float64)
     assert rel(lm.from_lib(yu), (orc.A @ uf.ravel()).reshape(-1, 3)) < 1e-12
+    check_rows(lm.from_lib(yu).ravel(), orc.A @ uf.ravel(), orc.A, uf, 1e-12, "A")
     yu, _ = run_apply(tng, ctx, mesh, tt, 2 | 8, torch.float64)
     assert rel(lm.from_lib(yu), (orc.BT_D @ p).reshape(-1, 3)) < 1e-12
+    check_rows(lm.from_lib(yu).ravel(), orc.BT_D @ p, orc.BT_D, p, 1e-12, "B^T_D")
     _, yp = run_apply(tng, ctx, mesh, tt, 4 | 8, torch.float64)
     assert rel(lmp.from_lib(yp), orc.B_D @ uf.ravel()) < 1e-12
+    check_rows(lmp.from_lib(yp), orc.B_D @ uf.ravel(), orc.B_D, uf, 1e-12, "B_D")
     yu, _ = run_apply(tng, ctx, mesh, tt, 1 | 8, torch.float64)
     assert rel(lm.from_lib(yu), (orc.A_D @ uf.ravel()).reshape(-1, 3)) < 1e-12
+    check_rows(lm.from_lib(yu).ravel(), orc.A_D @ uf.ravel(), orc.A_D, uf, 1e-12, "A_D")
 
 
 def test_unit_columns(tng, ctx):
@@ -154,6 +181,7 @@ def test_hourglass_controlled_operator(tng, ctx, mt, nr, prec):
     gu, gp = lm.from_lib(yu.double().cpu().numpy()), lmp.from_lib(yp.double().cpu().numpy())
     print(f"hg {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    check_K(orh, gu, gp, u, p, tol, f"hg {prec} ({mt},{nr})")
     # the stabilisation changes the result (it is not a no-op on random inputs)
     assert rel(ru, orc.apply(u, p)[0]) > 1e-3
     rng = np.random.default_rng(5)
@@ -180,6 +208,7 @@ def test_radial_split_columns(tng, ctx, mt, nr, prec):
     gp = lmp.from_lib(yp, check_dups=1e-6)
     print(f"split {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    check_K(orc, gu, gp, u, p, tol, f"split {prec} ({mt},{nr})")
 
 
 # ---- band partition: bands of unequal length (forced through the context) -------------
@@ -202,3 +231,81 @@ def test_forced_band_counts(tng, ctx, mt, nr, bands, prec):
     gp = lmp.from_lib(yp, check_dups=1e-6)
     print(f"bands {bands} {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}")
     assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    check_K(orc, gu, gp, u, p, tol, f"bands {bands} {prec} ({mt},{nr})")
+
+
+# ---- argument checks of the C entry points and the bandwidth probe --------------------
+
+def test_device_pointer_checks(tng, ctx):
+    """The check every entry point applies to its device pointers: host and pinned-host
+    memory are refused, device memory is accepted only up to its allocation's end.
+    (tng_check_device_buffer launches nothing, whatever it is given.)"""
+    import torch
+    a = np.zeros(1000)
+    with pytest.raises(tng.TngError, match="device memory"):
+        tng.check_device_buffer(ctx, a.ctypes.data, a.nbytes)
+    pinned = torch.zeros(1000, dtype=torch.float64, pin_memory=True)
+    with pytest.raises(tng.TngError, match="device memory"):
+        tng.check_device_buffer(ctx, pinned.data_ptr(), 8000)
+    t = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    tng.check_device_buffer(ctx, t.data_ptr(), 8000)
+    with pytest.raises(tng.TngError, match="too small"):
+        tng.check_device_buffer(ctx, t.data_ptr(), 64 << 20)
+
+
+def test_stream_copy(tng, ctx):
+    import torch
+    for n in (1 << 22, 4 * 12345 + 4):                # whole trips, and a ragged tail
+        x = torch.randn(n, dtype=torch.float32, device="cuda")
+        y = torch.full_like(x, float("nan"))
+        tng.stream_copy(ctx, x, y)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)
+
+
+# ---- free slip (Sec. 8 setup): rotated normal constraint on one or both spheres ---------
+
+FS_IN, FS_OUT = 16, 32
+
+
+@pytest.mark.parametrize("mt,nr,bc,prec", [
+    (8, 8, ("freeslip", "freeslip"), "f64"), (16, 10, ("noslip", "freeslip"), "f64"),
+    (8, 6, ("freeslip", "noslip"), "f64"), (16, 16, ("freeslip", "freeslip"), "f32"),
+    (4, 160, ("freeslip", "freeslip"), "f64"), (4, 288, ("noslip", "freeslip"), "f32")])
+def test_freeslip_operator(tng, ctx, mt, nr, bc, prec):
+    """K with free slip (y_u = P (A P u + B^T p) + N u on the free-slip spheres, y_p = B P u)
+    against the oracle assembled with the same conditions, element-wise, including radial
+    splits (nr 160, 288); then A, B^T and B alone."""
+    import torch
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    orf = StokesOracle(mt, nr, eta, hierarchy=om.h, bc=bc)
+    rng = np.random.default_rng(9)
+    uf = rng.uniform(-1, 1, u.shape)                     # nonzero on both spheres
+    flags = OPS_ALL | (FS_IN if bc[0] == "freeslip" else 0) | (FS_OUT if bc[1] == "freeslip" else 0)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    e = t["eta"].to(dt)
+    ut = torch.tensor(lm.to_lib(uf), device="cuda").to(dt).contiguous()
+    pt = t["p"].to(dt)
+    yu, yp = torch.full_like(ut, float("nan")), torch.full_like(pt, float("nan"))
+    tng.stokes_apply(ctx, mesh, 0, flags, e, ut, pt, yu, yp)
+    gu = lm.from_lib(yu.double().cpu().numpy(), check_dups=1e-6)
+    gp = lmp.from_lib(yp.double().cpu().numpy(), check_dups=1e-6)
+    ru, rp = orf.apply(uf, p)
+    print(f"freeslip {bc} {prec} ({mt},{nr}) rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}", flush=True)
+    assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    check_K(orf, gu, gp, uf, p, tol, f"freeslip {bc} {prec} ({mt},{nr})")
+    # the condition changes the result (not the no-slip operator)
+    assert rel(ru, orc.apply(uf, p)[0]) > 1e-3
+    fsb = flags & (FS_IN | FS_OUT)
+    for blk, M, x in ((1 | 8, orf.A_D, uf), (2 | 8, orf.BT_D, p), (4 | 8, orf.B_D, uf)):
+        yu.fill_(float("nan"))
+        yp.fill_(float("nan"))
+        tng.stokes_apply(ctx, mesh, 0, blk | fsb, e, ut if blk != (2 | 8) else None,
+                         pt if blk == (2 | 8) else None, yu if blk != (4 | 8) else None, yp if blk == (4 | 8) else None)
+        if blk == (4 | 8):
+            got = lmp.from_lib(yp.double().cpu().numpy())
+        else:
+            got = lm.from_lib(yu.double().cpu().numpy()).ravel()
+        want = M @ np.asarray(x).ravel()
+        assert rel(got, want) < tol, blk
+        check_rows(got, want, M, x, tol, f"freeslip block {blk}")

@@ -5,10 +5,13 @@ launches it (K = A + B^T + B with Dirichlet rows, FP64 and FP32).
 
 The oracle cannot assemble this operator, so it evaluates sampled rows one at
 a time (``oracle.rows``).  The samples cover random nodes plus the places
-where the kernel's decomposition changes: diamond edges and poles (duplicate
-groups), tile seams (node columns that are multiples of 8), band seams (node
-rows that are multiples of 16), the radial chunk seam of the FP64 kernel
-(layer 64), and the Dirichlet spheres.  Every copy of a sampled node in the
+where the kernel's decomposition changes, read from the decomposition the
+library reports for exactly these launches (``tng_stokes_apply_layout``, FP32
+and FP64): diamond edges and poles (duplicate groups), the tile seams (node
+columns at multiples of the tile width), the band seams and the halo row above
+each (node rows j0 - 1 and j0 of every band start j0), their crossings, the
+radial stretch and range seams, the coarse pressure nodes on all of these, and
+the Dirichlet spheres.  Every copy of a sampled node in the
 duplicated layout is checked.  Tolerance per row: |y - y_ref| <= tol * s with
 s the sum of the magnitudes of the row's terms (tol 1e-12 FP64, 1e-5 FP32);
 the FP32 run gets the FP64 inputs rounded to FP32 and is compared with the
@@ -31,15 +34,28 @@ E, F = math.log(1e3), math.log(10.0)
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-def _special_lateral(m):
+def _seams(lay, m):
+    """Tile-seam node columns, band-start node rows and radial seam layers of a launch."""
+    cols = [t * lay["tile"] for t in range(1, lay["ntile"])]
+    rows = [2 * ((b * (m // 2)) // lay["bands"]) for b in range(1, lay["bands"])]
+    stretch = 64 * lay["cpl"]
+    layers = sorted({k for k in range(stretch, NR, stretch)} | {c * lay["range"] for c in range(1, lay["nchunk"])})
+    return cols, rows, layers
+
+
+def _special_lateral(m, cols, rows, rng):
     """(d, i, j) slots at the decomposition's boundaries."""
     out = []
     for d in (0, 3, 5, 9):
         out += [(d, 0, 0), (d, m, 0), (d, 0, m), (d, m, m)]          # diamond corners (poles, ring vertices)
         out += [(d, 0, 37), (d, 41, 0), (d, m, 50), (d, 77, m)]      # diamond edges
-        out += [(d, 8, 40), (d, 64, 17), (d, 120, 99)]               # tile seams
-        out += [(d, 33, 16), (d, 70, 96), (d, 5, 112)]               # band seams
-        out += [(d, 8, 16), (d, 63, 63)]
+        for c in rng.choice(cols, min(4, len(cols)), replace=False):  # tile seams
+            out.append((d, int(c), int(rng.integers(1, m))))
+        for r in rows:                                               # band starts and their halo rows
+            out.append((d, int(rng.integers(1, m)), r))
+            out.append((d, int(rng.integers(1, m)), r - 1))
+            out.append((d, int(cols[(r // 2) % len(cols)]) if cols else 0, r))   # crossings
+        out += [(d, 63, 63)]
     return out
 
 
@@ -60,28 +76,48 @@ def case():
     u = rng.uniform(-1.0, 1.0, (om.n_nodes, 3))
     p = rng.uniform(-1.0, 1.0, omp.n_nodes)
 
-    # velocity samples: oracle nodes, then every library copy of each
+    # the decomposition of the benchmark's launches (FP32 and FP64 full operator)
+    flags = tng.OP_A | tng.OP_BT | tng.OP_B | tng.OP_DIRICHLET
     m, n = MT, NR
-    lat_slots = [(d * (m + 1) + i) * (m + 1) + j for d, i, j in _special_lateral(m)]
-    ks = [0, 1, 2, 63, 64, 65, 126, 127, 128]
+    layouts = {prec: tng.stokes_apply_layout(ctx, mesh, 0, flags, prec == "f64") for prec in ("f32", "f64")}
+    cols, rows, layers = set(), set(), set()
+    for lay in layouts.values():
+        c_, r_, k_ = _seams(lay, m)
+        cols |= set(c_)
+        rows |= set(r_)
+        layers |= set(k_)
+    cols, rows, layers = sorted(cols), sorted(rows), sorted(layers)
+    print(f"layouts {layouts}; tile seams {cols}; band starts {rows}; radial seams {layers}", flush=True)
+    # velocity samples: oracle nodes, then every library copy of each
+    lat_slots = [(d * (m + 1) + i) * (m + 1) + j for d, i, j in _special_lateral(m, cols, rows, rng)]
+    ks = sorted({0, 1, 2, n // 2, n - 2, n - 1, n} | {k + dk for k in layers for dk in (-1, 0, 1)})
     nodes = [lm.slot2lat[s] * (n + 1) + k for s in lat_slots for k in ks[::2]]
     nodes += [lm.slot2lat[s] * (n + 1) + k for s in lat_slots[::3] for k in ks[1::2]]
     nodes += list(rng.choice(om.n_nodes, 200, replace=False))
     nodes = np.unique(np.asarray(nodes, dtype=np.int64))
-    # pressure samples: coarse library slots on coarse seams and chunk seams, plus random
+    # pressure samples: coarse slots on the coarse images of the seams (tile seam
+    # columns / 2, band starts / 2, radial seams / 2), plus random
     mc, nc = m // 2, n // 2
+    pcols = sorted({c // 2 for c in cols}) or [0]
+    prows = sorted({r // 2 for r in rows}) or [0]
     pl = []
     for d in (0, 4, 7):
-        for I, J in ((0, 0), (mc, mc), (4, 20), (32, 8), (12, 40), (0, 21), (mc, 9), (31, 31)):
+        for I, J in ((0, 0), (mc, mc), (0, 21), (mc, 9), (31, 31)):
             pl.append((d * (mc + 1) + I) * (mc + 1) + J)
-    qs = [lmp.slot2lat[s] * (nc + 1) + K for s in pl for K in (0, 1, 31, 32, 33, nc)]
+        for q, J in enumerate(prows):
+            pl.append((d * (mc + 1) + pcols[q % len(pcols)]) * (mc + 1) + J)          # crossings
+            pl.append((d * (mc + 1) + int(rng.integers(1, mc))) * (mc + 1) + J)
+        for I in pcols[::2]:
+            pl.append((d * (mc + 1) + I) * (mc + 1) + int(rng.integers(1, mc)))
+    Ks = sorted({0, 1, nc - 1, nc} | {k // 2 + dk for k in layers for dk in (0, 1)})
+    qs = [lmp.slot2lat[s] * (nc + 1) + K for s in pl for K in Ks]
     qs += list(rng.choice(omp.n_nodes, 100, replace=False))
     qs = np.unique(np.asarray(qs, dtype=np.int64))
 
-    rows = StokesRows(om)
+    ro = StokesRows(om)
     eta_of = lambda w: eta_law(om, T, w, E, F)
-    ref_u = [rows.velocity_row(int(nd), eta_of, u, p) for nd in nodes]
-    ref_p = [rows.pressure_row(int(q), eta_of, u) for q in qs]
+    ref_u = [ro.velocity_row(int(nd), eta_of, u, p) for nd in nodes]
+    ref_p = [ro.pressure_row(int(q), eta_of, u) for q in qs]
     return dict(tng=tng, ctx=ctx, mesh=mesh, om=om, lm=lm, lmp=lmp, T=T, u=u, p=p,
                 nodes=nodes, qs=qs, ref_u=ref_u, ref_p=ref_p)
 

@@ -100,8 +100,8 @@ def test_failed_request_is_isolated(tng, ctx):
 
 
 def test_tight_budget_serves_everything(tng, ctx):
-    """A budget of about two (16,16) slots (~20 MB each): requests queue, slots are reused,
-    and an idle slot of the other level is released when needed."""
+    """A budget of about two (16,16) slots (~20 MB each): requests queue and slots are
+    reused (the release of another level's idle slot is tested below)."""
     srv = tng.Server(ctx, LEVELS, budget_bytes=45 << 20, max_slots=8, mixed=1)
     reqs = []
     for i in range(8):
@@ -116,6 +116,51 @@ def test_tight_budget_serves_everything(tng, ctx):
     for t in reqs:
         assert srv.poll(t)["rc"] == 0
     srv.close()
+
+
+def _slot_bytes(tng, ctx, level):
+    """Device bytes of one solver slot of `level`, measured with a server of that level alone."""
+    srv = tng.Server(ctx, [level], budget_bytes=8 << 30, max_slots=1, mixed=1)
+    Tt, u, p = request_fields(tng, ctx, *level, 77)
+    srv.wait(srv.submit(0, Tt, 2.0, 1e5, u, p))
+    b = srv.stats()["bytes_in_use"]
+    srv.close()
+    return b
+
+
+def _poll_until_done(srv, ticket, seconds):
+    import time
+    t_end = time.time() + seconds
+    while time.time() < t_end:
+        r = srv.poll(ticket)
+        if r["done"]:
+            return r
+        time.sleep(0.05)
+    return None
+
+
+def test_starved_level_gets_an_idle_slot_released(tng, ctx):
+    """The budget holds one (8,8) slot plus a little less than one (16,16) slot.  After an
+    (8,8) request leaves its slot idle, a (16,16) request only fits if that idle slot is
+    released; the server must do so by itself.  Polled against a host deadline, so a
+    regression fails instead of waiting forever."""
+    b8, b16 = _slot_bytes(tng, ctx, LEVELS[0]), _slot_bytes(tng, ctx, LEVELS[1])
+    assert 0 < b8 < b16
+    srv = tng.Server(ctx, LEVELS, budget_bytes=b8 + b16 - 1, max_slots=4, mixed=1)
+    try:
+        T8, u8, p8 = request_fields(tng, ctx, 8, 8, 61)
+        r = _poll_until_done(srv, srv.submit(0, T8, 2.0, 1e5, u8, p8), 60.0)
+        assert r is not None and r["rc"] == 0
+        st = srv.stats()
+        assert st["slots"] == 1 and st["busy"] == 0 and st["bytes_in_use"] == b8, st
+        T16, u16, p16 = request_fields(tng, ctx, 16, 16, 62)
+        r = _poll_until_done(srv, srv.submit(1, T16, 2.0, 1e5, u16, p16), 60.0)
+        st = srv.stats()
+        print("starved level:", st, flush=True)
+        assert r is not None, f"the (16,16) request was never admitted: {st}"
+        assert r["rc"] == 0 and st["slots"] == 1 and st["bytes_in_use"] == b16, st
+    finally:
+        srv.close()
 
 
 @pytest.mark.parametrize("mixed,nreq", [(1, 18), (0, 3)])

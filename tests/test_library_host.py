@@ -91,3 +91,47 @@ def test_pressure_level_nests():
     x1, r1 = m.coords(1)
     assert np.array_equal(x0[:, ::2, ::2], x1)
     assert np.array_equal(r0[::2], r1)
+
+
+def test_binding_refuses_bad_tensors_before_any_call():
+    """The binding checks device, dtype, contiguity and size of every field before
+    it reaches the library (which sees only raw pointers)."""
+    import torch
+    tng = _lib()
+    mesh = tng.Mesh(None, 4, 4, levels=2)
+
+    class Ctx:                      # stands in for a context on device 0; never reaches the library
+        device = 0
+        h = None
+
+    shp = (3,) + mesh.shape(0)
+    eta = torch.ones(mesh.wedge_shape(0), dtype=torch.float64)
+    u = torch.zeros(shp, dtype=torch.float64)
+    y = torch.zeros(shp, dtype=torch.float64)
+    with pytest.raises(TypeError, match="cuda:0"):
+        tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, eta, u, None, y, None)
+    # the remaining checks, on tensors that claim to be on the device
+    class Fake:
+        def __init__(self, t, is_cuda=True):
+            self.t, self.is_cuda = t, is_cuda
+            self.device = torch.device("cuda", 0)
+            self.dtype, self.shape = t.dtype, t.shape
+
+        def is_contiguous(self):
+            return self.t.is_contiguous()
+
+        def numel(self):
+            return self.t.numel()
+
+        def __getitem__(self, i):
+            return Fake(self.t[i])
+
+        def __len__(self):
+            return len(self.t)
+
+    with pytest.raises(TypeError, match="dtype"):
+        tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, Fake(eta.float()), Fake(u), None, Fake(y), None)
+    with pytest.raises(ValueError, match="values"):
+        tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, Fake(eta.reshape(-1)[:10].clone()), Fake(u), None, Fake(y), None)
+    with pytest.raises(ValueError, match="contiguous"):
+        tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, Fake(eta), Fake(u.transpose(1, 2)), None, Fake(y), None)

@@ -1,0 +1,105 @@
+"""Pins of the oracle's free-slip boundary condition (the setup of the paper's
+verification runs, Sec. 8: zero normal velocity and zero tangential traction
+on the spheres, imposed by rotating a boundary node's velocity to the frame
+(rhat, two tangents) and making the normal component a Dirichlet DoF).
+
+* With free slip on both spheres the rigid rotations u = w x x are tangential
+  and strain-free, so they span the null space of the viscous block exactly
+  (three zero eigenvalues, the rest positive); they are divergence-free, so
+  B annihilates them too.
+* With no slip on either sphere there is no null space (positive definite).
+* In the rotated frame the normal row is an identity row and the normal input
+  does not enter any other row.
+Each property is also checked to reject a planted mistake.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.mesh import ShellMesh
+from oracle.stokes import StokesOracle, boundary_projections
+
+MT = NR = 4
+
+
+@pytest.fixture(scope="module")
+def shell():
+    om = ShellMesh(MT, NR)
+    eta = 10.0 ** np.random.default_rng(3).uniform(-1.0, 1.0, om.n_wedges)
+    return om, eta
+
+
+def _rotations(om):
+    x = om.node_xyz()
+    return np.stack([np.cross(np.tile(w, (om.n_nodes, 1)), x).ravel() for w in np.eye(3)], axis=1)
+
+
+def test_noslip_projection_is_the_dirichlet_operator(shell):
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h)
+    d = (~np.repeat(om.boundary_nodes(), 3)).astype(float)
+    A_D = sp.diags(d) @ o.A @ sp.diags(d) + sp.diags(1.0 - d)
+    assert abs(o.A_D - A_D).max() == 0.0
+    assert abs(o.BT_D - sp.diags(d) @ o.B.T).max() == 0.0
+
+
+def test_freeslip_rotations_span_the_null_space(shell):
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h, bc=("freeslip", "freeslip"))
+    A = o.A_D.toarray()
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    R = _rotations(om)
+    assert np.abs(o.P_bc @ R - R).max() < 1e-15            # tangential on both spheres
+    assert np.abs(A @ R).max() < 1e-12 * np.abs(A).max()
+    assert np.abs(o.B_D @ R).max() < 1e-12 * np.abs(o.B_D).max()
+    lam = np.linalg.eigvalsh(A)
+    top = lam.max()
+    assert np.all(lam > -1e-12 * top)
+    assert np.sum(lam < 1e-10 * top) == 3
+    assert lam[3] > 1e-6 * top
+    # planted mistake: the normal identity rows left out (P A P alone) adds a zero
+    # eigenvalue for every boundary node's normal direction
+    lam_bad = np.linalg.eigvalsh((o.P_bc @ o.A @ o.P_bc).toarray())
+    assert np.sum(lam_bad < 1e-10 * top) > 3
+
+
+def test_noslip_inner_freeslip_outer_is_positive_definite(shell):
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h, bc=("noslip", "freeslip"))
+    lam = np.linalg.eigvalsh(o.A_D.toarray())
+    assert lam.min() > 1e-6 * lam.max()
+    # a rigid rotation is no longer admissible on the no-slip sphere: it has energy
+    R = _rotations(om)
+    assert np.linalg.norm(o.A_D @ R) > 1e-3 * np.linalg.norm(R)
+
+
+def test_freeslip_normal_rows_are_identity_rows(shell):
+    """rhat . (K x)_i = rhat . u_i at every free-slip node, and changing the normal
+    input component of a boundary node changes no other row; the operator stays
+    symmetric.  A one-sided projection (A P + N, a plausible slip) is not."""
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h, bc=("freeslip", "freeslip"))
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((om.n_nodes, 3))
+    p = rng.standard_normal(o.n_p)
+    yu, yp = o.apply(u, p)
+    bnd = om.boundary_nodes()
+    x = om.node_xyz()
+    rhat = x / np.linalg.norm(x, axis=1)[:, None]
+    assert np.allclose((yu * rhat).sum(1)[bnd], (u * rhat).sum(1)[bnd], rtol=0, atol=1e-13)
+    u2 = u.copy()
+    u2[bnd] += 0.7 * rhat[bnd]                                # normal components only
+    yu2, yp2 = o.apply(u2, p)
+    change = yu2 - yu
+    assert np.allclose(change[~bnd], 0.0, atol=1e-13) and np.allclose(yp2, yp, atol=1e-13)
+    assert np.allclose(change[bnd], 0.7 * rhat[bnd], atol=1e-13)
+    K = o.K
+    assert abs(K - K.T).max() <= 1e-14 * abs(K).max()
+    one_sided = (o.A @ o.P_bc + o.N_bc).tocsr()
+    assert abs(one_sided - one_sided.T).max() > 1e-6 * abs(o.A).max()
+
+
+def test_boundary_projections_reject_unknown_kinds():
+    om = ShellMesh(2, 2)
+    with pytest.raises(ValueError):
+        boundary_projections(om, ("slip", "noslip"))

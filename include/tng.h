@@ -99,7 +99,14 @@ enum {
      * free-slip bit set is free slip whatever TNG_OP_DIRICHLET says; the other
      * sphere is no slip with TNG_OP_DIRICHLET and unconstrained without it. */
     TNG_OP_FREESLIP_INNER = 16,
-    TNG_OP_FREESLIP_OUTER = 32
+    TNG_OP_FREESLIP_OUTER = 32,
+    /* Compressible mass balance (TALA, Sec. 1 eq:mass, div(rhobar u) = 0): the
+     * divergence rows become -(psi_I, div(rhobar u)) with the mass flux
+     * rhobar u interpolated nodally (rhobar(r_j) u_j, rhobar from
+     * tng_mesh_set_density), i.e. y_p = B R u with R = diag(rhobar(r_j)); the
+     * momentum rows keep B^T (eq:stokes).  With TNG_OP_B, alone or in the full
+     * operator; not with free slip or hourglass control. */
+    TNG_OP_TALA = 64
 };
 
 /* Message of the last failed call on this thread ("" if none).  Library-owned. */
@@ -169,6 +176,11 @@ int tng_mesh_coords(const tng_mesh* mesh, int level, double* unit_xyz_host, doub
  * numbered by first appearance in slot order; equal ids = one duplicate group. */
 int tng_mesh_dup_groups(const tng_mesh* mesh, int level, int* unique_id_host);
 int tng_mesh_destroy(tng_mesh* mesh);
+/* Reference density of the compressible (TALA) terms, Sec. 1: rho_host[k] =
+ * rhobar(r_k) at the nr + 1 radial node layers of the finest level (host
+ * array, copied; every value finite and > 0).  Level l uses the values of its
+ * own layers (every 2^l-th).  The mesh must have been built with a context. */
+int tng_mesh_set_density(tng_mesh* mesh, const double* rho_host);
 
 /* ---- operator (Sec. 3 eq:matfree, eq:epsq, eq:localapply) -------------- */
 /* y = K(eta) x restricted to the blocks in op_flags, on level `level`.
@@ -340,6 +352,14 @@ int tng_stokes_solver_vcycle(tng_solver* solver, const void* const b[3], void* c
  * Dirichlet rows zero.  T: device node field; f[3]: device velocity out. */
 int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
                      void* const f[3]);
+/* Buoyancy of the compressible (TALA) form of eq:stokes, with the split
+ * T = Tbar(r) + T' of eq:tsplit: f_(i,c) = sum_e V_e N_i(q_c) Ra
+ * (rhobar alphabar)(q_c) T'(q_c) rhat_c(q_c), both factors the W1 interpolants
+ * of their nodal values, T'_j = T_j - Tbar(r_j).  Tbar_host, rhoalpha_host:
+ * host arrays of the n + 1 radial node layers of `level` (Tbar(r_k) and
+ * rhobar(r_k) alphabar(r_k)).  Otherwise as tng_rhs_buoyancy. */
+int tng_rhs_buoyancy_tala(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
+                          const double* Tbar_host, const double* rhoalpha_host, void* const f[3]);
 /* Backward-Euler SUPG energy operator (unit diffusivity, Sec. 6 scheme list):
  * y_i = sum_e V_e [ N_i T_i / dt + grad phi_i . grad T + N_i ubar . grad T
  *                   + tau_e (ubar . grad phi_i)(ubar . grad T) ],

@@ -43,10 +43,58 @@ class SchurSolver:
                             options=dict(SymmetricMode=True))
         self.minv = 1.0 / lumped_pressure_mass(orc, eta_wedge)
         self.BT = orc.BT_D.tocsr()
-        self.B = orc.B_D.tocsr()
+        self.B = orc.B_mass.tocsr()
+        # a mass block other than B_D (the reference density of TALA) makes S
+        # non-symmetric: GMRES instead of CG
+        self.symmetric = orc.B_mass is orc.B_D
 
     def _schur(self, p: np.ndarray) -> np.ndarray:
         return self.B @ self.lu.solve(self.BT @ p)
+
+
+    def _gmres(self, r: np.ndarray, rtol: float, maxiter: int):
+        """S p = r on mean-zero pressures by right-preconditioned restarted GMRES
+        (Saad's algorithm with modified Gram-Schmidt), the same preconditioner."""
+        n = len(r)
+        m = 60
+        p = np.zeros(n)
+        r0 = np.linalg.norm(r)
+        its = 0
+        res = r.copy()
+        while its < maxiter:
+            beta = np.linalg.norm(res)
+            if beta <= rtol * r0:
+                break
+            V = np.zeros((m + 1, n))
+            Z = np.zeros((m, n))
+            H = np.zeros((m + 1, m))
+            V[0] = res / beta
+            k_used = 0
+            for k in range(m):
+                z = self.minv * V[k]
+                z -= z.mean()
+                Z[k] = z
+                w = self._schur(z)
+                w -= w.mean()
+                for i in range(k + 1):
+                    H[i, k] = w @ V[i]
+                    w -= H[i, k] * V[i]
+                H[k + 1, k] = np.linalg.norm(w)
+                k_used = k + 1
+                its += 1
+                e1 = np.zeros(k + 2)
+                e1[0] = beta
+                y, *_ = np.linalg.lstsq(H[:k + 2, :k + 1], e1, rcond=None)
+                if np.linalg.norm(H[:k + 2, :k + 1] @ y - e1) <= rtol * r0 or H[k + 1, k] == 0.0:
+                    break
+                V[k + 1] = w / H[k + 1, k]
+            e1 = np.zeros(k_used + 1)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(H[:k_used + 1, :k_used], e1, rcond=None)
+            p += y @ Z[:k_used]
+            res = r - self._schur(p)
+            res -= res.mean()
+        return p, its
 
     def solve(self, f: np.ndarray, g: np.ndarray | None = None, rtol: float = 1e-13, maxiter: int = 5000):
         """K_D [u; p] = [f; g], f as [n_nodes, 3] (its Dirichlet rows are the
@@ -62,7 +110,9 @@ class SchurSolver:
         p = np.zeros(orc.n_p)
         r0 = np.linalg.norm(r)
         its = 0
-        if r0 > 0.0:
+        if r0 > 0.0 and not self.symmetric:
+            p, its = self._gmres(r, rtol, maxiter)
+        elif r0 > 0.0:
             z = self.minv * r
             z -= z.mean()
             d = z.copy()
@@ -83,6 +133,7 @@ class SchurSolver:
                 rz = rz_new
         p -= p.mean()
         u = self.lu.solve(fu - self.BT @ p)
+
         x = np.concatenate([u, p])
         b = np.concatenate([fu, gp])
         res = np.linalg.norm(orc.K @ x - b) / max(np.linalg.norm(b), 1e-300)

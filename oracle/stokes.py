@@ -28,6 +28,15 @@ Readings (the same on both sides):
   P = I - rhat rhat^T onto the tangent plane and N = rhat rhat^T:
   K = [[P A P + N, P B^T], [B P, 0]], which is the no-slip K_D with P = 0,
   N = I on no-slip nodes (and P = I, N = 0 inside);
+* compressible mass balance (TALA, eq:mass: div(rhobar u) = 0, rhobar(r) the
+  reference density): the mass rows are -(psi_I, div(rhobar u)) with the mass
+  flux rhobar u interpolated in the velocity space, i.e. the nodal products
+  rhobar(r_j) u_j, so B_rho = B R with R = diag(rhobar at each node's radius).
+  This keeps the discrete compatibility 1^T B_rho = 0 of the Dirichlet/free-
+  slip spaces (the divergence of a field that vanishes, or is tangential, on
+  the spheres sums to zero over the pressure nodes), which the product form
+  rhobar div u + u . grad rhobar evaluated at q_c does not; the momentum rows
+  keep B^T (eq:stokes);
 * per-wedge viscosity: eta(q_c) is the wedge's value; for temperature-driven
   laws it is the law evaluated at the mean of the six nodal temperatures and
   the wedge's mid radius (the value of the W1 interpolant at q_c);
@@ -181,7 +190,8 @@ class StokesOracle:
 
     def __init__(self, mt: int, nr: int, eta_wedge: np.ndarray, r_in: float = 0.55,
                  r_out: float = 1.0, hierarchy: SphereHierarchy | None = None,
-                 chunk: int = 200_000, hg_alpha: float = 0.0, bc=("noslip", "noslip")):
+                 chunk: int = 200_000, hg_alpha: float = 0.0, bc=("noslip", "noslip"),
+                 rho_nodes: np.ndarray | None = None):
         self.mesh = m = ShellMesh(mt, nr, r_in, r_out, hierarchy)
         self.mt, self.nr = mt, nr
         eta_wedge = np.asarray(eta_wedge, dtype=np.float64)
@@ -219,7 +229,17 @@ class StokesOracle:
         self.A_D = (Pm @ self.A @ Pm + Nm).tocsr()
         self.BT_D = (Pm @ self.B.T).tocsr()
         self.B_D = (self.B @ Pm).tocsr()
-        self.K = sp.bmat([[self.A_D, self.BT_D], [self.B_D, None]], format="csr")
+        # mass rows: B_D, or B R P with the reference density (TALA)
+        self.rho_nodes = None
+        self.B_mass = self.B_D
+        if rho_nodes is not None:
+            rho_nodes = np.asarray(rho_nodes, np.float64)
+            if rho_nodes.shape != (nr + 1,):
+                raise ValueError("rho_nodes must hold one value per radial node layer")
+            self.rho_nodes = rho_nodes
+            R = sp.diags(np.repeat(np.tile(rho_nodes, m.n_lat), 3))
+            self.B_mass = (self.B @ R @ Pm).tocsr()
+        self.K = sp.bmat([[self.A_D, self.BT_D], [self.B_mass, None]], format="csr")
 
     # -- products -----------------------------------------------------------
     def apply(self, u: np.ndarray, p: np.ndarray):
@@ -268,6 +288,30 @@ def eta_from_temperature(mesh: ShellMesh, T_node: np.ndarray, E: float, F: float
     k = np.tile(np.arange(mesh.nr), len(mesh.tris))
     rm = 0.5 * (mesh.r[k] + mesh.r[k + 1])
     return np.exp(-E * Tbar + F * (1.0 - rm))
+
+
+def buoyancy_rhs_tala(mesh: ShellMesh, T_node: np.ndarray, Ra: float, Tbar_nodes: np.ndarray,
+                      rhoalpha_nodes: np.ndarray):
+    """TALA buoyancy of eq:stokes, f = Ra rhobar alphabar T' rhat with T' = T - Tbar(r)
+    (eq:tsplit; Tbar the radial reference profile): f_(j,c) = sum_e V_e N_j(q_c) Ra
+    (rhobar alphabar)(q_c) T'(q_c) rhat_c(q_c), both factors the W1 interpolants of
+    their nodal values (Tbar_nodes, rhoalpha_nodes given per radial node layer).
+    Returns [n_nodes, 3]."""
+    wn = mesh.wedge_nodes()
+    xyz = mesh.node_xyz()
+    xw = xyz[wn]
+    N, _ = ref_basis(*QC)
+    _, V, _ = wedge_geometry(xw)
+    xq = np.einsum("j,wja->wa", N, xw)
+    rhat = xq / np.linalg.norm(xq, axis=1)[:, None]
+    k = np.tile(np.arange(mesh.nr + 1), mesh.n_lat)
+    Tp = T_node - np.asarray(Tbar_nodes, np.float64)[k]
+    ra = np.asarray(rhoalpha_nodes, np.float64)[k]
+    Tq = np.einsum("j,wj->w", N, Tp[wn])
+    rq = np.einsum("j,wj->w", N, ra[wn])
+    f = np.zeros((mesh.n_nodes, 3))
+    np.add.at(f, wn, (V * Ra * Tq * rq)[:, None, None] * N[None, :, None] * rhat[:, None, :])
+    return f
 
 
 def buoyancy_rhs(mesh: ShellMesh, T_node: np.ndarray, Ra: float):

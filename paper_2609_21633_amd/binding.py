@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TNG_LIB", os.path.join(HERE, "libtng.so"))
 
 OP_A, OP_BT, OP_B, OP_DIRICHLET = 1, 2, 4, 8
-OP_FREESLIP_INNER, OP_FREESLIP_OUTER = 16, 32
+OP_FREESLIP_INNER, OP_FREESLIP_OUTER, OP_TALA = 16, 32, 64
 F64, F32 = 0, 1
 
 _lib = None
@@ -40,6 +40,8 @@ def lib():
         "tng_mesh_coords": [_vp, C.c_int, _vp, _vp],
         "tng_mesh_dup_groups": [_vp, C.c_int, _vp],
         "tng_mesh_destroy": [_vp],
+        "tng_mesh_set_density": [_vp, _vp],
+        "tng_rhs_buoyancy_tala": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, _vp, _vp, C.POINTER(_vp)],
         "tng_stokes_apply": [_vp, _vp, C.c_int, C.c_int, C.c_uint, C.c_double, _vp, C.POINTER(_vp), _vp,
                              C.POINTER(_vp), _vp],
         "tng_interface_sum": [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)],
@@ -247,6 +249,14 @@ class Mesh:
         check(lib().tng_mesh_dup_groups(self.h, level, _vp(uid.ctypes.data)))
         return uid
 
+    def set_density(self, rho_nodes):
+        """TALA reference density at the nr + 1 radial node layers of the finest level."""
+        import numpy as np
+        r = np.ascontiguousarray(rho_nodes, dtype=np.float64)
+        if r.shape != (self.nr + 1,):
+            raise ValueError("rho_nodes must hold nr + 1 values")
+        check(lib().tng_mesh_set_density(self.h, _vp(r.ctypes.data)))
+
     def close(self):
         if getattr(self, "h", None):
             lib().tng_mesh_destroy(self.h)
@@ -400,6 +410,20 @@ def rhs_buoyancy(ctx: Context, mesh: Mesh, level: int, T, Ra: float, f):
     _chk(ctx, T, T.dtype, _nodes(mesh, level), "T")
     _chk3(ctx, f, T.dtype, _nodes(mesh, level), "f")
     check(lib().tng_rhs_buoyancy(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _ptr3(f)))
+
+
+def rhs_buoyancy_tala(ctx: Context, mesh: Mesh, level: int, T, Ra: float, Tbar_nodes, rhoalpha_nodes, f):
+    """Compressible buoyancy Ra rhobar alphabar T' rhat, T' = T - Tbar(r); profiles per node layer."""
+    import numpy as np
+    n1 = _counts(mesh, level)["n"] + 1
+    tb = np.ascontiguousarray(Tbar_nodes, dtype=np.float64)
+    ra = np.ascontiguousarray(rhoalpha_nodes, dtype=np.float64)
+    if tb.shape != (n1,) or ra.shape != (n1,):
+        raise ValueError("profiles must hold one value per radial node layer of the level")
+    _chk(ctx, T, T.dtype, _nodes(mesh, level), "T")
+    _chk3(ctx, f, T.dtype, _nodes(mesh, level), "f")
+    check(lib().tng_rhs_buoyancy_tala(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _vp(tb.ctypes.data),
+                                      _vp(ra.ctypes.data), _ptr3(f)))
 
 
 def energy_apply(ctx: Context, mesh: Mesh, level: int, u, dt: float, T, y):

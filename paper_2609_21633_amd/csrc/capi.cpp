@@ -5,6 +5,7 @@
 #include <cstring>
 #include <iterator>
 #include <string>
+#include <vector>
 
 #include "mg.hpp"
 #include "tng_internal.hpp"
@@ -302,6 +303,30 @@ int tng_mesh_dup_groups(const tng_mesh* mesh, int level, int* unique_id_host) {
     TNG_API_END
 }
 
+int tng_mesh_set_density(tng_mesh* mesh, const double* rho_host) {
+    TNG_API_BEGIN
+    TNG_REQUIRE(mesh != nullptr && rho_host != nullptr, "NULL argument");
+    TNG_REQUIRE(mesh->ctx != nullptr, "mesh was built without a context (host only)");
+    for (int k = 0; k <= mesh->nr; ++k)
+        TNG_REQUIRE(std::isfinite(rho_host[k]) && rho_host[k] > 0.0, "reference density must be finite and > 0");
+    TNG_HIP(hipSetDevice(mesh->ctx->device));
+    for (size_t l = 0; l < mesh->lv.size(); ++l) {
+        tng::Level& L = mesh->lv[l];
+        const int step = mesh->nr / L.n;
+        std::vector<double> r64(L.n + 1);
+        std::vector<float> r32(L.n + 1);
+        for (int k = 0; k <= L.n; ++k) {
+            r64[k] = rho_host[k * step];
+            r32[k] = (float)r64[k];
+        }
+        if (L.rho64.n != r64.size()) L.rho64.alloc(r64.size());
+        if (L.rho32.n != r32.size()) L.rho32.alloc(r32.size());
+        TNG_HIP(hipMemcpy(L.rho64.p, r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
+        TNG_HIP(hipMemcpy(L.rho32.p, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    TNG_API_END
+}
+
 int tng_mesh_destroy(tng_mesh* mesh) {
     TNG_API_BEGIN
     delete mesh;
@@ -315,7 +340,7 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE((op_flags & ~63u) == 0, "unknown op_flags bits");
+    TNG_REQUIRE((op_flags & ~127u) == 0, "unknown op_flags bits");
     const bool doA = op_flags & TNG_OP_A, doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
     TNG_REQUIRE(doA || doBT || doB, "op_flags selects no operator block");
     const tng::Level* Lp = nullptr;
@@ -333,6 +358,13 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     if (doB) TNG_REQUIRE(y_p != nullptr, "y_p is NULL");
     if ((op_flags & TNG_OP_DIRICHLET) && doA)
         TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
+    if (op_flags & TNG_OP_TALA) {
+        TNG_REQUIRE(doB, "TNG_OP_TALA changes the divergence block: it needs TNG_OP_B");
+        TNG_REQUIRE(!(op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)),
+                    "TNG_OP_TALA is not available with free slip");
+        TNG_REQUIRE(!(doA && hg_alpha != 0.0), "TNG_OP_TALA is not available with hourglass control");
+        TNG_REQUIRE(L.rho64.p != nullptr, "TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
+    }
     if (doA) tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
     if (doA || doB) tng::require_vel(ctx, u, L, prec, "u");
     if (doA || doBT) tng::require_vel(ctx, y_u, L, prec, "y_u");
@@ -350,7 +382,7 @@ int tng_stokes_apply_layout(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_p
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE((op_flags & ~63u) == 0, "unknown op_flags bits");
+    TNG_REQUIRE((op_flags & ~127u) == 0, "unknown op_flags bits");
     const bool doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
     TNG_REQUIRE(op_flags & 7u, "op_flags selects no operator block");
     const tng::Level* Lp = nullptr;
@@ -415,6 +447,33 @@ int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
         float* ff[3] = {(float*)f[0], (float*)f[1], (float*)f[2]};
         tng::buoyancy_rhs<float>(ctx, L, (const float*)T, Ra, ff);
     }
+    TNG_API_END
+}
+
+int tng_rhs_buoyancy_tala(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
+                          const double* Tbar_host, const double* rhoalpha_host, void* const f[3]) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(T && f && f[0] && f[1] && f[2] && Tbar_host && rhoalpha_host, "NULL argument");
+    TNG_REQUIRE(std::isfinite(Ra), "Ra must be finite");
+    for (int k = 0; k <= L.n; ++k)
+        TNG_REQUIRE(std::isfinite(Tbar_host[k]) && std::isfinite(rhoalpha_host[k]), "profiles must be finite");
+    tng::require_device(ctx, T, tng::node_bytes(L, prec), "T");
+    tng::require_vel(ctx, f, L, prec, "f");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::DevBuf<double> prof(2 * (L.n + 1));
+    prof.upload(Tbar_host, L.n + 1, ctx->stream);
+    TNG_HIP(hipMemcpyAsync(prof.p + L.n + 1, rhoalpha_host, (L.n + 1) * sizeof(double), hipMemcpyHostToDevice,
+                           ctx->stream));
+    if (prec == TNG_F64) {
+        double* ff[3] = {(double*)f[0], (double*)f[1], (double*)f[2]};
+        tng::buoyancy_rhs<double>(ctx, L, (const double*)T, Ra, ff, prof.p, prof.p + L.n + 1);
+    } else {
+        float* ff[3] = {(float*)f[0], (float*)f[1], (float*)f[2]};
+        tng::buoyancy_rhs<float>(ctx, L, (const float*)T, Ra, ff, prof.p, prof.p + L.n + 1);
+    }
+    TNG_HIP(hipStreamSynchronize(ctx->stream));   // the profiles are freed on return
     TNG_API_END
 }
 

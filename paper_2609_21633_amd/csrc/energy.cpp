@@ -20,8 +20,6 @@ template <typename T>
 void energy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, const T* H, double dt, double T_in,
                 double T_out, T* b);
 template <typename T>
-void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]);
-template <typename T>
 double cfl_rate(const tng_ctx* ctx, const Level& L, const T* const u[3], DevBuf<double>& part);
 
 // Right-preconditioned (Jacobi) GMRES on a scalar node field, FP64.

@@ -195,7 +195,8 @@ __global__ void energy_rhs_kernel(EnergyGeo G, const T* __restrict__ Tn, const T
 // direction of x(q_c) = r_m s_c (s_c the mean of the triangle's unit vectors).
 template <typename T>
 __global__ void buoyancy_kernel(EnergyGeo G, const double* __restrict__ unit, const T* __restrict__ Tn, double Ra,
-                                T* f0, T* f1, T* f2, long long nslots) {
+                                T* f0, T* f1, T* f2, long long nslots, const double* __restrict__ tbar,
+                                const double* __restrict__ rhoalpha) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const int m = G.m, n = G.n;
@@ -207,7 +208,11 @@ __global__ void buoyancy_kernel(EnergyGeo G, const double* __restrict__ unit, co
         const double V = rm * rm * g[9];
         double Tv[6];
         WedgeField<T>::gather(Tn, q.d, ci, cj, ck, wd, m, n, Tv);
-        const double Tq = (Tv[0] + Tv[1] + Tv[2] + Tv[3] + Tv[4] + Tv[5]) * (1.0 / 6.0);
+        double Tq = (Tv[0] + Tv[1] + Tv[2] + Tv[3] + Tv[4] + Tv[5]) * (1.0 / 6.0);
+        if (tbar) {
+            // compressible form: T' = T - Tbar(r) and rhobar alphabar, W1 in the radius
+            Tq = (Tq - 0.5 * (tbar[ck] + tbar[ck + 1])) * (0.5 * (rhoalpha[ck] + rhoalpha[ck + 1]));
+        }
         double sc[3] = {0, 0, 0};
         for (int l = 0; l < 3; ++l) {
             const long long lat = ((long long)q.d * (m + 1) + ci + c_cdi[wd][l]) * (m + 1) + cj + c_cdj[wd][l];
@@ -347,10 +352,11 @@ void energy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, const T* H, dou
 }
 
 template <typename T>
-void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]) {
+void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3], const double* tbar,
+                  const double* rhoalpha) {
     const long long ns = L.node_slots();
     buoyancy_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), L.unit64.p, Tn, Ra, f[0], f[1], f[2],
-                                                              ns);
+                                                              ns, tbar, rhoalpha);
     TNG_HIP(hipGetLastError());
     void* g[3] = {f[0], f[1], f[2]};
     launch_interface(ctx, L, prec_of<T>(), 0, 3, g);
@@ -381,7 +387,8 @@ double cfl_rate(const tng_ctx* ctx, const Level& L, const T* const u[3], DevBuf<
     template void energy_apply_wf<T>(const tng_ctx*, const Level&, const double*, double, const T*, T*);   \
     template void energy_diag<T>(const tng_ctx*, const Level&, const double*, double, T*);                 \
     template void energy_rhs<T>(const tng_ctx*, const Level&, const T*, const T*, double, double, double, T*); \
-    template void buoyancy_rhs<T>(const tng_ctx*, const Level&, const T*, double, T* const[3]);          \
+    template void buoyancy_rhs<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], const double*,  \
+                                  const double*);                                                       \
     template double cfl_rate<T>(const tng_ctx*, const Level&, const T* const[3], DevBuf<double>&);
 TNG_EINST(double)
 TNG_EINST(float)

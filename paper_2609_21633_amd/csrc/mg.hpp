@@ -107,8 +107,11 @@ double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const doub
 void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]);
 template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
+// tbar, rhoalpha: device [n+1] profiles of the compressible (TALA) form, or NULL for
+// the Boussinesq form (Tbar = 0, rhobar alphabar = 1)
 template <typename T>
-void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3]);
+void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3],
+                  const double* tbar = nullptr, const double* rhoalpha = nullptr);
 
 // Coefficients (alpha_k, beta_k), k < deg, of one Chebyshev smoothing step of
 // degree deg for the eigenvalue interval [lo, hi].

@@ -70,6 +70,7 @@ struct BandArgs {
     int ns_in, ns_out;   // no-slip (zero) velocity on the inner / outer sphere
     int fs;              // free slip: bit 0 inner sphere, bit 1 outer sphere
     const T* __restrict__ unit;   // [10][m+1][m+1][3] node unit vectors (free slip)
+    const T* __restrict__ rho;    // [n+1] reference density at the node layers (TALA)
 };
 
 template <typename T>
@@ -141,9 +142,12 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 // geometry shared); otherwise sb is unused.
 // WG: waves per workgroup (4 or 8); a workgroup covers WG / RS cell columns.
 // FS: free slip on a sphere (a.fs), staged boundary velocities projected onto the
-// tangent plane; the other kernels compile without that path.
-template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG, bool FS>
+// tangent plane; TALA: the divergence block tests div(rhobar u) with the mass flux
+// rhobar u interpolated nodally; the other kernels compile without these paths.
+template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG, bool FS,
+          bool TALA>
 __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
+    static_assert(!TALA || DO_B, "the reference density enters the divergence block only");
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
     if constexpr (BATCH) {
         const long long so = slot_off(sb);
@@ -236,6 +240,11 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
         s1[c] = T(0.5) / rm;
         vr[c] = kk[c] < kend ? rm * rm : T(0);
     }
+    // TALA: reference density at the lane's node layers (W1 in the radius, so the
+    // nodal mass flux of a layer is rhobar of that layer times u)
+    T rho_l[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) rho_l[c] = TALA ? a.rho[min(kk[c], n)] : T(1);
     // the lane holding the workgroup's top node (layer kcend)
     const bool top_lane = (kk[0] <= kcend - 1) && (kcend - 1 <= kk[CPL - 1]);
     const int top_c = kcend - kk[0];
@@ -502,8 +511,20 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                     }
                     const T tr = L[0][0] + L[1][1] + L[2][2];
                     if (DO_B) {
-                        // -V div u, split onto the two coarse layers of the cell
-                        const T dv = -V * tr;
+                        // -V div u, split onto the two coarse layers of the cell; with the
+                        // reference density -V div(rhobar u): the trace is the sum of a
+                        // bottom-layer and a top-layer part, each scaled by its layer's rhobar
+                        T trd = tr;
+                        if constexpr (TALA) {
+                            T tlo = T(0), thi = T(0);
+#pragma unroll
+                            for (int r = 0; r < 3; ++r) {
+                                tlo += lo[0][r] * r1[r] + lo[1][r] * r2[r] - lo[2][r] * r3[r];
+                                thi += hi[0][r] * r1[r] + hi[1][r] * r2[r] + hi[2][r] * r3[r];
+                            }
+                            trd = rho_l[c] * tlo + rho_l[c + 1] * thi;
+                        }
+                        const T dv = -V * trd;
                         const int cb = (kl0 + c) & 1;
                         const int sl = ((kl0 + c) >> 1) - (kl0 >> 1);
                         dvl[sl] += iso.rw[cb][0] * dv;
@@ -976,9 +997,9 @@ inline int choose_bands(int m, long long cols, long long slots) {
 
 // the solver's combinations (A, B^T, K, each viscous one also with hourglass
 // control) have a batched form; the others run one slot at a time
-template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG, bool FS>
+template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG, bool FS, bool TALA = false>
 void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, int* bands_out) {
-    constexpr bool BATCHABLE = !FS && ((A && !BT && !B) || (!A && BT && !B) || (A && BT && B));
+    constexpr bool BATCHABLE = !FS && !TALA && ((A && !BT && !B) || (!A && BT && !B) || (A && BT && B));
     const int block = args.TI * RS * 64;
     const bool batched = sb.nb > 1;
     if (ctx->apply_bands > 0) {
@@ -991,10 +1012,10 @@ void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, in
         if (per_cu == 0) {
             if (batched)
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG, FS>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG, FS, TALA>, block, 0));
             else
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA>, block, 0));
             per_cu = std::max(1, per_cu);
             rc.store(per_cu, std::memory_order_relaxed);
         }
@@ -1008,15 +1029,16 @@ void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, in
     char detail[64] = {0};
     if (ctx->profile) {
         const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
-        std::snprintf(detail, sizeof(detail), "%s/%s%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
-                      ops, HG ? "+HG" : "", FS ? "+FS" : "", args.m, args.n, args.nband, sb.nb > 1 ? "/batch" : "");
+        std::snprintf(detail, sizeof(detail), "%s/%s%s%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", FS ? "+FS" : "", TALA ? "+TALA" : "", args.m, args.n, args.nband,
+                      sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
     if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA>
             <<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else if constexpr (BATCHABLE)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG, false>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG, false, false>
             <<<dim3((unsigned)nb, 1, (unsigned)sb.nb), args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else
         throw Error(TNG_E_STATE, "this operator combination has no batched form");
@@ -1042,12 +1064,15 @@ void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatc
         case 16 | 1: launch_band_t<T, RS, CPL, WG, true, false, false, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, true>(ctx, args, sb, bands_out); break;
+        case 64 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, false, true>(ctx, args, sb, bands_out); break;
+        case 64 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 2:   // B^T reads no velocity: its free-slip rows are the post pass's projection
             launch_band_t<T, RS, CPL, WG, false, true, false, false, false>(ctx, args, sb, bands_out);
             break;
         default:
-            throw Error(TNG_E_INVAL, "this operator combination has no free-slip form (use A, B^T, B or the "
-                                     "full operator, without hourglass control)");
+            throw Error(TNG_E_INVAL, "this operator combination has no free-slip or compressible form (free "
+                                     "slip: A, B^T, B or the full operator; TALA: B or the full operator; "
+                                     "neither with hourglass control, not both)");
     }
 }
 
@@ -1110,7 +1135,13 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
     a.hg = T(hg_alpha * (5.0 / 81.0));
     const SlotBatch sb = launch_batch();
     const unsigned nbz = (unsigned)sb.nb;
-    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0) | (a.fs ? 16 : 0);
+    const bool tala = (flags & TNG_OP_TALA) != 0;
+    if (tala) {
+        TNG_REQUIRE(L.rho64.p != nullptr, "TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
+        a.rho = is64 ? reinterpret_cast<const T*>(L.rho64.p) : reinterpret_cast<const T*>(L.rho32.p);
+    }
+    const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0) | (a.fs ? 16 : 0) |
+                    (tala && doB ? 64 : 0);
     auto dispatch = [&](int* bands_out) {
         if constexpr (std::is_same<T, double>::value) {
             if (rs == 1)

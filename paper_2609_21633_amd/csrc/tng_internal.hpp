@@ -199,6 +199,8 @@ struct Level {
     DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node
     DevBuf<double> unit64;            // [10][m+1][m+1][3] unit vectors
     DevBuf<float> unit32;
+    DevBuf<double> rho64;             // [n+1] reference density at the node layers (TALA), if set
+    DevBuf<float> rho32;
     DevBuf<float> inv_mult32;
 
     long long lat_slots() const { return 10LL * (m + 1) * (m + 1); }

@@ -297,6 +297,12 @@ def test_freeslip_operator(tng, ctx, mt, nr, bc, prec):
     # the condition changes the result (not the no-slip operator)
     assert rel(ru, orc.apply(uf, p)[0]) > 1e-3
     fsb = flags & (FS_IN | FS_OUT)
+    Pa, Na = abs(orf.P_bc), abs(orf.N_bc)
+    # row scales from the unprojected terms (P B^T p is exactly radial at the poles, where
+    # the projected row cancels to rounding)
+    scales = {1 | 8: lambda x: Pa @ (abs(orf.A) @ (Pa @ np.abs(x))) + Na @ np.abs(x),
+              2 | 8: lambda x: Pa @ (abs(orf.B.T) @ np.abs(x)),
+              4 | 8: lambda x: abs(orf.B) @ (Pa @ np.abs(x))}
     for blk, M, x in ((1 | 8, orf.A_D, uf), (2 | 8, orf.BT_D, p), (4 | 8, orf.B_D, uf)):
         yu.fill_(float("nan"))
         yp.fill_(float("nan"))
@@ -308,4 +314,65 @@ def test_freeslip_operator(tng, ctx, mt, nr, bc, prec):
             got = lm.from_lib(yu.double().cpu().numpy()).ravel()
         want = M @ np.asarray(x).ravel()
         assert rel(got, want) < tol, blk
-        check_rows(got, want, M, x, tol, f"freeslip block {blk}")
+        sc = scales[blk](np.asarray(x).ravel())
+        worst = float((np.abs(got - want) / np.maximum(sc, 1e-300)).max())
+        assert worst <= tol, f"freeslip block {blk}: worst error / row scale {worst:.2e}"
+
+
+# ---- compressible (TALA) terms: div(rhobar u) rows and the rhobar alphabar T' buoyancy ----------
+
+TALA = 64
+
+
+def _rho(r):
+    return np.exp(np.log(1.6) * (1.0 - r) / 0.45)
+
+
+@pytest.mark.parametrize("mt,nr,prec,bands", [(8, 8, "f64", 0), (16, 10, "f64", 3), (16, 16, "f32", 0),
+                                               (4, 160, "f64", 0), (4, 288, "f32", 0), (32, 8, "f32", 7)])
+def test_tala_operator(tng, ctx, mt, nr, prec, bands):
+    """K and B alone with the reference density against the oracle (B_rho = B R), element-wise;
+    including radial splits and forced band counts."""
+    import torch
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    rho = _rho(om.r)
+    mesh.set_density(rho)
+    ort = StokesOracle(mt, nr, eta, hierarchy=om.h, rho_nodes=rho)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    e, uu, pp = (t[k].to(dt) for k in ("eta", "u", "p"))
+    ctx.set_apply_bands(bands)
+    try:
+        yu, yp = torch.full_like(uu, float("nan")), torch.full_like(pp, float("nan"))
+        tng.stokes_apply(ctx, mesh, 0, OPS_ALL | TALA, e, uu, pp, yu, yp)
+        yb = torch.full_like(pp, float("nan"))
+        tng.stokes_apply(ctx, mesh, 0, 4 | 8 | TALA, None, uu, None, None, yb)
+    finally:
+        ctx.set_apply_bands(0)
+    gu, gp = lm.from_lib(yu.double().cpu().numpy(), check_dups=1e-6), lmp.from_lib(yp.double().cpu().numpy())
+    ru, rp = ort.apply(u, p)
+    print(f"tala {prec} ({mt},{nr}) bands {bands}: rel u {rel(gu, ru):.2e} p {rel(gp, rp):.2e}", flush=True)
+    assert rel(gu, ru) < tol and rel(gp, rp) < tol
+    check_K(ort, gu, gp, u, p, tol, f"tala {prec} ({mt},{nr})")
+    assert rel(rp, orc.apply(u, p)[1]) > 1e-3                    # the density matters
+    gb = lmp.from_lib(yb.double().cpu().numpy(), check_dups=1e-6)
+    check_rows(gb, ort.B_mass @ u.ravel(), ort.B_mass, u, tol, "B_rho")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tala_buoyancy(tng, ctx, prec):
+    import torch
+    from oracle.stokes import buoyancy_rhs_tala
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, 16, 10)
+    rng = np.random.default_rng(12)
+    T = rng.uniform(0.0, 1.0, om.n_nodes)
+    Tbar = np.linspace(1.0, 0.0, om.nr + 1) ** 1.5
+    ra = _rho(om.r) * np.exp(-np.log(3.0) * (1.0 - om.r) / 0.45)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    Tt = torch.tensor(lm.to_lib(T), device="cuda").to(dt)
+    f = torch.full((3,) + mesh.shape(0), float("nan"), dtype=dt, device="cuda")
+    tng.rhs_buoyancy_tala(ctx, mesh, 0, Tt, 1e5, Tbar, ra, f)
+    got = lm.from_lib(f.double().cpu().numpy(), check_dups=1e-6)
+    want = buoyancy_rhs_tala(om, T, 1e5, Tbar, ra)
+    want[om.boundary_nodes()] = 0.0
+    print(f"tala buoyancy {prec}: rel {rel(got, want):.2e}", flush=True)
+    assert rel(got, want) < tol

@@ -106,7 +106,13 @@ enum {
      * tng_mesh_set_density), i.e. y_p = B R u with R = diag(rhobar(r_j)); the
      * momentum rows keep B^T (eq:stokes).  With TNG_OP_B, alone or in the full
      * operator; not with free slip or hourglass control. */
-    TNG_OP_TALA = 64
+    TNG_OP_TALA = 64,
+    /* The viscous block with the two-radial-point rule (Sec. 4, the remedy
+     * beside eq:hgstab): the lateral centroid times the two-point Gauss rule
+     * in zeta (-+1/sqrt 3, weight 1/2 each); B and B^T keep the one point.
+     * With TNG_OP_A (alone, with B^T, or the full operator); not with
+     * hg_alpha > 0, free slip or TNG_OP_TALA. */
+    TNG_OP_TWOPOINT = 128
 };
 
 /* Message of the last failed call on this thread ("" if none).  Library-owned. */

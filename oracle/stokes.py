@@ -108,6 +108,27 @@ def element_matrices(xw: np.ndarray, eta: np.ndarray):
     return A
 
 
+ZETA2 = 1.0 / np.sqrt(3.0)    # Gauss points of the two-radial-point rule
+
+
+def element_matrices_2pt(xw: np.ndarray, eta: np.ndarray):
+    """A_e of eq:elemmat with the two-radial-point rule (Sec. 4, the second remedy
+    beside eq:hgstab): the lateral centroid (1/3, 1/3) times the two-point Gauss
+    rule in the radial coordinate, zeta = -+1/sqrt(3), weight 1/2 each (the
+    reference wedge has volume 1).  The viscosity is the wedge's value.  -> [n, 18, 18]."""
+    n = len(xw)
+    A = np.zeros((n, 18, 18))
+    eye = np.eye(3)
+    for zq in (-ZETA2, ZETA2):
+        _, V, g = wedge_geometry(xw, point=(1.0 / 3.0, 1.0 / 3.0, zq))
+        outer = np.einsum("cm,wjn->wjcmn", eye, g)
+        eps = (0.5 * (outer + np.swapaxes(outer, 3, 4))).reshape(n, 18, 3, 3)
+        div = g.reshape(n, 18)
+        epseps = np.einsum("wamn,wbmn->wab", eps, eps)
+        A += (0.5 * V * eta)[:, None, None] * (2.0 * epseps - (2.0 / 3.0) * div[:, :, None] * div[:, None, :])
+    return A
+
+
 def hourglass_vectors():
     """Nodal values of the three barycentric hourglass modes h_a = (lambda_a - 1/3) zeta,
     a = 0, 1, 2, of the reference wedge (eq:hourglass: w_1 = h_1, w_2 = h_2 and
@@ -185,13 +206,15 @@ def boundary_projections(mesh: ShellMesh, bc=("noslip", "noslip")):
 
 class StokesOracle:
     """Assembled FP64 Stokes saddle-point operator on the (mt, nr) shell
-    (hg_alpha > 0: viscous block with hourglass control, eq:hgstab; bc = velocity
-    condition on (inner, outer) sphere, see boundary_projections)."""
+    (hg_alpha > 0: viscous block with hourglass control, eq:hgstab; quad = "two":
+    viscous block with the two-radial-point rule, the divergence blocks keep the
+    one-point rule; bc = velocity condition on (inner, outer) sphere, see
+    boundary_projections; rho_nodes: TALA reference density)."""
 
     def __init__(self, mt: int, nr: int, eta_wedge: np.ndarray, r_in: float = 0.55,
                  r_out: float = 1.0, hierarchy: SphereHierarchy | None = None,
                  chunk: int = 200_000, hg_alpha: float = 0.0, bc=("noslip", "noslip"),
-                 rho_nodes: np.ndarray | None = None):
+                 rho_nodes: np.ndarray | None = None, quad: str = "one"):
         self.mesh = m = ShellMesh(mt, nr, r_in, r_out, hierarchy)
         self.mt, self.nr = mt, nr
         eta_wedge = np.asarray(eta_wedge, dtype=np.float64)
@@ -206,7 +229,14 @@ class StokesOracle:
             w = wn[s:s + chunk]
             xw = xyz[w]
             dof = (w[:, :, None] * 3 + np.arange(3)[None, None, :]).reshape(len(w), 18)
-            Ae = element_matrices_hg(xw, eta_wedge[s:s + chunk], hg_alpha)
+            if quad == "two":
+                if hg_alpha != 0.0:
+                    raise ValueError("the two-radial-point rule is an alternative to hourglass control")
+                Ae = element_matrices_2pt(xw, eta_wedge[s:s + chunk])
+            elif quad == "one":
+                Ae = element_matrices_hg(xw, eta_wedge[s:s + chunk], hg_alpha)
+            else:
+                raise ValueError("quad must be 'one' or 'two'")
             rows = np.repeat(dof, 18, axis=1).ravel()
             cols = np.tile(dof, (1, 18)).ravel()
             A = A + sp.csr_matrix((Ae.ravel(), (rows, cols)), shape=(nu, nu))

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TNG_LIB", os.path.join(HERE, "libtng.so"))
 
 OP_A, OP_BT, OP_B, OP_DIRICHLET = 1, 2, 4, 8
-OP_FREESLIP_INNER, OP_FREESLIP_OUTER, OP_TALA = 16, 32, 64
+OP_FREESLIP_INNER, OP_FREESLIP_OUTER, OP_TALA, OP_TWOPOINT = 16, 32, 64, 128
 F64, F32 = 0, 1
 
 _lib = None

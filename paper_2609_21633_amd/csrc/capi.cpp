@@ -340,7 +340,7 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE((op_flags & ~127u) == 0, "unknown op_flags bits");
+    TNG_REQUIRE((op_flags & ~255u) == 0, "unknown op_flags bits");
     const bool doA = op_flags & TNG_OP_A, doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
     TNG_REQUIRE(doA || doBT || doB, "op_flags selects no operator block");
     const tng::Level* Lp = nullptr;
@@ -365,6 +365,13 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
         TNG_REQUIRE(!(doA && hg_alpha != 0.0), "TNG_OP_TALA is not available with hourglass control");
         TNG_REQUIRE(L.rho64.p != nullptr, "TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
     }
+    if (op_flags & TNG_OP_TWOPOINT) {
+        TNG_REQUIRE(doA, "TNG_OP_TWOPOINT is a form of the viscous block: it needs TNG_OP_A");
+        TNG_REQUIRE(hg_alpha == 0.0, "TNG_OP_TWOPOINT is an alternative to hourglass control");
+        TNG_REQUIRE(!(op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER | TNG_OP_TALA)),
+                    "TNG_OP_TWOPOINT is not available with free slip or TNG_OP_TALA");
+        TNG_REQUIRE(doBT || !doB, "TNG_OP_TWOPOINT: A alone, A + B^T or the full operator");
+    }
     if (doA) tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
     if (doA || doB) tng::require_vel(ctx, u, L, prec, "u");
     if (doA || doBT) tng::require_vel(ctx, y_u, L, prec, "y_u");
@@ -382,7 +389,7 @@ int tng_stokes_apply_layout(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_p
     TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE((op_flags & ~127u) == 0, "unknown op_flags bits");
+    TNG_REQUIRE((op_flags & ~255u) == 0, "unknown op_flags bits");
     const bool doBT = op_flags & TNG_OP_BT, doB = op_flags & TNG_OP_B;
     TNG_REQUIRE(op_flags & 7u, "op_flags selects no operator block");
     const tng::Level* Lp = nullptr;

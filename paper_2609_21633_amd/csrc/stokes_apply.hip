@@ -144,10 +144,13 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 // FS: free slip on a sphere (a.fs), staged boundary velocities projected onto the
 // tangent plane; TALA: the divergence block tests div(rhobar u) with the mass flux
 // rhobar u interpolated nodally; the other kernels compile without these paths.
+// TWOPT: the viscous block with the two-radial-point rule (Sec. 4) instead of the one
+// point (the divergence blocks keep the one point).
 template <typename T, int RS, int CPL, bool DO_A, bool DO_BT, bool DO_B, bool DO_HG, bool BATCH, int WG, bool FS,
-          bool TALA>
+          bool TALA, bool TWOPT = false>
 __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, SlotBatch sb) {
     static_assert(!TALA || DO_B, "the reference density enters the divergence block only");
+    static_assert(!TWOPT || (DO_A && !DO_HG), "the two-point rule is a form of the viscous block");
     static_assert(DO_A || !DO_HG, "hourglass control belongs to the viscous block");
     if constexpr (BATCH) {
         const long long so = slot_off(sb);
@@ -531,6 +534,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                         dvl[sl + 1] += iso.rw[cb][1] * dv;
                     }
                     T za[3][3];   // Z_m = (V sigma) rho_m, rows m = 1, 2, 3
+                    T zt[3][3];   // two-point rule: the rows for the wedge's top-face nodes
                     T hx[3], hy[3];
                     if (DO_HG) {
                         const T e3 = a.hg * rin.eta[c][t] * V * (s1[c] * s1[c] * hgA + hgB);
@@ -548,7 +552,65 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                             pbar = iso.rw[cb][0] * plat[sl] + iso.rw[cb][1] * plat[sl + 1];
                         }
                         T S[3][3];
-                        if (DO_A) {
+                        if constexpr (TWOPT) {
+                            // two radial points zeta = -+1/sqrt 3, weight 1/2 each, at radius
+                            // r_q = r_m + zeta dr/2 (the Jacobian there is G diag(r_q, r_q, dr/2)):
+                            // the lateral differences carry (1 -+ zeta) for the bottom / top
+                            // layer, and each point's rows Z_1, Z_2 reach the bottom-face
+                            // nodes with weight (1 - zeta) and the top-face nodes with (1 + zeta);
+                            // B^T stays at q_c (both faces, weight 1)
+                            const T rm = a.r_in + (T(kk[c]) + T(0.5)) * a.dr;
+                            const T vis = vr[c] != T(0) ? rin.eta[c][t] * gt[9] * T(0.5) : T(0);
+#pragma unroll
+                            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                                for (int r = 0; r < 3; ++r) {
+                                    const T bt = DO_BT ? -V * pbar * (x == 0 ? r1[r] : (x == 1 ? r2[r] : r3[r]))
+                                                       : T(0);
+                                    za[x][r] = bt;
+                                    zt[x][r] = bt;
+                                }
+#pragma unroll
+                            for (int qq = 0; qq < 2; ++qq) {
+                                const T zq = qq == 0 ? T(-0.57735026918962576451) : T(0.57735026918962576451);
+                                const T rq = rm + zq * (T(0.5) * a.dr);
+                                const T s1q = T(0.5) / rq;
+                                const T q1[3] = {gt[0] * s1q, gt[1] * s1q, gt[2] * s1q};
+                                const T q2[3] = {gt[3] * s1q, gt[4] * s1q, gt[5] * s1q};
+                                T Lq[3][3];
+#pragma unroll
+                                for (int r = 0; r < 3; ++r) {
+                                    const T Ar = (T(1) - zq) * lo[0][r] + (T(1) + zq) * hi[0][r];
+                                    const T Br = (T(1) - zq) * lo[1][r] + (T(1) + zq) * hi[1][r];
+                                    const T Cr = hi[2][r] - lo[2][r];
+#pragma unroll
+                                    for (int x = 0; x < 3; ++x) Lq[r][x] = Ar * q1[x] + Br * q2[x] + Cr * r3[x];
+                                }
+                                const T trq = Lq[0][0] + Lq[1][1] + Lq[2][2];
+                                const T e1 = vis * rq * rq;          // eta V_q
+                                const T e2 = e1 + e1;
+                                const T qd = e2 * trq * T(1.0 / 3.0);
+                                T Sq[3][3];
+                                Sq[0][0] = e2 * Lq[0][0] - qd;
+                                Sq[1][1] = e2 * Lq[1][1] - qd;
+                                Sq[2][2] = e2 * Lq[2][2] - qd;
+                                Sq[0][1] = Sq[1][0] = e1 * (Lq[0][1] + Lq[1][0]);
+                                Sq[0][2] = Sq[2][0] = e1 * (Lq[0][2] + Lq[2][0]);
+                                Sq[1][2] = Sq[2][1] = e1 * (Lq[1][2] + Lq[2][1]);
+#pragma unroll
+                                for (int r = 0; r < 3; ++r) {
+                                    const T z1 = Sq[r][0] * q1[0] + Sq[r][1] * q1[1] + Sq[r][2] * q1[2];
+                                    const T z2 = Sq[r][0] * q2[0] + Sq[r][1] * q2[1] + Sq[r][2] * q2[2];
+                                    const T z3 = Sq[r][0] * r3[0] + Sq[r][1] * r3[1] + Sq[r][2] * r3[2];
+                                    za[0][r] += (T(1) - zq) * z1;
+                                    za[1][r] += (T(1) - zq) * z2;
+                                    za[2][r] += z3;
+                                    zt[0][r] += (T(1) + zq) * z1;
+                                    zt[1][r] += (T(1) + zq) * z2;
+                                    zt[2][r] += z3;
+                                }
+                            }
+                        } else if (DO_A) {
                             const T e1 = rin.eta[c][t] * V;
                             const T e2 = e1 + e1;
                             const T qd = e2 * tr * T(1.0 / 3.0) + (DO_BT ? V * pbar : T(0));
@@ -565,11 +627,13 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
 #pragma unroll
                                 for (int x = 0; x < 3; ++x) S[r][x] = (r == x) ? -qd : T(0);
                         }
+                        if constexpr (!TWOPT) {
 #pragma unroll
-                        for (int r = 0; r < 3; ++r) {
-                            za[0][r] = S[r][0] * r1[0] + S[r][1] * r1[1] + S[r][2] * r1[2];
-                            za[1][r] = S[r][0] * r2[0] + S[r][1] * r2[1] + S[r][2] * r2[2];
-                            za[2][r] = S[r][0] * r3[0] + S[r][1] * r3[1] + S[r][2] * r3[2];
+                            for (int r = 0; r < 3; ++r) {
+                                za[0][r] = S[r][0] * r1[0] + S[r][1] * r1[1] + S[r][2] * r1[2];
+                                za[1][r] = S[r][0] * r2[0] + S[r][1] * r2[1] + S[r][2] * r2[2];
+                                za[2][r] = S[r][0] * r3[0] + S[r][1] * r3[1] + S[r][2] * r3[2];
+                            }
                         }
                         // nodal values of layer c: test functions of the wedge above
                         // (g' = (-1,-1,-1), (1,0,-1), (0,1,-1)) and, from c = 1 on,
@@ -604,7 +668,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
 #pragma unroll
                         for (int x = 0; x < 3; ++x)
 #pragma unroll
-                            for (int r = 0; r < 3; ++r) zb[x][r] = za[x][r];
+                            for (int r = 0; r < 3; ++r) zb[x][r] = TWOPT ? zt[x][r] : za[x][r];
                         if (DO_HG) {
 #pragma unroll
                             for (int r = 0; r < 3; ++r) {
@@ -997,9 +1061,10 @@ inline int choose_bands(int m, long long cols, long long slots) {
 
 // the solver's combinations (A, B^T, K, each viscous one also with hourglass
 // control) have a batched form; the others run one slot at a time
-template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG, bool FS, bool TALA = false>
+template <typename T, int RS, int CPL, int WG, bool A, bool BT, bool B, bool HG, bool FS, bool TALA = false,
+          bool TWOPT = false>
 void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, int* bands_out) {
-    constexpr bool BATCHABLE = !FS && !TALA && ((A && !BT && !B) || (!A && BT && !B) || (A && BT && B));
+    constexpr bool BATCHABLE = !FS && !TALA && !TWOPT && ((A && !BT && !B) || (!A && BT && !B) || (A && BT && B));
     const int block = args.TI * RS * 64;
     const bool batched = sb.nb > 1;
     if (ctx->apply_bands > 0) {
@@ -1012,10 +1077,10 @@ void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, in
         if (per_cu == 0) {
             if (batched)
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG, FS, TALA>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, BATCHABLE, WG, FS, TALA, TWOPT>, block, 0));
             else
                 TNG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA>, block, 0));
+                    &per_cu, stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA, TWOPT>, block, 0));
             per_cu = std::max(1, per_cu);
             rc.store(per_cu, std::memory_order_relaxed);
         }
@@ -1029,13 +1094,13 @@ void launch_band_t(const tng_ctx* ctx, BandArgs<T> args, const SlotBatch& sb, in
     char detail[64] = {0};
     if (ctx->profile) {
         const char* ops = A ? (BT ? (B ? "K" : "A+BT") : (B ? "A+B" : "A")) : (BT ? (B ? "BT+B" : "BT") : "B");
-        std::snprintf(detail, sizeof(detail), "%s/%s%s%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
-                      ops, HG ? "+HG" : "", FS ? "+FS" : "", TALA ? "+TALA" : "", args.m, args.n, args.nband,
-                      sb.nb > 1 ? "/batch" : "");
+        std::snprintf(detail, sizeof(detail), "%s/%s%s%s%s%s/%dx%d/b%d%s", std::is_same<T, double>::value ? "f64" : "f32",
+                      ops, HG ? "+HG" : "", FS ? "+FS" : "", TALA ? "+TALA" : "", TWOPT ? "+2PT" : "", args.m,
+                      args.n, args.nband, sb.nb > 1 ? "/batch" : "");
     }
     ScopedKernelTimer timer(ctx, "stokes_apply", detail);
     if (sb.nb == 1)   // a single slot is always the reference slot (offset 0)
-        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA>
+        stokes_band_kernel<T, RS, CPL, A, BT, B, HG, false, WG, FS, TALA, TWOPT>
             <<<(unsigned)nb, args.TI * RS * 64, 0, ctx->stream>>>(args, sb);
     else if constexpr (BATCHABLE)
         stokes_band_kernel<T, RS, CPL, A, BT, B, HG, true, WG, false, false>
@@ -1064,15 +1129,19 @@ void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatc
         case 16 | 1: launch_band_t<T, RS, CPL, WG, true, false, false, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, true>(ctx, args, sb, bands_out); break;
+        case 128 | 1: launch_band_t<T, RS, CPL, WG, true, false, false, false, false, false, true>(ctx, args, sb, bands_out); break;
+        case 128 | 3: launch_band_t<T, RS, CPL, WG, true, true, false, false, false, false, true>(ctx, args, sb, bands_out); break;
+        case 128 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false, false, true>(ctx, args, sb, bands_out); break;
         case 64 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, false, true>(ctx, args, sb, bands_out); break;
         case 64 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false, true>(ctx, args, sb, bands_out); break;
         case 16 | 2:   // B^T reads no velocity: its free-slip rows are the post pass's projection
             launch_band_t<T, RS, CPL, WG, false, true, false, false, false>(ctx, args, sb, bands_out);
             break;
         default:
-            throw Error(TNG_E_INVAL, "this operator combination has no free-slip or compressible form (free "
-                                     "slip: A, B^T, B or the full operator; TALA: B or the full operator; "
-                                     "neither with hourglass control, not both)");
+            throw Error(TNG_E_INVAL, "this operator combination has no free-slip, compressible or two-point form "
+                                     "(free slip: A, B^T, B or the full operator; TALA: B or the full operator; "
+                                     "two-point rule: A, A+B^T or the full operator; none with hourglass control, "
+                                     "at most one of them)");
     }
 }
 
@@ -1140,8 +1209,9 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         TNG_REQUIRE(L.rho64.p != nullptr, "TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
         a.rho = is64 ? reinterpret_cast<const T*>(L.rho64.p) : reinterpret_cast<const T*>(L.rho32.p);
     }
+    const bool twopt = doA && (flags & TNG_OP_TWOPOINT) != 0;
     const int key = (doA ? 1 : 0) | (doBT ? 2 : 0) | (doB ? 4 : 0) | (doHG ? 8 : 0) | (a.fs ? 16 : 0) |
-                    (tala && doB ? 64 : 0);
+                    (tala && doB ? 64 : 0) | (twopt ? 128 : 0);
     auto dispatch = [&](int* bands_out) {
         if constexpr (std::is_same<T, double>::value) {
             if (rs == 1)

@@ -41,14 +41,14 @@ def _fields(stokes: bool):
     return lam(u), lam(f), lam(eta), lam(p)
 
 
-def _discrete(mt, fu, ff, fe, hg_alpha=0.0):
+def _discrete(mt, fu, ff, fe, hg_alpha=0.0, quad="one"):
     m = ShellMesh(mt, mt, R_IN, R_OUT)
     xyz = m.node_xyz()
     wn = m.wedge_nodes()
     xw = xyz[wn]
     N, _ = ref_basis(*QC)
     xq = np.einsum("j,wja->wa", N, xw)                   # x(q_c) of each wedge
-    o = StokesOracle(mt, mt, fe(*xq.T), R_IN, R_OUT, hg_alpha=hg_alpha)
+    o = StokesOracle(mt, mt, fe(*xq.T), R_IN, R_OUT, hg_alpha=hg_alpha, quad=quad)
     _, V, _ = wedge_geometry(xw)
     fq = np.array(ff(*xq.T)).T
     F = np.zeros((m.n_nodes, 3))
@@ -59,13 +59,14 @@ def _discrete(mt, fu, ff, fe, hg_alpha=0.0):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("hg_alpha", [0.0, 0.05])
-def test_viscous_block_second_order(hg_alpha):
-    """Also with hourglass control (eq:hgstab): the error keeps the optimal order."""
+@pytest.mark.parametrize("hg_alpha,quad", [(0.0, "one"), (0.05, "one"), (0.0, "two")])
+def test_viscous_block_second_order(hg_alpha, quad):
+    """Also with hourglass control (eq:hgstab) and with the two-radial-point rule: the
+    error keeps the optimal order."""
     fu, ff, fe, _ = _fields(stokes=False)
     errs = []
     for mt in (4, 8):
-        m, o, F, ue = _discrete(mt, fu, ff, fe, hg_alpha)
+        m, o, F, ue = _discrete(mt, fu, ff, fe, hg_alpha, quad)
         uh = spla.spsolve(o.A_D.tocsc(), F.ravel()).reshape(-1, 3)
         errs.append(np.sqrt(np.mean((uh - ue) ** 2)))
     assert errs[0] / errs[1] > 3.4, errs

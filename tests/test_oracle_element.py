@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.mesh import ShellMesh
-from oracle.stokes import QC, element_divergence, element_matrices, ref_basis, wedge_geometry
+from oracle.stokes import QC, element_divergence, element_matrices, hourglass_vectors, ref_basis, wedge_geometry
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -263,3 +263,75 @@ def test_hourglass_control_independent_of_vertex_numbering():
         B = element_matrices_hg(xw[:, node, :], eta, 0.08)
         for a, b in zip(A, B):
             assert np.abs(a[np.ix_(dof, dof)] - b).max() < 1e-13 * np.abs(a).max()
+
+
+# ---- two-radial-point rule (Sec. 4, the remedy beside eq:hgstab) --------------------------
+
+def _basis_and_map(xs):
+    def N(xi, et, ze):
+        lat = (1.0 - xi - et, xi, et)
+        rad = (0.5 * (1.0 - ze), 0.5 * (1.0 + ze))
+        return np.array([lat[j % 3] * rad[j // 3] for j in range(6)])
+    return N, (lambda pt: N(*pt) @ xs)
+
+
+def test_two_point_element_matrix_equals_brute_force_quadrature():
+    """A_e = sum over the points (1/3, 1/3, -+1/sqrt 3), weight 1/2, of V(q) eta
+    [2 eps:eps - 2/3 div div](q), every quantity from the wedge's own map and basis
+    by central differences (exact for the map's quadratic terms), in plain loops."""
+    from oracle.stokes import element_matrices_2pt
+    m = ShellMesh(2, 2)
+    wn = m.wedge_nodes()
+    xyz = m.node_xyz()
+    for w in (0, 7, 33):
+        xs = xyz[wn[w]]
+        N, x_of = _basis_and_map(xs)
+        A = np.zeros((18, 18))
+        h = 1e-3
+        for zq in (-1.0 / np.sqrt(3.0), 1.0 / np.sqrt(3.0)):
+            q = np.array([1.0 / 3.0, 1.0 / 3.0, zq])
+            J = np.empty((3, 3))
+            dN = np.empty((6, 3))
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = h
+                J[:, a] = (x_of(q + e) - x_of(q - e)) / (2 * h)
+                dN[:, a] = (N(*(q + e)) - N(*(q - e))) / (2 * h)
+            grads = dN @ np.linalg.inv(J)                   # rows: grad phi_j
+            V = 0.5 * abs(np.linalg.det(J))
+            for i in range(18):
+                for k in range(18):
+                    ji, ci, jk, ck = i // 3, i % 3, k // 3, k % 3
+                    Gi = np.zeros((3, 3))
+                    Gi[ci] = grads[ji]
+                    Gk = np.zeros((3, 3))
+                    Gk[ck] = grads[jk]
+                    ei, ek = 0.5 * (Gi + Gi.T), 0.5 * (Gk + Gk.T)
+                    A[i, k] += V * 1.7 * (2.0 * np.sum(ei * ek) - (2.0 / 3.0) * np.trace(Gi) * np.trace(Gk))
+        got = element_matrices_2pt(xs[None], np.array([1.7]))[0]
+        assert np.abs(got - A).max() < 1e-9 * np.abs(A).max()
+
+
+def test_two_point_rule_controls_the_hourglass_modes():
+    """With two radial points the element energy sees the hourglass modes.  The energy is
+    2 |dev eps|^2 at two points: 10 conditions on 18 DoFs, so the null space has dimension
+    8 -- the translations, rotations and the dilation, plus one volumetric mode (deviatoric
+    strain zero at both points, its volume change left to the divergence block) -- and every
+    hourglass mode w_m (x) e_d has energy."""
+    from oracle.stokes import element_matrices_2pt
+    m = ShellMesh(2, 2)
+    xs = m.node_xyz()[m.wedge_nodes()[5]]
+    A = element_matrices_2pt(xs[None], np.array([1.0]))[0]
+    lam, vec = np.linalg.eigh(A)
+    assert np.sum(lam < 1e-10 * lam.max()) == 8 and lam.min() > -1e-12 * lam.max()
+    # rigid motions and the dilation x are in the null space
+    rigid = [np.tile(e, 6) for e in np.eye(3)]
+    rigid += [np.cross(np.tile(w, (6, 1)), xs).ravel() for w in np.eye(3)] + [xs.ravel()]
+    for v in rigid:
+        assert np.abs(A @ v).max() < 1e-12 * lam.max() * np.abs(v).max()
+    h = hourglass_vectors()
+    for a in range(3):
+        for d in range(3):
+            v = np.zeros(18)
+            v[d::3] = h[a]
+            assert v @ A @ v > 1e-3 * lam.max() * (v @ v)

@@ -375,6 +375,15 @@ int tng_rhs_buoyancy_tala(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_pre
 int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* const u[3],
                      double dt, const void* T, void* y);
 
+/* The advection half of an MMOC step (Sec. 6, eq:departure): T_hat at every
+ * node = T at the node's departure point, traced back over dt with the
+ * explicit midpoint rule along the velocity u (both W1 fields, linear
+ * interpolation in the wedge that contains the point; a point outside the
+ * shell is brought back radially onto it).  u[3], T: device FP64 node fields
+ * of `level`; T_hat: device FP64 out (equal in all copies of a node). */
+int tng_mmoc_advect(tng_ctx* ctx, const tng_mesh* mesh, int level, const double* const u[3], double dt,
+                    const double* T, double* T_hat);
+
 /* Coupled time step.  Ra: Rayleigh number; eta = exp(-E T + F (1 - r));
  * dt > 0 fixes the time step, else dt = courant * min_e h_e / |ubar_e|;
  * T_inner / T_outer: temperature on the inner / outer sphere; the energy
@@ -385,6 +394,14 @@ typedef struct {
     double T_inner, T_outer;
     double energy_rtol;
     int energy_max_iters, energy_restart;
+    /* energy scheme (Sec. 6): 0 = SUPG-stabilised backward Euler; 1 = the
+     * modified method of characteristics (eq:mmoc): T at the departure points
+     * of the nodes (explicit midpoint rule backwards along u, W1
+     * interpolation), then the implicit diffusion step (M/dt + K) T^{n+1} =
+     * M (That/dt + H) by the same Jacobi-GMRES; with courant > 0 and dt <= 0
+     * the step is courant x the CFL step (MMOC is not CFL-bound, so courant
+     * may exceed 1). */
+    int scheme;
 } tng_step_opts;
 
 typedef struct {

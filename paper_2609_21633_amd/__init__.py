@@ -9,5 +9,5 @@ does, and fails loudly if ``libtng.so`` has not been built.
 from .binding import (  # noqa: F401
     OP_A, OP_B, OP_BT, OP_DIRICHLET, OP_FREESLIP_INNER, OP_FREESLIP_OUTER, OP_TALA, OP_TWOPOINT, TngError, Context, Mesh, StokesSolver, diag_A, eta_coarsen,
     eta_from_temperature, interface_sum, lib, pressure_mass, prolong, restrict, smooth, stokes_apply,
-    rhs_buoyancy, energy_apply, Server, smooth_noalloc, stokes_apply_layout, stream_copy, check_device_buffer, rhs_buoyancy_tala,
+    rhs_buoyancy, energy_apply, Server, smooth_noalloc, stokes_apply_layout, stream_copy, check_device_buffer, rhs_buoyancy_tala, mmoc_advect,
 )

@@ -71,6 +71,7 @@ def lib():
         "tng_rhs_buoyancy": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
         "tng_energy_apply": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
         "tng_energy_step": [_vp, _vp, _vp, _vp, C.POINTER(_vp), _vp, _vp],
+        "tng_mmoc_advect": [_vp, _vp, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
         "tng_server_create": [_vp, C.POINTER(C.c_int), C.c_int, C.c_size_t, C.c_int, _vp, C.POINTER(_vp)],
         "tng_server_submit": [_vp, C.c_int, _vp, C.c_double, C.c_double, C.POINTER(_vp), _vp,
                               C.POINTER(C.c_longlong)],
@@ -398,7 +399,8 @@ class SolveInfo(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("Ra", C.c_double), ("E", C.c_double), ("F", C.c_double), ("dt", C.c_double),
                 ("courant", C.c_double), ("T_inner", C.c_double), ("T_outer", C.c_double),
-                ("energy_rtol", C.c_double), ("energy_max_iters", C.c_int), ("energy_restart", C.c_int)]
+                ("energy_rtol", C.c_double), ("energy_max_iters", C.c_int), ("energy_restart", C.c_int),
+                ("scheme", C.c_int)]
 
 
 class StepInfo(C.Structure):
@@ -424,6 +426,16 @@ def rhs_buoyancy_tala(ctx: Context, mesh: Mesh, level: int, T, Ra: float, Tbar_n
     _chk3(ctx, f, T.dtype, _nodes(mesh, level), "f")
     check(lib().tng_rhs_buoyancy_tala(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _vp(tb.ctypes.data),
                                       _vp(ra.ctypes.data), _ptr3(f)))
+
+
+def mmoc_advect(ctx: Context, mesh: Mesh, level: int, u, dt: float, T, T_hat):
+    """T_hat = T at the departure points of the nodes (MMOC advection step), FP64."""
+    import torch
+    n = _nodes(mesh, level)
+    _chk3(ctx, u, torch.float64, n, "u")
+    _chk(ctx, T, torch.float64, n, "T")
+    _chk(ctx, T_hat, torch.float64, n, "T_hat")
+    check(lib().tng_mmoc_advect(ctx.h, mesh.h, level, _ptr3(u), float(dt), _ptr(T), _ptr(T_hat)))
 
 
 def energy_apply(ctx: Context, mesh: Mesh, level: int, u, dt: float, T, y):
@@ -475,10 +487,14 @@ class StokesSolver:
         return out
 
     def energy_step(self, T, u, p, H=None, Ra=1e5, E=0.0, F=0.0, dt=0.0, courant=1.0, T_inner=1.0,
-                    T_outer=0.0, energy_rtol=1e-8, energy_max_iters=200, energy_restart=20,
+                    T_outer=0.0, energy_rtol=1e-8, energy_max_iters=200, energy_restart=20, scheme: str = "supg",
                     raise_on_fail: bool = True) -> dict:
-        """One coupled step: Stokes solve with eta(T), then the energy solve (T in/out)."""
-        o = StepOpts(Ra, E, F, dt, courant, T_inner, T_outer, energy_rtol, energy_max_iters, energy_restart)
+        """One coupled step: Stokes solve with eta(T), then the energy solve (T in/out);
+        scheme "supg" or "mmoc"."""
+        if scheme not in ("supg", "mmoc"):
+            raise ValueError("scheme must be 'supg' or 'mmoc'")
+        o = StepOpts(Ra, E, F, dt, courant, T_inner, T_outer, energy_rtol, energy_max_iters, energy_restart,
+                     1 if scheme == "mmoc" else 0)
         info = StepInfo()
         rc = lib().tng_energy_step(self.h, C.byref(o), _ptr(H), _ptr(T), _ptr3(u), _ptr(p), C.byref(info))
         out = {"rc": rc, "energy_its": info.energy_its, "energy_rel_res": info.energy_rel_res,

@@ -505,6 +505,21 @@ int tng_energy_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
     TNG_API_END
 }
 
+int tng_mmoc_advect(tng_ctx* ctx, const tng_mesh* mesh, int level, const double* const u[3], double dt,
+                    const double* T, double* T_hat) {
+    TNG_API_BEGIN
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(u && u[0] && u[1] && u[2] && T && T_hat, "NULL argument");
+    TNG_REQUIRE(std::isfinite(dt) && dt >= 0.0, "dt must be finite and >= 0");
+    tng::require_vel(ctx, (const void* const*)u, L, TNG_F64, "u");
+    tng::require_device(ctx, T, tng::node_bytes(L, TNG_F64), "T");
+    tng::require_device(ctx, T_hat, tng::node_bytes(L, TNG_F64), "T_hat");
+    TNG_REQUIRE(T != T_hat, "T and T_hat must not alias");
+    TNG_HIP(hipSetDevice(ctx->device));
+    tng::mmoc_departure(ctx, L, u, dt, T, T_hat);
+    TNG_API_END
+}
+
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
                double hg_alpha, void* const diag[3]) {
     TNG_API_BEGIN

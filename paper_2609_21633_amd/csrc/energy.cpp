@@ -176,6 +176,23 @@ int energy_solve(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
     return energy_gmres(ctx, L, W, dt, T, rtol, maxit, its, rel);
 }
 
+// MMOC step (eq:mmoc): That = T^n at the departure points, then the implicit diffusion
+// step (M_L / dt + K) T^{n+1} = M_L (That / dt + H) by the same Jacobi-GMRES with the
+// flow terms off (zero mean velocity and tau).
+int energy_solve_mmoc(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], const double* H,
+                      double dt, double T_in, double T_out, double* T, double rtol, int maxit, int restart, int* its,
+                      double* rel) {
+    ews_init(W, L, restart);
+    double* That = W.f.p;                       // scratch of one node field
+    mmoc_departure(ctx, L, u, dt, T, That);
+    energy_rhs<double>(ctx, L, That, H, dt, T_in, T_out, W.b.p);
+    vec_fill<double>(ctx, (long long)L.cells() * 2 * 4, 0.0, W.wf.p);
+    energy_diag<double>(ctx, L, W.wf.p, dt, W.invd.p);
+    vec_invert<double>(ctx, W.ns, W.invd.p);
+    TNG_HIP(hipMemcpyAsync(T, That, W.ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    return energy_gmres(ctx, L, W, dt, T, rtol, maxit, its, rel);
+}
+
 double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double courant) {
     const double rate = cfl_rate<double>(ctx, L, u, W.part);
     return rate > 0 ? courant / rate : 1e30;

@@ -104,6 +104,13 @@ int energy_solve(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
                  double dt, double T_in, double T_out, double* T, double rtol, int maxit, int restart, int* its,
                  double* rel);
 double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double courant);
+int energy_solve_mmoc(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], const double* H,
+                      double dt, double T_in, double T_out, double* T, double rtol, int maxit, int restart, int* its,
+                      double* rel);
+// That = T^n at the departure points of the nodes (explicit midpoint rule backwards
+// over dt along the W1 velocity u), W1-interpolated (eq:departure); FP64 node fields.
+void mmoc_departure(const tng_ctx* ctx, const Level& L, const double* const u[3], double dt, const double* Tn,
+                    double* That);
 void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]);
 template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);

@@ -1374,6 +1374,7 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     TNG_REQUIRE(std::isfinite(o->Ra) && std::isfinite(o->E) && std::isfinite(o->F), "non-finite parameter");
     TNG_REQUIRE(o->dt > 0 || o->courant > 0, "need dt > 0 or courant > 0");
     TNG_REQUIRE(o->energy_restart >= 1 && o->energy_restart + 1 <= tng::MAX_MDOT, "energy_restart in 1..23");
+    TNG_REQUIRE(o->scheme == 0 || o->scheme == 1, "scheme must be 0 (SUPG) or 1 (MMOC)");
     {
         const size_t nsb = (size_t)s->ns0 * sizeof(double);
         if (H) tng::require_device(s->ctx, H, nsb, "H");
@@ -1401,8 +1402,11 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     const double dt = o->dt > 0 ? o->dt : tng::energy_cfl_dt(s->ctx, L, *s->ews, uc, o->courant);
     int eits = 0;
     double erel = 0.0;
-    const int erc = tng::energy_solve(s->ctx, L, *s->ews, uc, H, dt, o->T_inner, o->T_outer, T, o->energy_rtol,
-                                      o->energy_max_iters, o->energy_restart, &eits, &erel);
+    const int erc = o->scheme == 1
+                        ? tng::energy_solve_mmoc(s->ctx, L, *s->ews, uc, H, dt, o->T_inner, o->T_outer, T,
+                                                 o->energy_rtol, o->energy_max_iters, o->energy_restart, &eits, &erel)
+                        : tng::energy_solve(s->ctx, L, *s->ews, uc, H, dt, o->T_inner, o->T_outer, T, o->energy_rtol,
+                                            o->energy_max_iters, o->energy_restart, &eits, &erel);
     TNG_HIP(hipStreamSynchronize(s->ctx->stream));
     if (info) {
         info->stokes = sinfo;

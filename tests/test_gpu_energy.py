@@ -91,3 +91,59 @@ def test_coupled_step_energy_matches_oracle(tng, ctx):
     assert rel(got, want) < 1e-9
     assert info["stokes"]["rel_res"] <= 1e-8
     assert np.abs(ug).max() > 0
+
+
+# ---- modified method of characteristics (Sec. 6, eq:departure, eq:mmoc) ----------------
+
+def test_mmoc_advection_matches_oracle(tng, ctx):
+    """T at the departure points: the GPU's hierarchical point location and W1
+    interpolation against the oracle's brute-force location, on a rotating flow with a
+    random perturbation, a displacement of up to about two cells, and departure points that
+    leave the shell (brought back radially on both sides)."""
+    import torch
+    mesh, om, lm = setup(tng, ctx, 8)
+    from oracle.mmoc import departure_points, interpolate
+    rng = np.random.default_rng(21)
+    x = om.node_xyz()
+    u = np.cross(np.tile([0.4, -0.3, 1.0], (om.n_nodes, 1)), x) + 0.3 * rng.standard_normal((om.n_nodes, 3))
+    T = rng.uniform(0.0, 1.0, om.n_nodes)
+    dt = 0.25
+    want = interpolate(om, T, departure_points(om, u, dt))
+    ut = torch.tensor(lm.to_lib(u), device="cuda").contiguous()
+    Tt = torch.tensor(lm.to_lib(T), device="cuda")
+    Th = torch.full_like(Tt, float("nan"))
+    tng.mmoc_advect(ctx, mesh, 0, ut, dt, Tt, Th)
+    torch.cuda.synchronize()
+    got = lm.from_lib(Th.cpu().numpy(), check_dups=0.0)
+    err = np.abs(got - want).max()
+    print(f"mmoc advection (8,8): max |That - oracle| {err:.2e}", flush=True)
+    assert err < 1e-12
+    # zero velocity: the nodes themselves (located by barycentric weights that carry rounding)
+    tng.mmoc_advect(ctx, mesh, 0, torch.zeros_like(ut), dt, Tt, Th)
+    torch.cuda.synchronize()
+    assert np.abs(lm.from_lib(Th.cpu().numpy()) - T).max() < 1e-13
+
+
+def test_coupled_mmoc_step_matches_oracle(tng, ctx):
+    """One coupled step with the MMOC energy scheme (courant 3, beyond the CFL limit): the
+    GPU velocity is fed to the oracle's MMOC step with the same dt."""
+    import torch
+    from oracle.mmoc import mmoc_step
+    mt = 8
+    mesh, om, lm = setup(tng, ctx, mt, levels=3)
+    T0 = synthetic.temperature(om.s, om.r, seed=4).ravel()
+    H = synthetic.heating(om.n_nodes, seed=5)
+    s = tng.StokesSolver(ctx, mesh, mixed=1, rtol=1e-8)
+    Tt = torch.tensor(lm.to_lib(T0), device="cuda")
+    Ht = torch.tensor(lm.to_lib(H), device="cuda")
+    u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    info = s.energy_step(Tt, u, p, H=Ht, Ra=1e5, E=math.log(1e3), F=math.log(10.0), courant=3.0,
+                         energy_rtol=1e-11, scheme="mmoc")
+    print("mmoc step", info, flush=True)
+    ug = lm.from_lib(u.cpu().numpy(), check_dups=1e-12)
+    _, want = mmoc_step(om, T0, ug, info["dt"], H)
+    got = lm.from_lib(Tt.cpu().numpy(), check_dups=1e-12)
+    print(f"mmoc step (8,8): rel error {rel(got, want):.2e}", flush=True)
+    assert rel(got, want) < 1e-9
+    assert np.abs(ug).max() > 0

@@ -216,7 +216,7 @@ def variant_bytes(name):
     cells = 10 * m * m * n
     npr = 10 * (m // 2 + 1) ** 2 * (n // 2 + 1)
     if kern == "energy_apply":
-        return es * 5 * ns                                   # T, u (3) in, y out
+        return es * (5 if var == "SUPG" else 2) * ns         # T, u (3) in, y out; no flow: T in, y out
     # values moved per variant: u in / y out (3 node fields each), two viscosities per cell,
     # p in and y_p out (one pressure field each)
     table = {"A": 6 * ns + 2 * cells, "BT": 3 * ns + npr, "B": 3 * ns + npr,
@@ -224,6 +224,47 @@ def variant_bytes(name):
              "BT+B": 6 * ns + 2 * npr, "K": 6 * ns + 2 * cells + 2 * npr}
     b = table[var.replace("+HG", "")]
     return es * b
+
+
+def bench_energy_apply(tng, ctx, mt, nr, steps, warmup):
+    """The SUPG energy apply y = E(u) T alone on the (mt, nr) shell, FP64 and FP32:
+    kernel time from HIP events on the launch stream, wall time per call (with the
+    tile-seam zeroing, interface sum and Dirichlet rows), and the algorithmic
+    bandwidth (T and u read, y written once: 5 values per node slot)."""
+    import torch
+    mesh = tng.Mesh(ctx, mt, nr, levels=1)
+    T64 = shell_fields(tng, ctx, mesh, seed=4, lmax=8)
+    g = torch.Generator(device="cpu").manual_seed(6)
+    # velocities of the coupled Ra 1e7 runs' magnitude (|u| up to a few hundred)
+    u64 = ((torch.rand((3,) + mesh.shape(0), generator=g, dtype=torch.float64) * 2 - 1) * 300.0).to("cuda")
+    tng.interface_sum(ctx, mesh, 0, [u64[0], u64[1], u64[2]], mode=1)
+    ns = mesh.counts(0)["node_slots"]
+    out = {"workload": f"SUPG energy apply on the ({mt},{nr}) shell, T = conduction + spherical harmonics "
+                       "l=1..8, u = U(-300, 300) per component, dt = 1e-4",
+           "node_slots": ns}
+    for name, dtype, es in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        T, u = T64.to(dtype), u64.to(dtype)
+        y = torch.empty_like(T)
+        for _ in range(warmup):
+            tng.energy_apply(ctx, mesh, 0, u, 1e-4, T, y)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            tng.energy_apply(ctx, mesh, 0, u, 1e-4, T, y)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        kms, nl = ctx.kernel_stats("energy_apply")
+        ctx.profile(False)
+        kms /= max(nl, 1)
+        ab = 5 * es * ns
+        out[name] = {"kernel_ms": round(kms, 4), "wall_ms": round(wall * 1e3, 4), "alg_bytes": ab,
+                     "alg_gbs": round(ab / (kms * 1e-3) / 1e9, 1),
+                     "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] energy apply {name}: {out[name]}")
+        del T, u, y
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_coupled(tng, ctx, mt, nr, steps):
@@ -499,6 +540,9 @@ def main():
     ap.add_argument("--coupled", action="store_true",
                     help="instead: coupled Stokes-energy steps on the (--mt, --nr) shell (default (256,256), "
                          "--steps steps), one JSON report line")
+    ap.add_argument("--energy-apply", action="store_true",
+                    help="instead: the SUPG energy apply alone on the (--mt, --nr) shell (default (256,256)), "
+                         "FP64 and FP32; one JSON report line")
     ap.add_argument("--profile-solve", choices=["fp64", "mixed"],
                     help="instead: one Stokes solve of the contrast-1e6 field on the (--mt, --nr) shell, for "
                          "kernel traces; one JSON report line")
@@ -527,6 +571,13 @@ def main():
         print(json.dumps({"workload": f"Stokes solve to 1e-8, contrast 1e6, ({args.mt},{args.nr}) shell",
                           "mode": args.profile_solve, "seconds": round(s["wall"], 3), "inner_its": s["inner_its"],
                           "outer_its": s["outer_its"], "rel_res": s["rel_res"], "rc": s["rc"]}), flush=True)
+        return
+    if args.energy_apply:
+        em = args.mt if "--mt" in sys.argv else 256
+        en = args.nr if "--nr" in sys.argv else 256
+        es_ = args.steps if "--steps" in sys.argv else 50
+        ew = args.warmup if "--warmup" in sys.argv else 20
+        print(json.dumps(bench_energy_apply(tng, ctx, em, en, es_, ew)), flush=True)
         return
     if args.coupled:
         cm = args.mt if "--mt" in sys.argv else 256

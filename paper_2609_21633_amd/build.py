@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtng.so")
 SOURCES = ["capi.cpp", "mesh.cpp", "stokes_apply.hip", "interface.hip", "fields.hip", "mg_kernels.hip", "solver.cpp",
-           "energy.hip", "energy.cpp", "server.cpp", "noalloc.hip", "bandwidth.hip", "mmoc.hip"]
+           "energy.hip", "energy.cpp", "server.cpp", "noalloc.hip", "bandwidth.hip", "mmoc.hip",
+           "energy_stream.hip"]
 ARCH = "gfx950"
 
 

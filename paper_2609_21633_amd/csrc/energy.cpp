@@ -73,8 +73,18 @@ double rb(const tng_ctx* ctx, EnergyWS& W, const double* dev, int n) {
     return W.host[0];
 }
 
+// y = E x: the streaming apply with the velocity u (NULL: no flow terms) where it
+// fits, else the node-gather apply with the per-wedge flow data of W.wf.
+void energy_op(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const* u, double dt, const double* x,
+               double* y) {
+    if (energy_stream_fits(L))
+        energy_apply_stream<double>(ctx, L, u, dt, x, y);
+    else
+        energy_apply_wf<double>(ctx, L, W.wf.p, dt, x, y);
+}
+
 // Solves E x = b (b in W.b); x holds the initial guess on entry.
-int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, double dt, double* x,
+int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const* u, double dt, double* x,
                  double rtol, int maxit, int* its_out, double* rel_out) {
     const long long ns = W.ns;
     const int m = W.restart;
@@ -97,7 +107,7 @@ int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, double dt, dou
     }
     for (;;) {
         // r = b - E x
-        energy_apply_wf<double>(ctx, L, W.wf.p, dt, x, W.w.p);
+        energy_op(ctx, L, W, u, dt, x, W.w.p);
         vec_axpby<double>(ctx, ns, 1.0, W.b.p, -1.0, W.w.p);
         dot1(W.w.p, W.wptr.p + 1, dsc);
         const double beta = std::sqrt(std::max(0.0, rb(ctx, W, dsc, 1)));
@@ -110,7 +120,7 @@ int energy_gmres(const tng_ctx* ctx, const Level& L, EnergyWS& W, double dt, dou
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             vec_mul<double>(ctx, ns, W.invd.p, W.Vi(j), W.Zi(j));
-            energy_apply_wf<double>(ctx, L, W.wf.p, dt, W.Zi(j), W.w.p);
+            energy_op(ctx, L, W, u, dt, W.Zi(j), W.w.p);
             vec_mdot<double>(ctx, W.ds, ns, L.n + 1, nlat, L.owner.p, W.w.p, W.vptr.p, j + 1, dsc, false);
             vec_maxpy<double>(ctx, ns, dsc, -1.0, W.vptr.p, j + 1, W.w.p);
             vec_mdot<double>(ctx, W.ds, ns, L.n + 1, nlat, L.owner.p, W.w.p, W.vptr.p, j + 1, dsc + MAX_MDOT, false);
@@ -173,7 +183,7 @@ int energy_solve(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* 
     // initial guess: T^n with the boundary values imposed
     void* f[1] = {T};
     (void)f;
-    return energy_gmres(ctx, L, W, dt, T, rtol, maxit, its, rel);
+    return energy_gmres(ctx, L, W, u, dt, T, rtol, maxit, its, rel);
 }
 
 // MMOC step (eq:mmoc): That = T^n at the departure points, then the implicit diffusion
@@ -190,7 +200,7 @@ int energy_solve_mmoc(const tng_ctx* ctx, const Level& L, EnergyWS& W, const dou
     energy_diag<double>(ctx, L, W.wf.p, dt, W.invd.p);
     vec_invert<double>(ctx, W.ns, W.invd.p);
     TNG_HIP(hipMemcpyAsync(T, That, W.ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    return energy_gmres(ctx, L, W, dt, T, rtol, maxit, its, rel);
+    return energy_gmres(ctx, L, W, nullptr, dt, T, rtol, maxit, its, rel);
 }
 
 double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const double* const u[3], double courant) {

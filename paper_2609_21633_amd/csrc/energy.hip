@@ -319,6 +319,10 @@ void energy_apply_wf(const tng_ctx* ctx, const Level& L, const double* wf, doubl
 
 template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y) {
+    if (energy_stream_fits(L)) {
+        energy_apply_stream<T>(ctx, L, u, dt, Tin, y);
+        return;
+    }
     DevBuf<double> wf((size_t)L.cells() * 2 * WF);
     energy_wedge_flow<T>(ctx, L, u, wf.p);
     energy_apply_wf<T>(ctx, L, wf.p, dt, Tin, y);

@@ -187,6 +187,33 @@ void build_level(Level& L, int m, int n, double r_in, double r_out, bool device)
     std::vector<float> geo32(geo.begin(), geo.end());
     TNG_HIP(hipMemcpy(L.geo64.p, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice));
     TNG_HIP(hipMemcpy(L.geo32.p, geo32.data(), geo32.size() * sizeof(float), hipMemcpyHostToDevice));
+    {
+        const size_t ncol = (size_t)10 * m * m;
+        std::vector<double> eg(ncol * EG_PER_COL);
+        for (size_t c = 0; c < ncol; ++c)
+            for (int t = 0; t < 2; ++t) {
+                const double* g = &geo[c * GEO_PER_COL + t * GEO_PER_TRI];
+                double* e = &eg[c * EG_PER_COL + t * EG_PER_TRI];
+                auto dot = [&](int a, int b) { return g[a] * g[b] + g[a + 1] * g[b + 1] + g[a + 2] * g[b + 2]; };
+                for (int q = 0; q < 9; ++q) e[q] = g[q];
+                const double g9 = g[9];
+                e[9] = 0.25 * g9 * dot(0, 0);
+                e[10] = 0.25 * g9 * dot(0, 3);
+                e[11] = 0.25 * g9 * dot(3, 3);
+                e[12] = 0.5 * g9 * dot(0, 6);
+                e[13] = 0.5 * g9 * dot(3, 6);
+                e[14] = g9 * dot(6, 6);
+                e[15] = g9;
+                const double c13 = std::cbrt(g9);
+                e[16] = 0.25 * c13 * c13;
+                e[17] = 0.25 * g9 * c13 * c13;
+            }
+        L.eg64.alloc(eg.size());
+        L.eg32.alloc(eg.size());
+        std::vector<float> eg32(eg.begin(), eg.end());
+        TNG_HIP(hipMemcpy(L.eg64.p, eg.data(), eg.size() * sizeof(double), hipMemcpyHostToDevice));
+        TNG_HIP(hipMemcpy(L.eg32.p, eg32.data(), eg32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     L.grp_ptr.alloc(L.grp_ptr_h.size());
     TNG_HIP(hipMemcpy(L.grp_ptr.p, L.grp_ptr_h.data(), L.grp_ptr_h.size() * sizeof(int), hipMemcpyHostToDevice));
     L.grp_slot.alloc(L.grp_slot_h.size());

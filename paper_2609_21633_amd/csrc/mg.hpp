@@ -114,6 +114,12 @@ void mmoc_departure(const tng_ctx* ctx, const Level& L, const double* const u[3]
 void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]);
 template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
+// Streaming energy apply (levels with at most 256 radial layers): y = E(u) T with the
+// Dirichlet rows; u == NULL applies the operator without flow (lumped mass and
+// diffusion only).
+bool energy_stream_fits(const Level& L);
+template <typename T>
+void energy_apply_stream(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
 // tbar, rhoalpha: device [n+1] profiles of the compressible (TALA) form, or NULL for
 // the Boussinesq form (Tbar = 0, rhobar alphabar = 1)
 template <typename T>

@@ -180,6 +180,12 @@ class BatchScope {
 // of G^{-1} divided by 6h, and h |det G| (see mesh.cpp).
 constexpr int GEO_PER_TRI = 10;
 constexpr int GEO_PER_COL = 2 * GEO_PER_TRI;
+// Per-triangle data of the streaming energy apply (derived from the above):
+// g0, g1, g2 (9), the metric g9 (ga . gb) scaled to the wedge volume's radial
+// factors (m00, m01, m11 with g9/4; m02, m12 with g9/2; m22 with g9), g9, and the
+// SUPG length factors g9^(2/3)/4 and g9^(5/3)/4.
+constexpr int EG_PER_TRI = 18;
+constexpr int EG_PER_COL = 2 * EG_PER_TRI;
 
 struct Level {
     int m = 0, n = 0;                 // lateral intervals per diamond edge, radial intervals
@@ -194,6 +200,8 @@ struct Level {
     // device copies
     DevBuf<double> geo64;             // [10][m][m][GEO_PER_COL]
     DevBuf<float> geo32;
+    DevBuf<double> eg64;              // [10][m][m][EG_PER_COL] energy apply geometry
+    DevBuf<float> eg32;
     DevBuf<int> grp_ptr, grp_slot;    // duplicate groups (CSR over lateral slots)
     DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
     DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node

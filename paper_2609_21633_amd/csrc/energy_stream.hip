@@ -79,19 +79,42 @@ __device__ __forceinline__ double supg_coef(int k) {
     return c[k];
 }
 
-// F(x) from z = x^2
+// hardware reciprocal (square root) estimates
+__device__ __forceinline__ float hw_rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double hw_rsq(double v) { return __builtin_amdgcn_rsq(v); }
+__device__ __forceinline__ float hw_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double hw_rcp(double v) { return __builtin_amdgcn_rcp(v); }
+
+// F(x) from z = x^2: the series for z <= 1 and the closed form
+//   F = (x (1 + e) - (1 - e)) / (z (1 - e)),  e = exp(-2x),
+// for z > 1, the reciprocal square root and the reciprocal being the hardware
+// estimates refined by two Newton steps each.  FP32: the closed form only when a lane
+// of the wave needs it.  FP64: both evaluated and one selected, without a branch (any
+// branch here costs the FP64 kernel thirty to fifty registers, and a fourth wave per
+// SIMD).
 template <typename T>
 __device__ __forceinline__ T supg_F(T z) {
-    if (z <= T(1)) {
-        constexpr int N = SupgSeries<T>::N;
-        T f = T(supg_coef(N - 1));
+    constexpr int N = SupgSeries<T>::N;
+    const bool small = z <= T(1);
+    const T zs = small ? z : T(1);
+    T f = T(supg_coef(N - 1));
 #pragma unroll
-        for (int k = N - 2; k >= 0; --k) f = f * z + T(supg_coef(k));
-        return f;
-    }
-    const T x = sqrt(z);
+    for (int k = N - 2; k >= 0; --k) f = f * zs + T(supg_coef(k));
+    if constexpr (std::is_same<T, float>::value)
+        if (__builtin_amdgcn_ballot_w64(!small) == 0) return f;
+    const T zl = small ? T(4) : z;
+    T r = hw_rsq(zl);
+    r = r * (T(1.5) - T(0.5) * zl * r * r);
+    r = r * (T(1.5) - T(0.5) * zl * r * r);
+    const T x = zl * r;
     const T e = exp(T(-2) * x);
-    return ((T(1) + e) / (T(1) - e) - T(1) / x) / x;
+    const T om = T(1) - e;
+    const T den = zl * om;
+    T q = hw_rcp(den);
+    q = q * (T(2) - den * q);
+    q = q * (T(2) - den * q);
+    const T fl = (x * (T(1) + e) - om) * q;
+    return small ? f : fl;
 }
 
 // Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the
@@ -164,7 +187,6 @@ __global__ void __launch_bounds__(TC * RS * 64) energy_stream_kernel(EStreamArgs
     const T s1 = T(0.5) / rm;
     const T rm2 = cell ? rm * rm : T(0);
     const T r43 = cbrt(rm2 * rm2);               // rm^(4/3): h^2 = rm^(4/3) g9^(2/3)
-    const T r103 = rm2 * rm * cbrt(rm);          // rm^(10/3): V h^2 = rm^(10/3) g9^(5/3)
 
     // byte offsets (every node field of a supported level is below 4 GiB)
     constexpr unsigned SZ = sizeof(T);
@@ -198,17 +220,19 @@ __global__ void __launch_bounds__(TC * RS * 64) energy_stream_kernel(EStreamArgs
     // constant address space, so that it is loaded into scalar registers
     using CT = const __attribute__((address_space(4))) T;
 
-    // mean velocity ub = us / 6 of a wedge and F(Pe) of its SUPG parameter
+    // mean velocity ub = us / 6 of a wedge and V tau = V (h^2/4) F(Pe) of its SUPG
+    // parameter (h^2/4 = g16 rm^(4/3))
     auto flow = [&](CT* g, const T (&us)[3], T (&ub)[3]) -> T {
 #pragma unroll
         for (int x = 0; x < 3; ++x) ub[x] = us[x] * T(1.0 / 6.0);
-        const T z = (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]) * (g[16] * r43);   // Pe^2
-        return supg_F(z);
+        const T hq = g[16] * r43;
+        const T z = (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]) * hq;   // Pe^2
+        return (rm2 * g[15]) * hq * supg_F(z);
     };
 
     // one wedge from the temperatures tv[lat][layer] of its six nodes, its mean
-    // velocity ub and F(Pe); accumulates into out[lat][layer]
-    auto wedge = [&](CT* g, const T (&tv)[3][2], const T (&ub)[FLOW ? 3 : 1], T F, T* (&out)[3]) {
+    // velocity ub and V tau (VF); accumulates into out[lat][layer]
+    auto wedge = [&](CT* g, const T (&tv)[3][2], const T (&ub)[FLOW ? 3 : 1], T VF, T* (&out)[3]) {
         T A = (tv[1][0] - tv[0][0]) + (tv[1][1] - tv[0][1]);
         T B = (tv[2][0] - tv[0][0]) + (tv[2][1] - tv[0][1]);
         T C = (tv[0][1] + tv[1][1] + tv[2][1]) - (tv[0][0] + tv[1][0] + tv[2][0]);
@@ -225,7 +249,7 @@ __global__ void __launch_bounds__(TC * RS * 64) energy_stream_kernel(EStreamArgs
             const T q2 = ub[0] * g[6] + ub[1] * g[7] + ub[2] * g[8];
             const T e0 = s1 * q0, e1 = s1 * q1;
             const T adv = A * e0 + B * e1 + C * q2;              // ubar . grad T
-            const T wt = g[17] * r103 * F * adv;                  // V tau (ubar . grad T)
+            const T wt = VF * adv;                                // V tau (ubar . grad T)
             P0 += wt * e0;
             P1 += wt * e1;
             P2 += wt * q2;
@@ -255,31 +279,36 @@ __global__ void __launch_bounds__(TC * RS * 64) energy_stream_kernel(EStreamArgs
             if (active) {
                 load(j + 1, nxt);
                 CT* g = gcol + gbase + (unsigned)j * EG_PER_COL;
-                // flow data of both wedges first, while few values are live
-                T ub0[FLOW ? 3 : 1], ub1[FLOW ? 3 : 1], F0 = T(0), F1 = T(0);
-                if constexpr (FLOW) {
-                    T us0[3], us1[3];
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) {
-                        us0[x] = cur.su[x] + (nxt.su[x] - nxt.s1[x]);   // (i, j), (i+1, j), (i, j+1)
-                        us1[x] = cur.s1[x] + nxt.su[x];                 // (i+1, j+1), (i, j+1), (i+1, j)
-                    }
-                    F0 = flow(g, us0, ub0);
-                    F1 = flow(g + EG_PER_TRI, us1, ub1);
-                }
                 {
                     // wedge 0: lateral nodes (i, j), (i+1, j), (i, j+1)
+                    T ub[FLOW ? 3 : 1], VF = T(0);
+                    if constexpr (FLOW) {
+                        T us[3];
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) us[x] = cur.su[x] + (nxt.su[x] - nxt.s1[x]);
+                        VF = flow(g, us, ub);
+                    }
                     const T tv[3][2] = {{cur.t[0][0], cur.t[0][1]}, {cur.t[1][0], cur.t[1][1]},
                                         {nxt.t[0][0], nxt.t[0][1]}};
                     T* out[3] = {Rc[0], Rc[1], Rn[0]};
-                    wedge(g, tv, ub0, F0, out);
+                    wedge(g, tv, ub, VF, out);
                 }
+                // keeps the second wedge's geometry out of registers until here
+                __builtin_amdgcn_sched_barrier(0);
                 {
                     // wedge 1: (i+1, j+1), (i, j+1), (i+1, j)
+                    CT* g1 = g + EG_PER_TRI;
+                    T ub[FLOW ? 3 : 1], VF = T(0);
+                    if constexpr (FLOW) {
+                        T us[3];
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) us[x] = cur.s1[x] + nxt.su[x];
+                        VF = flow(g1, us, ub);
+                    }
                     const T tv[3][2] = {{nxt.t[1][0], nxt.t[1][1]}, {nxt.t[0][0], nxt.t[0][1]},
                                         {cur.t[1][0], cur.t[1][1]}};
                     T* out[3] = {Rn[1], Rn[0], Rc[1]};
-                    wedge(g + EG_PER_TRI, tv, ub1, F1, out);
+                    wedge(g1, tv, ub, VF, out);
                 }
             }
         }
@@ -420,23 +449,21 @@ void energy_apply_stream(const tng_ctx* ctx, const Level& L, const T* const u[3]
     a.dr = T(L.dr());
     a.inv_dt = T(1.0 / dt);
     const bool flow = u != nullptr;
-    // workgroups of TC columns x RS stretches; FP64 with the flow terms holds about 160
-    // registers per lane (three waves per SIMD, twelve-wave groups), the other forms
-    // fit four or more
-    constexpr bool F64 = std::is_same<T, double>::value;
+    // workgroups of 16 waves: TC columns x RS stretches (four waves per SIMD fit: at
+    // most 128 registers per lane)
     if (L.n <= 64) {
         if (flow)
-            launch_stream<T, true, F64 ? 12 : 16, 1>(ctx, L, a);
+            launch_stream<T, true, 16, 1>(ctx, L, a);
         else
             launch_stream<T, false, 16, 1>(ctx, L, a);
     } else if (L.n <= 128) {
         if (flow)
-            launch_stream<T, true, F64 ? 6 : 8, 2>(ctx, L, a);
+            launch_stream<T, true, 8, 2>(ctx, L, a);
         else
             launch_stream<T, false, 8, 2>(ctx, L, a);
     } else {
         if (flow)
-            launch_stream<T, true, F64 ? 3 : 4, 4>(ctx, L, a);
+            launch_stream<T, true, 4, 4>(ctx, L, a);
         else
             launch_stream<T, false, 4, 4>(ctx, L, a);
     }

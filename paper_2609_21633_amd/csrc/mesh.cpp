@@ -206,7 +206,6 @@ void build_level(Level& L, int m, int n, double r_in, double r_out, bool device)
                 e[15] = g9;
                 const double c13 = std::cbrt(g9);
                 e[16] = 0.25 * c13 * c13;
-                e[17] = 0.25 * g9 * c13 * c13;
             }
         L.eg64.alloc(eg.size());
         L.eg32.alloc(eg.size());

@@ -183,8 +183,8 @@ constexpr int GEO_PER_COL = 2 * GEO_PER_TRI;
 // Per-triangle data of the streaming energy apply (derived from the above):
 // g0, g1, g2 (9), the metric g9 (ga . gb) scaled to the wedge volume's radial
 // factors (m00, m01, m11 with g9/4; m02, m12 with g9/2; m22 with g9), g9, and the
-// SUPG length factors g9^(2/3)/4 and g9^(5/3)/4.
-constexpr int EG_PER_TRI = 18;
+// SUPG length factor g9^(2/3)/4 (h^2/4 = g9^(2/3)/4 r_m^(4/3) with h = V^(1/3)).
+constexpr int EG_PER_TRI = 17;
 constexpr int EG_PER_COL = 2 * EG_PER_TRI;
 
 struct Level {

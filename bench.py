@@ -264,6 +264,9 @@ def bench_energy_apply(tng, ctx, mt, nr, steps, warmup):
         log(f"[bench] energy apply {name}: {out[name]}")
         del T, u, y
         torch.cuda.empty_cache()
+    # one plain streaming copy of known size: the practical roof, and the scale of HBM
+    # byte counters taken over this run
+    out["practical_roof"] = bench_copy_roof(tng, ctx, reps=2)
     return out
 
 

@@ -78,14 +78,27 @@ __device__ __forceinline__ T shfl_up1(T v, int lane) {
     return __shfl(v, (lane + 63) & 63, 64);
 }
 
+// Element idx of a field addressed by a 32-bit byte offset from its (wave-uniform)
+// base, so that the compiler can use the scalar-base addressing form (64-bit base in
+// scalar registers, 32-bit offset per lane) instead of a 64-bit address per lane; the
+// host refuses fields of 4 GiB or more.
+template <typename T>
+__device__ __forceinline__ T* elem(T* base, unsigned idx) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& elem(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 // Emit one node value: plain store when this workgroup holds its complete
 // sum, atomic add (onto zeroed memory) on tile or chunk seams.
 template <typename T>
 __device__ __forceinline__ void emit(T* y, unsigned idx, T v, bool seam) {
     if (seam)
-        atomicAdd(y + idx, v);
+        atomicAdd(elem(y, idx), v);
     else
-        y[idx] = v;
+        *elem(y, idx) = v;
 }
 
 // The three components of one velocity node under a single seam branch.
@@ -93,10 +106,10 @@ template <typename T>
 __device__ __forceinline__ void emit3(T* const (&y)[3], unsigned idx, const T (&v)[3], bool seam) {
     if (seam) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) atomicAdd(y[r] + idx, v[r]);
+        for (int r = 0; r < 3; ++r) atomicAdd(elem(y[r], idx), v[r]);
     } else {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) y[r][idx] = v[r];
+        for (int r = 0; r < 3; ++r) *elem(y[r], idx) = v[r];
     }
 }
 
@@ -224,7 +237,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     const int k0 = kc0 + h * KC;                       // even: KC is a multiple of 64
     const int kend = min(kcend, k0 + KC);              // cells [k0, kend) of this wave
 
-    // 32-bit offsets: every field of a supported level has < 2^31 entries
+    // 32-bit element offsets (and byte offsets: every field is below 4 GiB)
     const unsigned ldj = n + 1;
     const unsigned ldi = (unsigned)(m + 1) * ldj;
     const unsigned colA = ((unsigned)d * (m + 1) + i) * ldi;   // node column i
@@ -299,14 +312,15 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     };
     auto stage = [&](unsigned col, int jrow, int slot, int wl) {
         const unsigned base = col + (unsigned)jrow * ldj + (unsigned)k0;
-        const T* const src[3] = {a.u0 + base, a.u1 + base, a.u2 + base};
+        const T* const src[3] = {a.u0, a.u1, a.u2};
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int t = 0; t < NCH; ++t)
                 if (lok[t])
                     __builtin_amdgcn_global_load_lds(
-                        reinterpret_cast<const unsigned*>(src[r]) + lane + 64 * t,
+                        reinterpret_cast<const unsigned*>(reinterpret_cast<const char*>(src[r]) +
+                                                          (base * (unsigned)sizeof(T) + 4u * (lane + 64 * t))),
                         reinterpret_cast<unsigned*>(&ring[slot][wl][r][0]) + h * KC * DW + 64 * t, 4, 0, 0);
     };
 
@@ -337,8 +351,8 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                 // a cell outside the wave's stretch reads the range's first cell: the wave's own
             // first cell lies past the column when the stretch is empty
             const int k = kk[c] < kend ? kk[c] : kc0;
-                r.eta[c][0] = a.eta[ecol + 2u * k];
-                r.eta[c][1] = a.eta[ecol + 2u * k + 1u];
+                r.eta[c][0] = elem(a.eta, ecol + 2u * k);
+                r.eta[c][1] = elem(a.eta, ecol + 2u * k + 1u);
             }
         }
         if (DO_BT) {
@@ -347,7 +361,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int s = 0; s < NKL; ++s) r.pk[q][s] = a.p[pbq[q] + Kp[s]];
+                for (int s = 0; s < NKL; ++s) r.pk[q][s] = elem(a.p, pbq[q] + Kp[s]);
         }
     };
 
@@ -875,6 +889,8 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
             sj2 = s;
         }
     };
+    // (two rows per trip with the register sets swapped instead of copied costs the
+    // compiler 20-40 more registers per lane)
     T Rs[2][NL][3];
     RowIn rin2;
     for (int j = jfirst; j <= jlast; ++j) {
@@ -1153,6 +1169,9 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
                 void* yp, int* layout = nullptr) {
     const bool doA = flags & TNG_OP_A, doBT = flags & TNG_OP_BT, doB = flags & TNG_OP_B;
     const bool is64 = std::is_same<T, double>::value;
+    // the kernel addresses every field by 32-bit byte offsets
+    TNG_REQUIRE((double)std::max(L.node_slots(), 2 * L.cells()) * sizeof(T) < 4294967296.0,
+                "operator apply: a field of this level reaches 4 GiB");
     BandArgs<T> a{};
     a.eta = static_cast<const T*>(eta);
     a.u0 = u ? static_cast<const T*>(u[0]) : nullptr;

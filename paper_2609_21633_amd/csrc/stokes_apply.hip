@@ -20,14 +20,16 @@
 // test-function sums of the result.  Contributions that cross a wave boundary
 // are combined in LDS (lateral, and radial between the stretches of a column)
 // or moved one lane up with a DPP wavefront shift (radial, inside a wave).  A
-// band starts one cell row early (the halo row) so that its first node row is
-// complete; nodes on the seams between tiles (node columns that are multiples
-// of TC) and between workgroup radial ranges (columns longer than RS
-// stretches) receive exactly two partial sums, added with atomics to memory
-// zeroed beforehand; two partials sum to the same value in either order, so
-// velocity results do not depend on timing.  Coarse pressure nodes where a
-// band seam crosses a tile seam receive up to four partials, whose order (and
-// so the last bit of the divergence block) can vary from run to run.
+// band starts one cell row early (the halo row; two with the divergence block)
+// so that its first node row and its first coarse pressure row are complete, and
+// every node row belongs to one band.  Nodes on the seams between tiles (node
+// columns that are multiples of TC) receive exactly two partial sums, added
+// with atomics to memory zeroed beforehand; two partials sum to the same value
+// in either order, so the result does not depend on timing.  Columns longer
+// than RS stretches are split into workgroup radial ranges, whose seam layers
+// also take two partials; where such a layer crosses a tile seam a node takes
+// four, whose order can vary from run to run (levels with more than 256
+// radial cells only).
 //
 // The divergence block is reduced per coarse pressure node through LDS, kept
 // by one owner thread per node and flushed once a coarse row is complete.
@@ -229,7 +231,10 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
     const int j0 = 2 * ((band * (m >> 1)) / a.nband);
     const bool last_band = (band == a.nband - 1);
     const int j1 = last_band ? m : 2 * (((band + 1) * (m >> 1)) / a.nband);
-    const int jfirst = j0 > 0 ? j0 - 1 : 0;            // halo row (computed, not owned)
+    // halo rows (computed, not owned): one for the velocity rows; the divergence
+    // kernels take a second one, so that the band's first coarse pressure row is
+    // complete in the band and every coarse row belongs to one band
+    const int jfirst = j0 > 0 ? j0 - (DO_B ? 2 : 1) : 0;
     const int jlast_cell = j1 - 1;
     const int jlast = last_band ? m : jlast_cell;      // last node row emitted
     const int kc0 = chunk * RS * KC;                   // workgroup's radial range [kc0, kcend)
@@ -762,7 +767,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                     for (int r = 0; r < 3; ++r) rxs[par][w][q][r] = row_cells ? top_out[q][r] : T(0);
             }
         }
-        if (DO_B && owned && row_cells) {
+        if (DO_B && row_cells) {
             // radial reduction of the coarse partials to one value per coarse layer
             if (CPL == 1) {
                 // lanes 2K' and 2K'+1 share coarse layers K', K'+1
@@ -860,7 +865,7 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                 Rn[1][0][r] += rxs[par][w - 1][3][r];
             }
         }
-        if (DO_B && owned && row_cells) {
+        if (DO_B && row_cells) {
             // owner threads add the (up to four) waves touching each coarse node, in
             // a fixed order, into the open rows J (corners 0, 1) and J+1 (corners 2, 3)
             if (owner) {
@@ -875,9 +880,9 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                 }
             }
             if (j & 1) {
-                // coarse row J has received all of this band's cells
-                const bool rowseam = (J == (j0 >> 1) && j0 > 0);
-                if (own_ok) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, rowseam || own_seam);
+                // coarse row J is complete (the one below the band's first row, from
+                // the halo rows, belongs to the band below)
+                if (own_ok && J >= (j0 >> 1)) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, own_seam);
                 pacc0 = pacc1;
                 pacc1 = T(0);
             }
@@ -903,10 +908,10 @@ __global__ void __launch_bounds__(WG * 64) stokes_band_kernel(BandArgs<T> a, Slo
                 for (int r = 0; r < 3; ++r) Rc[q][c][r] = Rs[q][c][r];
         rin = rin2;
     }
-    if (DO_B) {
-        // the coarse row above the band's last cell row: complete only on the last band
+    if (DO_B && last_band) {
+        // the coarse row above the last cell row (on other bands, the next band's)
         const int J = (jlast_cell >> 1) + 1;
-        if (own_ok && J <= mc) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, !last_band || own_seam);
+        if (own_ok && J <= mc) emit(a.yp, own_off + (unsigned)J * pldj, pacc0, own_seam);
     }
 }
 

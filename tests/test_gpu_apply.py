@@ -237,6 +237,30 @@ def test_forced_band_counts(tng, ctx, mt, nr, bands, prec):
     check_K(orc, gu, gp, u, p, tol, f"bands {bands} {prec} ({mt},{nr})")
 
 
+@pytest.mark.parametrize("prec,bands", [("f32", 0), ("f32", 8), ("f64", 0), ("f64", 6)])
+def test_apply_is_bitwise_reproducible(tng, ctx, prec, bands):
+    """Repeated applies of the full operator on the (32,32) shell, with the band
+    count chosen per launch or forced, agree bit for bit: every node sums its
+    partials in an order that does not depend on timing (coarse rows belong to one
+    band each, tile seams take two atomic partials)."""
+    import torch
+    mesh = tng.Mesh(ctx, 32, 32, levels=2)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(21)
+    t = {"u": torch.rand((3,) + mesh.shape(0), generator=g, dtype=torch.float64).cuda() * 2 - 1,
+         "p": torch.rand(mesh.shape(1), generator=g, dtype=torch.float64).cuda() * 2 - 1,
+         "eta": 10.0 ** (torch.rand(mesh.wedge_shape(0), generator=g, dtype=torch.float64).cuda() * 2 - 1)}
+    tng.interface_sum(ctx, mesh, 0, [t["u"][0], t["u"][1], t["u"][2]], mode=1)
+    tng.interface_sum(ctx, mesh, 1, [t["p"]], mode=1)
+    ctx.set_apply_bands(bands)
+    try:
+        runs = [run_apply(tng, ctx, mesh, t, OPS_ALL, dt) for _ in range(4)]
+    finally:
+        ctx.set_apply_bands(0)
+    for yu, yp in runs[1:]:
+        assert np.array_equal(yu, runs[0][0]) and np.array_equal(yp, runs[0][1])
+
+
 # ---- argument checks of the C entry points and the bandwidth probe --------------------
 
 def test_device_pointer_checks(tng, ctx):

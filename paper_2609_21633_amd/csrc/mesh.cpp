@@ -213,6 +213,13 @@ void build_level(Level& L, int m, int n, double r_in, double r_out, bool device)
         TNG_HIP(hipMemcpy(L.eg64.p, eg.data(), eg.size() * sizeof(double), hipMemcpyHostToDevice));
         TNG_HIP(hipMemcpy(L.eg32.p, eg32.data(), eg32.size() * sizeof(float), hipMemcpyHostToDevice));
     }
+    {
+        std::vector<int> lg(10 * nl, -1);
+        for (int g = 0; g < L.n_groups; ++g)
+            for (int q = L.grp_ptr_h[g]; q < L.grp_ptr_h[g + 1]; ++q) lg[L.grp_slot_h[q]] = g;
+        L.lat_grp.alloc(lg.size());
+        TNG_HIP(hipMemcpy(L.lat_grp.p, lg.data(), lg.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     L.grp_ptr.alloc(L.grp_ptr_h.size());
     TNG_HIP(hipMemcpy(L.grp_ptr.p, L.grp_ptr_h.data(), L.grp_ptr_h.size() * sizeof(int), hipMemcpyHostToDevice));
     L.grp_slot.alloc(L.grp_slot_h.size());

@@ -47,6 +47,18 @@ void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* 
 template <typename T>
 void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int k, const T* b, const T* y,
                      const T* invd, T* d, T* x);
+// One step of the two-term Chebyshev recurrence x_k+1 = x_k + alpha (x_k - x_k-1) +
+// beta D^-1 (b - A_D x_k) after a raw viscous apply y = A x_k (launch_stokes_apply_raw):
+// completes the duplicated nodes (sum of the copies) and the no-slip identity rows on
+// the fly.  xo: x_k-1 in (not read when alpha = 0 or prev_zero, then taken as 0),
+// x_k+1 out.  first: the step from x_k = 0 (y and xk not read).
+template <typename T>
+void vec_cheb_post_update(const tng_ctx* ctx, const Level& L, bool ns_in, bool ns_out, const double* ab_dev, int k,
+                          bool first, bool prev_zero, const T* b, const T* y, const T* invd, const T* xk, T* xo);
+// r = b - A_D x from a raw viscous apply y = A x (closing pass fused, as above)
+template <typename T>
+void vec_resid_post(const tng_ctx* ctx, const Level& L, bool ns_in, bool ns_out, const T* b, const T* x, const T* y,
+                    T* r);
 template <typename T>
 void vec_invert(const tng_ctx* ctx, long long n, T* a);
 template <typename TO, typename TI>

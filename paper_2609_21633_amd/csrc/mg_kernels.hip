@@ -429,6 +429,140 @@ __device__ __forceinline__ unsigned mdiv(unsigned t, MagicDiv m) {
     return (unsigned)((((unsigned long long)__umulhi(t, m.mul)) + t) >> m.sh);
 }
 
+// Residual r = b - A_D x from a raw viscous apply y (the closing pass fused as in
+// cheb_post_update_kernel: copies summed in group order, identity rows r = b - x).
+template <typename T>
+__global__ void __launch_bounds__(256) resid_post_kernel(int ns, int n1, MagicDiv dn1, const int* __restrict__ lat_grp,
+                                                        const int* __restrict__ gp, const int* __restrict__ gs,
+                                                        int ns_in, int ns_out, const T* __restrict__ b,
+                                                        const T* __restrict__ x, const T* y, T* r, SlotBatch sb) {
+    const long long so = slot_off(sb);
+    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= (unsigned)ns) return;
+    const long long e = (long long)blockIdx.y * ns + t;
+    const unsigned lat = mdiv(t, dn1);
+    const int kk = (int)(t - lat * (unsigned)n1);
+    T yv;
+    if ((ns_in && kk == 0) || (ns_out && kk == n1 - 1)) {
+        yv = at_slot(x, so)[e];
+    } else {
+        const int g = lat_grp[lat];
+        const T* yy = at_slot(y, so) + (long long)blockIdx.y * ns;
+        if (g < 0) {
+            yv = yy[t];
+        } else {
+            const int s0 = gp[g], s1 = gp[g + 1];
+            yv = yy[(long long)gs[s0] * n1 + kk];
+            for (int q = s0 + 1; q < s1; ++q) yv += yy[(long long)gs[q] * n1 + kk];
+        }
+    }
+    at_slot(r, so)[e] = at_slot(b, so)[e] - yv;
+}
+
+// One Chebyshev step of the smoother in its two-term form
+//   x_k+1 = x_k + alpha (x_k - x_k-1) + beta D^-1 (b - A_D x_k)
+// (the form with the direction d_k = x_k+1 - x_k needs one more vector per step),
+// fused with the closing pass of the raw viscous apply before it (y = A_D x_k with
+// each diamond's partial sums on duplicated nodes and nothing on the no-slip rows):
+// per node, the completed A_D x_k is the sum of the node's copies in group order
+// (the interface pass's order), or x_k itself on an identity row.  xo holds x_k-1
+// on entry (read when alpha != 0 and not prev_zero; x_k-1 = 0 otherwise) and x_k+1
+// on return, element by element in place.  first: the step from x_k = 0
+// (y and x_k are not read).  Each thread takes one 16-byte vector of the flat
+// [3][node slots] arrays (16-byte aligned; the tail of fewer than one vector is the
+// first block's) and locates its elements' node (component, lateral slot, layer)
+// incrementally.
+template <typename T>
+__global__ void __launch_bounds__(256) cheb_post_update_kernel(unsigned ns, int n1, MagicDiv dns, MagicDiv dn1,
+                                                              const int* __restrict__ lat_grp,
+                                                              const int* __restrict__ gp, const int* __restrict__ gs,
+                                                              int ns_in, int ns_out, const double* __restrict__ ab,
+                                                              int k, int first, int prev_zero,
+                                                              const T* __restrict__ b, const T* __restrict__ y,
+                                                              const T* __restrict__ invd, const T* __restrict__ xk,
+                                                              T* xo, SlotBatch sb) {
+    using V = typename Vec16<T>::type;
+    constexpr int L = 16 / sizeof(T);
+    const long long so = slot_off(sb);
+    ab = at_slot(ab, so);
+    b = at_slot(b, so);
+    y = at_slot(y, so);
+    invd = at_slot(invd, so);
+    xk = at_slot(xk, so);
+    xo = at_slot(xo, so);
+    const T alpha = T(ab[2 * k]), beta = T(ab[2 * k + 1]);
+    const bool use_prev = alpha != T(0) && !prev_zero;
+    const unsigned n = 3u * ns, nv = n / L;
+    const unsigned v = blockIdx.x * 256u + threadIdx.x;
+    // completed A_D x_k at element e (component c, lateral slot lat, layer kk)
+    auto yat = [&](unsigned c, unsigned lat, int kk, T yraw, T xv) -> T {
+        if ((ns_in && kk == 0) || (ns_out && kk == n1 - 1)) return xv;
+        const int g = lat_grp[lat];
+        if (g < 0) return yraw;
+        const T* yy = y + (size_t)c * ns;
+        const int s0 = gp[g], s1 = gp[g + 1];
+        T acc = yy[(size_t)gs[s0] * n1 + kk];
+        for (int q = s0 + 1; q < s1; ++q) acc += yy[(size_t)gs[q] * n1 + kk];
+        return acc;
+    };
+    auto step = [&](T bq, T iq, T yq, T xq, T pq) -> T {
+        const T r = beta * iq * (bq - yq);
+        return use_prev ? xq + (alpha * (xq - pq) + r) : (alpha == T(0) ? xq + r : xq + (alpha * xq + r));
+    };
+    if (v < nv) {
+        const V bv = reinterpret_cast<const V*>(b)[v], iv = reinterpret_cast<const V*>(invd)[v];
+        const T* pb = reinterpret_cast<const T*>(&bv);
+        const T* pi = reinterpret_cast<const T*>(&iv);
+        V ov{};
+        T* po = reinterpret_cast<T*>(&ov);
+        if (first) {
+#pragma unroll
+            for (int q = 0; q < L; ++q) po[q] = beta * pi[q] * (pb[q] - T(0));
+        } else {
+            const V yv = reinterpret_cast<const V*>(y)[v], xv = reinterpret_cast<const V*>(xk)[v];
+            V pv{};
+            if (use_prev) pv = reinterpret_cast<const V*>(xo)[v];
+            const T* py = reinterpret_cast<const T*>(&yv);
+            const T* px = reinterpret_cast<const T*>(&xv);
+            const T* pp = reinterpret_cast<const T*>(&pv);
+            const unsigned e0 = v * L;
+            unsigned c = mdiv(e0, dns);
+            unsigned t = e0 - c * ns;
+            unsigned lat = mdiv(t, dn1);
+            int kk = (int)(t - lat * (unsigned)n1);
+#pragma unroll
+            for (int q = 0; q < L; ++q) {
+                po[q] = step(pb[q], pi[q], yat(c, lat, kk, py[q], px[q]), px[q], pp[q]);
+                // next element: the next layer, column or component
+                if (++kk == n1) {
+                    kk = 0;
+                    if (++t == ns) {
+                        t = 0;
+                        ++c;
+                        lat = 0;
+                    } else {
+                        ++lat;
+                    }
+                } else {
+                    ++t;
+                }
+            }
+        }
+        reinterpret_cast<V*>(xo)[v] = ov;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * L) {
+        const unsigned e = nv * L + threadIdx.x;
+        if (first) {
+            xo[e] = beta * invd[e] * (b[e] - T(0));
+        } else {
+            const unsigned c = mdiv(e, dns), t = e - c * ns, lat = mdiv(t, dn1);
+            const int kk = (int)(t - lat * (unsigned)n1);
+            const T xe = xk[e];
+            xo[e] = step(b[e], invd[e], yat(c, lat, kk, y[e], xe), xe, use_prev ? xo[e] : T(0));
+        }
+    }
+}
+
 // A pointer read from a table lost its address space; loads through this
 // global-memory pointer type are global, not flat, instructions.
 template <class T>
@@ -568,8 +702,15 @@ __global__ void __launch_bounds__(256) mdot_final_kernel(int nblocks, int nq, co
     nq = slot_count(sb, nq);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q = wv; q < nq; q += 4) {
-        double v = 0.0;
-        for (int b = lane; b < nblocks; b += 64) v += part[(long long)b * MAX_MDOT + q];
+        // eight independent partial sums per lane keep eight loads in flight (the loads
+        // are a strided gather, latency-bound one by one); combined in a fixed order
+        double v8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = lane;
+        for (; b + 7 * 64 < nblocks; b += 8 * 64)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v8[u] += part[(long long)(b + u * 64) * MAX_MDOT + q];
+        for (; b < nblocks; b += 64) v8[0] += part[(long long)b * MAX_MDOT + q];
+        double v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if (lane == 0) out[q] = accumulate ? out[q] + v : v;
     }
@@ -1019,6 +1160,33 @@ void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int 
 }
 
 template <typename T>
+void vec_cheb_post_update(const tng_ctx* ctx, const Level& L, bool ns_in, bool ns_out, const double* ab_dev, int k,
+                          bool first, bool prev_zero, const T* b, const T* y, const T* invd, const T* xk, T* xo) {
+    const SlotBatch sb = launch_batch();
+    const long long ns = L.node_slots();
+    TNG_REQUIRE(3 * ns < (1LL << 32), "smoother update: more than 2^32 values");
+    TNG_REQUIRE(aligned16(b) && aligned16(y) && aligned16(invd) && aligned16(xk) && aligned16(xo),
+                "smoother update: vectors must be 16-byte aligned");
+    const long long nv = 3 * ns / (16 / (long long)sizeof(T));
+    cheb_post_update_kernel<T><<<dim3(std::max(1u, nblk(nv, 256)), 1, sb.nb), 256, 0, ctx->stream>>>(
+        (unsigned)ns, L.n + 1, magic_div((unsigned)ns), magic_div((unsigned)(L.n + 1)), L.lat_grp.p, L.grp_ptr.p,
+        L.grp_slot.p, ns_in ? 1 : 0, ns_out ? 1 : 0, ab_dev, k, first ? 1 : 0, prev_zero ? 1 : 0, b, y, invd, xk, xo,
+        sb);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_resid_post(const tng_ctx* ctx, const Level& L, bool ns_in, bool ns_out, const T* b, const T* x, const T* y,
+                    T* r) {
+    const SlotBatch sb = launch_batch();
+    const long long ns = L.node_slots();
+    resid_post_kernel<T><<<dim3(std::max(1u, nblk(ns, 256)), 3, sb.nb), 256, 0, ctx->stream>>>(
+        (int)ns, L.n + 1, magic_div((unsigned)(L.n + 1)), L.lat_grp.p, L.grp_ptr.p, L.grp_slot.p, ns_in ? 1 : 0,
+        ns_out ? 1 : 0, b, x, y, r, sb);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
 void vec_invert(const tng_ctx* ctx, long long n, T* a) {
     require_unbatched("vec_invert");
     invert_kernel<T><<<nblk(n, 256), 256, 0, ctx->stream>>>(n, a);
@@ -1257,6 +1425,9 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
                                  T* const[3]);                                                             \
+    template void vec_resid_post<T>(const tng_ctx*, const Level&, bool, bool, const T*, const T*, const T*, T*); \
+    template void vec_cheb_post_update<T>(const tng_ctx*, const Level&, bool, bool, const double*, int, bool,   \
+                                          bool, const T*, const T*, const T*, const T*, T*);                 \
     template void vec_cheb_update<T>(const tng_ctx*, long long, const double*, int, const T*, const T*,   \
                                      const T*, T*, T*);                                                    \
     template void vec_invert<T>(const tng_ctx*, long long, T*);                                           \
@@ -1285,5 +1456,7 @@ TNG_INST(float)
 #undef TNG_INST
 template void vec_cast<float, double>(const tng_ctx*, long long, const double*, float*);
 template void vec_cast<double, float>(const tng_ctx*, long long, const float*, double*);
+template void vec_cast<float, float>(const tng_ctx*, long long, const float*, float*);
+template void vec_cast<double, double>(const tng_ctx*, long long, const double*, double*);
 
 }  // namespace tng

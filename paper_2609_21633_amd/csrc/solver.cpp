@@ -194,25 +194,26 @@ void chebyshev_coefficients(int deg, double lo, double hi, double* ab) {
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
                      T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero) {
-    const long long ns = L.node_slots(), n3 = 3 * ns;
+    const long long ns = L.node_slots();
+    // each update: the raw viscous apply, then one pass that completes its duplicated
+    // nodes and identity rows and takes the two-term Chebyshev step (the apply's
+    // closing pass and the update fused).  x_k alternates between x and d: a step of
+    // degree deg starts from x and, for even deg, ends in x
     auto applyA = [&](const T* xin, T* yout) {
         const void* u[3] = {xin, xin + ns, xin + 2 * ns};
         void* yu[3] = {yout, yout + ns, yout + 2 * ns};
-        launch_stokes_apply(ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, hg_alpha, eta, u, nullptr,
-                            yu, nullptr);
+        launch_stokes_apply_raw(ctx, L, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, hg_alpha, eta, u, yu);
     };
     for (int st = 0; st < steps; ++st) {
-        if (x_zero && st == 0) {
-            vec_fill<T>(ctx, n3, T(0), x);
-            vec_fill<T>(ctx, n3, T(0), y);
-        } else {
-            applyA(x, y);
+        for (int k = 0; k < deg; ++k) {
+            const bool first = x_zero && st == 0 && k == 0;
+            const bool prev_zero = x_zero && st == 0 && k == 1;   // x_k-1 is the zero start
+            T* cur = (k & 1) ? d : x;
+            T* out = (k & 1) ? x : d;
+            if (!first) applyA(cur, y);
+            vec_cheb_post_update<T>(ctx, L, true, true, ab_dev, k, first, prev_zero, b, y, invd, cur, out);
         }
-        vec_cheb_update<T>(ctx, n3, ab_dev, 0, b, y, invd, d, x);
-        for (int k = 1; k < deg; ++k) {
-            applyA(x, y);
-            vec_cheb_update<T>(ctx, n3, ab_dev, k, b, y, invd, d, x);
-        }
+        if (deg & 1) vec_cast<T, T>(ctx, 3 * ns, d, x);
     }
 }
 
@@ -237,9 +238,16 @@ void vcycle(tng_solver* s, int l, const T* b, T* x) {
         return;
     }
     chebyshev<T>(s, l, b, x, true, s->opts.pre);
-    // r = b - A x
-    apply_A<T>(s, l, M.eta.p, x, M.r.p);
-    vec_axpby<T>(s->ctx, 3 * ns, 1.0, b, -1.0, M.r.p);
+    // r = b - A x: the raw apply into the smoother's work vector, then one pass that
+    // completes it and forms the residual
+    {
+        const Level& L = *M.L;
+        const void* u[3] = {x, x + ns, x + 2 * ns};
+        void* yu[3] = {M.y.p, M.y.p + ns, M.y.p + 2 * ns};
+        launch_stokes_apply_raw(s->ctx, L, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, s->opts.hg_alpha, M.eta.p, u,
+                                yu);
+        vec_resid_post<T>(s->ctx, L, true, true, b, x, M.y.p, M.r.p);
+    }
     MGLevel<T>& C = H[l + 1];
     const T* rf[3] = {M.r.p, M.r.p + ns, M.r.p + 2 * ns};
     T* bc[3] = {C.b.p, C.b.p + C.ns, C.b.p + 2 * C.ns};

@@ -1171,7 +1171,7 @@ void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatc
 template <typename T>
 void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned flags, double hg_alpha,
                 const void* eta, const void* const u[3], const void* p, void* const yu[3],
-                void* yp, int* layout = nullptr) {
+                void* yp, int* layout = nullptr, bool raw = false) {
     const bool doA = flags & TNG_OP_A, doBT = flags & TNG_OP_BT, doB = flags & TNG_OP_B;
     const bool is64 = std::is_same<T, double>::value;
     // the kernel addresses every field by 32-bit byte offsets
@@ -1283,6 +1283,7 @@ void band_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, unsigned fl
         }
     }
     dispatch(nullptr);
+    if (raw) return;   // the caller completes duplicates and Dirichlet rows
     // interface sums and Dirichlet rows (identity rows belong to the viscous block;
     // without it the rows are zero), one launch
     PostArgs q{};
@@ -1323,6 +1324,16 @@ void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tn
         band_apply<double>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
     else
         band_apply<float>(ctx, L, Lp, flags, hg_alpha, eta, u, p, yu, yp);
+}
+
+void launch_stokes_apply_raw(const tng_ctx* ctx, const Level& L, tng_prec prec, unsigned flags, double hg_alpha,
+                             const void* eta, const void* const u[3], void* const yu[3]) {
+    TNG_REQUIRE(!(flags & (TNG_OP_BT | TNG_OP_B | TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)),
+                "raw apply: the viscous block with no-slip rows only");
+    if (prec == TNG_F64)
+        band_apply<double>(ctx, L, nullptr, flags, hg_alpha, eta, u, nullptr, yu, nullptr, nullptr, true);
+    else
+        band_apply<float>(ctx, L, nullptr, flags, hg_alpha, eta, u, nullptr, yu, nullptr, nullptr, true);
 }
 
 void stokes_apply_layout(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec, unsigned flags,

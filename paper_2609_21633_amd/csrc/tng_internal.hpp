@@ -203,6 +203,7 @@ struct Level {
     DevBuf<double> eg64;              // [10][m][m][EG_PER_COL] energy apply geometry
     DevBuf<float> eg32;
     DevBuf<int> grp_ptr, grp_slot;    // duplicate groups (CSR over lateral slots)
+    DevBuf<int> lat_grp;              // [10][m+1][m+1]: the slot's duplicate group, -1 for none
     DevBuf<uint8_t> owner;            // [10][m+1][m+1]: 1 for the first copy of a node
     DevBuf<double> inv_mult64;        // [10][m+1][m+1]: 1 / number of copies of the node
     DevBuf<double> unit64;            // [10][m+1][m+1][3] unit vectors
@@ -268,6 +269,11 @@ inline const Level& device_level(const tng_ctx* ctx, const tng_mesh* mesh, int l
 void launch_stokes_apply(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec,
                          unsigned flags, double hg_alpha, const void* eta, const void* const u[3], const void* p,
                          void* const yu[3], void* yp);
+// The velocity apply without its closing pass: y holds each diamond's partial sums on
+// the duplicated (diamond-edge) nodes and nothing on Dirichlet rows, for a consumer that
+// completes both itself (the fused smoother update).
+void launch_stokes_apply_raw(const tng_ctx* ctx, const Level& L, tng_prec prec, unsigned flags, double hg_alpha,
+                             const void* eta, const void* const u[3], void* const yu[3]);
 // The decomposition launch_stokes_apply would use (tng_stokes_apply_layout);
 // launches nothing.
 void stokes_apply_layout(const tng_ctx* ctx, const Level& L, const Level* Lp, tng_prec prec, unsigned flags,

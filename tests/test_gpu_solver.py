@@ -90,11 +90,15 @@ def test_transfers(tng, ctx):
     assert rel(lm.from_lib(fo.cpu().numpy(), check_dups=1e-13), want_f) < 1e-13
 
 
+@pytest.mark.parametrize("mt", [8, 16])
 @pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 1e-5)])
-def test_chebyshev_smoother(tng, ctx, dtype, tol):
+def test_chebyshev_smoother(tng, ctx, dtype, tol, mt):
+    """Two Chebyshev steps of degree 2 against the textbook iteration on the assembled
+    operator: the smoother's two-term recurrence with the apply's closing pass fused
+    into the update, on one tile per diamond row (8,8) and with tile seams (16,16)."""
     import torch
     dt = getattr(torch, dtype)
-    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, mt)
     rng = np.random.default_rng(4)
     b = rng.standard_normal((om.n_nodes, 3))
     x = rng.standard_normal((om.n_nodes, 3))
@@ -106,7 +110,8 @@ def test_chebyshev_smoother(tng, ctx, dtype, tol):
     xt = vel(lm, x).to(dt)
     tng.smooth(ctx, mesh, 0, eta_t.to(dt), d, vel(lm, b).to(dt), xt, 2, 2, 0.3, 3.3)
     want = chebyshev(orc.A_D, orc.diag_A().ravel(), b.ravel(), x.ravel(), 2, 2, 0.3, 3.3).reshape(-1, 3)
-    got = lm.from_lib(xt.double().cpu().numpy())
+    got = lm.from_lib(xt.double().cpu().numpy(), check_dups=tol)
+    print(f"chebyshev ({mt},{mt}) {dtype}: rel {rel(got, want):.2e}", flush=True)
     assert rel(got, want) < tol
 
 

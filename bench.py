@@ -314,6 +314,85 @@ def bench_coupled(tng, ctx, mt, nr, steps):
             "per_step": per_step, "kernels": kernels}
 
 
+def vcycle_rates(tng, ctx, mesh, eta, cycles=9, **variant):
+    """Residual reduction per cycle of the stand-alone V-cycle on the viscous block
+    A_D (x <- x + V(b - A x), b = 0, a seeded random start holding every mode), the
+    solver's V-cycle with the same operator variant on every level."""
+    import torch
+    s = tng.StokesSolver(ctx, mesh, mixed=0, **variant)
+    s.setup(eta)
+    shp = (3,) + mesh.shape(0)
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    x = (torch.rand(shp, generator=gen, dtype=torch.float64) - 0.5).cuda()
+    x[..., 0] = 0.0
+    x[..., -1] = 0.0
+    tng.interface_sum(ctx, mesh, 0, [x[0], x[1], x[2]], mode=1)
+    y, c = torch.empty_like(x), torch.empty_like(x)
+    flags = tng.OP_A | tng.OP_DIRICHLET | variant.get("op_flags", 0)
+    rates, prev = [], None
+    for _ in range(cycles + 1):
+        tng.stokes_apply(ctx, mesh, 0, flags, eta, x, None, y, None, hg_alpha=variant.get("hg_alpha", 0.0))
+        r = -y
+        nrm = float(r.norm())
+        if prev is not None:
+            rates.append(round(nrm / prev, 3))
+        prev = nrm
+        s.vcycle(r, c)
+        x += c
+    s.close()
+    return rates
+
+
+def bench_variants(tng, ctx):
+    """Viscous-block variants in the solve (Sec. 4): the one-point operator, hourglass
+    control (eq:hgstab, alpha 0.1) and the two-radial-point rule, each on every level
+    of the multigrid.  Stand-alone V-cycle rates on (32,32) and (64,64), then Stokes
+    solves to 1e-8 on (64,64) and (128,128) (FGMRES iterations and wall time)."""
+    import torch
+    variants = (("one-point", {}), ("hourglass 0.1", {"hg_alpha": 0.1}),
+                ("two-point", {"op_flags": tng.OP_TWOPOINT}))
+    laws = (("const", 0.0, 0.0), ("c1e3+depth", math.log(1e3), math.log(10.0)), ("c1e6", math.log(1e6), 0.0))
+    out = {"workload": "stand-alone V-cycle on A_D and Stokes solves to 1e-8 with the viscous-block variants",
+           "vcycle": [], "solve": []}
+    for mt in (32, 64):
+        mesh = tng.Mesh(ctx, mt, mt, levels=int(math.log2(mt)))
+        T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
+        for law, E, F in (laws[0], laws[2]):
+            eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
+            tng.eta_from_temperature(ctx, mesh, 0, T64, E, F, eta)
+            for name, v in variants:
+                out["vcycle"].append({"shell": [mt, mt], "law": law, "variant": name,
+                                      "rates": vcycle_rates(tng, ctx, mesh, eta, **v)})
+                log(f"[variants] {out['vcycle'][-1]}")
+        mesh.close()
+    for mt in (64, 128):
+        mesh = tng.Mesh(ctx, mt, mt, levels=int(math.log2(mt)))
+        T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
+        for law, E, F in laws[1:]:
+            eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
+            tng.eta_from_temperature(ctx, mesh, 0, T64, E, F, eta)
+            f = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+            tng.rhs_buoyancy(ctx, mesh, 0, T64, 1e5, f)
+            u = torch.empty_like(f)
+            p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
+            for name, v in variants:
+                for mixed in (0, 1):
+                    sv = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-8, max_iters=600, **v)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = sv.solve(f, None, u, p, eta=eta, raise_on_fail=False)
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t0
+                    sv.close()
+                    out["solve"].append({"shell": [mt, mt], "law": law, "variant": name,
+                                         "mode": "mixed" if mixed else "fp64", "its": info["inner_its"],
+                                         "refinements": info["outer_its"], "rel_res": info["rel_res"],
+                                         "seconds": round(wall, 3), "rc": info["rc"]})
+                    log(f"[variants] {out['solve'][-1]}")
+        mesh.close()
+    return out
+
+
 def serving_fields(tng, nreq):
     """Seeded requests over (16,16), (32,32), (64,64) shells and their device buffers."""
     import torch
@@ -546,6 +625,9 @@ def main():
     ap.add_argument("--energy-apply", action="store_true",
                     help="instead: the SUPG energy apply alone on the (--mt, --nr) shell (default (256,256)), "
                          "FP64 and FP32; one JSON report line")
+    ap.add_argument("--variants", action="store_true",
+                    help="instead: stand-alone V-cycle rates and Stokes solve iterations with the one-point, "
+                         "hourglass-controlled and two-radial-point viscous blocks; one JSON report line")
     ap.add_argument("--profile-solve", choices=["fp64", "mixed"],
                     help="instead: one Stokes solve of the contrast-1e6 field on the (--mt, --nr) shell, for "
                          "kernel traces; one JSON report line")
@@ -565,6 +647,9 @@ def main():
     ctx = tng.Context(0)
     if args.serving_sweep:
         print(json.dumps(bench_serving_sweep(tng, ctx)), flush=True)
+        return
+    if args.variants:
+        print(json.dumps(bench_variants(tng, ctx)), flush=True)
         return
     if args.profile_solve:
         mesh = tng.Mesh(ctx, args.mt, args.nr, levels=int(math.log2(args.mt)))

@@ -242,6 +242,12 @@ int tng_eta_coarsen(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec
  * tng_stokes_apply), 1 on Dirichlet rows.  diag[3]: device velocity field out. */
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
                double hg_alpha, void* const diag[3]);
+/* diag(A) of the viscous block with the two-radial-point rule (Sec. 4; the
+ * operator of TNG_OP_TWOPOINT): the sum over the node's wedges and over the
+ * two points zeta = -+1/sqrt 3 of (V_q / 2) eta (|grad phi|^2 + 1/3
+ * (d_c phi)^2), 1 on Dirichlet rows.  Arguments as in tng_diag_A. */
+int tng_diag_A_twopoint(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+                        void* const diag[3]);
 /* Row-sum lumped inverse-viscosity pressure mass of eq:pmass on the pressure
  * level of `level` (i.e. level + 1): m_I = sum_e (V_e / eta_e) psi_I(q_c^e).
  * mass: device node field of level + 1 out.  The Schur preconditioner is
@@ -299,7 +305,18 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  *   block on every level: the solve is then of that stabilised operator.
  * graphs: 1 (default) replays the preconditioner of each Krylov index as a
  *   HIP graph captured at its first use (on a private stream ordered with the
- *   context's stream by events); 0 launches every kernel from the host. */
+ *   context's stream by events); 0 launches every kernel from the host.
+ * op_flags: operator variant of the solve (Sec. 4, eq:stokes), 0 (default) or
+ *   one of
+ *   TNG_OP_TWOPOINT: the viscous block with the two-radial-point rule on every
+ *     level (outer operator, smoother and residual applies, diag(A) and the
+ *     coarsest matrix), so that the multigrid works on the operator without
+ *     one-point hourglass modes; hg_alpha must be 0;
+ *   TNG_OP_TALA: the outer operator's mass rows -(psi, div(rhobar u)) with the
+ *     mesh's reference density (tng_mesh_set_density before the solver is
+ *     created); the preconditioner keeps A, B^T and M_{1/eta}.  The right-hand
+ *     side g must sum to zero over unique pressure nodes (1^T B_rho = 0).
+ *   Not for the serving batches, which take op_flags 0. */
 typedef struct {
     int mixed;
     int restart;
@@ -315,6 +332,7 @@ typedef struct {
     int power_its;
     double hg_alpha;
     int graphs;
+    unsigned op_flags;
 } tng_solver_opts;
 
 /* outer_its: refinement steps (1 in FP64 mode); inner_its: FGMRES iterations

@@ -55,6 +55,7 @@ def lib():
         "tng_eta_from_temperature": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.c_double, _vp],
         "tng_eta_coarsen": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
         "tng_diag_A": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
+        "tng_diag_A_twopoint": [_vp, _vp, C.c_int, C.c_int, _vp, C.POINTER(_vp)],
         "tng_pressure_mass": [_vp, _vp, C.c_int, C.c_int, _vp, _vp],
         "tng_smooth": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
                        C.c_int, C.c_int, C.c_double, C.c_double],
@@ -336,11 +337,17 @@ def eta_coarsen(ctx: Context, mesh: Mesh, fine_level: int, eta_fine, eta_coarse)
                                 _ptr(eta_coarse)))
 
 
-def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag, hg_alpha: float = 0.0):
-    """Diagonal of the viscous block (Dirichlet rows 1) into diag ([3, ...])."""
+def diag_A(ctx: Context, mesh: Mesh, level: int, eta, diag, hg_alpha: float = 0.0, twopoint: bool = False):
+    """Diagonal of the viscous block (Dirichlet rows 1) into diag ([3, ...]);
+    twopoint: of the two-radial-point operator."""
     _chk(ctx, eta, eta.dtype, _wedges(mesh, level), "eta")
     _chk3(ctx, diag, eta.dtype, _nodes(mesh, level), "diag")
-    check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag)))
+    if twopoint:
+        if hg_alpha != 0.0:
+            raise ValueError("the two-radial-point rule is an alternative to hourglass control")
+        check(lib().tng_diag_A_twopoint(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), _ptr3(diag)))
+    else:
+        check(lib().tng_diag_A(ctx.h, mesh.h, level, _prec(eta), _ptr(eta), float(hg_alpha), _ptr3(diag)))
 
 
 def pressure_mass(ctx: Context, mesh: Mesh, level: int, eta, mass):
@@ -388,7 +395,7 @@ class SolverOpts(C.Structure):
                 ("cheb_degree", C.c_int), ("pre", C.c_int), ("post", C.c_int), ("levels", C.c_int),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("inner_rtol", C.c_double),
                 ("inner_max_iters", C.c_int), ("max_outer", C.c_int), ("power_its", C.c_int),
-                ("hg_alpha", C.c_double), ("graphs", C.c_int)]
+                ("hg_alpha", C.c_double), ("graphs", C.c_int), ("op_flags", C.c_uint)]
 
 
 class SolveInfo(C.Structure):

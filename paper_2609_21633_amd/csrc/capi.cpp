@@ -100,6 +100,23 @@ using tng::Error;
 
 namespace tng {
 namespace {
+void diag_A_t(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge, double hg_alpha,
+              bool twopt, void* const diag[3]) {
+    const tng::Level& L = tng::device_level(ctx, mesh, level);
+    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
+    TNG_REQUIRE(eta_wedge && diag && diag[0] && diag[1] && diag[2], "NULL argument");
+    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
+    tng::require_vel(ctx, diag, L, prec, "diag");
+    TNG_HIP(hipSetDevice(ctx->device));
+    if (prec == TNG_F64) {
+        double* d[3] = {(double*)diag[0], (double*)diag[1], (double*)diag[2]};
+        tng::mg_diag_A<double>(ctx, L, (const double*)eta_wedge, hg_alpha, d, twopt);
+    } else {
+        float* d[3] = {(float*)diag[0], (float*)diag[1], (float*)diag[2]};
+        tng::mg_diag_A<float>(ctx, L, (const float*)eta_wedge, hg_alpha, d, twopt);
+    }
+}
+
 template <typename T>
 void smooth_t(tng_ctx* ctx, const tng::Level& L, const void* eta, double hg_alpha, const void* const diag[3],
               const void* const b[3], void* const x[3], int degree, int steps, double lmin, double lmax) {
@@ -523,19 +540,15 @@ int tng_mmoc_advect(tng_ctx* ctx, const tng_mesh* mesh, int level, const double*
 int tng_diag_A(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
                double hg_alpha, void* const diag[3]) {
     TNG_API_BEGIN
-    const tng::Level& L = tng::device_level(ctx, mesh, level);
-    TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
-    TNG_REQUIRE(eta_wedge && diag && diag[0] && diag[1] && diag[2], "NULL argument");
-    tng::require_device(ctx, eta_wedge, tng::wedge_bytes(L, prec), "eta_wedge");
-    tng::require_vel(ctx, diag, L, prec, "diag");
-    TNG_HIP(hipSetDevice(ctx->device));
-    if (prec == TNG_F64) {
-        double* d[3] = {(double*)diag[0], (double*)diag[1], (double*)diag[2]};
-        tng::mg_diag_A<double>(ctx, L, (const double*)eta_wedge, hg_alpha, d);
-    } else {
-        float* d[3] = {(float*)diag[0], (float*)diag[1], (float*)diag[2]};
-        tng::mg_diag_A<float>(ctx, L, (const float*)eta_wedge, hg_alpha, d);
-    }
+    TNG_REQUIRE(hg_alpha >= 0.0 && std::isfinite(hg_alpha), "hg_alpha must be finite and >= 0");
+    tng::diag_A_t(ctx, mesh, level, prec, eta_wedge, hg_alpha, false, diag);
+    TNG_API_END
+}
+
+int tng_diag_A_twopoint(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* eta_wedge,
+                        void* const diag[3]) {
+    TNG_API_BEGIN
+    tng::diag_A_t(ctx, mesh, level, prec, eta_wedge, 0.0, true, diag);
     TNG_API_END
 }
 

@@ -36,7 +36,8 @@ struct CoarseDense {
 };
 
 template <typename T>
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3]);
+// twopt: the viscous block with the two-radial-point rule (hg_alpha must then be 0)
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt = false);
 template <typename T>
 void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag);
 template <typename T>
@@ -107,7 +108,8 @@ void vec_tab_copy(const tng_ctx* ctx, long long n, const T* src, const T* const*
 void scal_gather(const tng_ctx* ctx, const double* src, int k, double* staging);
 void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst);
 template <typename T>
-void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha);
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha,
+                     bool twopt = false);
 
 struct EnergyWS;
 EnergyWS* energy_ws_create();
@@ -145,6 +147,6 @@ std::vector<double> chebyshev_coefficients(int deg, double lo, double hi);
 void chebyshev_coefficients(int deg, double lo, double hi, double* ab);
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
-                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero);
+                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero, bool twopt = false);
 
 }  // namespace tng

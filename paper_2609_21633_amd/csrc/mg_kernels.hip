@@ -50,6 +50,21 @@ __device__ __forceinline__ void basis_grad(const double* g, double s1, int lat, 
     for (int x = 0; x < 3; ++x) out[x] = a * s1 * g[x] + b * s1 * g[3 + x] + c * g[6 + x];
 }
 
+// Two-radial-point rule (Sec. 4): points zeta = -+1/sqrt 3 on the lateral centroid,
+// weight 1/2 each.  There the Jacobian is G diag(r_q, r_q, dr/2) with r_q = r_m +
+// zeta dr/2, so the lateral part of a basis gradient carries 1/r_q and the radial
+// shape factor (1 + zeta) on the top face, (1 - zeta) on the bottom face; the
+// radial part is the one of q_c.  s1q = 1/(2 r_q).
+constexpr double TWOPT_ZETA = 0.57735026918962576451;
+__device__ __forceinline__ void basis_grad_at(const double* g, double s1q, double zq, int lat, int top,
+                                              double out[3]) {
+    const double a = lat == 0 ? -1.0 : (lat == 1 ? 1.0 : 0.0);
+    const double b = lat == 0 ? -1.0 : (lat == 2 ? 1.0 : 0.0);
+    const double c = top ? 1.0 : -1.0;
+    const double f = top ? 1.0 + zq : 1.0 - zq;
+    for (int x = 0; x < 3; ++x) out[x] = f * (a * s1q * g[x] + b * s1q * g[3 + x]) + c * g[6 + x];
+}
+
 // Hourglass-control scale of a wedge (eq:hgstab over the three barycentric
 // modes): eps_e = alpha mean(diag A_e) = alpha 5/27 eta V sum_j |grad phi_j|^2,
 // sum_j |grad phi_j|^2 = 4 (|rho1~|^2 + |rho2~|^2 + rho1~.rho2~) + 6 |rho3'|^2.
@@ -62,10 +77,12 @@ __device__ __forceinline__ double hg_eps(const double* g, double s1, double V, d
 
 // diag(A)_(node,c) = sum over the node's wedges of V eta (|grad phi|^2 + 1/3 (d_c phi)^2),
 // the diagonal of eq:elemmat with the one-point rule, plus 2/3 eps_e with hourglass
-// control (sum_a h_a[j]^2 = 2/3 for every node).  Per-diamond partial sums.
+// control (sum_a h_a[j]^2 = 2/3 for every node); twopt: the same sum over the two
+// radial points, each with V_q = r_q^2 |det G| / 2.  Per-diamond partial sums.
 template <typename T>
 __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restrict__ geo, int m, int n,
-                              double r_in, double dr, double hg_alpha, T* d0, T* d1, T* d2, long long nslots) {
+                              double r_in, double dr, double hg_alpha, int twopt, T* d0, T* d1, T* d2,
+                              long long nslots) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const NodeIdx q = decode_node(t, m, n);
@@ -89,9 +106,20 @@ __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restric
                     if (lat < 0) continue;
                     const double* g = gcol + wd * GEO_PER_TRI;
                     double gr[3];
+                    const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
+                    if (twopt) {
+                        for (int qq = 0; qq < 2; ++qq) {
+                            const double zq = qq == 0 ? -TWOPT_ZETA : TWOPT_ZETA;
+                            const double rq = rm + zq * (0.5 * dr);
+                            basis_grad_at(g, 0.5 / rq, zq, lat, top, gr);
+                            const double Vq = 0.5 * rq * rq * g[9];
+                            const double nn = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+                            for (int c = 0; c < 3; ++c) acc[c] += Vq * e * (nn + gr[c] * gr[c] / 3.0);
+                        }
+                        continue;
+                    }
                     basis_grad(g, s1, lat, top, gr);
                     const double V = rm * rm * g[9];
-                    const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
                     const double nn = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
                     const double hg = hg_alpha != 0.0 ? (2.0 / 3.0) * hg_eps(g, s1, V, e, hg_alpha) : 0.0;
                     for (int c = 0; c < 3; ++c) acc[c] += V * e * (nn + gr[c] * gr[c] / 3.0) + hg;
@@ -1032,7 +1060,7 @@ template <typename T>
 __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr, const int* __restrict__ copy_slot,
                                        const int* __restrict__ slot_dof, long long nslots, const T* __restrict__ eta,
                                        const double* __restrict__ geo, int m, int n, double r_in, double dr,
-                                       double hg_alpha, double* __restrict__ Ad) {
+                                       double hg_alpha, int twopt, double* __restrict__ Ad) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= nd) return;
     for (int r = 0; r < nd; ++r) Ad[(long long)col * nd + r] = 0.0;
@@ -1060,29 +1088,42 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
                             if (cdi[wd][l] == di && cdj[wd][l] == dj) lat = l;
                         if (lat < 0) continue;
                         const double* g = gcol + wd * GEO_PER_TRI;
-                        const double V = rm * rm * g[9];
                         const double e = (double)eta[((((long long)q.d * m + ci) * m + cj) * n + ck) * 2 + wd];
-                        double gj[3];
-                        basis_grad(g, s1, lat, top, gj);
-                        const double eps = hg_alpha != 0.0 ? hg_eps(g, s1, V, e, hg_alpha) : 0.0;
-                        for (int l2 = 0; l2 < 6; ++l2) {
-                            const int lat2 = l2 % 3, top2 = l2 / 3;
-                            double gl[3];
-                            basis_grad(g, s1, lat2, top2, gl);
-                            const long long s2 = (((long long)q.d * (m + 1) + ci + cdi[wd][lat2]) * (m + 1) +
-                                                  cj + cdj[wd][lat2]) * (n + 1) + ck + top2;
-                            const double gg = gj[0] * gl[0] + gj[1] * gl[1] + gj[2] * gl[2];
-                            for (int d2 = 0; d2 < 3; ++d2) {
-                                const int row = slot_dof[d2 * nslots + s2];
-                                if (row < 0) continue;
-                                // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c - 2/3 (g_j)_c (g_l)_d]
-                                double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
-                                                    (2.0 / 3.0) * gj[ccomp] * gl[d2]);
-                                // hourglass term: eps delta_cd zeta_j zeta_l (delta_{lat_j, lat_l} - 1/3)
-                                if (ccomp == d2)
-                                    v += eps * (top ? 1.0 : -1.0) * (top2 ? 1.0 : -1.0) *
-                                         ((lat == lat2 ? 1.0 : 0.0) - 1.0 / 3.0);
-                                Ad[(long long)col * nd + row] += v;
+                        // quadrature points: q_c (weight 1), or the two radial points
+                        const int nq = twopt ? 2 : 1;
+                        for (int qq = 0; qq < nq; ++qq) {
+                            const double zq = twopt ? (qq == 0 ? -TWOPT_ZETA : TWOPT_ZETA) : 0.0;
+                            const double rq = twopt ? rm + zq * (0.5 * dr) : rm;
+                            const double V = (twopt ? 0.5 : 1.0) * rq * rq * g[9];
+                            double gj[3];
+                            if (twopt)
+                                basis_grad_at(g, 0.5 / rq, zq, lat, top, gj);
+                            else
+                                basis_grad(g, s1, lat, top, gj);
+                            const double eps = hg_alpha != 0.0 ? hg_eps(g, s1, V, e, hg_alpha) : 0.0;
+                            for (int l2 = 0; l2 < 6; ++l2) {
+                                const int lat2 = l2 % 3, top2 = l2 / 3;
+                                double gl[3];
+                                if (twopt)
+                                    basis_grad_at(g, 0.5 / rq, zq, lat2, top2, gl);
+                                else
+                                    basis_grad(g, s1, lat2, top2, gl);
+                                const long long s2 = (((long long)q.d * (m + 1) + ci + cdi[wd][lat2]) * (m + 1) +
+                                                      cj + cdj[wd][lat2]) * (n + 1) + ck + top2;
+                                const double gg = gj[0] * gl[0] + gj[1] * gl[1] + gj[2] * gl[2];
+                                for (int d2 = 0; d2 < 3; ++d2) {
+                                    const int row = slot_dof[d2 * nslots + s2];
+                                    if (row < 0) continue;
+                                    // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c
+                                    //                              - 2/3 (g_j)_c (g_l)_d]
+                                    double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
+                                                        (2.0 / 3.0) * gj[ccomp] * gl[d2]);
+                                    // hourglass term: eps delta_cd zeta_j zeta_l (delta_{lat_j, lat_l} - 1/3)
+                                    if (ccomp == d2)
+                                        v += eps * (top ? 1.0 : -1.0) * (top2 ? 1.0 : -1.0) *
+                                             ((lat == lat2 ? 1.0 : 0.0) - 1.0 / 3.0);
+                                    Ad[(long long)col * nd + row] += v;
+                                }
                             }
                         }
                     }
@@ -1099,11 +1140,11 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3]) {
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt) {
     require_unbatched("mg_diag_A");
     const long long ns = L.node_slots();
     diag_A_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(),
-                                                             hg_alpha, d[0], d[1], d[2], ns);
+                                                             hg_alpha, twopt ? 1 : 0, d[0], d[1], d[2], ns);
     TNG_HIP(hipGetLastError());
     void* f[3] = {d[0], d[1], d[2]};
     launch_interface(ctx, L, prec_of<T>(), 0, 3, f);
@@ -1350,11 +1391,12 @@ void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst)
 }
 
 template <typename T>
-void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha) {
+void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha,
+                     bool twopt) {
     require_unbatched("coarse_assemble");
     coarse_assemble_kernel<T><<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(
         cd.ndof, cd.copy_ptr.p, cd.copy_slot.p, cd.slot_dof.p, cd.nslots, eta, L.geo64.p, L.m, L.n, L.r_in,
-        L.dr(), hg_alpha, cd.Ainv.p);
+        L.dr(), hg_alpha, twopt ? 1 : 0, cd.Ainv.p);
     TNG_HIP(hipGetLastError());
 }
 
@@ -1420,7 +1462,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 }
 
 #define TNG_INST(T)                                                                                        \
-    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3]);                      \
+    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], bool);                \
     template void mg_pmass<T>(const tng_ctx*, const Level&, const Level&, const T*, T*);                  \
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
@@ -1450,7 +1492,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
     template void vec_tab_copy<T>(const tng_ctx*, long long, const T*, const T* const*, T*, T* const*, int, \
                                   const double*);                                                          \
-    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double);
+    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double, bool);
 TNG_INST(double)
 TNG_INST(float)
 #undef TNG_INST

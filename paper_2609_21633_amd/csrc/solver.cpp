@@ -131,13 +131,18 @@ template <>
 float* pmass<float>(tng_solver* s) { return s->pm32.p; }
 
 // ---- operators ------------------------------------------------------------
+// the solve's operator options: the two-radial-point rule reaches every viscous
+// apply, the compressible mass rows only the outer operator K
+unsigned twopt_flag(const tng_solver* s) { return s->opts.op_flags & TNG_OP_TWOPOINT; }
+
 template <typename T>
 void apply_K(tng_solver* s, const T* eta0, const T* x, T* y) {
     const long long ns = s->ns0;
     const void* u[3] = {x, x + ns, x + 2 * ns};
     void* yu[3] = {y, y + ns, y + 2 * ns};
-    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_A | TNG_OP_BT | TNG_OP_B | TNG_OP_DIRICHLET,
-                        s->opts.hg_alpha, eta0, u, x + 3 * ns, yu, y + 3 * ns);
+    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(),
+                        TNG_OP_A | TNG_OP_BT | TNG_OP_B | TNG_OP_DIRICHLET | s->opts.op_flags, s->opts.hg_alpha,
+                        eta0, u, x + 3 * ns, yu, y + 3 * ns);
 }
 
 template <typename T>
@@ -146,8 +151,8 @@ void apply_A(tng_solver* s, int l, const T* eta, const T* x, T* y) {
     const long long ns = L.node_slots();
     const void* u[3] = {x, x + ns, x + 2 * ns};
     void* yu[3] = {y, y + ns, y + 2 * ns};
-    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, s->opts.hg_alpha, eta, u,
-                        nullptr, yu, nullptr);
+    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET | twopt_flag(s),
+                        s->opts.hg_alpha, eta, u, nullptr, yu, nullptr);
 }
 
 template <typename T>
@@ -193,8 +198,9 @@ void chebyshev_coefficients(int deg, double lo, double hi, double* ab) {
 
 template <typename T>
 void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, const T* invd, const T* b,
-                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero) {
+                     T* x, T* y, T* d, const double* ab_dev, int deg, int steps, bool x_zero, bool twopt) {
     const long long ns = L.node_slots();
+    const unsigned aflags = TNG_OP_A | TNG_OP_DIRICHLET | (twopt ? TNG_OP_TWOPOINT : 0u);
     // each update: the raw viscous apply, then one pass that completes its duplicated
     // nodes and identity rows and takes the two-term Chebyshev step (the apply's
     // closing pass and the update fused).  x_k alternates between x and d: a step of
@@ -202,7 +208,7 @@ void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg
     auto applyA = [&](const T* xin, T* yout) {
         const void* u[3] = {xin, xin + ns, xin + 2 * ns};
         void* yu[3] = {yout, yout + ns, yout + 2 * ns};
-        launch_stokes_apply_raw(ctx, L, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, hg_alpha, eta, u, yu);
+        launch_stokes_apply_raw(ctx, L, prec_of<T>(), aflags, hg_alpha, eta, u, yu);
     };
     for (int st = 0; st < steps; ++st) {
         for (int k = 0; k < deg; ++k) {
@@ -223,7 +229,7 @@ template <typename T>
 void chebyshev(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
     MGLevel<T>& M = hier<T>(s)[l];
     chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, M.invd.p, b, x, M.y.p, M.d.p, M.cheb.p,
-                       std::max(1, s->opts.cheb_degree), steps, x_zero);
+                       std::max(1, s->opts.cheb_degree), steps, x_zero, twopt_flag(s) != 0);
 }
 
 template <typename T>
@@ -244,8 +250,8 @@ void vcycle(tng_solver* s, int l, const T* b, T* x) {
         const Level& L = *M.L;
         const void* u[3] = {x, x + ns, x + 2 * ns};
         void* yu[3] = {M.y.p, M.y.p + ns, M.y.p + 2 * ns};
-        launch_stokes_apply_raw(s->ctx, L, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET, s->opts.hg_alpha, M.eta.p, u,
-                                yu);
+        launch_stokes_apply_raw(s->ctx, L, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET | twopt_flag(s),
+                                s->opts.hg_alpha, M.eta.p, u, yu);
         vec_resid_post<T>(s->ctx, L, true, true, b, x, M.y.p, M.r.p);
     }
     MGLevel<T>& C = H[l + 1];
@@ -560,7 +566,7 @@ void setup_level_operators(tng_solver* s) {
     for (int l = 0; l < s->nlev - 1; ++l) {
         MGLevel<T>& M = H[l];
         T* d[3] = {M.invd.p, M.invd.p + M.ns, M.invd.p + 2 * M.ns};
-        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d);
+        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d, twopt_flag(s) != 0);
         vec_invert<T>(s->ctx, 3 * M.ns, M.invd.p);
         M.lmax = power_lmax<T>(s, l);
         M.cheb_h = chebyshev_coefficients(std::max(1, s->opts.cheb_degree), s->opts.cheb_lo * M.lmax,
@@ -576,7 +582,8 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
                            s->ctx->stream));
     for (int l = 0; l + 1 < s->nlev; ++l) launch_eta_coarsen(s->ctx, s->mesh->lv[l + 1], TNG_F64, H[l].eta.p, H[l + 1].eta.p);
     // coarsest level: dense inverse of D A D over its interior DoFs
-    coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p, s->opts.hg_alpha);
+    coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p, s->opts.hg_alpha,
+                            twopt_flag(s) != 0);
     coarse_invert(s->ctx, s->cd);
     mg_pmass<double>(s->ctx, L0(s), L1(s), H[0].eta.p, s->pm64.p);
     if (!mixed) {
@@ -594,9 +601,10 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
 }  // namespace
 
 template void chebyshev_steps<double>(const tng_ctx*, const Level&, const double*, double, const double*,
-                                      const double*, double*, double*, double*, const double*, int, int, bool);
+                                      const double*, double*, double*, double*, const double*, int, int, bool,
+                                      bool);
 template void chebyshev_steps<float>(const tng_ctx*, const Level&, const float*, double, const float*,
-                                     const float*, float*, float*, float*, const double*, int, int, bool);
+                                     const float*, float*, float*, float*, const double*, int, int, bool, bool);
 
 // ---- lockstep batch of solver slots (serving) --------------------------------
 // A slot is a solver built inside its own arena, so the buffers of all slots
@@ -1175,6 +1183,7 @@ int tng_solver_opts_default(tng_solver_opts* o) {
     o->power_its = 10;
     o->hg_alpha = 0.0;
     o->graphs = 1;
+    o->op_flags = 0;
     TNG_API_END
 }
 
@@ -1205,6 +1214,13 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     TNG_REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "bad Chebyshev interval");
     TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
     TNG_REQUIRE(opts->hg_alpha >= 0.0 && std::isfinite(opts->hg_alpha), "hg_alpha must be finite and >= 0");
+    TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT || opts->op_flags == TNG_OP_TALA,
+                "op_flags must be 0, TNG_OP_TWOPOINT or TNG_OP_TALA");
+    TNG_REQUIRE(!(opts->op_flags & TNG_OP_TWOPOINT) || opts->hg_alpha == 0.0,
+                "the two-radial-point rule is an alternative to hourglass control (hg_alpha must be 0)");
+    TNG_REQUIRE(!(opts->op_flags & TNG_OP_TALA) || mesh->lv[0].rho64.p != nullptr,
+                "op_flags TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
+    TNG_REQUIRE(!batch_slot || opts->op_flags == 0, "the serving batches take the plain operator only (op_flags 0)");
     const int nlev = opts->levels > 0 ? opts->levels : (int)mesh->lv.size();
     TNG_REQUIRE(nlev >= 2 && nlev <= (int)mesh->lv.size(), "levels out of range");
     for (int l = 0; l + 1 < nlev; ++l)
@@ -1383,6 +1399,8 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     TNG_REQUIRE(o->dt > 0 || o->courant > 0, "need dt > 0 or courant > 0");
     TNG_REQUIRE(o->energy_restart >= 1 && o->energy_restart + 1 <= tng::MAX_MDOT, "energy_restart in 1..23");
     TNG_REQUIRE(o->scheme == 0 || o->scheme == 1, "scheme must be 0 (SUPG) or 1 (MMOC)");
+    TNG_REQUIRE(!(s->opts.op_flags & TNG_OP_TALA),
+                "the coupled step is of the Boussinesq form: its solver must not take TNG_OP_TALA");
     {
         const size_t nsb = (size_t)s->ns0 * sizeof(double);
         if (H) tng::require_device(s->ctx, H, nsb, "H");

@@ -256,3 +256,94 @@ def test_graph_preconditioner_equals_eager(tng, ctx, mt, mixed):
     # the replays after re-setup reproduce the first solve bit for bit as well
     assert np.array_equal(out[(1, "a2")][0], out[(1, "a")][0])
     assert np.array_equal(out[(1, "a2")][1], out[(1, "a")][1])
+
+
+# ---- operator variants of the solve: two-radial-point rule, compressible mass rows ----------
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 1e-6)])
+def test_diag_twopoint(tng, ctx, dtype, tol):
+    """diag(A) of the two-radial-point operator against the oracle's assembled
+    two-point matrix, entry by entry."""
+    import torch
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    or2 = StokesOracle(8, 8, eta, hierarchy=om.h, quad="two")
+    dt = getattr(torch, dtype)
+    d = torch.empty((3,) + mesh.shape(0), dtype=dt, device="cuda")
+    tng.diag_A(ctx, mesh, 0, eta_t.to(dt), d, twopoint=True)
+    got = lm.from_lib(d.double().cpu().numpy(), check_dups=0.0)
+    ref = or2.diag_A()
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < tol
+    # the rule is really the two-point one: its diagonal is not the one-point diagonal
+    assert np.max(np.abs(orc.diag_A() - ref) / np.abs(ref)) > 1e-3
+
+
+def _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed, op_flags):
+    import torch
+    s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-10, max_iters=400, op_flags=op_flags)
+    u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    info = s.solve(vel(lm, f), None, u, p, eta=eta_t)
+    s.close()
+    return (lm.from_lib(u.cpu().numpy(), check_dups=1e-12), lmp.from_lib(p.cpu().numpy(), check_dups=1e-12),
+            info)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_twopoint_solve_matches_direct_solve(tng, ctx, mixed):
+    """With TNG_OP_TWOPOINT every viscous apply of the solve (outer operator,
+    smoothers, residuals, diagonal, coarsest matrix) takes the two-radial-point
+    rule; the solution matches the oracle's direct solve of the two-point system
+    and differs from the one-point solution."""
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    or2 = StokesOracle(8, 8, eta, hierarchy=om.h, quad="two")
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((om.n_nodes, 3))
+    f[om.boundary_nodes()] = 0.0
+    gu, gp, info = _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed, tng.OP_TWOPOINT)
+    uo, po = or2.solve(f)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"two-point solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7
+    u1, _ = orc.solve(f)
+    assert rel(u1, uo) > 1e-4
+
+
+def _rho(r):
+    return np.exp(np.log(1.6) * (1.0 - r) / 0.45)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_tala_solve_matches_direct_solve(tng, ctx, mixed):
+    """With TNG_OP_TALA the outer operator's mass rows are -(psi, div(rhobar u));
+    the solution of the (non-symmetric) system matches the oracle's direct solve
+    with the same reference density, and differs from the Boussinesq solution."""
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    rho = _rho(om.r)
+    mesh.set_density(rho)
+    ort = StokesOracle(8, 8, eta, hierarchy=om.h, rho_nodes=rho)
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((om.n_nodes, 3))
+    f[om.boundary_nodes()] = 0.0
+    gu, gp, info = _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed, tng.OP_TALA)
+    uo, po = ort.solve(f)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"TALA solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7
+    # the discrete mass balance of the TALA rows holds for the computed velocity
+    assert np.linalg.norm(ort.B_mass @ gu.ravel()) < 1e-6 * np.linalg.norm(ort.B_D @ gu.ravel())
+    u1, _ = orc.solve(f)
+    assert rel(u1, uo) > 1e-4
+
+
+def test_solver_variant_options_are_checked(tng, ctx):
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    with pytest.raises(tng.TngError):
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT, hg_alpha=0.05)
+    with pytest.raises(tng.TngError):
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT | tng.OP_TALA)
+    with pytest.raises(tng.TngError):
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_OUTER)

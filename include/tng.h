@@ -316,7 +316,20 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  *     mesh's reference density (tng_mesh_set_density before the solver is
  *     created); the preconditioner keeps A, B^T and M_{1/eta}.  The right-hand
  *     side g must sum to zero over unique pressure nodes (1^T B_rho = 0).
- *   Not for the serving batches, which take op_flags 0. */
+ *   TNG_OP_FREESLIP_INNER or TNG_OP_FREESLIP_OUTER: free slip on that sphere
+ *     (rows P A P + N, P = I - rhat rhat^T at its nodes, as in tng_stokes_apply),
+ *     no slip on the other, on every level: the smoother keeps the iterate
+ *     tangential there (normal rows solved exactly, an isotropic diagonal
+ *     trace(P A_jj P) / 2), transfers keep the layer, the coarsest matrix
+ *     includes it.  The normal component of f at its nodes is the prescribed
+ *     normal velocity (0 for an impermeable sphere; the coupled step projects
+ *     its buoyancy so).  The node-normal projection keeps the constant pressure
+ *     in the null space only to O(h^2) (B_D^T 1 != 0): the solve takes the mass
+ *     rows modulo constants with a zero-mean pressure, the gauge of the no-slip
+ *     case.  Free slip on both spheres (the rigid rotations a null space) is
+ *     not taken.
+ *   Not for the serving batches, which take op_flags 0; hg_alpha must be 0
+ *   with every option but TNG_OP_TALA. */
 typedef struct {
     int mixed;
     int restart;

@@ -302,6 +302,28 @@ class StokesOracle:
         p = x[self.n_u:]
         return u, p - p.mean()
 
+    def solve_gauged(self, f: np.ndarray, g: np.ndarray | None = None):
+        """Exact discrete solution with the pressure gauge fixed by a Lagrange
+        multiplier c (Sec. 7 saddle point): A_D u + B_D^T p = f, B_D u - c 1 = g,
+        1^T p = 0, i.e. the mass rows modulo constants and a zero-mean pressure.
+
+        With no slip 1^T B_D = 0 and B_D^T 1 = 0, so c = 0 and this is the solution
+        of solve().  With free slip the node-normal projection P = I - rhat rhat^T
+        keeps the constant pressure in the null space only to O(h^2) (the boundary
+        flux of a velocity tangential at the nodes does not vanish on the chordal
+        facets): K_D is then non-singular with a pressure mean fixed by that
+        discretisation residue, and this gauged problem is the reading the solve
+        takes (the no-slip gauge kept).  Returns (u, p, c).
+        """
+        nk = self.K.shape[0]
+        one = np.concatenate([np.zeros(self.n_u), -np.ones(self.n_p)])
+        col = sp.csr_matrix(one[:, None])
+        Kb = sp.bmat([[self.K, col], [col.T, None]], format="csc")
+        b = np.concatenate([np.asarray(f, np.float64).ravel(),
+                            np.zeros(self.n_p) if g is None else np.asarray(g, np.float64), [0.0]])
+        x = spla.splu(Kb).solve(b)
+        return x[:self.n_u].reshape(-1, 3), x[self.n_u:nk], float(x[nk])
+
     def diag_A(self):
         return self.A_D.diagonal().reshape(-1, 3)
 

@@ -36,14 +36,23 @@ struct CoarseDense {
 };
 
 template <typename T>
-// twopt: the viscous block with the two-radial-point rule (hg_alpha must then be 0)
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt = false);
+// twopt: the viscous block with the two-radial-point rule (hg_alpha must then be 0);
+// fs: free-slip spheres (bit 0 inner, bit 1 outer, the TNG_OP_FREESLIP_* bits >> 4),
+// whose rows get the isotropic projected diagonal trace(P A_jj P) / 2
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt = false,
+               unsigned fs = 0);
+// x <- P x + N b at the free-slip layers fs (b == nullptr: b = 0)
+template <typename T>
+void vec_fs_project(const tng_ctx* ctx, const Level& L, unsigned fs, T* const x[3], const T* const b[3]);
 template <typename T>
 void mg_pmass(const tng_ctx* ctx, const Level& L, const Level& Lp, const T* eta, T* mdiag);
 template <typename T>
 void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* const f[3], bool add);
 template <typename T>
-void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]);
+// fs: free-slip spheres of the coarse level, whose layers are restricted like the
+// interior and then projected (no-slip layers are zero)
+void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3],
+                 unsigned fs = 0);
 // x, d <- one Chebyshev step with (alpha, beta) = ab_dev[2k], ab_dev[2k + 1]
 template <typename T>
 void vec_cheb_update(const tng_ctx* ctx, long long n, const double* ab_dev, int k, const T* b, const T* y,
@@ -109,7 +118,7 @@ void scal_gather(const tng_ctx* ctx, const double* src, int k, double* staging);
 void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst);
 template <typename T>
 void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha,
-                     bool twopt = false);
+                     bool twopt = false, unsigned fs = 0);
 
 struct EnergyWS;
 EnergyWS* energy_ws_create();

@@ -78,14 +78,21 @@ __device__ __forceinline__ double hg_eps(const double* g, double s1, double V, d
 // diag(A)_(node,c) = sum over the node's wedges of V eta (|grad phi|^2 + 1/3 (d_c phi)^2),
 // the diagonal of eq:elemmat with the one-point rule, plus 2/3 eps_e with hourglass
 // control (sum_a h_a[j]^2 = 2/3 for every node); twopt: the same sum over the two
-// radial points, each with V_q = r_q^2 |det G| / 2.  Per-diamond partial sums.
+// radial points, each with V_q = r_q^2 |det G| / 2.  On a free-slip sphere (fs bit 0
+// inner, bit 1 outer) the row block is P A_jj P + N with P = I - rhat rhat^T: its two
+// tangential diagonal entries are replaced by their mean, the same value in all three
+// components, so that D^{-1} maps tangential vectors to tangential vectors:
+// trace(P A_jj P) / 2 = sum_e V eta (|grad phi|^2 + (|grad phi|^2 - (rhat.grad phi)^2) / 6).
+// Per-diamond partial sums.
 template <typename T>
 __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restrict__ geo, int m, int n,
-                              double r_in, double dr, double hg_alpha, int twopt, T* d0, T* d1, T* d2,
-                              long long nslots) {
+                              double r_in, double dr, double hg_alpha, int twopt, int fs,
+                              const double* __restrict__ unit, T* d0, T* d1, T* d2, long long nslots) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
     const NodeIdx q = decode_node(t, m, n);
+    const bool proj = ((fs & 1) && q.k == 0) || ((fs & 2) && q.k == n);
+    const double* rh = unit + 3 * ((((long long)q.d * (m + 1) + q.i) * (m + 1)) + q.j);
     double acc[3] = {0, 0, 0};
     for (int ci = q.i - 1; ci <= q.i; ++ci) {
         if (ci < 0 || ci >= m) continue;
@@ -121,6 +128,12 @@ __global__ void diag_A_kernel(const T* __restrict__ eta, const double* __restric
                     basis_grad(g, s1, lat, top, gr);
                     const double V = rm * rm * g[9];
                     const double nn = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+                    if (proj) {
+                        const double gn = rh[0] * gr[0] + rh[1] * gr[1] + rh[2] * gr[2];
+                        const double v = V * e * (nn + (nn - gn * gn) / 6.0);
+                        for (int c = 0; c < 3; ++c) acc[c] += v;
+                        continue;
+                    }
                     const double hg = hg_alpha != 0.0 ? (2.0 / 3.0) * hg_eps(g, s1, V, e, hg_alpha) : 0.0;
                     for (int c = 0; c < 3; ++c) acc[c] += V * e * (nn + gr[c] * gr[c] / 3.0) + hg;
                 }
@@ -215,11 +228,12 @@ __global__ void prolong_kernel(int mf, int nf, const T* __restrict__ c0, const T
 // Restriction R = P^T, per diamond: a coarse node gathers the fine nodes it
 // interpolates to, each weighted by its interpolation weight and by
 // 1/multiplicity of the fine node (so the interface sum over diamond copies
-// counts every fine node once).  Dirichlet layers of the result are zero.
+// counts every fine node once).  No-slip layers of the result are zero; the layer of
+// a free-slip sphere (fs bit 0 inner, bit 1 outer) is restricted like the interior.
 template <typename T>
 __global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const T* __restrict__ f1,
                                 const T* __restrict__ f2, const T* __restrict__ inv_mult,
-                                T* c0, T* c1, T* c2, long long ncslots, SlotBatch sb) {
+                                T* c0, T* c1, T* c2, long long ncslots, int fs, SlotBatch sb) {
     const long long so = slot_off(sb);
     f0 = at_slot(f0, so);
     f1 = at_slot(f1, so);
@@ -232,7 +246,7 @@ __global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const 
     const int mc = mf / 2, nc = nf / 2;
     const NodeIdx q = decode_node(t, mc, nc);
     T s[3] = {0, 0, 0};
-    if (q.k > 0 && q.k < nc) {
+    if ((q.k > 0 || (fs & 1)) && (q.k < nc || (fs & 2))) {
         // lateral fine neighbours that interpolate from this coarse node
         const int di[7] = {0, 1, -1, 0, 0, 1, -1};
         const int dj[7] = {0, 0, 0, 1, -1, -1, 1};
@@ -245,6 +259,7 @@ __global__ void restrict_kernel(int mf, int nf, const T* __restrict__ f0, const 
             const T wm = wl[l] * inv_mult[lat];
             for (int dk = -1; dk <= 1; ++dk) {
                 const int fk = 2 * q.k + dk;
+                if (fk < 0 || fk > nf) continue;
                 const T w = dk == 0 ? wm : T(0.5) * wm;
                 const long long fidx = lat * (nf + 1) + fk;
                 for (int c = 0; c < 3; ++c) s[c] += w * fs[c][fidx];
@@ -390,15 +405,37 @@ __global__ void invert_kernel(long long n, T* a) {
     if (t < n) a[t] = T(1) / a[t];
 }
 
-// Dirichlet rows of a velocity diagonal are identity rows.
+// Dirichlet (no-slip) rows of a velocity diagonal are identity rows; fs: free-slip
+// spheres (bit 0 inner, bit 1 outer), whose rows keep their diagonal.
 template <typename T>
-__global__ void diag_dirichlet_kernel(long long ncol, int n, T* d0, T* d1, T* d2) {
+__global__ void diag_dirichlet_kernel(long long ncol, int n, int fs, T* d0, T* d1, T* d2) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * ncol) return;
+    if ((t & 1) ? (fs & 2) : (fs & 1)) return;
     const long long idx = (t >> 1) * (n + 1) + ((t & 1) ? n : 0);
     d0[idx] = T(1);
     d1[idx] = T(1);
     d2[idx] = T(1);
+}
+
+// Free-slip boundary rows of an iterate: x <- P x + N b = x + (rhat.b - rhat.x) rhat at
+// the layers of the free-slip spheres (fs bit 0 inner, bit 1 outer), b == nullptr: b = 0.
+// The normal rows of P A P + N are identity rows, so this solves them exactly and leaves
+// the tangential part to the smoother.
+template <typename T>
+__global__ void fs_project_kernel(long long ncol, int n, int fs, const T* __restrict__ unit, T* x0, T* x1, T* x2,
+                                  const T* __restrict__ b0, const T* __restrict__ b1, const T* __restrict__ b2) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * ncol) return;
+    if (!((t & 1) ? (fs & 2) : (fs & 1))) return;
+    const long long col = t >> 1;
+    const long long idx = col * (n + 1) + ((t & 1) ? n : 0);
+    const T r0 = unit[3 * col], r1 = unit[3 * col + 1], r2 = unit[3 * col + 2];
+    const T dx = r0 * x0[idx] + r1 * x1[idx] + r2 * x2[idx];
+    const T db = b0 ? r0 * b0[idx] + r1 * b1[idx] + r2 * b2[idx] : T(0);
+    x0[idx] += (db - dx) * r0;
+    x1[idx] += (db - dx) * r1;
+    x2[idx] += (db - dx) * r2;
 }
 
 template <typename TO, typename TI>
@@ -1060,15 +1097,21 @@ template <typename T>
 __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr, const int* __restrict__ copy_slot,
                                        const int* __restrict__ slot_dof, long long nslots, const T* __restrict__ eta,
                                        const double* __restrict__ geo, int m, int n, double r_in, double dr,
-                                       double hg_alpha, int twopt, double* __restrict__ Ad) {
+                                       double hg_alpha, int twopt, int fs, const double* __restrict__ unit,
+                                       double* __restrict__ Ad) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= nd) return;
     for (int r = 0; r < nd; ++r) Ad[(long long)col * nd + r] = 0.0;
+    auto on_fs = [&](int k) { return ((fs & 1) && k == 0) || ((fs & 2) && k == n); };
     for (int cp = copy_ptr[col]; cp < copy_ptr[col + 1]; ++cp) {
         const int sc = copy_slot[cp];
         const long long slot = sc >> 2;
         const int ccomp = sc & 3;
         const NodeIdx q = decode_node(slot, m, n);
+        // free slip: the column is (P A P) e_c, P = I - rhat rhat^T at the column node and
+        // at every row node on a free-slip sphere
+        const bool pc = on_fs(q.k);
+        const double* nc = unit + 3 * ((((long long)q.d * (m + 1) + q.i) * (m + 1)) + q.j);
         for (int ci = q.i - 1; ci <= q.i; ++ci) {
             if (ci < 0 || ci >= m) continue;
             for (int cj = q.j - 1; cj <= q.j; ++cj) {
@@ -1111,23 +1154,56 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
                                 const long long s2 = (((long long)q.d * (m + 1) + ci + cdi[wd][lat2]) * (m + 1) +
                                                       cj + cdj[wd][lat2]) * (n + 1) + ck + top2;
                                 const double gg = gj[0] * gl[0] + gj[1] * gl[1] + gj[2] * gl[2];
+                                // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c
+                                //                              - 2/3 (g_j)_c (g_l)_d]
+                                // hourglass term: eps delta_cd zeta_j zeta_l (delta_{lat_j, lat_l} - 1/3)
+                                auto entry = [&](int d2, int cc) {
+                                    double v = V * e * ((cc == d2 ? gg : 0.0) + gj[d2] * gl[cc] -
+                                                        (2.0 / 3.0) * gj[cc] * gl[d2]);
+                                    if (cc == d2)
+                                        v += eps * (top ? 1.0 : -1.0) * (top2 ? 1.0 : -1.0) *
+                                             ((lat == lat2 ? 1.0 : 0.0) - 1.0 / 3.0);
+                                    return v;
+                                };
+                                double w[3];
+                                for (int d2 = 0; d2 < 3; ++d2) {
+                                    if (!pc) {
+                                        w[d2] = entry(d2, ccomp);
+                                    } else {
+                                        w[d2] = 0.0;
+                                        for (int cc = 0; cc < 3; ++cc)
+                                            w[d2] += entry(d2, cc) * ((cc == ccomp ? 1.0 : 0.0) - nc[cc] * nc[ccomp]);
+                                    }
+                                }
+                                if (on_fs(ck + top2)) {
+                                    const double* nr = unit + 3 * ((((long long)q.d * (m + 1) + ci + cdi[wd][lat2]) *
+                                                                    (m + 1)) + cj + cdj[wd][lat2]);
+                                    const double dw = nr[0] * w[0] + nr[1] * w[1] + nr[2] * w[2];
+                                    for (int a2 = 0; a2 < 3; ++a2) w[a2] -= dw * nr[a2];
+                                }
                                 for (int d2 = 0; d2 < 3; ++d2) {
                                     const int row = slot_dof[d2 * nslots + s2];
                                     if (row < 0) continue;
-                                    // (A_e)_{(j,c),(l,d)} = V eta [delta_cd g_j.g_l + (g_j)_d (g_l)_c
-                                    //                              - 2/3 (g_j)_c (g_l)_d]
-                                    double v = V * e * ((ccomp == d2 ? gg : 0.0) + gj[d2] * gl[ccomp] -
-                                                        (2.0 / 3.0) * gj[ccomp] * gl[d2]);
-                                    // hourglass term: eps delta_cd zeta_j zeta_l (delta_{lat_j, lat_l} - 1/3)
-                                    if (ccomp == d2)
-                                        v += eps * (top ? 1.0 : -1.0) * (top2 ? 1.0 : -1.0) *
-                                             ((lat == lat2 ? 1.0 : 0.0) - 1.0 / 3.0);
-                                    Ad[(long long)col * nd + row] += v;
+                                    Ad[(long long)col * nd + row] += w[d2];
                                 }
                             }
                         }
                     }
                 }
+            }
+        }
+    }
+    // the normal row of a free-slip node: + N e_c = rhat rhat_c, once per DoF
+    {
+        const int sc = copy_slot[copy_ptr[col]];
+        const long long slot = sc >> 2;
+        const int ccomp = sc & 3;
+        const NodeIdx q = decode_node(slot, m, n);
+        if (on_fs(q.k)) {
+            const double* nc = unit + 3 * ((((long long)q.d * (m + 1) + q.i) * (m + 1)) + q.j);
+            for (int a2 = 0; a2 < 3; ++a2) {
+                const int row = slot_dof[a2 * nslots + slot];
+                if (row >= 0) Ad[(long long)col * nd + row] += nc[a2] * nc[ccomp];
             }
         }
     }
@@ -1140,16 +1216,18 @@ __global__ void coarse_assemble_kernel(int nd, const int* __restrict__ copy_ptr,
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt) {
+void mg_diag_A(const tng_ctx* ctx, const Level& L, const T* eta, double hg_alpha, T* const d[3], bool twopt,
+               unsigned fs) {
     require_unbatched("mg_diag_A");
     const long long ns = L.node_slots();
     diag_A_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(eta, L.geo64.p, L.m, L.n, L.r_in, L.dr(),
-                                                             hg_alpha, twopt ? 1 : 0, d[0], d[1], d[2], ns);
+                                                             hg_alpha, twopt ? 1 : 0, (int)fs, L.unit64.p,
+                                                             d[0], d[1], d[2], ns);
     TNG_HIP(hipGetLastError());
     void* f[3] = {d[0], d[1], d[2]};
     launch_interface(ctx, L, prec_of<T>(), 0, 3, f);
-    diag_dirichlet_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(L.lat_slots(), L.n, d[0],
-                                                                                  d[1], d[2]);
+    diag_dirichlet_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(L.lat_slots(), L.n, (int)fs,
+                                                                                  d[0], d[1], d[2]);
     TNG_HIP(hipGetLastError());
 }
 
@@ -1173,15 +1251,28 @@ void mg_prolong(const tng_ctx* ctx, const Level& Lf, const T* const c[3], T* con
 }
 
 template <typename T>
-void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3]) {
+void mg_restrict(const tng_ctx* ctx, const Level& Lf, const Level& Lc, const T* const f[3], T* const c[3],
+                 unsigned fs) {
     const long long ns = Lc.node_slots();
     const T* im = std::is_same<T, double>::value ? (const T*)Lf.inv_mult64.p : (const T*)Lf.inv_mult32.p;
     const SlotBatch sb = launch_batch();
     restrict_kernel<T><<<dim3(nblk(ns, 256), 1, sb.nb), 256, 0, ctx->stream>>>(Lf.m, Lf.n, f[0], f[1], f[2], im,
-                                                                               c[0], c[1], c[2], ns, sb);
+                                                                               c[0], c[1], c[2], ns, (int)fs, sb);
     TNG_HIP(hipGetLastError());
     void* g[3] = {c[0], c[1], c[2]};
     launch_interface(ctx, Lc, prec_of<T>(), 0, 3, g);
+    if (fs) vec_fs_project<T>(ctx, Lc, fs, c, nullptr);
+}
+
+template <typename T>
+void vec_fs_project(const tng_ctx* ctx, const Level& L, unsigned fs, T* const x[3], const T* const b[3]) {
+    if (!fs) return;
+    require_unbatched("vec_fs_project");
+    const T* un = std::is_same<T, double>::value ? (const T*)L.unit64.p : (const T*)L.unit32.p;
+    fs_project_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(
+        L.lat_slots(), L.n, (int)fs, un, x[0], x[1], x[2], b ? b[0] : nullptr, b ? b[1] : nullptr,
+        b ? b[2] : nullptr);
+    TNG_HIP(hipGetLastError());
 }
 
 template <typename T>
@@ -1392,11 +1483,11 @@ void scal_scatter(const tng_ctx* ctx, const double* staging, int k, double* dst)
 
 template <typename T>
 void coarse_assemble(const tng_ctx* ctx, const CoarseDense& cd, const Level& L, const T* eta, double hg_alpha,
-                     bool twopt) {
+                     bool twopt, unsigned fs) {
     require_unbatched("coarse_assemble");
     coarse_assemble_kernel<T><<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(
         cd.ndof, cd.copy_ptr.p, cd.copy_slot.p, cd.slot_dof.p, cd.nslots, eta, L.geo64.p, L.m, L.n, L.r_in,
-        L.dr(), hg_alpha, twopt ? 1 : 0, cd.Ainv.p);
+        L.dr(), hg_alpha, twopt ? 1 : 0, (int)fs, L.unit64.p, cd.Ainv.p);
     TNG_HIP(hipGetLastError());
 }
 
@@ -1462,11 +1553,12 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 }
 
 #define TNG_INST(T)                                                                                        \
-    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], bool);                \
+    template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], bool, unsigned);      \
+    template void vec_fs_project<T>(const tng_ctx*, const Level&, unsigned, T* const[3], const T* const[3]);      \
     template void mg_pmass<T>(const tng_ctx*, const Level&, const Level&, const T*, T*);                  \
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \
-                                 T* const[3]);                                                             \
+                                 T* const[3], unsigned);                                                   \
     template void vec_resid_post<T>(const tng_ctx*, const Level&, bool, bool, const T*, const T*, const T*, T*); \
     template void vec_cheb_post_update<T>(const tng_ctx*, const Level&, bool, bool, const double*, int, bool,   \
                                           bool, const T*, const T*, const T*, const T*, T*);                 \
@@ -1492,7 +1584,8 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
     template void vec_tab_copy<T>(const tng_ctx*, long long, const T*, const T* const*, T*, T* const*, int, \
                                   const double*);                                                          \
-    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double, bool);
+    template void coarse_assemble<T>(const tng_ctx*, const CoarseDense&, const Level&, const T*, double, bool,  \
+                                     unsigned);
 TNG_INST(double)
 TNG_INST(float)
 #undef TNG_INST

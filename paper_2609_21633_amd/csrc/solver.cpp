@@ -65,6 +65,9 @@ struct tng_solver {
     tng::DevBuf<double> pm64;           // lumped M_{1/eta} on the pressure level
     tng::DevBuf<float> pm32;
     tng::DevBuf<double> ones_p;         // pressure-level ones (mean projection)
+    tng::DevBuf<float> ones_p32;
+    tng::DevBuf<const double*> onesp64; // [ones_p]
+    tng::DevBuf<const float*> onesp32;  // [ones_p32]
     tng::DevBuf<double> xo, ro, bo;     // outer FP64 vectors (mixed precision)
     tng::DevBuf<float> r32, d32;
     tng::DevBuf<double> scal;           // device scalars
@@ -131,10 +134,37 @@ template <>
 float* pmass<float>(tng_solver* s) { return s->pm32.p; }
 
 // ---- operators ------------------------------------------------------------
-// the solve's operator options: the two-radial-point rule reaches every viscous
-// apply, the compressible mass rows only the outer operator K
+// the solve's operator options: the two-radial-point rule and free slip reach every
+// viscous apply, the compressible mass rows only the outer operator K
 unsigned twopt_flag(const tng_solver* s) { return s->opts.op_flags & TNG_OP_TWOPOINT; }
+unsigned fs_flag(const tng_solver* s) { return s->opts.op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER); }
+// the same as bits 0 (inner) and 1 (outer sphere)
+unsigned fs_bits(const tng_solver* s) { return fs_flag(s) >> 4; }
 
+template <typename T>
+const T* const* ones_ptr(tng_solver* s);
+template <>
+const double* const* ones_ptr<double>(tng_solver* s) { return s->onesp64.p; }
+template <>
+const float* const* ones_ptr<float>(tng_solver* s) { return s->onesp32.p; }
+
+// p <- p - mean(p) over unique pressure nodes
+template <typename T>
+void project_mean(tng_solver* s, T* p) {
+    const Level& P = L1(s);
+    vec_mdot<T>(s->ctx, *s->ds, P.node_slots(), P.n + 1, P.lat_slots(), P.owner.p, p, ones_ptr<T>(s), 1,
+                s->scal.p + 40, false);
+    vec_shift<T>(s->ctx, P.node_slots(), s->scal.p + 40, p);
+}
+
+// With free slip the velocity projection P = I - rhat rhat^T at the nodes does not
+// keep the constant pressure in the null space exactly: the boundary flux of a
+// velocity that is tangential at the nodes is O(h^2), so B_D^T 1 = P B^T 1 != 0 and
+// 1^T B_D != 0 by as much.  The solve keeps the pressure gauge of the no-slip case:
+// the mass rows are taken modulo constants and the pressure at zero mean, i.e. the
+// operator is diag(I, Pi) K diag(I, Pi), Pi = I - 1 1^T / n, which has the exact null
+// space (0, 1) again.  The Krylov vectors' pressures have zero mean (projected in the
+// preconditioner), so Pi on the input is implied and K's mass rows are projected here.
 template <typename T>
 void apply_K(tng_solver* s, const T* eta0, const T* x, T* y) {
     const long long ns = s->ns0;
@@ -143,6 +173,7 @@ void apply_K(tng_solver* s, const T* eta0, const T* x, T* y) {
     launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(),
                         TNG_OP_A | TNG_OP_BT | TNG_OP_B | TNG_OP_DIRICHLET | s->opts.op_flags, s->opts.hg_alpha,
                         eta0, u, x + 3 * ns, yu, y + 3 * ns);
+    if (fs_flag(s)) project_mean<T>(s, y + 3 * ns);
 }
 
 template <typename T>
@@ -151,7 +182,7 @@ void apply_A(tng_solver* s, int l, const T* eta, const T* x, T* y) {
     const long long ns = L.node_slots();
     const void* u[3] = {x, x + ns, x + 2 * ns};
     void* yu[3] = {y, y + ns, y + 2 * ns};
-    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET | twopt_flag(s),
+    launch_stokes_apply(s->ctx, L, nullptr, prec_of<T>(), TNG_OP_A | TNG_OP_DIRICHLET | twopt_flag(s) | fs_flag(s),
                         s->opts.hg_alpha, eta, u, nullptr, yu, nullptr);
 }
 
@@ -159,8 +190,8 @@ template <typename T>
 void apply_BT(tng_solver* s, const T* p, T* yu) {
     const long long ns = s->ns0;
     void* y[3] = {yu, yu + ns, yu + 2 * ns};
-    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_BT | TNG_OP_DIRICHLET, 0.0, nullptr, nullptr, p,
-                        y, nullptr);
+    launch_stokes_apply(s->ctx, L0(s), &L1(s), prec_of<T>(), TNG_OP_BT | TNG_OP_DIRICHLET | fs_flag(s), 0.0,
+                        nullptr, nullptr, p, y, nullptr);
 }
 
 // squared owner-masked norm of a velocity vector of level l into device scalar
@@ -225,8 +256,32 @@ void chebyshev_steps(const tng_ctx* ctx, const Level& L, const T* eta, double hg
 
 namespace {
 
+// The smoother with a free-slip sphere: the whole apply (interface sums and the
+// boundary rows P A P + N), the Chebyshev step in direction form, then the normal
+// rows solved exactly (x <- P x + N b), so that the iterate stays tangential there
+// and D^{-1} (isotropic on those rows) only ever sees tangential residuals.
+template <typename T>
+void chebyshev_fs(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
+    MGLevel<T>& M = hier<T>(s)[l];
+    const long long ns = M.ns, n3 = 3 * ns;
+    T* xx[3] = {x, x + ns, x + 2 * ns};
+    const T* bb[3] = {b, b + ns, b + 2 * ns};
+    if (x_zero && steps > 0) vec_fill<T>(s->ctx, n3, T(0), x);
+    const int deg = std::max(1, s->opts.cheb_degree);
+    for (int st = 0; st < steps; ++st)
+        for (int k = 0; k < deg; ++k) {
+            apply_A<T>(s, l, M.eta.p, x, M.y.p);
+            vec_cheb_update<T>(s->ctx, n3, M.cheb.p, k, b, M.y.p, M.invd.p, M.d.p, x);
+            vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), xx, bb);
+        }
+}
+
 template <typename T>
 void chebyshev(tng_solver* s, int l, const T* b, T* x, bool x_zero, int steps) {
+    if (fs_flag(s)) {
+        chebyshev_fs<T>(s, l, b, x, x_zero, steps);
+        return;
+    }
     MGLevel<T>& M = hier<T>(s)[l];
     chebyshev_steps<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, M.invd.p, b, x, M.y.p, M.d.p, M.cheb.p,
                        std::max(1, s->opts.cheb_degree), steps, x_zero, twopt_flag(s) != 0);
@@ -246,7 +301,12 @@ void vcycle(tng_solver* s, int l, const T* b, T* x) {
     chebyshev<T>(s, l, b, x, true, s->opts.pre);
     // r = b - A x: the raw apply into the smoother's work vector, then one pass that
     // completes it and forms the residual
-    {
+    if (fs_flag(s)) {
+        // free slip: the whole apply, then r = b - y
+        apply_A<T>(s, l, M.eta.p, x, M.y.p);
+        vec_cast<T, T>(s->ctx, 3 * ns, b, M.r.p);
+        vec_axpby<T>(s->ctx, 3 * ns, -1.0, M.y.p, 1.0, M.r.p);
+    } else {
         const Level& L = *M.L;
         const void* u[3] = {x, x + ns, x + 2 * ns};
         void* yu[3] = {M.y.p, M.y.p + ns, M.y.p + 2 * ns};
@@ -257,11 +317,15 @@ void vcycle(tng_solver* s, int l, const T* b, T* x) {
     MGLevel<T>& C = H[l + 1];
     const T* rf[3] = {M.r.p, M.r.p + ns, M.r.p + 2 * ns};
     T* bc[3] = {C.b.p, C.b.p + C.ns, C.b.p + 2 * C.ns};
-    mg_restrict<T>(s->ctx, *M.L, *C.L, rf, bc);
+    mg_restrict<T>(s->ctx, *M.L, *C.L, rf, bc, fs_bits(s));
     vcycle<T>(s, l + 1, C.b.p, C.x.p);
     const T* xc[3] = {C.x.p, C.x.p + C.ns, C.x.p + 2 * C.ns};
     T* xf[3] = {x, x + ns, x + 2 * ns};
     mg_prolong<T>(s->ctx, *M.L, xc, xf, true);
+    if (fs_flag(s)) {
+        const T* bf[3] = {b, b + ns, b + 2 * ns};
+        vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), xf, bf);
+    }
     chebyshev<T>(s, l, b, x, false, s->opts.post);
 }
 
@@ -271,6 +335,7 @@ void precond(tng_solver* s, const T* v, T* z) {
     KrylovWS<T>& K = kws<T>(s);
     const long long ns = s->ns0, np = s->np;
     vec_schur<T>(s->ctx, np, v + 3 * ns, pmass<T>(s), z + 3 * ns);
+    if (fs_flag(s)) project_mean<T>(s, z + 3 * ns);             // free slip: zero-mean pressures
     apply_BT<T>(s, z + 3 * ns, K.t.p);                           // t = B^T z_p
     vec_axpby<T>(s->ctx, 3 * ns, 1.0, v, -1.0, K.t.p);           // t = v_u - B^T z_p
     vcycle<T>(s, 0, K.t.p, z);                                   // z_u ~ A^{-1} t
@@ -439,11 +504,13 @@ void build_coarse_maps(tng_solver* s) {
     std::vector<int> owner_of(C.n_unique_lat, -1);
     for (long long q = 0; q < nl; ++q)
         if (owner_of[C.uid[q]] < 0) owner_of[C.uid[q]] = (int)q;
+    // unknowns: interior layers, and the layer of a free-slip sphere
+    const int k0 = (fs_bits(s) & 1) ? 0 : 1, k1 = (fs_bits(s) & 2) ? n : n - 1;
     std::vector<int> dof_of_uid_k((size_t)C.n_unique_lat * (n + 1) * 3, -1);
     std::vector<int> dof_slot;
     for (long long q = 0; q < nl; ++q) {
         if (owner_of[C.uid[q]] != q) continue;
-        for (int k = 1; k < n; ++k)
+        for (int k = k0; k <= k1; ++k)
             for (int c = 0; c < 3; ++c) {
                 dof_of_uid_k[((size_t)C.uid[q] * (n + 1) + k) * 3 + c] = (int)dof_slot.size();
                 dof_slot.push_back((int)(((q * (n + 1) + k) << 2) | c));
@@ -456,7 +523,7 @@ void build_coarse_maps(tng_solver* s) {
     std::vector<int> slot_dof((size_t)3 * nsl, -1);
     std::vector<std::vector<int>> copies(nd);
     for (long long q = 0; q < nl; ++q)
-        for (int k = 1; k < n; ++k)
+        for (int k = k0; k <= k1; ++k)
             for (int c = 0; c < 3; ++c) {
                 const int dof = dof_of_uid_k[((size_t)C.uid[q] * (n + 1) + k) * 3 + c];
                 const long long slot = q * (n + 1) + k;
@@ -543,12 +610,18 @@ double power_lmax(tng_solver* s, int l) {
         void* f[3] = {M.x.p, M.x.p + M.ns, M.x.p + 2 * M.ns};
         launch_interface(s->ctx, *M.L, prec_of<T>(), 1, 3, f);
     }
+    // free slip: the normal rows of D^{-1} (P A P + N) have eigenvalue 1 / d, outside
+    // the smoother's spectrum; the iteration stays tangential there
+    T* xv[3] = {M.x.p, M.x.p + M.ns, M.x.p + 2 * M.ns};
+    T* yv[3] = {M.y.p, M.y.p + M.ns, M.y.p + 2 * M.ns};
+    vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), xv, nullptr);
     const T* const* xp = M.xy.p;
     const T* const* yp = M.xy.p + 1;
     double lam = 1.0;
     for (int it = 0; it < s->opts.power_its; ++it) {
         apply_A<T>(s, l, M.eta.p, M.x.p, M.y.p);
         vec_mul<T>(s->ctx, n3, M.invd.p, M.y.p, M.y.p);
+        vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), yv, nullptr);
         vel_dot<T>(s, l, M.x.p, xp, s->scal.p);
         vel_dot<T>(s, l, M.y.p, yp, s->scal.p + 1);
         readback(s, s->scal.p, 2);
@@ -566,7 +639,7 @@ void setup_level_operators(tng_solver* s) {
     for (int l = 0; l < s->nlev - 1; ++l) {
         MGLevel<T>& M = H[l];
         T* d[3] = {M.invd.p, M.invd.p + M.ns, M.invd.p + 2 * M.ns};
-        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d, twopt_flag(s) != 0);
+        mg_diag_A<T>(s->ctx, *M.L, M.eta.p, s->opts.hg_alpha, d, twopt_flag(s) != 0, fs_bits(s));
         vec_invert<T>(s->ctx, 3 * M.ns, M.invd.p);
         M.lmax = power_lmax<T>(s, l);
         M.cheb_h = chebyshev_coefficients(std::max(1, s->opts.cheb_degree), s->opts.cheb_lo * M.lmax,
@@ -583,7 +656,7 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
     for (int l = 0; l + 1 < s->nlev; ++l) launch_eta_coarsen(s->ctx, s->mesh->lv[l + 1], TNG_F64, H[l].eta.p, H[l + 1].eta.p);
     // coarsest level: dense inverse of D A D over its interior DoFs
     coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p, s->opts.hg_alpha,
-                            twopt_flag(s) != 0);
+                            twopt_flag(s) != 0, fs_bits(s));
     coarse_invert(s->ctx, s->cd);
     mg_pmass<double>(s->ctx, L0(s), L1(s), H[0].eta.p, s->pm64.p);
     if (!mixed) {
@@ -1214,8 +1287,13 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     TNG_REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "bad Chebyshev interval");
     TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
     TNG_REQUIRE(opts->hg_alpha >= 0.0 && std::isfinite(opts->hg_alpha), "hg_alpha must be finite and >= 0");
-    TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT || opts->op_flags == TNG_OP_TALA,
-                "op_flags must be 0, TNG_OP_TWOPOINT or TNG_OP_TALA");
+    TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT || opts->op_flags == TNG_OP_TALA ||
+                    opts->op_flags == TNG_OP_FREESLIP_INNER || opts->op_flags == TNG_OP_FREESLIP_OUTER,
+                "op_flags must be 0, TNG_OP_TWOPOINT, TNG_OP_TALA, TNG_OP_FREESLIP_INNER or TNG_OP_FREESLIP_OUTER "
+                "(free slip on both spheres leaves the rigid rotations as a null space, which the solver does not "
+                "remove)");
+    TNG_REQUIRE(!(opts->op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) || opts->hg_alpha == 0.0,
+                "free slip has no hourglass-controlled form (hg_alpha must be 0)");
     TNG_REQUIRE(!(opts->op_flags & TNG_OP_TWOPOINT) || opts->hg_alpha == 0.0,
                 "the two-radial-point rule is an alternative to hourglass control (hg_alpha must be 0)");
     TNG_REQUIRE(!(opts->op_flags & TNG_OP_TALA) || mesh->lv[0].rho64.p != nullptr,
@@ -1256,6 +1334,16 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     }
     s->ones_p.alloc(s->np);
     tng::vec_fill<double>(ctx, s->np, 1.0, s->ones_p.p);
+    s->ones_p32.alloc(s->np);
+    tng::vec_fill<float>(ctx, s->np, 1.0f, s->ones_p32.p);
+    {
+        const double* o64 = s->ones_p.p;
+        const float* o32 = s->ones_p32.p;
+        s->onesp64.alloc(1);
+        s->onesp32.alloc(1);
+        TNG_HIP(hipMemcpy(s->onesp64.p, &o64, sizeof(o64), hipMemcpyHostToDevice));
+        TNG_HIP(hipMemcpy(s->onesp32.p, &o32, sizeof(o32), hipMemcpyHostToDevice));
+    }
     s->scal.alloc(64);
     {
         const double* dp[4] = {s->bo.p, s->ro.p, s->xo.p + 3 * s->ns0, s->k64.w.p};
@@ -1265,6 +1353,7 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
         const tng::Level& P = mesh->lv[1];
         const double cnt = (double)P.n_unique_lat * (P.n + 1);
         TNG_HIP(hipMemcpy(s->scal.p + 33, &cnt, sizeof(double), hipMemcpyHostToDevice));
+        TNG_HIP(hipMemcpy(s->scal.p + 41, &cnt, sizeof(double), hipMemcpyHostToDevice));
     }
     TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host), 256 * sizeof(double), hipHostMallocDefault));
     if (opts->graphs && !batch_slot) {
@@ -1322,6 +1411,7 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
         TNG_HIP(hipMemcpyAsync(bvec + 3 * ns, g, np * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
         tng::vec_fill<double>(s->ctx, np, 0.0, bvec + 3 * ns);
+    if (tng::fs_flag(s)) tng::project_mean<double>(s, bvec + 3 * ns);   // mass rows modulo constants
     const double* const* bp = s->dptr.p;         // -> bo
     const double* const* rp = s->dptr.p + 1;     // -> ro
     tng::vec_smdot<double>(s->ctx, *s->ds, tng::L0(s), tng::L1(s), bvec, bp, 1, s->scal.p + 1, false);
@@ -1419,6 +1509,8 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     tng::launch_eta_from_T(s->ctx, L, TNG_F64, T, s->eta_step.p, o->E, o->F);
     double* f[3] = {s->f_step.p, s->f_step.p + ns, s->f_step.p + 2 * ns};
     tng::energy_buoyancy(s->ctx, L, T, o->Ra, f);
+    // a free-slip sphere is impermeable: its normal rows prescribe zero normal velocity
+    tng::vec_fs_project<double>(s->ctx, L, tng::fs_bits(s), f, nullptr);
     const double* fc[3] = {f[0], f[1], f[2]};
     tng_solve_info sinfo{};
     const int rc = tng_stokes_solve(s, s->eta_step.p, fc, nullptr, u, p, &sinfo);

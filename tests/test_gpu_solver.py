@@ -345,5 +345,35 @@ def test_solver_variant_options_are_checked(tng, ctx):
         tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT, hg_alpha=0.05)
     with pytest.raises(tng.TngError):
         tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT | tng.OP_TALA)
+    with pytest.raises(tng.TngError):        # rigid rotations: a null space the solver does not remove
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER)
     with pytest.raises(tng.TngError):
-        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_OUTER)
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_OUTER, hg_alpha=0.05)
+
+
+@pytest.mark.parametrize("side,mixed", [("outer", 0), ("outer", 1), ("inner", 0), ("inner", 1)])
+def test_freeslip_solve_matches_direct_solve(tng, ctx, side, mixed):
+    """Free slip on one sphere through the whole multigrid (projected smoother,
+    transfers and coarsest matrix), no slip on the other: the solution matches the
+    oracle's direct solve of that system with the pressure gauge of the no-slip case
+    (mass rows modulo constants, zero-mean pressure).  The body force keeps a normal
+    part on the free-slip sphere, which is the prescribed normal velocity there."""
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    bc = ("noslip", "freeslip") if side == "outer" else ("freeslip", "noslip")
+    flag = tng.OP_FREESLIP_OUTER if side == "outer" else tng.OP_FREESLIP_INNER
+    ofs = StokesOracle(8, 8, eta, hierarchy=om.h, bc=bc)
+    rng = np.random.default_rng(13)
+    f = rng.standard_normal((om.n_nodes, 3))
+    k = np.tile(np.arange(9), om.n_lat)
+    f[k == (0 if side == "outer" else 8)] = 0.0          # the no-slip sphere
+    gu, gp, info = _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed, flag)
+    uo, po, c = ofs.solve_gauged(f)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"free-slip ({side}) solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e} multiplier {c:.2e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7
+    fsn = k == (8 if side == "outer" else 0)
+    rhat = om.node_xyz()[fsn]
+    rhat /= np.linalg.norm(rhat, axis=1)[:, None]
+    assert np.allclose(np.sum(gu[fsn] * rhat, 1), np.sum(f[fsn] * rhat, 1), rtol=0, atol=1e-7)

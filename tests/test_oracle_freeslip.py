@@ -103,3 +103,73 @@ def test_boundary_projections_reject_unknown_kinds():
     om = ShellMesh(2, 2)
     with pytest.raises(ValueError):
         boundary_projections(om, ("slip", "noslip"))
+
+
+# ---- the gauged direct solve (pressure mean fixed by a multiplier) ----------------------
+
+def _layers(om):
+    k = np.tile(np.arange(NR + 1), om.n_lat)
+    return k == 0, k == NR
+
+
+def _rhs(om, bc, seed):
+    """Random body force, zero on no-slip rows; on free-slip rows the normal part
+    is the prescribed normal velocity."""
+    f = np.random.default_rng(seed).standard_normal((om.n_nodes, 3))
+    inner, outer = _layers(om)
+    if bc[0] == "noslip":
+        f[inner] = 0.0
+    if bc[1] == "noslip":
+        f[outer] = 0.0
+    return f
+
+
+def test_gauged_solve_is_the_pinned_solve_with_no_slip(shell):
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h)
+    f = _rhs(om, ("noslip", "noslip"), 11)
+    u1, p1 = o.solve(f)
+    u2, p2, c = o.solve_gauged(f)
+    assert np.linalg.norm(u2 - u1) < 1e-10 * np.linalg.norm(u1)
+    assert np.linalg.norm(p2 - p1) < 1e-10 * np.linalg.norm(p1)
+    assert abs(c) < 1e-12 * np.abs(p1).max()
+
+
+def test_freeslip_keeps_the_constant_pressure_null_space_only_to_h2(shell):
+    """B_D^T 1 vanishes with no slip, not with free slip (node normals against the
+    chordal boundary facets), and shrinks like h^2 under refinement."""
+    om, eta = shell
+    one = lambda o: np.ones(o.n_p)
+    o_ns = StokesOracle(MT, NR, eta, hierarchy=om.h)
+    assert np.linalg.norm(o_ns.BT_D @ one(o_ns)) < 1e-13 * abs(o_ns.BT_D).max()
+    res = []
+    for mt in (4, 8):
+        m = ShellMesh(mt, mt)
+        o = StokesOracle(mt, mt, np.ones(m.n_wedges), hierarchy=m.h, bc=("noslip", "freeslip"))
+        r = np.linalg.norm(o.BT_D @ one(o))
+        assert np.linalg.norm(one(o) @ o.B_D) == pytest.approx(r, rel=1e-10)   # symmetric
+        res.append(r)
+    assert res[0] > 1e-3 and 3.0 < res[0] / res[1] < 6.0
+
+
+@pytest.mark.parametrize("bc", [("noslip", "freeslip"), ("freeslip", "noslip")])
+def test_gauged_freeslip_solve_satisfies_its_equations(shell, bc):
+    om, eta = shell
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h, bc=bc)
+    f = _rhs(om, bc, 12)
+    u, p, c = o.solve_gauged(f)
+    fn = np.linalg.norm(f)
+    assert np.linalg.norm(o.A_D @ u.ravel() + o.BT_D @ p - f.ravel()) < 1e-10 * fn
+    assert np.linalg.norm(o.B_D @ u.ravel() - c) < 1e-10 * np.linalg.norm(u)
+    assert abs(p.mean()) < 1e-12 * np.abs(p).max()
+    assert abs(c) > 1e-8                                 # the multiplier is needed here
+    # normal velocity on the free-slip sphere = the normal part of f
+    inner, outer = _layers(om)
+    fsn = inner if bc[0] == "freeslip" else outer
+    rhat = om.node_xyz()[fsn]
+    rhat /= np.linalg.norm(rhat, axis=1)[:, None]
+    assert np.allclose(np.sum(u[fsn] * rhat, 1), np.sum(f[fsn] * rhat, 1), rtol=0, atol=1e-12 * fn)
+    # planted contrast: the pinned solve of the no-slip case, taken as it is, leaves a
+    # momentum residual of the size of c B_D^T 1
+    u1, p1 = o.solve(f)
+    assert np.linalg.norm(o.A_D @ u1.ravel() + o.BT_D @ p1 - f.ravel()) > 1e-6 * fn

@@ -316,18 +316,21 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  *     mesh's reference density (tng_mesh_set_density before the solver is
  *     created); the preconditioner keeps A, B^T and M_{1/eta}.  The right-hand
  *     side g must sum to zero over unique pressure nodes (1^T B_rho = 0).
- *   TNG_OP_FREESLIP_INNER or TNG_OP_FREESLIP_OUTER: free slip on that sphere
+ *   TNG_OP_FREESLIP_INNER and/or TNG_OP_FREESLIP_OUTER: free slip on that sphere
  *     (rows P A P + N, P = I - rhat rhat^T at its nodes, as in tng_stokes_apply),
- *     no slip on the other, on every level: the smoother keeps the iterate
+ *     no slip on a sphere without the bit, on every level: the smoother keeps the iterate
  *     tangential there (normal rows solved exactly, an isotropic diagonal
  *     trace(P A_jj P) / 2), transfers keep the layer, the coarsest matrix
  *     includes it.  The normal component of f at its nodes is the prescribed
- *     normal velocity (0 for an impermeable sphere; the coupled step projects
- *     its buoyancy so).  The node-normal projection keeps the constant pressure
- *     in the null space only to O(h^2) (B_D^T 1 != 0): the solve takes the mass
- *     rows modulo constants with a zero-mean pressure, the gauge of the no-slip
- *     case.  Free slip on both spheres (the rigid rotations a null space) is
- *     not taken.
+ *     normal velocity (0 for an impermeable sphere: tng_rhs_buoyancy_bc; the
+ *     coupled step does so).  The node-normal projection keeps the constant
+ *     pressure in the null space only to O(h^2) (B_D^T 1 != 0): the solve takes
+ *     the mass rows modulo constants with a zero-mean pressure, the gauge of the
+ *     no-slip case.  Both bits: free slip on both spheres; the rigid rotations
+ *     e_a x x are then a null space too: f must be orthogonal to them (a
+ *     buoyancy force is), the coarsest matrix is shifted by sigma Q Q^T on them
+ *     (Q orthonormal, sigma its mean diagonal) and the solution is returned
+ *     orthogonal to them (inner products over unique DoFs).
  *   Not for the serving batches, which take op_flags 0; hg_alpha must be 0
  *   with every option but TNG_OP_TALA. */
 typedef struct {
@@ -389,6 +392,13 @@ int tng_stokes_solver_vcycle(tng_solver* solver, const void* const b[3], void* c
  * Dirichlet rows zero.  T: device node field; f[3]: device velocity out. */
 int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
                      void* const f[3]);
+/* tng_rhs_buoyancy for free-slip spheres (the setup of Sec. 8): bc_flags holds
+ * TNG_OP_FREESLIP_INNER and/or TNG_OP_FREESLIP_OUTER; the rows of such a sphere
+ * keep the tangential part of the buoyancy and a zero normal part (zero
+ * normal velocity in the free-slip rows of the solve), the rows of the other
+ * spheres are zero.  bc_flags 0 is tng_rhs_buoyancy. */
+int tng_rhs_buoyancy_bc(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, unsigned bc_flags,
+                        const void* T, double Ra, void* const f[3]);
 /* Buoyancy of the compressible (TALA) form of eq:stokes, with the split
  * T = Tbar(r) + T' of eq:tsplit: f_(i,c) = sum_e V_e N_i(q_c) Ra
  * (rhobar alphabar)(q_c) T'(q_c) rhat_c(q_c), both factors the W1 interpolants

@@ -313,16 +313,30 @@ class StokesOracle:
         flux of a velocity tangential at the nodes does not vanish on the chordal
         facets): K_D is then non-singular with a pressure mean fixed by that
         discretisation residue, and this gauged problem is the reading the solve
-        takes (the no-slip gauge kept).  Returns (u, p, c).
+        takes (the no-slip gauge kept).  With free slip on both spheres the velocity
+        is also taken orthogonal to the rigid rotations.  Returns (u, p, c).
         """
         nk = self.K.shape[0]
-        one = np.concatenate([np.zeros(self.n_u), -np.ones(self.n_p)])
-        col = sp.csr_matrix(one[:, None])
-        Kb = sp.bmat([[self.K, col], [col.T, None]], format="csc")
+        cols = [np.concatenate([np.zeros(self.n_u), -np.ones(self.n_p)])]
+        if self.bc == ("freeslip", "freeslip"):
+            # the rigid rotations are a null space of A_D too: the velocity is taken
+            # orthogonal to them (R^T u = 0, multipliers lambda; f must be orthogonal
+            # to them for lambda = 0)
+            for w in self.rotations().T:
+                cols.append(np.concatenate([w, np.zeros(self.n_p)]))
+        C = sp.csr_matrix(np.stack(cols, axis=1))
+        Kb = sp.bmat([[self.K, C], [C.T, None]], format="csc")
         b = np.concatenate([np.asarray(f, np.float64).ravel(),
-                            np.zeros(self.n_p) if g is None else np.asarray(g, np.float64), [0.0]])
+                            np.zeros(self.n_p) if g is None else np.asarray(g, np.float64), np.zeros(len(cols))])
         x = spla.splu(Kb).solve(b)
+        self.last_rotation_multipliers = x[nk + 1:]
         return x[:self.n_u].reshape(-1, 3), x[self.n_u:nk], float(x[nk])
+
+    def rotations(self):
+        """The rigid rotations e_a x x at the nodes, as three columns over the
+        velocity DoFs ([node][component] order)."""
+        x = self.mesh.node_xyz()
+        return np.stack([np.cross(np.tile(e, (self.mesh.n_nodes, 1)), x).ravel() for e in np.eye(3)], axis=1)
 
     def diag_A(self):
         return self.A_D.diagonal().reshape(-1, 3)

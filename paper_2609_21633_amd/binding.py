@@ -70,6 +70,7 @@ def lib():
         "tng_stokes_solve": [_vp, _vp, C.POINTER(_vp), _vp, C.POINTER(_vp), _vp, _vp],
         "tng_stokes_solver_vcycle": [_vp, C.POINTER(_vp), C.POINTER(_vp)],
         "tng_rhs_buoyancy": [_vp, _vp, C.c_int, C.c_int, _vp, C.c_double, C.POINTER(_vp)],
+        "tng_rhs_buoyancy_bc": [_vp, _vp, C.c_int, C.c_int, C.c_uint, _vp, C.c_double, C.POINTER(_vp)],
         "tng_energy_apply": [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
         "tng_energy_step": [_vp, _vp, _vp, _vp, C.POINTER(_vp), _vp, _vp],
         "tng_mmoc_advect": [_vp, _vp, C.c_int, C.POINTER(_vp), C.c_double, _vp, _vp],
@@ -415,10 +416,15 @@ class StepInfo(C.Structure):
                 ("dt", C.c_double), ("seconds", C.c_double)]
 
 
-def rhs_buoyancy(ctx: Context, mesh: Mesh, level: int, T, Ra: float, f):
+def rhs_buoyancy(ctx: Context, mesh: Mesh, level: int, T, Ra: float, f, bc_flags: int = 0):
+    """Buoyancy Ra T rhat; bc_flags: OP_FREESLIP_INNER / OP_FREESLIP_OUTER spheres keep the
+    tangential part in their rows (others zero)."""
     _chk(ctx, T, T.dtype, _nodes(mesh, level), "T")
     _chk3(ctx, f, T.dtype, _nodes(mesh, level), "f")
-    check(lib().tng_rhs_buoyancy(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _ptr3(f)))
+    if bc_flags:
+        check(lib().tng_rhs_buoyancy_bc(ctx.h, mesh.h, level, _prec(T), bc_flags, _ptr(T), Ra, _ptr3(f)))
+    else:
+        check(lib().tng_rhs_buoyancy(ctx.h, mesh.h, level, _prec(T), _ptr(T), Ra, _ptr3(f)))
 
 
 def rhs_buoyancy_tala(ctx: Context, mesh: Mesh, level: int, T, Ra: float, Tbar_nodes, rhoalpha_nodes, f):

@@ -456,20 +456,28 @@ int tng_interface_sum(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pr
 
 int tng_rhs_buoyancy(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, const void* T, double Ra,
                      void* const f[3]) {
+    return tng_rhs_buoyancy_bc(ctx, mesh, level, prec, 0u, T, Ra, f);
+}
+
+int tng_rhs_buoyancy_bc(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec prec, unsigned bc_flags,
+                        const void* T, double Ra, void* const f[3]) {
     TNG_API_BEGIN
     const tng::Level& L = tng::device_level(ctx, mesh, level);
     TNG_REQUIRE(prec == TNG_F64 || prec == TNG_F32, "bad precision");
     TNG_REQUIRE(T && f && f[0] && f[1] && f[2], "NULL argument");
     TNG_REQUIRE(std::isfinite(Ra), "Ra must be finite");
+    TNG_REQUIRE((bc_flags & ~(unsigned)(TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) == 0,
+                "bc_flags: TNG_OP_FREESLIP_INNER and/or TNG_OP_FREESLIP_OUTER only");
     tng::require_device(ctx, T, tng::node_bytes(L, prec), "T");
     tng::require_vel(ctx, f, L, prec, "f");
     TNG_HIP(hipSetDevice(ctx->device));
+    const unsigned fs = bc_flags >> 4;
     if (prec == TNG_F64) {
         double* ff[3] = {(double*)f[0], (double*)f[1], (double*)f[2]};
-        tng::buoyancy_rhs<double>(ctx, L, (const double*)T, Ra, ff);
+        tng::buoyancy_rhs<double>(ctx, L, (const double*)T, Ra, ff, nullptr, nullptr, fs);
     } else {
         float* ff[3] = {(float*)f[0], (float*)f[1], (float*)f[2]};
-        tng::buoyancy_rhs<float>(ctx, L, (const float*)T, Ra, ff);
+        tng::buoyancy_rhs<float>(ctx, L, (const float*)T, Ra, ff, nullptr, nullptr, fs);
     }
     TNG_API_END
 }

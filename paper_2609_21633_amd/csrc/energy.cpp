@@ -208,8 +208,9 @@ double energy_cfl_dt(const tng_ctx* ctx, const Level& L, EnergyWS& W, const doub
     return rate > 0 ? courant / rate : 1e30;
 }
 
-void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]) {
-    buoyancy_rhs<double>(ctx, L, T, Ra, f);
+void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3],
+                     unsigned fs) {
+    buoyancy_rhs<double>(ctx, L, T, Ra, f, nullptr, nullptr, fs);
 }
 
 }  // namespace tng

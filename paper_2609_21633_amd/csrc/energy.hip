@@ -275,11 +275,13 @@ __global__ void set_layers_kernel(long long ncol, int n, T* y, const T* src, dou
     y[idx] = src ? src[idx] : T((t & 1) ? v1 : v0);
 }
 
-// velocity Dirichlet rows of a vector field to zero
+// velocity Dirichlet rows of a vector field to zero (fs: free-slip spheres, bit 0 inner,
+// bit 1 outer, whose layers are left alone)
 template <typename T>
-__global__ void zero_layers3_kernel(long long ncol, int n, T* a0, T* a1, T* a2) {
+__global__ void zero_layers3_kernel(long long ncol, int n, int fs, T* a0, T* a1, T* a2) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * ncol) return;
+    if ((t & 1) ? (fs & 2) : (fs & 1)) return;
     const long long idx = (t >> 1) * (n + 1) + ((t & 1) ? n : 0);
     a0[idx] = T(0);
     a1[idx] = T(0);
@@ -357,16 +359,18 @@ void energy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, const T* H, dou
 
 template <typename T>
 void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3], const double* tbar,
-                  const double* rhoalpha) {
+                  const double* rhoalpha, unsigned fs) {
     const long long ns = L.node_slots();
     buoyancy_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(make_geo(L), L.unit64.p, Tn, Ra, f[0], f[1], f[2],
                                                               ns, tbar, rhoalpha);
     TNG_HIP(hipGetLastError());
     void* g[3] = {f[0], f[1], f[2]};
     launch_interface(ctx, L, prec_of<T>(), 0, 3, g);
-    zero_layers3_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(L.lat_slots(), L.n, f[0], f[1],
-                                                                                 f[2]);
+    zero_layers3_kernel<T><<<nblk(2 * L.lat_slots(), 256), 256, 0, ctx->stream>>>(L.lat_slots(), L.n, (int)fs,
+                                                                                 f[0], f[1], f[2]);
     TNG_HIP(hipGetLastError());
+    // an impermeable free-slip sphere: the normal rows prescribe zero normal velocity
+    vec_fs_project<T>(ctx, L, fs, f, nullptr);
 }
 
 // max over wedges of |ubar| / h into host memory (synchronises)
@@ -392,7 +396,7 @@ double cfl_rate(const tng_ctx* ctx, const Level& L, const T* const u[3], DevBuf<
     template void energy_diag<T>(const tng_ctx*, const Level&, const double*, double, T*);                 \
     template void energy_rhs<T>(const tng_ctx*, const Level&, const T*, const T*, double, double, double, T*); \
     template void buoyancy_rhs<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], const double*,  \
-                                  const double*);                                                       \
+                                  const double*, unsigned);                                                       \
     template double cfl_rate<T>(const tng_ctx*, const Level&, const T* const[3], DevBuf<double>&);
 TNG_EINST(double)
 TNG_EINST(float)

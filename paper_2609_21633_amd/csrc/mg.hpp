@@ -33,7 +33,15 @@ struct CoarseDense {
     DevBuf<int> copy_ptr;   // [ndof + 1]: copies of each DoF (CSR)
     DevBuf<int> copy_slot;  //   (slot << 2) | component of every copy
     DevBuf<double> Ainv;    // ndof x ndof
+    DevBuf<double> rotq;    // [3][ndof] orthonormal rigid rotations + sigma (free slip on both spheres)
 };
+
+// free slip on both spheres: A <- A + sigma Q Q^T over the coarsest DoFs, Q the
+// orthonormalised rigid rotations, sigma the mean diagonal (before coarse_invert)
+void coarse_rotation_shift(const tng_ctx* ctx, CoarseDense& cd, const Level& L);
+// rigid rotation e_a x x at every node slot of L, in three component fields
+template <typename T>
+void vec_rotation(const tng_ctx* ctx, const Level& L, int a, T* const out[3]);
 
 template <typename T>
 // twopt: the viscous block with the two-radial-point rule (hg_alpha must then be 0);
@@ -134,7 +142,9 @@ int energy_solve_mmoc(const tng_ctx* ctx, const Level& L, EnergyWS& W, const dou
 // over dt along the W1 velocity u), W1-interpolated (eq:departure); FP64 node fields.
 void mmoc_departure(const tng_ctx* ctx, const Level& L, const double* const u[3], double dt, const double* Tn,
                     double* That);
-void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3]);
+// fs: free-slip spheres (bit 0 inner, bit 1 outer): their rows keep the tangential part
+void energy_buoyancy(const tng_ctx* ctx, const Level& L, const double* T, double Ra, double* const f[3],
+                     unsigned fs = 0);
 template <typename T>
 void energy_apply(const tng_ctx* ctx, const Level& L, const T* const u[3], double dt, const T* Tin, T* y);
 // Streaming energy apply (levels with at most 256 radial layers): y = E(u) T with the
@@ -147,7 +157,7 @@ void energy_apply_stream(const tng_ctx* ctx, const Level& L, const T* const u[3]
 // the Boussinesq form (Tbar = 0, rhobar alphabar = 1)
 template <typename T>
 void buoyancy_rhs(const tng_ctx* ctx, const Level& L, const T* Tn, double Ra, T* const f[3],
-                  const double* tbar = nullptr, const double* rhoalpha = nullptr);
+                  const double* tbar = nullptr, const double* rhoalpha = nullptr, unsigned fs = 0);
 
 // Coefficients (alpha_k, beta_k), k < deg, of one Chebyshev smoothing step of
 // degree deg for the eigenvalue interval [lo, hi].

@@ -438,6 +438,71 @@ __global__ void fs_project_kernel(long long ncol, int n, int fs, const T* __rest
     x2[idx] += (db - dx) * r2;
 }
 
+// Rigid rotation e_a x x of the shell's nodes (x = r_k rhat), component c at every
+// node slot: a null vector of the viscous block with free slip on both spheres.
+template <typename T>
+__global__ void rotation_fill_kernel(int m, int n, double r_in, double dr, const double* __restrict__ unit, int a,
+                                     T* o0, T* o1, T* o2, long long nslots) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const long long lat = t / (n + 1);
+    const double r = r_in + (double)(t % (n + 1)) * dr;
+    const double x = r * unit[3 * lat], y = r * unit[3 * lat + 1], z = r * unit[3 * lat + 2];
+    const double v0 = a == 0 ? 0.0 : (a == 1 ? z : -y);
+    const double v1 = a == 0 ? -z : (a == 1 ? 0.0 : x);
+    const double v2 = a == 0 ? y : (a == 1 ? -x : 0.0);
+    o0[t] = T(v0);
+    o1[t] = T(v1);
+    o2[t] = T(v2);
+}
+
+// The coarsest matrix with free slip on both spheres is singular (the three rigid
+// rotations).  q: the rotations over the coarse DoFs, orthonormalised (Gram-Schmidt in
+// DoF order), and sigma the mean diagonal entry; one thread.
+__global__ void coarse_rotation_basis_kernel(int nd, const int* __restrict__ dof_slot, int m, int n, double r_in,
+                                             double dr, const double* __restrict__ unit,
+                                             const double* __restrict__ Ad, double* q) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int a = 0; a < 3; ++a) {
+        double* qa = q + (long long)a * nd;
+        for (int d = 0; d < nd; ++d) {
+            const long long slot = dof_slot[d] >> 2;
+            const int c = dof_slot[d] & 3;
+            const long long lat = slot / (n + 1);
+            const double r = r_in + (double)(slot % (n + 1)) * dr;
+            const double x[3] = {r * unit[3 * lat], r * unit[3 * lat + 1], r * unit[3 * lat + 2]};
+            // (e_a x x)_c = eps_{c a b} x_b
+            const int b = 3 - a - c;
+            qa[d] = a == c ? 0.0 : (((a - c + 3) % 3 == 1) ? x[b] : -x[b]);
+        }
+        for (int b2 = 0; b2 < a; ++b2) {
+            const double* qb = q + (long long)b2 * nd;
+            double dt = 0.0;
+            for (int d = 0; d < nd; ++d) dt += qa[d] * qb[d];
+            for (int d = 0; d < nd; ++d) qa[d] -= dt * qb[d];
+        }
+        double nn = 0.0;
+        for (int d = 0; d < nd; ++d) nn += qa[d] * qa[d];
+        const double inv = 1.0 / sqrt(nn);
+        for (int d = 0; d < nd; ++d) qa[d] *= inv;
+    }
+    double tr = 0.0;
+    for (int d = 0; d < nd; ++d) tr += Ad[(long long)d * nd + d];
+    q[3LL * nd] = tr / nd;
+}
+
+// A <- A + sigma sum_a q_a q_a^T: the rotations get eigenvalue sigma, the rest of the
+// spectrum is unchanged (the q_a span the null space), so for a right-hand side
+// orthogonal to them the inverse gives the solution orthogonal to them.
+__global__ void coarse_rotation_shift_kernel(int nd, const double* __restrict__ q, double* Ad) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= nd) return;
+    const double sigma = q[3LL * nd];
+    const double c0 = q[col], c1 = q[nd + col], c2 = q[2LL * nd + col];
+    for (int r = 0; r < nd; ++r)
+        Ad[(long long)col * nd + r] += sigma * (c0 * q[r] + c1 * q[nd + r] + c2 * q[2LL * nd + r]);
+}
+
 template <typename TO, typename TI>
 __global__ void cast_kernel(long long n, const TI* __restrict__ a, TO* __restrict__ b, SlotBatch sb) {
     const long long so = slot_off(sb);
@@ -1524,6 +1589,25 @@ void coarse_gather(const tng_ctx* ctx, const CoarseDense& cd, int col, const T* 
     TNG_HIP(hipGetLastError());
 }
 
+void coarse_rotation_shift(const tng_ctx* ctx, CoarseDense& cd, const Level& L) {
+    require_unbatched("coarse_rotation_shift");
+    if (cd.rotq.n != (size_t)(3 * cd.ndof + 1)) cd.rotq.alloc(3 * cd.ndof + 1);
+    coarse_rotation_basis_kernel<<<1, 1, 0, ctx->stream>>>(cd.ndof, cd.dof_slot.p, L.m, L.n, L.r_in, L.dr(),
+                                                         L.unit64.p, cd.Ainv.p, cd.rotq.p);
+    TNG_HIP(hipGetLastError());
+    coarse_rotation_shift_kernel<<<nblk(cd.ndof, 64), 64, 0, ctx->stream>>>(cd.ndof, cd.rotq.p, cd.Ainv.p);
+    TNG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void vec_rotation(const tng_ctx* ctx, const Level& L, int a, T* const out[3]) {
+    require_unbatched("vec_rotation");
+    const long long ns = L.node_slots();
+    rotation_fill_kernel<T><<<nblk(ns, 256), 256, 0, ctx->stream>>>(L.m, L.n, L.r_in, L.dr(), L.unit64.p, a, out[0],
+                                                                   out[1], out[2], ns);
+    TNG_HIP(hipGetLastError());
+}
+
 void coarse_invert(const tng_ctx* ctx, CoarseDense& cd) {
     require_unbatched("coarse_invert");
     gauss_jordan_kernel<<<1, 1024, 0, ctx->stream>>>(cd.ndof, cd.Ainv.p);
@@ -1555,6 +1639,7 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 #define TNG_INST(T)                                                                                        \
     template void mg_diag_A<T>(const tng_ctx*, const Level&, const T*, double, T* const[3], bool, unsigned);      \
     template void vec_fs_project<T>(const tng_ctx*, const Level&, unsigned, T* const[3], const T* const[3]);      \
+    template void vec_rotation<T>(const tng_ctx*, const Level&, int, T* const[3]);                                \
     template void mg_pmass<T>(const tng_ctx*, const Level&, const Level&, const T*, T*);                  \
     template void mg_prolong<T>(const tng_ctx*, const Level&, const T* const[3], T* const[3], bool);      \
     template void mg_restrict<T>(const tng_ctx*, const Level&, const Level&, const T* const[3],           \

@@ -68,6 +68,11 @@ struct tng_solver {
     tng::DevBuf<float> ones_p32;
     tng::DevBuf<const double*> onesp64; // [ones_p]
     tng::DevBuf<const float*> onesp32;  // [ones_p32]
+    // free slip on both spheres: the rigid rotations e_a x x (three velocity vectors),
+    // device pointers to them, and the inverse of their Gram matrix over unique DoFs
+    tng::DevBuf<double> rot64;
+    tng::DevBuf<const double*> rotptr;
+    double rot_ginv[9] = {};
     tng::DevBuf<double> xo, ro, bo;     // outer FP64 vectors (mixed precision)
     tng::DevBuf<float> r32, d32;
     tng::DevBuf<double> scal;           // device scalars
@@ -486,6 +491,23 @@ int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxi
     return std::isfinite(res) ? TNG_OK : TNG_E_NOTCONV;
 }
 
+// free slip on both spheres: u <- u - R (R^T R)^{-1} R^T u for the outer solution xo,
+// R the rigid rotations, inner products over unique DoFs (the solution is fixed up to
+// rotations as the pressure is up to its mean)
+void remove_rotations(tng_solver* s) {
+    if (fs_bits(s) != 3) return;
+    const Level& L = L0(s);
+    const long long n3 = 3 * s->ns0;
+    vec_mdot<double>(s->ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, s->xo.p, s->rotptr.p, 3,
+                     s->scal.p + 42, false);
+    readback(s, s->scal.p + 42, 3);
+    const double d[3] = {s->host[0], s->host[1], s->host[2]};
+    for (int a = 0; a < 3; ++a) {
+        const double c = s->rot_ginv[3 * a] * d[0] + s->rot_ginv[3 * a + 1] * d[1] + s->rot_ginv[3 * a + 2] * d[2];
+        vec_axpby<double>(s->ctx, n3, -c, s->rot64.p + a * n3, 1.0, s->xo.p);
+    }
+}
+
 // p <- p - mean(p) over unique pressure nodes of the outer solution xo
 void remove_pressure_mean(tng_solver* s) {
     const Level& P = L1(s);
@@ -657,6 +679,7 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
     // coarsest level: dense inverse of D A D over its interior DoFs
     coarse_assemble<double>(s->ctx, s->cd, s->mesh->lv[s->nlev - 1], H[s->nlev - 1].eta.p, s->opts.hg_alpha,
                             twopt_flag(s) != 0, fs_bits(s));
+    if (fs_bits(s) == 3) coarse_rotation_shift(s->ctx, s->cd, s->mesh->lv[s->nlev - 1]);
     coarse_invert(s->ctx, s->cd);
     mg_pmass<double>(s->ctx, L0(s), L1(s), H[0].eta.p, s->pm64.p);
     if (!mixed) {
@@ -1288,10 +1311,9 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
     TNG_REQUIRE(opts->hg_alpha >= 0.0 && std::isfinite(opts->hg_alpha), "hg_alpha must be finite and >= 0");
     TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT || opts->op_flags == TNG_OP_TALA ||
-                    opts->op_flags == TNG_OP_FREESLIP_INNER || opts->op_flags == TNG_OP_FREESLIP_OUTER,
-                "op_flags must be 0, TNG_OP_TWOPOINT, TNG_OP_TALA, TNG_OP_FREESLIP_INNER or TNG_OP_FREESLIP_OUTER "
-                "(free slip on both spheres leaves the rigid rotations as a null space, which the solver does not "
-                "remove)");
+                    (opts->op_flags & ~(unsigned)(TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) == 0,
+                "op_flags must be 0, TNG_OP_TWOPOINT, TNG_OP_TALA or free-slip bits (TNG_OP_FREESLIP_INNER, "
+                "TNG_OP_FREESLIP_OUTER or both)");
     TNG_REQUIRE(!(opts->op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) || opts->hg_alpha == 0.0,
                 "free slip has no hourglass-controlled form (hg_alpha must be 0)");
     TNG_REQUIRE(!(opts->op_flags & TNG_OP_TWOPOINT) || opts->hg_alpha == 0.0,
@@ -1354,6 +1376,34 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
         const double cnt = (double)P.n_unique_lat * (P.n + 1);
         TNG_HIP(hipMemcpy(s->scal.p + 33, &cnt, sizeof(double), hipMemcpyHostToDevice));
         TNG_HIP(hipMemcpy(s->scal.p + 41, &cnt, sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (tng::fs_bits(s.get()) == 3) {
+        // rigid rotations of the velocity level and the inverse of their Gram matrix
+        const tng::Level& L = mesh->lv[0];
+        const long long n3 = 3 * s->ns0;
+        s->rot64.alloc(3 * n3);
+        const double* rp[3];
+        for (int a = 0; a < 3; ++a) {
+            double* o[3] = {s->rot64.p + a * n3, s->rot64.p + a * n3 + s->ns0, s->rot64.p + a * n3 + 2 * s->ns0};
+            tng::vec_rotation<double>(ctx, L, a, o);
+            rp[a] = s->rot64.p + a * n3;
+        }
+        s->rotptr.alloc(3);
+        TNG_HIP(hipMemcpy(s->rotptr.p, rp, sizeof(rp), hipMemcpyHostToDevice));
+        for (int a = 0; a < 3; ++a)
+            tng::vec_mdot<double>(ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, rp[a], s->rotptr.p, 3,
+                                  s->scal.p + 48 + 3 * a, false);
+        double G[9];
+        TNG_HIP(hipMemcpyAsync(G, s->scal.p + 48, sizeof(G), hipMemcpyDeviceToHost, ctx->stream));
+        TNG_HIP(hipStreamSynchronize(ctx->stream));
+        // inverse of the symmetric positive definite 3 x 3 Gram matrix (cofactors)
+        const double c00 = G[4] * G[8] - G[5] * G[7], c01 = G[5] * G[6] - G[3] * G[8], c02 = G[3] * G[7] - G[4] * G[6];
+        const double det = G[0] * c00 + G[1] * c01 + G[2] * c02;
+        TNG_REQUIRE(det > 0.0 && std::isfinite(det), "rigid rotations: singular Gram matrix");
+        const double inv[9] = {c00, G[2] * G[7] - G[1] * G[8], G[1] * G[5] - G[2] * G[4],
+                               c01, G[0] * G[8] - G[2] * G[6], G[2] * G[3] - G[0] * G[5],
+                               c02, G[1] * G[6] - G[0] * G[7], G[0] * G[4] - G[1] * G[3]};
+        for (int i = 0; i < 9; ++i) s->rot_ginv[i] = inv[i] / det;
     }
     TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host), 256 * sizeof(double), hipHostMallocDefault));
     if (opts->graphs && !batch_slot) {
@@ -1422,6 +1472,7 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     double relres = bn > 0 ? 1.0 : 0.0;
     auto true_residual = [&]() {
         tng::remove_pressure_mean(s);
+        tng::remove_rotations(s);
         tng::apply_K<double>(s, s->h64[0].eta.p, xo, ro);
         tng::vec_axpby<double>(s->ctx, N, 1.0, bvec, -1.0, ro);
         tng::vec_smdot<double>(s->ctx, *s->ds, tng::L0(s), tng::L1(s), ro, rp, 1, s->scal.p, false);
@@ -1508,9 +1559,8 @@ int tng_energy_step(tng_solver* s, const tng_step_opts* o, const double* H, doub
     // viscosity of the current temperature, buoyancy, Stokes solve
     tng::launch_eta_from_T(s->ctx, L, TNG_F64, T, s->eta_step.p, o->E, o->F);
     double* f[3] = {s->f_step.p, s->f_step.p + ns, s->f_step.p + 2 * ns};
-    tng::energy_buoyancy(s->ctx, L, T, o->Ra, f);
-    // a free-slip sphere is impermeable: its normal rows prescribe zero normal velocity
-    tng::vec_fs_project<double>(s->ctx, L, tng::fs_bits(s), f, nullptr);
+    // rows of a free-slip sphere: the tangential part of the buoyancy (zero normal velocity)
+    tng::energy_buoyancy(s->ctx, L, T, o->Ra, f, tng::fs_bits(s));
     const double* fc[3] = {f[0], f[1], f[2]};
     tng_solve_info sinfo{};
     const int rc = tng_stokes_solve(s, s->eta_step.p, fc, nullptr, u, p, &sinfo);

@@ -345,8 +345,8 @@ def test_solver_variant_options_are_checked(tng, ctx):
         tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT, hg_alpha=0.05)
     with pytest.raises(tng.TngError):
         tng.StokesSolver(ctx, mesh, op_flags=tng.OP_TWOPOINT | tng.OP_TALA)
-    with pytest.raises(tng.TngError):        # rigid rotations: a null space the solver does not remove
-        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER)
+    with pytest.raises(tng.TngError):        # no free-slip form of the two-point rule
+        tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_OUTER | tng.OP_TWOPOINT)
     with pytest.raises(tng.TngError):
         tng.StokesSolver(ctx, mesh, op_flags=tng.OP_FREESLIP_OUTER, hg_alpha=0.05)
 
@@ -377,3 +377,53 @@ def test_freeslip_solve_matches_direct_solve(tng, ctx, side, mixed):
     rhat = om.node_xyz()[fsn]
     rhat /= np.linalg.norm(rhat, axis=1)[:, None]
     assert np.allclose(np.sum(gu[fsn] * rhat, 1), np.sum(f[fsn] * rhat, 1), rtol=0, atol=1e-7)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_freeslip_both_spheres_solve_matches_direct_solve(tng, ctx, mixed):
+    """Free slip on both spheres: the rigid rotations are a null space as well; for a
+    body force orthogonal to them the solution, returned orthogonal to them, matches
+    the oracle's gauged direct solve with the rotation constraints."""
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    bc = ("freeslip", "freeslip")
+    ofs = StokesOracle(8, 8, eta, hierarchy=om.h, bc=bc)
+    R = ofs.rotations()
+    f = np.random.default_rng(16).standard_normal(3 * om.n_nodes)
+    f -= R @ np.linalg.solve(R.T @ R, R.T @ f)
+    f = f.reshape(-1, 3)
+    gu, gp, info = _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed,
+                                  tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER)
+    uo, po, c = ofs.solve_gauged(f)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"free-slip (both) solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e} rotations {np.linalg.norm(R.T @ gu.ravel()):.1e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7
+    assert np.linalg.norm(R.T @ gu.ravel()) < 1e-9 * np.linalg.norm(R) * np.linalg.norm(gu)
+
+
+@pytest.mark.parametrize("flags", ["inner", "outer", "both"])
+def test_buoyancy_with_freeslip_rows(tng, ctx, flags):
+    """tng_rhs_buoyancy_bc: the one-point buoyancy of the oracle, rows of a no-slip
+    sphere zero, rows of a free-slip sphere without their normal part; element-wise."""
+    import torch
+    from oracle.stokes import buoyancy_rhs
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    bits = {"inner": tng.OP_FREESLIP_INNER, "outer": tng.OP_FREESLIP_OUTER,
+            "both": tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER}[flags]
+    T = np.random.default_rng(17).uniform(0.0, 1.0, om.n_nodes)
+    ref = buoyancy_rhs(om, T, 1e5)
+    k = np.tile(np.arange(9), om.n_lat)
+    rhat = om.node_xyz() / np.linalg.norm(om.node_xyz(), axis=1)[:, None]
+    for layer, bit in ((0, tng.OP_FREESLIP_INNER), (8, tng.OP_FREESLIP_OUTER)):
+        sel = k == layer
+        if bits & bit:
+            ref[sel] -= np.sum(ref[sel] * rhat[sel], 1)[:, None] * rhat[sel]
+        else:
+            ref[sel] = 0.0
+    Tt = torch.tensor(lm.to_lib(T), device="cuda")
+    f = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    tng.rhs_buoyancy(ctx, mesh, 0, Tt, 1e5, f, bc_flags=bits)
+    got = lm.from_lib(f.cpu().numpy(), check_dups=1e-12)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) < 1e-12 * scale

@@ -173,3 +173,29 @@ def test_gauged_freeslip_solve_satisfies_its_equations(shell, bc):
     # momentum residual of the size of c B_D^T 1
     u1, p1 = o.solve(f)
     assert np.linalg.norm(o.A_D @ u1.ravel() + o.BT_D @ p1 - f.ravel()) > 1e-6 * fn
+
+
+def test_gauged_solve_with_free_slip_on_both_spheres(shell):
+    """Both spheres free: the rotations are a null space, the solve takes u
+    orthogonal to them; for a body force orthogonal to them the rotation
+    multipliers vanish and every equation holds.  A buoyancy-type force (radial
+    at the wedge centroid, one-point rule) is orthogonal to them exactly."""
+    om, eta = shell
+    bc = ("freeslip", "freeslip")
+    o = StokesOracle(MT, NR, eta, hierarchy=om.h, bc=bc)
+    R = o.rotations()
+    f = _rhs(om, bc, 14).ravel()
+    f -= R @ np.linalg.solve(R.T @ R, R.T @ f)
+    u, p, c = o.solve_gauged(f.reshape(-1, 3))
+    fn = np.linalg.norm(f)
+    assert np.linalg.norm(o.last_rotation_multipliers) < 1e-10 * fn
+    assert np.linalg.norm(o.A_D @ u.ravel() + o.BT_D @ p - f) < 1e-10 * fn
+    assert np.linalg.norm(o.B_D @ u.ravel() - c) < 1e-10 * np.linalg.norm(u)
+    assert np.linalg.norm(R.T @ u.ravel()) < 1e-10 * np.linalg.norm(u) * np.linalg.norm(R)
+    # adding a rotation to u changes no equation (the null space)
+    assert np.linalg.norm(o.A_D @ R[:, 0]) < 1e-12 * np.linalg.norm(R[:, 0])
+    # the body force Ra T rhat(q_c) of the one-point rule is orthogonal to the rotations
+    from oracle.stokes import buoyancy_rhs
+    T = np.random.default_rng(15).uniform(0.0, 1.0, om.n_nodes)
+    fb = buoyancy_rhs(om, T, 1e5).ravel()
+    assert np.linalg.norm(R.T @ fb) < 1e-12 * np.linalg.norm(fb) * np.linalg.norm(R)

@@ -347,7 +347,8 @@ def bench_variants(tng, ctx):
     """Viscous-block variants in the solve (Sec. 4): the one-point operator, hourglass
     control (eq:hgstab, alpha 0.1) and the two-radial-point rule, each on every level
     of the multigrid.  Stand-alone V-cycle rates on (32,32) and (64,64), then Stokes
-    solves to 1e-8 on (64,64) and (128,128) (FGMRES iterations and wall time)."""
+    solves to 1e-8 on (64,64) and (128,128) (FGMRES iterations and wall time), also
+    with free slip on the outer sphere and on both spheres."""
     import torch
     variants = (("one-point", {}), ("hourglass 0.1", {"hg_alpha": 0.1}),
                 ("two-point", {"op_flags": tng.OP_TWOPOINT}))
@@ -365,6 +366,15 @@ def bench_variants(tng, ctx):
                                       "rates": vcycle_rates(tng, ctx, mesh, eta, **v)})
                 log(f"[variants] {out['vcycle'][-1]}")
         mesh.close()
+    # solves: the variants above, then free-slip spheres (the buoyancy's normal part removed
+    # there) and the one-point operator with a longer restart (FGMRES(23))
+    fs_o, fs_b = tng.OP_FREESLIP_OUTER, tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER
+    solves = [(name, v, 0) for name, v in variants] + [
+        ("restart 23", {"restart": 23}, 0),
+        ("free slip outer", {"op_flags": fs_o}, fs_o),
+        ("free slip outer, restart 23", {"op_flags": fs_o, "restart": 23}, fs_o),
+        ("free slip both", {"op_flags": fs_b}, fs_b),
+        ("free slip both, restart 23", {"op_flags": fs_b, "restart": 23}, fs_b)]
     for mt in (64, 128):
         mesh = tng.Mesh(ctx, mt, mt, levels=int(math.log2(mt)))
         T64 = shell_fields(tng, ctx, mesh, seed=1, lmax=8)
@@ -372,12 +382,12 @@ def bench_variants(tng, ctx):
             eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
             tng.eta_from_temperature(ctx, mesh, 0, T64, E, F, eta)
             f = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
-            tng.rhs_buoyancy(ctx, mesh, 0, T64, 1e5, f)
             u = torch.empty_like(f)
             p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
-            for name, v in variants:
+            for name, v, bits in solves:
+                tng.rhs_buoyancy(ctx, mesh, 0, T64, 1e5, f, bc_flags=bits)
                 for mixed in (0, 1):
-                    sv = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-8, max_iters=600, **v)
+                    sv = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-8, max_iters=1200, max_outer=40, **v)
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     info = sv.solve(f, None, u, p, eta=eta, raise_on_fail=False)

@@ -117,6 +117,48 @@ def test_coupled_step_energy_matches_oracle(tng, ctx):
     assert np.abs(ug).max() > 0
 
 
+def test_coupled_step_with_free_slip_spheres(tng, ctx):
+    """The coupled step with free slip on both spheres (the setup of the paper's
+    verification runs): the step's velocity is the oracle's gauged direct solve of
+    the free-slip system with eta(T) and the buoyancy whose normal part is removed on
+    the spheres (tangential to them, orthogonal to the rotations), and T^{n+1} the
+    oracle's energy solve with that velocity."""
+    import torch
+    from oracle.stokes import StokesOracle
+    mt = 8
+    mesh, om, lm = setup(tng, ctx, mt, levels=3)
+    T0 = synthetic.temperature(om.s, om.r, seed=4).ravel()
+    H = synthetic.heating(om.n_nodes, seed=5)
+    E, F, Ra = math.log(1e3), math.log(10.0), 1e5
+    fs = tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER
+    s = tng.StokesSolver(ctx, mesh, mixed=1, rtol=1e-11, op_flags=fs)
+    Tt = torch.tensor(lm.to_lib(T0), device="cuda")
+    Ht = torch.tensor(lm.to_lib(H), device="cuda")
+    u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+    p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+    info = s.energy_step(Tt, u, p, H=Ht, Ra=Ra, E=E, F=F, courant=1.0, energy_rtol=1e-11)
+    print("free-slip step", info)
+    assert info["stokes"]["rel_res"] <= 1e-11
+    ug = lm.from_lib(u.cpu().numpy(), check_dups=1e-12)
+    # Stokes part against the oracle
+    so = StokesOracle(mt, mt, eta_from_temperature(om, T0, E, F), hierarchy=om.h, bc=("freeslip", "freeslip"))
+    f = buoyancy_rhs(om, T0, Ra)
+    k = np.tile(np.arange(mt + 1), om.n_lat)
+    rhat = om.node_xyz() / np.linalg.norm(om.node_xyz(), axis=1)[:, None]
+    for sel in (k == 0, k == mt):
+        f[sel] -= np.sum(f[sel] * rhat[sel], 1)[:, None] * rhat[sel]
+    uo, po, c = so.solve_gauged(f)
+    eu = rel(ug, uo)
+    print(f"free-slip step: velocity vs oracle {eu:.2e}, rotation multipliers "
+          f"{np.abs(so.last_rotation_multipliers).max():.1e}")
+    assert eu < 1e-8
+    assert np.abs(np.sum(ug[(k == 0) | (k == mt)] * rhat[(k == 0) | (k == mt)], 1)).max() < 1e-10 * np.abs(ug).max()
+    # energy part with the GPU velocity
+    eo = EnergyOracle(om, ug, info["dt"])
+    got = lm.from_lib(Tt.cpu().numpy(), check_dups=1e-12)
+    assert rel(got, eo.step(T0, H)) < 1e-9
+
+
 # ---- modified method of characteristics (Sec. 6, eq:departure, eq:mmoc) ----------------
 
 def test_mmoc_advection_matches_oracle(tng, ctx):

@@ -68,11 +68,12 @@ struct tng_solver {
     tng::DevBuf<float> ones_p32;
     tng::DevBuf<const double*> onesp64; // [ones_p]
     tng::DevBuf<const float*> onesp32;  // [ones_p32]
-    // free slip on both spheres: the rigid rotations e_a x x (three velocity vectors),
-    // device pointers to them, and the inverse of their Gram matrix over unique DoFs
+    // free slip on both spheres: the rigid rotations e_a x x orthonormalised over unique
+    // DoFs (three velocity vectors, FP64 and FP32) and device pointers to them
     tng::DevBuf<double> rot64;
-    tng::DevBuf<const double*> rotptr;
-    double rot_ginv[9] = {};
+    tng::DevBuf<float> rot32;
+    tng::DevBuf<const double*> rotptr64;
+    tng::DevBuf<const float*> rotptr32;
     tng::DevBuf<double> xo, ro, bo;     // outer FP64 vectors (mixed precision)
     tng::DevBuf<float> r32, d32;
     tng::DevBuf<double> scal;           // device scalars
@@ -160,6 +161,25 @@ void project_mean(tng_solver* s, T* p) {
     vec_mdot<T>(s->ctx, *s->ds, P.node_slots(), P.n + 1, P.lat_slots(), P.owner.p, p, ones_ptr<T>(s), 1,
                 s->scal.p + 40, false);
     vec_shift<T>(s->ctx, P.node_slots(), s->scal.p + 40, p);
+}
+
+template <typename T>
+const T* const* rot_ptr(tng_solver* s);
+template <>
+const double* const* rot_ptr<double>(tng_solver* s) { return s->rotptr64.p; }
+template <>
+const float* const* rot_ptr<float>(tng_solver* s) { return s->rotptr32.p; }
+
+// free slip on both spheres: u <- u - Q Q^T u, Q the orthonormalised rigid rotations
+// (inner products over unique DoFs; the rotations are a null space of K, so this changes
+// no residual and fixes the solution up to them as the pressure is fixed up to its mean)
+template <typename T>
+void project_rotations(tng_solver* s, T* u) {
+    if (fs_bits(s) != 3) return;
+    const Level& L = L0(s);
+    const long long n3 = 3 * s->ns0;
+    vec_mdot<T>(s->ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, u, rot_ptr<T>(s), 3, s->scal.p + 56, false);
+    vec_maxpy<T>(s->ctx, n3, s->scal.p + 56, -1.0, rot_ptr<T>(s), 3, u);
 }
 
 // With free slip the velocity projection P = I - rhat rhat^T at the nodes does not
@@ -344,6 +364,10 @@ void precond(tng_solver* s, const T* v, T* z) {
     apply_BT<T>(s, z + 3 * ns, K.t.p);                           // t = B^T z_p
     vec_axpby<T>(s->ctx, 3 * ns, 1.0, v, -1.0, K.t.p);           // t = v_u - B^T z_p
     vcycle<T>(s, 0, K.t.p, z);                                   // z_u ~ A^{-1} t
+    // free slip on both spheres: keep the Krylov directions free of the rigid rotations
+    // (the null space of K), so that the iterate's rotation content cannot grow and
+    // swamp its other components in finite precision
+    project_rotations<T>(s, z);
 }
 
 template <typename T>
@@ -491,22 +515,7 @@ int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxi
     return std::isfinite(res) ? TNG_OK : TNG_E_NOTCONV;
 }
 
-// free slip on both spheres: u <- u - R (R^T R)^{-1} R^T u for the outer solution xo,
-// R the rigid rotations, inner products over unique DoFs (the solution is fixed up to
-// rotations as the pressure is up to its mean)
-void remove_rotations(tng_solver* s) {
-    if (fs_bits(s) != 3) return;
-    const Level& L = L0(s);
-    const long long n3 = 3 * s->ns0;
-    vec_mdot<double>(s->ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, s->xo.p, s->rotptr.p, 3,
-                     s->scal.p + 42, false);
-    readback(s, s->scal.p + 42, 3);
-    const double d[3] = {s->host[0], s->host[1], s->host[2]};
-    for (int a = 0; a < 3; ++a) {
-        const double c = s->rot_ginv[3 * a] * d[0] + s->rot_ginv[3 * a + 1] * d[1] + s->rot_ginv[3 * a + 2] * d[2];
-        vec_axpby<double>(s->ctx, n3, -c, s->rot64.p + a * n3, 1.0, s->xo.p);
-    }
-}
+void remove_rotations(tng_solver* s) { project_rotations<double>(s, s->xo.p); }
 
 // p <- p - mean(p) over unique pressure nodes of the outer solution xo
 void remove_pressure_mean(tng_solver* s) {
@@ -1378,32 +1387,44 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
         TNG_HIP(hipMemcpy(s->scal.p + 41, &cnt, sizeof(double), hipMemcpyHostToDevice));
     }
     if (tng::fs_bits(s.get()) == 3) {
-        // rigid rotations of the velocity level and the inverse of their Gram matrix
+        // rigid rotations of the velocity level, orthonormalised over unique DoFs by the
+        // Cholesky factor of their Gram matrix (Q = R L^{-T})
         const tng::Level& L = mesh->lv[0];
         const long long n3 = 3 * s->ns0;
         s->rot64.alloc(3 * n3);
+        double* r[3];
         const double* rp[3];
         for (int a = 0; a < 3; ++a) {
-            double* o[3] = {s->rot64.p + a * n3, s->rot64.p + a * n3 + s->ns0, s->rot64.p + a * n3 + 2 * s->ns0};
+            r[a] = s->rot64.p + a * n3;
+            rp[a] = r[a];
+            double* o[3] = {r[a], r[a] + s->ns0, r[a] + 2 * s->ns0};
             tng::vec_rotation<double>(ctx, L, a, o);
-            rp[a] = s->rot64.p + a * n3;
         }
-        s->rotptr.alloc(3);
-        TNG_HIP(hipMemcpy(s->rotptr.p, rp, sizeof(rp), hipMemcpyHostToDevice));
+        s->rotptr64.alloc(3);
+        TNG_HIP(hipMemcpy(s->rotptr64.p, rp, sizeof(rp), hipMemcpyHostToDevice));
         for (int a = 0; a < 3; ++a)
-            tng::vec_mdot<double>(ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, rp[a], s->rotptr.p, 3,
+            tng::vec_mdot<double>(ctx, *s->ds, n3, L.n + 1, L.lat_slots(), L.owner.p, rp[a], s->rotptr64.p, 3,
                                   s->scal.p + 48 + 3 * a, false);
         double G[9];
         TNG_HIP(hipMemcpyAsync(G, s->scal.p + 48, sizeof(G), hipMemcpyDeviceToHost, ctx->stream));
         TNG_HIP(hipStreamSynchronize(ctx->stream));
-        // inverse of the symmetric positive definite 3 x 3 Gram matrix (cofactors)
-        const double c00 = G[4] * G[8] - G[5] * G[7], c01 = G[5] * G[6] - G[3] * G[8], c02 = G[3] * G[7] - G[4] * G[6];
-        const double det = G[0] * c00 + G[1] * c01 + G[2] * c02;
-        TNG_REQUIRE(det > 0.0 && std::isfinite(det), "rigid rotations: singular Gram matrix");
-        const double inv[9] = {c00, G[2] * G[7] - G[1] * G[8], G[1] * G[5] - G[2] * G[4],
-                               c01, G[0] * G[8] - G[2] * G[6], G[2] * G[3] - G[0] * G[5],
-                               c02, G[1] * G[6] - G[0] * G[7], G[0] * G[4] - G[1] * G[3]};
-        for (int i = 0; i < 9; ++i) s->rot_ginv[i] = inv[i] / det;
+        const double l00 = std::sqrt(G[0]);
+        const double l10 = G[3] / l00, l20 = G[6] / l00;
+        const double l11 = std::sqrt(G[4] - l10 * l10);
+        const double l21 = (G[7] - l20 * l10) / l11;
+        const double l22 = std::sqrt(G[8] - l20 * l20 - l21 * l21);
+        TNG_REQUIRE(std::isfinite(l22) && l22 > 0.0, "rigid rotations: singular Gram matrix");
+        tng::vec_axpby<double>(ctx, n3, 0.0, r[0], 1.0 / l00, r[0]);                       // q0 = r0 / l00
+        tng::vec_axpby<double>(ctx, n3, -l10, r[0], 1.0, r[1]);                             // q1
+        tng::vec_axpby<double>(ctx, n3, 0.0, r[1], 1.0 / l11, r[1]);
+        tng::vec_axpby<double>(ctx, n3, -l20, r[0], 1.0, r[2]);                             // q2
+        tng::vec_axpby<double>(ctx, n3, -l21, r[1], 1.0, r[2]);
+        tng::vec_axpby<double>(ctx, n3, 0.0, r[2], 1.0 / l22, r[2]);
+        s->rot32.alloc(3 * n3);
+        tng::vec_cast<float, double>(ctx, 3 * n3, s->rot64.p, s->rot32.p);
+        const float* rp32[3] = {s->rot32.p, s->rot32.p + n3, s->rot32.p + 2 * n3};
+        s->rotptr32.alloc(3);
+        TNG_HIP(hipMemcpy(s->rotptr32.p, rp32, sizeof(rp32), hipMemcpyHostToDevice));
     }
     TNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->host), 256 * sizeof(double), hipHostMallocDefault));
     if (opts->graphs && !batch_slot) {

@@ -105,13 +105,16 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 template <typename T>
 void vec_fill(const tng_ctx* ctx, long long n, T v, T* a);
 template <typename T>
+// vs_aligned: every vector of vs_dev is 16-byte aligned (then, in FP32 with x aligned and
+// no slot batch, the kernel takes 16-byte accesses)
 void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
-               const T* const* vs_dev, int nq, double* out_dev, bool accumulate);
+               const T* const* vs_dev, int nq, double* out_dev, bool accumulate, bool vs_aligned = false);
 // y <- y + sign * sum_q coef[q] v_q over a Stokes vector, then out = the owner-masked
 // dots of the new y with v_0..v_{nq-1} (norm false) or its squared norm (norm true)
 template <typename T>
 void vec_maxpy_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const double* coef_dev,
-                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm);
+                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm,
+                     bool vs_aligned = false);
 template <typename T>
 void vec_rand(const tng_ctx* ctx, long long n, unsigned long long seed, T* a);
 template <typename T>

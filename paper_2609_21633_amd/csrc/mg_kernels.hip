@@ -1099,6 +1099,144 @@ __global__ void __launch_bounds__(DOT_BS) maxpy_dot_kernel(unsigned ns, MagicDiv
     block_partials<NA>(acc, NORM ? 1 : nq, part);
 }
 
+// 16 bytes of T values as a native vector (it loads out of the global address space
+// as one 16-byte access)
+template <typename T>
+struct Pack16 {
+    typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+template <typename T>
+__device__ __forceinline__ bool stokes_owned(unsigned t, unsigned nu, MagicDiv dn1u, unsigned nlat_u,
+                                             const uint8_t* __restrict__ ou, MagicDiv dn1p,
+                                             const uint8_t* __restrict__ op) {
+    if (t < nu) {
+        unsigned lat = mdiv(t, dn1u);
+        lat = lat >= nlat_u ? lat - nlat_u : lat;
+        lat = lat >= nlat_u ? lat - nlat_u : lat;
+        return ou[lat] != 0;
+    }
+    return op[mdiv(t - nu, dn1p)] != 0;
+}
+
+// smdot_partial_kernel and maxpy_dot_kernel with 16-byte accesses, for one problem (no
+// slot batch) whose vectors are all 16-byte aligned (the Krylov basis): a thread takes
+// L = 16 / sizeof(T) consecutive values of every vector per load, block 0 also the n % L
+// tail.  Same arithmetic per value (FP64 products and sums); the owner mask of every value.
+template <typename T, int NQ>
+__global__ void __launch_bounds__(DOT_BS) smdot_vec_kernel(unsigned ns, MagicDiv dn1u, unsigned nlat_u,
+                                                           const uint8_t* __restrict__ ou, unsigned np,
+                                                           MagicDiv dn1p, const uint8_t* __restrict__ op,
+                                                           const T* __restrict__ x,
+                                                           const T* const* __restrict__ vs, int nq,
+                                                           double* __restrict__ part) {
+    using V = typename Pack16<T>::type;
+    constexpr int L = 16 / sizeof(T);
+    using gvptr = const __attribute__((address_space(1))) V*;
+    gvptr vp[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) vp[q] = (gvptr)vs[q < nq ? q : 0];
+    const gvptr xp = (gvptr)x;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    const unsigned nu = 3u * ns, n = nu + np, nv = n / L;
+    const unsigned stride = gridDim.x * DOT_BS;
+    for (unsigned c = blockIdx.x * DOT_BS + threadIdx.x; c < nv; c += stride) {
+        const V xv = xp[c];
+        V v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = vp[q < nq ? q : 0][c];
+        const V px = xv;
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            if (!stokes_owned<T>(c * L + e, nu, dn1u, nlat_u, ou, dn1p, op)) continue;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)px[e] * (double)v[q][e];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * L) {
+        const unsigned t = nv * L + threadIdx.x;
+        if (stokes_owned<T>(t, nu, dn1u, nlat_u, ou, dn1p, op)) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) acc[q] += (double)x[t] * (double)vs[q][t];
+        }
+    }
+    block_partials<NQ>(acc, nq, part);
+}
+
+template <typename T, int NQ, bool NORM>
+__global__ void __launch_bounds__(DOT_BS) maxpy_dot_vec_kernel(unsigned ns, MagicDiv dn1u, unsigned nlat_u,
+                                                               const uint8_t* __restrict__ ou, unsigned np,
+                                                               MagicDiv dn1p, const uint8_t* __restrict__ op,
+                                                               const double* __restrict__ coef, double sign,
+                                                               const T* const* __restrict__ vs, int nq, T* y,
+                                                               double* __restrict__ part) {
+    using V = typename Pack16<T>::type;
+    constexpr int L = 16 / sizeof(T);
+    using gvptr = const __attribute__((address_space(1))) V*;
+    gvptr vp[NQ];
+    double cf[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        vp[q] = (gvptr)vs[q < nq ? q : 0];
+        cf[q] = q < nq ? sign * coef[q] : 0.0;
+    }
+    constexpr int NA = NORM ? 1 : NQ;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    const unsigned nu = 3u * ns, n = nu + np, nv = n / L;
+    const unsigned stride = gridDim.x * DOT_BS;
+    V* yv = reinterpret_cast<V*>(y);
+    for (unsigned c = blockIdx.x * DOT_BS + threadIdx.x; c < nv; c += stride) {
+        V w = yv[c];
+        V v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = vp[q < nq ? q : 0][c];
+        #pragma unroll
+        for (int e = 0; e < L; ++e) {
+            double a2 = (double)w[e];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) a2 += cf[q] * (double)v[q][e];
+            w[e] = T(a2);
+        }
+        yv[c] = w;
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            if (!stokes_owned<T>(c * L + e, nu, dn1u, nlat_u, ou, dn1p, op)) continue;
+            const double yn = (double)w[e];
+            if (NORM) {
+                acc[0] += yn * yn;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NA; ++q) acc[q] += (double)v[q][e] * yn;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * L) {
+        const unsigned t = nv * L + threadIdx.x;
+        double a2 = (double)y[t];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nq) a2 += cf[q] * (double)vs[q][t];
+        const T yn = T(a2);
+        y[t] = yn;
+        if (stokes_owned<T>(t, nu, dn1u, nlat_u, ou, dn1p, op)) {
+            if (NORM) {
+                acc[0] += (double)yn * (double)yn;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NA; ++q)
+                    if (q < nq) acc[q] += (double)vs[q][t] * (double)yn;
+            }
+        }
+    }
+    block_partials<NA>(acc, NORM ? 1 : nq, part);
+}
+
 // Counter-based uniform numbers in [-1, 1) (splitmix64 of seed and index).
 template <typename T>
 __global__ void rand_kernel(unsigned n, unsigned long long seed, T* a) {
@@ -1462,14 +1600,27 @@ void vec_maxpy(const tng_ctx* ctx, long long n, const double* coef_dev, double s
 
 template <typename T>
 void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
-               const T* const* vs_dev, int nq, double* out_dev, bool accumulate) {
+               const T* const* vs_dev, int nq, double* out_dev, bool accumulate, bool vs_aligned) {
     TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-dot");
     const long long n = 3 * Lu.node_slots() + Lp.node_slots();
     TNG_REQUIRE(n < (1LL << 32), "multi-dot length out of range");
-    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
     const SlotBatch sb = launch_batch();
     check_counts(sb);
     const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
+    // 16-byte accesses pay in FP32 (four values per load); the FP64 kernel already streams at
+    // about 5.6 TB/s with its two 8-byte loads per vector and step
+    if (sizeof(T) == 4 && vs_aligned && sb.nb == 1 && !sb.has_cnt && aligned16(x)) {
+        const long long nv = n / (16 / (long long)sizeof(T));
+        const int nb = (int)std::max<long long>(1, std::min<long long>(DOT_BLOCKS, (nv + DOT_BS - 1) / DOT_BS));
+        TNG_NQ_DISPATCH(count_class(sb, nq), (smdot_vec_kernel<T, NQ><<<nb, DOT_BS, 0, ctx->stream>>>(
+                                (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                                (unsigned)Lp.node_slots(), dp, Lp.owner.p, x, vs_dev, nq, ds.part.p)));
+        TNG_HIP(hipGetLastError());
+        mdot_final_kernel<<<1, 256, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0, sb);
+        TNG_HIP(hipGetLastError());
+        return;
+    }
+    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
     TNG_NQ_DISPATCH(count_class(sb, nq),
                     (smdot_partial_kernel<T, NQ><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
                         (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
@@ -1481,14 +1632,33 @@ void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level&
 
 template <typename T>
 void vec_maxpy_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const double* coef_dev,
-                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm) {
+                     double sign, const T* const* vs_dev, int nq, T* y, double* out_dev, bool norm, bool vs_aligned) {
     TNG_REQUIRE(nq >= 1 && nq <= MAX_MDOT, "too many vectors in a multi-axpy");
     const long long n = 3 * Lu.node_slots() + Lp.node_slots();
     TNG_REQUIRE(n < (1LL << 32), "vector length out of range");
-    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
     const SlotBatch sb = launch_batch();
     check_counts(sb);
     const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
+    if (sizeof(T) == 4 && vs_aligned && sb.nb == 1 && !sb.has_cnt && aligned16(y)) {
+        const long long nv = n / (16 / (long long)sizeof(T));
+        const int nb = (int)std::max<long long>(1, std::min<long long>(DOT_BLOCKS, (nv + DOT_BS - 1) / DOT_BS));
+        if (norm) {
+            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, true><<<nb, DOT_BS, 0, ctx->stream>>>(
+                                    (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                                    (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y,
+                                    ds.part.p)));
+        } else {
+            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, false><<<nb, DOT_BS, 0, ctx->stream>>>(
+                                    (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
+                                    (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y,
+                                    ds.part.p)));
+        }
+        TNG_HIP(hipGetLastError());
+        mdot_final_kernel<<<1, 256, 0, ctx->stream>>>(nb, norm ? 1 : nq, ds.part.p, out_dev, 0, sb);
+        TNG_HIP(hipGetLastError());
+        return;
+    }
+    const int nb = (int)std::min<long long>(DOT_BLOCKS, (n + DOT_BS - 1) / DOT_BS);
     if (norm) {
         TNG_NQ_DISPATCH(count_class(sb, nq),
                         (maxpy_dot_kernel<T, NQ, true><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
@@ -1662,9 +1832,9 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
     template void vec_fill<T>(const tng_ctx*, long long, T, T*);                                          \
     template void vec_mul<T>(const tng_ctx*, long long, const T*, const T*, T*);                          \
     template void vec_smdot<T>(const tng_ctx*, DotScratch&, const Level&, const Level&, const T*,         \
-                               const T* const*, int, double*, bool);                                       \
+                               const T* const*, int, double*, bool, bool);                                 \
     template void vec_maxpy_smdot<T>(const tng_ctx*, DotScratch&, const Level&, const Level&, const double*,  \
-                                     double, const T* const*, int, T*, double*, bool);                       \
+                                     double, const T* const*, int, T*, double*, bool, bool);                 \
     template void vec_rand<T>(const tng_ctx*, long long, unsigned long long, T*);                         \
     template void vec_scale_rsqrt<T>(const tng_ctx*, long long, const double*, const T*, T*);             \
     template void vec_tab_copy<T>(const tng_ctx*, long long, const T*, const T* const*, T*, T* const*, int, \

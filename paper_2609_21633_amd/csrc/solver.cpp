@@ -458,10 +458,12 @@ int fgmres(tng_solver* s, const T* eta0, const T* b, T* x, double rtol, int maxi
             apply_K<T>(s, eta0, K.Zi(j), K.w.p);
             // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 with h2 = V^T w in the
             // same pass; w -= V h2 with |w|^2 in the same pass
-            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc, false);
-            vec_maxpy_smdot<T>(s->ctx, *s->ds, Lu, Lp, dsc, -1.0, K.vptr.p, j + 1, K.w.p, dsc + MAX_MDOT, false);
+            // (the basis vectors sit at 256-byte strides: 16-byte accesses)
+            vec_smdot<T>(s->ctx, *s->ds, Lu, Lp, K.w.p, K.vptr.p, j + 1, dsc, false, true);
+            vec_maxpy_smdot<T>(s->ctx, *s->ds, Lu, Lp, dsc, -1.0, K.vptr.p, j + 1, K.w.p, dsc + MAX_MDOT, false,
+                               true);
             vec_maxpy_smdot<T>(s->ctx, *s->ds, Lu, Lp, dsc + MAX_MDOT, -1.0, K.vptr.p, j + 1, K.w.p,
-                               dsc + 2 * MAX_MDOT, true);
+                               dsc + 2 * MAX_MDOT, true, true);
             vec_scale_rsqrt<T>(s->ctx, N, dsc + 2 * MAX_MDOT, K.w.p, K.Vi(j + 1));
             readback(s, dsc, 2 * MAX_MDOT + 1);
             double* h = &H[(size_t)j * (m + 1)];

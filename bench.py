@@ -468,7 +468,7 @@ def bench_serving(tng, ctx, nreq, rate_factor, budget):
             "levels": levels}
 
 
-def bench_serving_sweep(tng, ctx, nreq=256, factors=(0.25, 0.5, 0.75, 0.95), budget=200 << 30,
+def bench_serving_sweep(tng, ctx, nreq=256, factors=(0.25, 0.5, 0.75, 0.95), budget=200 * 10**9,
                         tight_budget=2 << 30):
     """The serving stream at its saturated rate mu and at Poisson arrival rates
     lambda = f mu, each with p50/p99 latency and throughput, then the saturated

@@ -105,8 +105,8 @@ void vec_schur(const tng_ctx* ctx, long long n, const T* r, const T* mdiag, T* z
 template <typename T>
 void vec_fill(const tng_ctx* ctx, long long n, T v, T* a);
 template <typename T>
-// vs_aligned: every vector of vs_dev is 16-byte aligned (then, in FP32 with x aligned and
-// no slot batch, the kernel takes 16-byte accesses)
+// vs_aligned: every vector of vs_dev (of every slot of a batch) is 16-byte aligned (then, in
+// FP32 with x aligned, the kernel takes 16-byte accesses)
 void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level& Lp, const T* x,
                const T* const* vs_dev, int nq, double* out_dev, bool accumulate, bool vs_aligned = false);
 // y <- y + sign * sum_q coef[q] v_q over a Stokes vector, then out = the owner-masked

@@ -1119,8 +1119,8 @@ __device__ __forceinline__ bool stokes_owned(unsigned t, unsigned nu, MagicDiv d
     return op[mdiv(t - nu, dn1p)] != 0;
 }
 
-// smdot_partial_kernel and maxpy_dot_kernel with 16-byte accesses, for one problem (no
-// slot batch) whose vectors are all 16-byte aligned (the Krylov basis): a thread takes
+// smdot_partial_kernel and maxpy_dot_kernel with 16-byte accesses, for vectors that are all
+// 16-byte aligned (the Krylov basis, also in the slots of a batch): a thread takes
 // L = 16 / sizeof(T) consecutive values of every vector per load, block 0 also the n % L
 // tail.  Same arithmetic per value (FP64 products and sums); the owner mask of every value.
 template <typename T, int NQ>
@@ -1129,10 +1129,15 @@ __global__ void __launch_bounds__(DOT_BS) smdot_vec_kernel(unsigned ns, MagicDiv
                                                            MagicDiv dn1p, const uint8_t* __restrict__ op,
                                                            const T* __restrict__ x,
                                                            const T* const* __restrict__ vs, int nq,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part, SlotBatch sb) {
     using V = typename Pack16<T>::type;
     constexpr int L = 16 / sizeof(T);
     using gvptr = const __attribute__((address_space(1))) V*;
+    const long long so = slot_off(sb);
+    x = at_slot(x, so);
+    vs = at_slot(vs, so);
+    part = at_slot(part, so);
+    nq = slot_count(sb, nq);
     gvptr vp[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) vp[q] = (gvptr)vs[q < nq ? q : 0];
@@ -1172,10 +1177,16 @@ __global__ void __launch_bounds__(DOT_BS) maxpy_dot_vec_kernel(unsigned ns, Magi
                                                                MagicDiv dn1p, const uint8_t* __restrict__ op,
                                                                const double* __restrict__ coef, double sign,
                                                                const T* const* __restrict__ vs, int nq, T* y,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part, SlotBatch sb) {
     using V = typename Pack16<T>::type;
     constexpr int L = 16 / sizeof(T);
     using gvptr = const __attribute__((address_space(1))) V*;
+    const long long so = slot_off(sb);
+    coef = at_slot(coef, so);
+    vs = at_slot(vs, so);
+    y = at_slot(y, so);
+    part = at_slot(part, so);
+    nq = slot_count(sb, nq);
     gvptr vp[NQ];
     double cf[NQ];
 #pragma unroll
@@ -1609,14 +1620,15 @@ void vec_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const Level&
     const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
     // 16-byte accesses pay in FP32 (four values per load); the FP64 kernel already streams at
     // about 5.6 TB/s with its two 8-byte loads per vector and step
-    if (sizeof(T) == 4 && vs_aligned && sb.nb == 1 && !sb.has_cnt && aligned16(x)) {
+    if (sizeof(T) == 4 && vs_aligned && aligned16(x)) {
         const long long nv = n / (16 / (long long)sizeof(T));
         const int nb = (int)std::max<long long>(1, std::min<long long>(DOT_BLOCKS, (nv + DOT_BS - 1) / DOT_BS));
-        TNG_NQ_DISPATCH(count_class(sb, nq), (smdot_vec_kernel<T, NQ><<<nb, DOT_BS, 0, ctx->stream>>>(
+        TNG_NQ_DISPATCH(count_class(sb, nq), (smdot_vec_kernel<T, NQ><<<dim3(nb, 1, sb.nb), DOT_BS, 0, ctx->stream>>>(
                                 (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
-                                (unsigned)Lp.node_slots(), dp, Lp.owner.p, x, vs_dev, nq, ds.part.p)));
+                                (unsigned)Lp.node_slots(), dp, Lp.owner.p, x, vs_dev, nq, ds.part.p, sb)));
         TNG_HIP(hipGetLastError());
-        mdot_final_kernel<<<1, 256, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev, accumulate ? 1 : 0, sb);
+        mdot_final_kernel<<<dim3(1, 1, sb.nb), 256, 0, ctx->stream>>>(nb, nq, ds.part.p, out_dev,
+                                                                      accumulate ? 1 : 0, sb);
         TNG_HIP(hipGetLastError());
         return;
     }
@@ -1639,22 +1651,26 @@ void vec_maxpy_smdot(const tng_ctx* ctx, DotScratch& ds, const Level& Lu, const 
     const SlotBatch sb = launch_batch();
     check_counts(sb);
     const MagicDiv du = magic_div((unsigned)(Lu.n + 1)), dp = magic_div((unsigned)(Lp.n + 1));
-    if (sizeof(T) == 4 && vs_aligned && sb.nb == 1 && !sb.has_cnt && aligned16(y)) {
+    if (sizeof(T) == 4 && vs_aligned && aligned16(y)) {
         const long long nv = n / (16 / (long long)sizeof(T));
         const int nb = (int)std::max<long long>(1, std::min<long long>(DOT_BLOCKS, (nv + DOT_BS - 1) / DOT_BS));
+        const dim3 grid(nb, 1, sb.nb);
         if (norm) {
-            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, true><<<nb, DOT_BS, 0, ctx->stream>>>(
+            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, true><<<grid, DOT_BS, 0, ctx->stream>>>(
                                     (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
                                     (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y,
-                                    ds.part.p)));
+                                    ds.part.p, sb)));
         } else {
-            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, false><<<nb, DOT_BS, 0, ctx->stream>>>(
+            TNG_NQ_DISPATCH(count_class(sb, nq), (maxpy_dot_vec_kernel<T, NQ, false><<<grid, DOT_BS, 0, ctx->stream>>>(
                                     (unsigned)Lu.node_slots(), du, (unsigned)Lu.lat_slots(), Lu.owner.p,
                                     (unsigned)Lp.node_slots(), dp, Lp.owner.p, coef_dev, sign, vs_dev, nq, y,
-                                    ds.part.p)));
+                                    ds.part.p, sb)));
         }
         TNG_HIP(hipGetLastError());
-        mdot_final_kernel<<<1, 256, 0, ctx->stream>>>(nb, norm ? 1 : nq, ds.part.p, out_dev, 0, sb);
+        // the norm has one value for every slot: the per-slot counts do not apply to it
+        SlotBatch sf = sb;
+        if (norm) sf.has_cnt = 0;
+        mdot_final_kernel<<<dim3(1, 1, sf.nb), 256, 0, ctx->stream>>>(nb, norm ? 1 : nq, ds.part.p, out_dev, 0, sf);
         TNG_HIP(hipGetLastError());
         return;
     }

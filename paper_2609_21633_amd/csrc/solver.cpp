@@ -1053,10 +1053,11 @@ void step_group(tng_ctx* ctx, SolverBatch::Staging& st, const tng_solver_opts& o
     }
     {
         BatchScope bs(&bj1);                                                         // CGS2 against V_0..V_j
-        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc, false);
-        vec_maxpy_smdot<T>(ctx, *r->ds, L0(r), L1(r), dsc, -1.0, K.vptr.p, 1, K.w.p, dsc + MAX_MDOT, false);
+        // (every slot's basis sits in its arena at 256-byte strides: 16-byte accesses)
+        vec_smdot<T>(ctx, *r->ds, L0(r), L1(r), K.w.p, K.vptr.p, 1, dsc, false, true);
+        vec_maxpy_smdot<T>(ctx, *r->ds, L0(r), L1(r), dsc, -1.0, K.vptr.p, 1, K.w.p, dsc + MAX_MDOT, false, true);
         vec_maxpy_smdot<T>(ctx, *r->ds, L0(r), L1(r), dsc + MAX_MDOT, -1.0, K.vptr.p, 1, K.w.p,
-                           dsc + 2 * MAX_MDOT, true);
+                           dsc + 2 * MAX_MDOT, true, true);
     }
     {
         BatchScope bs(&bj1);

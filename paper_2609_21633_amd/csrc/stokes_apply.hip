@@ -1062,13 +1062,14 @@ inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / 
 // capacity (slots), all bands of a round about equally long, so a launch takes
 // about rounds x (band rows + halo row + start-up) row steps, the last round set
 // by the longest band; the start-up (ring fill, first loads) is about START_ROWS
-// row steps.  Bands have at least four rows.
+// row steps.  Bands have at least four rows, two on the small levels (m <= 16), whose
+// launches are latency-bound and fill a fraction of the chip.
 constexpr double START_ROWS = 2.0;
 inline int choose_bands(int m, long long cols, long long slots) {
-    if (m < 8) return 1;
+    if (m < 4) return 1;
     int best = 1;
     double best_cost = 1e300;
-    for (int nb = 1; nb <= m / 4; ++nb) {
+    for (int nb = 1; nb <= (m <= 16 ? m / 2 : m / 4); ++nb) {
         const long long rounds = (cols * nb + slots - 1) / slots;
         const double mean = (double)m / nb, longest = 2.0 * ((m / 2 + nb - 1) / nb);
         const double cost = (rounds - 1) * (mean + 1 + START_ROWS) + (longest + 1 + START_ROWS);

@@ -105,7 +105,7 @@ enum {
      * rhobar u interpolated nodally (rhobar(r_j) u_j, rhobar from
      * tng_mesh_set_density), i.e. y_p = B R u with R = diag(rhobar(r_j)); the
      * momentum rows keep B^T (eq:stokes).  With TNG_OP_B, alone or in the full
-     * operator; not with free slip or hourglass control. */
+     * operator, also with free slip (y_p = B R P u); not with hourglass control. */
     TNG_OP_TALA = 64,
     /* The viscous block with the two-radial-point rule (Sec. 4, the remedy
      * beside eq:hgstab): the lateral centroid times the two-point Gauss rule
@@ -312,10 +312,12 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  *     level (outer operator, smoother and residual applies, diag(A) and the
  *     coarsest matrix), so that the multigrid works on the operator without
  *     one-point hourglass modes; hg_alpha must be 0;
- *   TNG_OP_TALA: the outer operator's mass rows -(psi, div(rhobar u)) with the
- *     mesh's reference density (tng_mesh_set_density before the solver is
- *     created); the preconditioner keeps A, B^T and M_{1/eta}.  The right-hand
- *     side g must sum to zero over unique pressure nodes (1^T B_rho = 0).
+ *   TNG_OP_TALA (alone or with the free-slip bits): the outer operator's mass
+ *     rows -(psi, div(rhobar u)) with the mesh's reference density
+ *     (tng_mesh_set_density before the solver is created); the preconditioner
+ *     keeps A, B^T and M_{1/eta}.  The right-hand side g must sum to zero over
+ *     unique pressure nodes (with no slip 1^T B_rho = 0; with free slip the
+ *     mass rows are taken modulo constants, below).
  *   TNG_OP_FREESLIP_INNER and/or TNG_OP_FREESLIP_OUTER: free slip on that sphere
  *     (rows P A P + N, P = I - rhat rhat^T at its nodes, as in tng_stokes_apply),
  *     no slip on a sphere without the bit, on every level: the smoother keeps the iterate

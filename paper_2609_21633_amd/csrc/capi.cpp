@@ -377,8 +377,6 @@ int tng_stokes_apply(tng_ctx* ctx, const tng_mesh* mesh, int level, tng_prec pre
         TNG_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u is NULL");
     if (op_flags & TNG_OP_TALA) {
         TNG_REQUIRE(doB, "TNG_OP_TALA changes the divergence block: it needs TNG_OP_B");
-        TNG_REQUIRE(!(op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)),
-                    "TNG_OP_TALA is not available with free slip");
         TNG_REQUIRE(!(doA && hg_alpha != 0.0), "TNG_OP_TALA is not available with hourglass control");
         TNG_REQUIRE(L.rho64.p != nullptr, "TNG_OP_TALA needs the mesh's reference density (tng_mesh_set_density)");
     }

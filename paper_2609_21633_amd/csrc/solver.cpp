@@ -1322,9 +1322,9 @@ tng_solver* create_solver(tng_ctx* ctx, tng_mesh* mesh, const tng_solver_opts* o
     TNG_REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "bad Chebyshev interval");
     TNG_REQUIRE(opts->power_its >= 1, "power_its must be >= 1");
     TNG_REQUIRE(opts->hg_alpha >= 0.0 && std::isfinite(opts->hg_alpha), "hg_alpha must be finite and >= 0");
-    TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT || opts->op_flags == TNG_OP_TALA ||
-                    (opts->op_flags & ~(unsigned)(TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) == 0,
-                "op_flags must be 0, TNG_OP_TWOPOINT, TNG_OP_TALA or free-slip bits (TNG_OP_FREESLIP_INNER, "
+    TNG_REQUIRE(opts->op_flags == 0 || opts->op_flags == TNG_OP_TWOPOINT ||
+                    (opts->op_flags & ~(unsigned)(TNG_OP_TALA | TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) == 0,
+                "op_flags must be 0, TNG_OP_TWOPOINT, or TNG_OP_TALA and/or free-slip bits (TNG_OP_FREESLIP_INNER, "
                 "TNG_OP_FREESLIP_OUTER or both)");
     TNG_REQUIRE(!(opts->op_flags & (TNG_OP_FREESLIP_INNER | TNG_OP_FREESLIP_OUTER)) || opts->hg_alpha == 0.0,
                 "free slip has no hourglass-controlled form (hg_alpha must be 0)");

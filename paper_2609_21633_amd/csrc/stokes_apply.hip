@@ -1156,14 +1156,16 @@ void launch_band_ops(const tng_ctx* ctx, const BandArgs<T>& args, const SlotBatc
         case 128 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false, false, true>(ctx, args, sb, bands_out); break;
         case 64 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, false, true>(ctx, args, sb, bands_out); break;
         case 64 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, false, true>(ctx, args, sb, bands_out); break;
+        case 16 | 64 | 4: launch_band_t<T, RS, CPL, WG, false, false, true, false, true, true>(ctx, args, sb, bands_out); break;
+        case 16 | 64 | 7: launch_band_t<T, RS, CPL, WG, true, true, true, false, true, true>(ctx, args, sb, bands_out); break;
         case 16 | 2:   // B^T reads no velocity: its free-slip rows are the post pass's projection
             launch_band_t<T, RS, CPL, WG, false, true, false, false, false>(ctx, args, sb, bands_out);
             break;
         default:
             throw Error(TNG_E_INVAL, "this operator combination has no free-slip, compressible or two-point form "
-                                     "(free slip: A, B^T, B or the full operator; TALA: B or the full operator; "
-                                     "two-point rule: A, A+B^T or the full operator; none with hourglass control, "
-                                     "at most one of them)");
+                                     "(free slip: A, B^T, B or the full operator; TALA: B or the full operator, also "
+                                     "with free slip; two-point rule: A, A+B^T or the full operator; none with "
+                                     "hourglass control)");
     }
 }
 

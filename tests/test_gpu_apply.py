@@ -450,3 +450,34 @@ def test_two_point_operator(tng, ctx, mt, nr, prec):
     tng.stokes_apply(ctx, mesh, 0, 1 | TWOPT, e, ut, None, yu, None)
     got = lm.from_lib(yu.double().cpu().numpy()).ravel()
     check_rows(got, or2.A @ uf.ravel(), or2.A, uf, tol, f"two-point A {prec} ({mt},{nr})")
+
+
+@pytest.mark.parametrize("mt,nr,prec,bc", [(8, 8, "f64", ("noslip", "freeslip")), (16, 10, "f64", ("freeslip", "freeslip")),
+                                            (16, 16, "f32", ("freeslip", "noslip")), (4, 160, "f64", ("noslip", "freeslip"))])
+def test_tala_with_free_slip(tng, ctx, mt, nr, prec, bc):
+    """The compressible mass rows with free-slip spheres: y_p = B R P u and the full
+    operator against the oracle with both (B_mass = B R P), element-wise."""
+    import torch
+    mesh, om, lm, lmp, eta, u, p, orc, t = setup_case(tng, ctx, mt, nr)
+    rho = _rho(om.r)
+    mesh.set_density(rho)
+    ort = StokesOracle(mt, nr, eta, hierarchy=om.h, rho_nodes=rho, bc=bc)
+    fsb = (FS_IN if bc[0] == "freeslip" else 0) | (FS_OUT if bc[1] == "freeslip" else 0)
+    dt, tol = (torch.float64, 1e-12) if prec == "f64" else (torch.float32, 1e-5)
+    # nonzero on both spheres: a zero sphere velocity leaves the rows of the nodes whose
+    # rhat lies on a coordinate axis (a zero row of P, N u = 0) with only rounding residue
+    uf = np.random.default_rng(11).uniform(-1, 1, u.shape)
+    e, pp = (t[k].to(dt) for k in ("eta", "p"))
+    uu = torch.tensor(lm.to_lib(uf), device="cuda").to(dt).contiguous()
+    yu, yp = torch.full_like(uu, float("nan")), torch.full_like(pp, float("nan"))
+    tng.stokes_apply(ctx, mesh, 0, OPS_ALL | TALA | fsb, e, uu, pp, yu, yp)
+    yb = torch.full_like(pp, float("nan"))
+    tng.stokes_apply(ctx, mesh, 0, 4 | 8 | TALA | fsb, None, uu, None, None, yb)
+    gu, gp = lm.from_lib(yu.double().cpu().numpy(), check_dups=1e-6), lmp.from_lib(yp.double().cpu().numpy())
+    check_K(ort, gu, gp, uf, p, tol, f"tala+fs {prec} ({mt},{nr}) {bc}")
+    gb = lmp.from_lib(yb.double().cpu().numpy(), check_dups=1e-6)
+    check_rows(gb, ort.B_mass @ uf.ravel(), ort.B_mass, uf, tol, "B_rho P")
+    # both options matter: not the free-slip operator without density, nor TALA with no slip
+    orf = StokesOracle(mt, nr, eta, hierarchy=om.h, bc=bc)
+    assert rel(gp, orf.apply(uf, p)[1]) > 1e-3
+    assert rel(gp, StokesOracle(mt, nr, eta, hierarchy=om.h, rho_nodes=rho).apply(uf, p)[1]) > 1e-6

@@ -427,3 +427,26 @@ def test_buoyancy_with_freeslip_rows(tng, ctx, flags):
     got = lm.from_lib(f.cpu().numpy(), check_dups=1e-12)
     scale = np.abs(ref).max()
     assert np.max(np.abs(got - ref)) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_tala_freeslip_solve_matches_direct_solve(tng, ctx, mixed):
+    """The compressible mass rows with a free-slip outer sphere (no slip inside), the
+    setup of the paper's production runs in its compressible form: against the
+    oracle's gauged direct solve with both."""
+    mesh, om, omp, lm, lmp, eta, orc, eta_t = case(tng, ctx, 8)
+    rho = _rho(om.r)
+    mesh.set_density(rho)
+    bc = ("noslip", "freeslip")
+    ofs = StokesOracle(8, 8, eta, hierarchy=om.h, bc=bc, rho_nodes=rho)
+    rng = np.random.default_rng(18)
+    f = rng.standard_normal((om.n_nodes, 3))
+    k = np.tile(np.arange(9), om.n_lat)
+    f[k == 0] = 0.0
+    gu, gp, info = _variant_solve(tng, ctx, mesh, lm, lmp, f, eta_t, mixed, tng.OP_TALA | tng.OP_FREESLIP_OUTER)
+    uo, po, c = ofs.solve_gauged(f)
+    eu, ep = rel(gu, uo), rel(gp, po)
+    print(f"TALA + free-slip solve (8,8) mixed={mixed}: its {info['inner_its']} res {info['rel_res']:.2e} "
+          f"err u {eu:.2e} p {ep:.2e}")
+    assert info["rel_res"] <= 1e-10
+    assert eu < 1e-7 and ep < 1e-7

@@ -291,12 +291,14 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  *   correction, pressure-mean projection, coarsest solve in FP64) around an
  *   FP32 inner FGMRES (FP32 applies, smoothers and Krylov basis).
  * restart: FGMRES restart length (paper: 10; 1..23).
- * max_iters: FGMRES iteration limit (FP64 mode).  rtol: target of
+ * max_iters: FGMRES iteration limit (FP64 mode, and of the FP64 inner solves
+ *   of a mixed solve whose refinement stalled).  rtol: target of
  *   ||b - K x||_2 / ||b||_2 over unique DoFs, both blocks, x0 = 0.
  * cheb_degree, pre, post: Chebyshev smoother of degree cheb_degree on
  *   D^{-1} A, pre/post steps per level (paper: 2, 2, 2), on the interval
  *   [cheb_lo, cheb_hi] * lambda_max(D^{-1} A), lambda_max from power_its
- *   seeded power iterations.
+ *   seeded power iterations (at least 100 with a free-slip sphere, whose
+ *   weak-viscosity nodes can hold the largest eigenvalue).
  * levels: multigrid levels used (0 = all levels of the mesh); the coarsest
  *   one is solved exactly and must have at most 1024 interior DoFs.
  * inner_rtol, inner_max_iters, max_outer: mixed-precision inner tolerance and
@@ -355,12 +357,19 @@ typedef struct {
 
 /* outer_its: refinement steps (1 in FP64 mode); inner_its: FGMRES iterations
  * in total; rel_res: final true FP64 relative residual; seconds: wall time
- * of the call; status: TNG_OK or TNG_E_NOTCONV. */
+ * of the call; status: TNG_OK or TNG_E_NOTCONV; fp64_its: the FGMRES
+ * iterations made in FP64 (all of them in FP64 mode).  A mixed-precision
+ * solve whose refinement stalls (two steps in a row each leaving the residual
+ * above 0.9 of the best so far: FP32 cannot resolve modes of K whose relative
+ * eigenvalue is near its roundoff, as with free slip over a much weaker core)
+ * finishes with FP64 inner FGMRES (at most max_iters iterations), allocating
+ * the FP64 multigrid scratch and Krylov basis on first use. */
 typedef struct {
     int outer_its, inner_its;
     double rel_res;
     double seconds;
     int status;
+    int fp64_its;
 } tng_solve_info;
 
 /* Fills the defaults listed above (FP64, restart 10, rtol 1e-8, degree 2, 2+2). */

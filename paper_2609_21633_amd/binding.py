@@ -401,7 +401,7 @@ class SolverOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("outer_its", C.c_int), ("inner_its", C.c_int), ("rel_res", C.c_double),
-                ("seconds", C.c_double), ("status", C.c_int)]
+                ("seconds", C.c_double), ("status", C.c_int), ("fp64_its", C.c_int)]
 
 
 class StepOpts(C.Structure):

@@ -76,6 +76,11 @@ struct tng_solver {
     tng::DevBuf<const float*> rotptr32;
     tng::DevBuf<double> xo, ro, bo;     // outer FP64 vectors (mixed precision)
     tng::DevBuf<float> r32, d32;
+    // mixed precision after a stalled refinement: FP64 inner solves (level scratch,
+    // Krylov basis on ro, correction d64), set up on first use; fp64_ops: the FP64
+    // level operators are those of the current viscosity
+    bool fp64_inner = false, fp64_ops = false;
+    tng::DevBuf<double> d64;
     tng::DevBuf<double> scal;           // device scalars
     tng::DevBuf<const double*> dptr;    // [bo, ro, pressure of xo, k64.w]
     double* host = nullptr;             // pinned read-back buffer
@@ -582,6 +587,9 @@ void build_coarse_maps(tng_solver* s) {
 }
 
 template <typename T>
+void alloc_level_scratch(tng_solver* s, MGLevel<T>& M);
+
+template <typename T>
 void alloc_hierarchy(tng_solver* s, bool scratch) {
     auto& H = hier<T>(s);
     H.clear();
@@ -591,19 +599,24 @@ void alloc_hierarchy(tng_solver* s, bool scratch) {
         M.L = &s->mesh->lv[l];
         M.ns = M.L->node_slots();
         M.eta.alloc(2 * M.L->cells());
-        if (!scratch) continue;
-        const long long n3 = 3 * M.ns;
-        M.invd.alloc(n3);
-        M.x.alloc(n3);
-        M.b.alloc(n3);
-        M.r.alloc(n3);
-        M.y.alloc(n3);
-        M.d.alloc(n3);
-        M.cheb.alloc(2 * (size_t)std::max(1, s->opts.cheb_degree));
-        const T* xy[2] = {M.x.p, M.y.p};
-        M.xy.alloc(2);
-        TNG_HIP(hipMemcpy(M.xy.p, xy, sizeof(xy), hipMemcpyHostToDevice));
+        if (scratch) alloc_level_scratch<T>(s, M);
     }
+}
+
+// smoother, residual and transfer vectors of one level
+template <typename T>
+void alloc_level_scratch(tng_solver* s, MGLevel<T>& M) {
+    const long long n3 = 3 * M.ns;
+    M.invd.alloc(n3);
+    M.x.alloc(n3);
+    M.b.alloc(n3);
+    M.r.alloc(n3);
+    M.y.alloc(n3);
+    M.d.alloc(n3);
+    M.cheb.alloc(2 * (size_t)std::max(1, s->opts.cheb_degree));
+    const T* xy[2] = {M.x.p, M.y.p};
+    M.xy.alloc(2);
+    TNG_HIP(hipMemcpy(M.xy.p, xy, sizeof(xy), hipMemcpyHostToDevice));
 }
 
 template <typename T>
@@ -634,6 +647,8 @@ void alloc_krylov(tng_solver* s, const T* rhs) {
 }
 
 // largest eigenvalue of D^{-1} A on level l by seeded power iteration
+constexpr int FS_POWER_ITS = 100;
+
 template <typename T>
 double power_lmax(tng_solver* s, int l) {
     MGLevel<T>& M = hier<T>(s)[l];
@@ -650,8 +665,15 @@ double power_lmax(tng_solver* s, int l) {
     vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), xv, nullptr);
     const T* const* xp = M.xy.p;
     const T* const* yp = M.xy.p + 1;
+    // free slip: the largest eigenvalue of D^{-1} A can belong to a mode localised at a
+    // free-slip sphere under weak viscosity (the isotropic diagonal there), which holds
+    // little of the random start and has its neighbours close in the spectrum; a short
+    // iteration stops below it, Chebyshev then amplifies that mode on every step and
+    // the FP32 V-cycle, whose rounding seeds it, diverges within a few cycles (contrast
+    // 1e6 with free slip on the inner sphere).  At least FS_POWER_ITS iterations there.
+    const int its = fs_flag(s) ? std::max(s->opts.power_its, FS_POWER_ITS) : s->opts.power_its;
     double lam = 1.0;
-    for (int it = 0; it < s->opts.power_its; ++it) {
+    for (int it = 0; it < its; ++it) {
         apply_A<T>(s, l, M.eta.p, M.x.p, M.y.p);
         vec_mul<T>(s->ctx, n3, M.invd.p, M.y.p, M.y.p);
         vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), yv, nullptr);
@@ -683,6 +705,7 @@ void setup_level_operators(tng_solver* s) {
 
 void setup_viscosity(tng_solver* s, const double* eta_dev) {
     const bool mixed = s->opts.mixed != 0;
+    s->fp64_ops = false;
     auto& H = s->h64;
     TNG_HIP(hipMemcpyAsync(H[0].eta.p, eta_dev, 2 * L0(s).cells() * sizeof(double), hipMemcpyDeviceToDevice,
                            s->ctx->stream));
@@ -703,6 +726,25 @@ void setup_viscosity(tng_solver* s, const double* eta_dev) {
     }
     sync(s);
     s->ready = true;
+}
+
+// Mixed precision: the FP32 inner solves cannot resolve near-null modes whose relative
+// eigenvalue is below about the FP32 unit roundoff times the growth of the
+// preconditioner (free slip over a 1e6-weaker core: the core turning against the lid),
+// and the refinement then stalls.  The solve goes on with FP64 inner solves: level
+// scratch, operators and a Krylov basis on ro, allocated and set up here on first use.
+void enable_fp64_inner(tng_solver* s) {
+    if (!s->fp64_inner) {
+        for (auto& M : s->h64) alloc_level_scratch<double>(s, M);
+        alloc_krylov<double>(s, s->ro.p);
+        s->d64.alloc(s->N);
+        s->fp64_inner = true;
+    }
+    if (!s->fp64_ops) {
+        setup_level_operators<double>(s);
+        sync(s);
+        s->fp64_ops = true;
+    }
 }
 
 }  // namespace
@@ -942,6 +984,7 @@ namespace {
 void set_info(BSlot* sl) {
     sl->info.outer_its = sl->outer;
     sl->info.inner_its = sl->inner_total;
+    sl->info.fp64_its = sl->s->opts.mixed ? 0 : sl->inner_total;
     sl->info.rel_res = sl->relres;
     sl->info.status = sl->rc;
     sl->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl->t0).count();
@@ -1492,7 +1535,7 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     tng::readback(s, s->scal.p + 1, 1);
     const double bn = std::sqrt(s->host[0]);
     int status = TNG_OK;
-    int inner_total = 0, outer = 0;
+    int inner_total = 0, outer = 0, fp64_total = 0;
     double relres = bn > 0 ? 1.0 : 0.0;
     auto true_residual = [&]() {
         tng::remove_pressure_mean(s);
@@ -1514,7 +1557,34 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     } else {
         tng::vec_fill<double>(s->ctx, N, 0.0, xo);
         TNG_HIP(hipMemcpyAsync(ro, bvec, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        double best = relres;
+        int stalled = 0;
         while (relres > s->opts.rtol && outer < s->opts.max_outer) {
+            if (stalled >= 2) {
+                // two refinement steps in a row left the residual above 0.9 of the best
+                // one: FGMRES in FP64 on K d = r to the remaining tolerance
+                tng::enable_fp64_inner(s);
+                int its = 0;
+                double est = 0.0;
+                const int left = std::max(1, s->opts.max_iters - fp64_total);
+                const int rc = tng::fgmres<double>(s, s->h64[0].eta.p, ro, s->d64.p, s->opts.rtol / relres, left,
+                                                   &its, &est);
+                inner_total += its;
+                fp64_total += its;
+                ++outer;
+                if (rc != TNG_OK) {
+                    status = rc;
+                    break;
+                }
+                tng::vec_axpby<double>(s->ctx, N, 1.0, s->d64.p, 1.0, xo);
+                relres = true_residual();
+                if (!std::isfinite(relres)) {
+                    status = TNG_E_NOTCONV;
+                    break;
+                }
+                if (fp64_total >= s->opts.max_iters) break;
+                continue;
+            }
             tng::vec_cast<float, double>(s->ctx, N, ro, s->r32.p);
             int its = 0;
             double inner_rel = 0.0;
@@ -1534,6 +1604,8 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
                 status = TNG_E_NOTCONV;
                 break;
             }
+            stalled = relres > 0.9 * best ? stalled + 1 : 0;
+            best = std::min(best, relres);
         }
     }
     if (status == TNG_OK && !(relres <= s->opts.rtol)) status = TNG_E_NOTCONV;
@@ -1544,6 +1616,7 @@ int tng_stokes_solve(tng_solver* s, const double* eta_wedge, const double* const
     if (info) {
         info->outer_its = outer;
         info->inner_its = inner_total;
+        info->fp64_its = mixed ? fp64_total : inner_total;
         info->rel_res = relres;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->status = status;

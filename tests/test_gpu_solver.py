@@ -450,3 +450,79 @@ def test_tala_freeslip_solve_matches_direct_solve(tng, ctx, mixed):
           f"err u {eu:.2e} p {ep:.2e}")
     assert info["rel_res"] <= 1e-10
     assert eu < 1e-7 and ep < 1e-7
+
+
+def test_contrast1e6_freeslip_both_matches_direct_solve(tng, ctx):
+    """Free slip on both spheres under viscosity contrast 1e6 (eta = exp(-ln(1e6) Tbar),
+    the hot inner sphere 1e6 weaker than the cold lid), FP64 and mixed, against the
+    oracle's gauged direct solve with the rotation constraints on the (8,8) shell."""
+    import torch
+    from oracle.stokes import buoyancy_rhs, eta_from_temperature
+    mt = 8
+    mesh, om, omp, lm, lmp, _, _, _ = case(tng, ctx, mt)
+    T = synthetic.temperature(om.s, om.r, seed=1, lmin=1, lmax=8, amp=0.01).ravel()
+    eta = eta_from_temperature(om, T, np.log(1e6), 0.0)
+    ofs = StokesOracle(mt, mt, eta, hierarchy=om.h, bc=("freeslip", "freeslip"))
+    # the buoyancy with its normal part removed on both spheres, orthogonal to the rotations
+    f = buoyancy_rhs(om, T, 1e5)
+    rhat = om.node_xyz() / np.linalg.norm(om.node_xyz(), axis=1)[:, None]
+    k = np.tile(np.arange(mt + 1), om.n_lat)
+    sph = (k == 0) | (k == mt)
+    f[sph] -= np.sum(f[sph] * rhat[sph], 1)[:, None] * rhat[sph]
+    R = ofs.rotations()
+    f = (f.ravel() - R @ np.linalg.solve(R.T @ R, R.T @ f.ravel())).reshape(-1, 3)
+    uo, po, _ = ofs.solve_gauged(f)
+    eta_t = torch.tensor(eta[lm.wedge_index()], device="cuda")
+    bits = tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER
+    for mixed in (0, 1):
+        s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-10, restart=23, max_iters=2000, max_outer=40,
+                             op_flags=bits)
+        u = torch.empty((3,) + mesh.shape(0), dtype=torch.float64, device="cuda")
+        p = torch.empty(mesh.shape(1), dtype=torch.float64, device="cuda")
+        info = s.solve(vel(lm, f), None, u, p, eta=eta_t, raise_on_fail=False)
+        s.close()
+        eu = rel(lm.from_lib(u.cpu().numpy(), check_dups=1e-12), uo)
+        ep = rel(lmp.from_lib(p.cpu().numpy(), check_dups=1e-12), po)
+        print(f"contrast 1e6, free slip both (8,8) mixed={mixed}: its {info['inner_its']} "
+              f"(FP64 {info['fp64_its']}) refinements {info['outer_its']} res {info['rel_res']:.2e} "
+              f"err u {eu:.2e} p {ep:.2e}", flush=True)
+        assert info["rc"] == 0 and info["rel_res"] <= 1e-10
+        assert eu < 1e-7 and ep < 1e-7
+        assert info["fp64_its"] == (0 if mixed else info["inner_its"])
+
+
+def test_mixed_falls_back_to_fp64_when_refinement_stalls(tng, ctx):
+    """The contrast-1e6 free-slip (both spheres) solve on the (64,64) shell: the weak core
+    turning against the lid is a near-null mode that FP32 inner solves cannot resolve at
+    this resolution, the mixed refinement stalls and the solve finishes with FP64 inner
+    FGMRES: it reaches the tolerance with FP32 iterations first and FP64 ones after, and
+    its solution is the FP64 solve's (both to relative residual 1e-9)."""
+    import torch
+    mt = 64
+    mesh = tng.Mesh(ctx, mt, mt, levels=6)
+    xyz, r = mesh.coords(0)
+    T = synthetic.temperature(xyz.reshape(-1, 3), r, seed=1, lmin=1, lmax=8, amp=0.01)
+    Tt = torch.tensor(T.reshape(mesh.shape(0)), device="cuda", dtype=torch.float64)
+    eta = torch.empty(mesh.wedge_shape(0), device="cuda", dtype=torch.float64)
+    tng.eta_from_temperature(ctx, mesh, 0, Tt, float(np.log(1e6)), 0.0, eta)
+    bits = tng.OP_FREESLIP_INNER | tng.OP_FREESLIP_OUTER
+    f = torch.empty((3,) + mesh.shape(0), device="cuda", dtype=torch.float64)
+    tng.rhs_buoyancy(ctx, mesh, 0, Tt, 1e5, f, bc_flags=bits)
+    out = {}
+    for mixed in (0, 1):
+        s = tng.StokesSolver(ctx, mesh, mixed=mixed, rtol=1e-9, restart=23, max_iters=2000, max_outer=40,
+                             op_flags=bits)
+        u = torch.empty_like(f)
+        p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
+        info = s.solve(f, None, u, p, eta=eta, raise_on_fail=False)
+        s.close()
+        out[mixed] = (info, u, p)
+        print(f"contrast 1e6, free slip both (64,64) mixed={mixed}: its {info['inner_its']} "
+              f"(FP64 {info['fp64_its']}) refinements {info['outer_its']} res {info['rel_res']:.2e}", flush=True)
+        assert info["rc"] == 0 and info["rel_res"] <= 1e-9
+    info = out[1][0]
+    assert 0 < info["fp64_its"] < info["inner_its"]      # FP32 first, then FP64
+    du = float((out[1][1] - out[0][1]).norm() / out[0][1].norm())
+    dp = float((out[1][2] - out[0][2]).norm() / out[0][2].norm())
+    print(f"mixed vs FP64 solution: u {du:.2e} p {dp:.2e}", flush=True)
+    assert du < 1e-7 and dp < 1e-7

@@ -397,6 +397,7 @@ def bench_variants(tng, ctx):
                     sv.close()
                     out["solve"].append({"shell": [mt, mt], "law": law, "variant": name,
                                          "mode": "mixed" if mixed else "fp64", "its": info["inner_its"],
+                                         "fp64_its": info["fp64_its"],
                                          "refinements": info["outer_its"], "rel_res": info["rel_res"],
                                          "seconds": round(wall, 3), "rc": info["rc"]})
                     log(f"[variants] {out['solve'][-1]}")

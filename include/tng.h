@@ -297,8 +297,11 @@ int tng_prolong(tng_ctx* ctx, const tng_mesh* mesh, int fine_level, tng_prec pre
  * cheb_degree, pre, post: Chebyshev smoother of degree cheb_degree on
  *   D^{-1} A, pre/post steps per level (paper: 2, 2, 2), on the interval
  *   [cheb_lo, cheb_hi] * lambda_max(D^{-1} A), lambda_max from power_its
- *   seeded power iterations (at least 100 with a free-slip sphere, whose
- *   weak-viscosity nodes can hold the largest eigenvalue).
+ *   seeded power iterations.  With free slip on a sphere of much weaker
+ *   viscosity (contrast 1e6) the largest eigenvalue can belong to a mode
+ *   localised there that 10 iterations miss; the stand-alone FP32 V-cycle
+ *   then needs about 100; a mixed solve there stalls and finishes with FP64
+ *   inner solves (tng_solve_info).
  * levels: multigrid levels used (0 = all levels of the mesh); the coarsest
  *   one is solved exactly and must have at most 1024 interior DoFs.
  * inner_rtol, inner_max_iters, max_outer: mixed-precision inner tolerance and

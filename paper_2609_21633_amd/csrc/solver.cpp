@@ -647,8 +647,6 @@ void alloc_krylov(tng_solver* s, const T* rhs) {
 }
 
 // largest eigenvalue of D^{-1} A on level l by seeded power iteration
-constexpr int FS_POWER_ITS = 100;
-
 template <typename T>
 double power_lmax(tng_solver* s, int l) {
     MGLevel<T>& M = hier<T>(s)[l];
@@ -665,15 +663,8 @@ double power_lmax(tng_solver* s, int l) {
     vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), xv, nullptr);
     const T* const* xp = M.xy.p;
     const T* const* yp = M.xy.p + 1;
-    // free slip: the largest eigenvalue of D^{-1} A can belong to a mode localised at a
-    // free-slip sphere under weak viscosity (the isotropic diagonal there), which holds
-    // little of the random start and has its neighbours close in the spectrum; a short
-    // iteration stops below it, Chebyshev then amplifies that mode on every step and
-    // the FP32 V-cycle, whose rounding seeds it, diverges within a few cycles (contrast
-    // 1e6 with free slip on the inner sphere).  At least FS_POWER_ITS iterations there.
-    const int its = fs_flag(s) ? std::max(s->opts.power_its, FS_POWER_ITS) : s->opts.power_its;
     double lam = 1.0;
-    for (int it = 0; it < its; ++it) {
+    for (int it = 0; it < s->opts.power_its; ++it) {
         apply_A<T>(s, l, M.eta.p, M.x.p, M.y.p);
         vec_mul<T>(s->ctx, n3, M.invd.p, M.y.p, M.y.p);
         vec_fs_project<T>(s->ctx, *M.L, fs_bits(s), yv, nullptr);

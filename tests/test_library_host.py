@@ -135,3 +135,46 @@ def test_binding_refuses_bad_tensors_before_any_call():
         tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, Fake(eta.reshape(-1)[:10].clone()), Fake(u), None, Fake(y), None)
     with pytest.raises(ValueError, match="contiguous"):
         tng.stokes_apply(Ctx, mesh, 0, tng.OP_A, Fake(eta), Fake(u.transpose(1, 2)), None, Fake(y), None)
+
+
+def test_binding_structs_mirror_the_header(tmp_path):
+    """The ctypes mirrors of the option and result structs have the C header's size
+    and field offsets (a field added to one side only shifts every later one)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2609_21633_amd import binding as b
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tng_solver_opts": b.SolverOpts, "tng_solve_info": b.SolveInfo,
+               "tng_step_opts": b.StepOpts, "tng_step_info": b.StepInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tng.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+    # the same field names in the same order (a field added in the padding of the last
+    # one keeps the size)
+    hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "tng.h")).read(), flags=re.S)
+    for cname, py in structs.items():
+        body = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + cname + r"\s*;", hdr).group(1)
+        names = []
+        for decl in filter(None, (d.strip() for d in body.split(";"))):
+            for part in decl.split(","):
+                names.append(re.findall(r"[A-Za-z_][A-Za-z0-9_]*", part.split("[")[0])[-1])
+        assert names == [f for f, _ in py._fields_], (cname, names)

@@ -515,6 +515,15 @@ def test_mixed_falls_back_to_fp64_when_refinement_stalls(tng, ctx):
         u = torch.empty_like(f)
         p = torch.empty(mesh.shape(1), device="cuda", dtype=torch.float64)
         info = s.solve(f, None, u, p, eta=eta, raise_on_fail=False)
+        if mixed:
+            # a second solve on the same solver: the viscosity set up again (the FP64 level
+            # operators redone at the next stall), the FP64 scratch, basis and preconditioner
+            # graphs of the first fallback reused; the solves are deterministic
+            u2, p2 = torch.empty_like(u), torch.empty_like(p)
+            info2 = s.solve(f, None, u2, p2, eta=eta, raise_on_fail=False)
+            assert {k: info2[k] for k in ("inner_its", "fp64_its", "outer_its", "rel_res", "rc")} == \
+                   {k: info[k] for k in ("inner_its", "fp64_its", "outer_its", "rel_res", "rc")}
+            assert torch.equal(u2, u) and torch.equal(p2, p)
         s.close()
         out[mixed] = (info, u, p)
         print(f"contrast 1e6, free slip both (64,64) mixed={mixed}: its {info['inner_its']} "

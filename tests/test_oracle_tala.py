@@ -10,6 +10,8 @@ rhobar u interpolated nodally, B_rho = B R, R = diag(rhobar(r_j)).
   the product form rhobar div u + u . grad rhobar at q_c (a plausible
   alternative) violates it, which would leave the saddle point inconsistent.
 * A mass flux rhobar u that is a rigid rotation is divergence-free: B_rho u = 0.
+* With free slip the mass rows are B R P: a velocity normal to the spheres carries no
+  mass through them (it does without the projection), a tangential one enters unchanged.
 * Manufactured anelastic solution u = curl(psi) / rhobar: second order.
 * The TALA buoyancy reduces to the Boussinesq one for rhobar alphabar = 1, Tbar = 0,
   and vanishes for T = Tbar.
@@ -75,6 +77,30 @@ def test_compatibility_and_divergence_free_flux(shell):
     total_nodal_form = ones @ (o.B_mass @ uu.ravel())
     assert abs(total_nodal_form) < 1e-14 * np.abs(o.B_mass @ uu.ravel()).sum()
     assert abs(total_product_form) > 1e-6 * np.abs(o.B_mass @ uu.ravel()).sum()
+
+
+def test_freeslip_mass_rows_take_the_tangential_sphere_velocity(shell):
+    """With free slip the mass rows are B R P: a velocity normal to the spheres (at their
+    nodes only) carries no mass through them, while without the projection it does; a
+    tangential sphere velocity enters unchanged."""
+    om, eta = shell
+    rho = rho_of(om.r)
+    o_fs = StokesOracle(4, 4, eta, hierarchy=om.h, rho_nodes=rho, bc=("freeslip", "freeslip"))
+    o_no = StokesOracle(4, 4, eta, hierarchy=om.h, rho_nodes=rho, bc=("none", "none"))
+    x = om.node_xyz()
+    rhat = x / np.linalg.norm(x, axis=1)[:, None]
+    k = np.tile(np.arange(om.nr + 1), om.n_lat)
+    interior = (k != 0) & (k != om.nr)
+    rng = np.random.default_rng(8)
+    un = rhat * rng.standard_normal(om.n_nodes)[:, None]
+    un[interior] = 0.0
+    scale = abs(o_no.B_mass).max() * np.abs(un).max()
+    assert np.abs(o_fs.B_mass @ un.ravel()).max() <= 1e-14 * scale
+    assert np.abs(o_no.B_mass @ un.ravel()).max() > 1e-2 * scale
+    w = rng.standard_normal((om.n_nodes, 3))
+    ut = w - rhat * np.sum(w * rhat, 1)[:, None]
+    ut[interior] = w[interior]
+    assert np.abs(o_fs.B_mass @ ut.ravel() - o_no.B_mass @ ut.ravel()).max() <= 1e-14 * abs(o_no.B_mass).max() * 4
 
 
 def test_tala_buoyancy_special_cases(shell):
